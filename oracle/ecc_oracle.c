@@ -1,0 +1,185 @@
+/*
+ * ORACLE -- test infrastructure only.
+ *
+ * A plain, slow CPU computation of the Euler characteristic curve of a
+ * d-dimensional gray-scale image, written straight from the definitions of
+ * Heiss & Wagner, "Streaming Algorithm for Euler Characteristic Curves of
+ * Multidimensional Images" (arXiv 1705.02045), Section 2:
+ *
+ *  - Cubical cell (Sec. 2, "Cubical Cell"): a product of d factors, each an
+ *    interval [a, a+1] or a singleton {b}; its dimension is the number of
+ *    interval factors.  We index cells by doubled coordinates q in
+ *    prod_k [0, 2 n_k]: odd q_k = 2a+1 is the interval [a, a+1], even
+ *    q_k = 2b is the singleton {b}.
+ *  - Image as a complex (Sec. 2, "Consecutive Thresholded Images as Sublevel
+ *    Set Filtrations"): voxel (i_1..i_d) is the d-cell prod [i_k - 1, i_k]
+ *    (1-based in the paper; 0-based here, voxel a is [a, a+1]); K is the set of
+ *    all voxel cells and all their faces.  Every q above is a cell of K.
+ *  - Sublevel set filtration (Sec. 2, "Sublevel Set Filtration"): a cell's
+ *    value is the minimum of f over the voxels (maximal cells) containing it.
+ *    Those voxels are prod_k I_k with I_k = {a} for odd q_k and
+ *    I_k = {b-1, b} intersected with [0, n_k) for even q_k.
+ *  - Euler characteristic (Sec. 2, "Euler Characteristic"):
+ *    chi = sum_k (-1)^k n_k.
+ *  - VCEC (Sec. 3, "Tracking the Changes"): a_t = chi(T_t) - chi(T_{t-1}),
+ *    which is the signed count of cells whose value is exactly t; the curve
+ *    is its prefix sum (Sec. 3, "Post-Processing").
+ *
+ * Nothing here uses the paper's per-voxel "introduced faces" rule: every cell
+ * is visited once and its value is computed from its incident voxels.  Threads
+ * only split the cells by ranges of the first doubled coordinate, each thread
+ * into a private int64 array, and the arrays are summed at the end.
+ *
+ * Element types: 1 = uint8, 2 = uint16, 4 = uint32.  Every value must be < m.
+ */
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MAXD 8
+
+typedef struct {
+    const void *img;
+    int elem, d;
+    int64_t n[MAXD], stride[MAXD];
+    int64_t m;
+    int64_t q0_lo, q0_hi;
+    int64_t *vcec;
+} job_t;
+
+static inline uint64_t load(const void *img, int elem, int64_t i) {
+    switch (elem) {
+    case 1: return ((const uint8_t *)img)[i];
+    case 2: return ((const uint16_t *)img)[i];
+    default: return ((const uint32_t *)img)[i];
+    }
+}
+
+/* Adds the signed count of every cell with first doubled coordinate in
+ * [q0_lo, q0_hi) into vcec[value]. */
+static void count_cells(const job_t *j) {
+    const int d = j->d;
+    int64_t q[MAXD], lo[MAXD], hi[MAXD], idx[MAXD];
+    for (int64_t q0 = j->q0_lo; q0 < j->q0_hi; ++q0) {
+        q[0] = q0;
+        for (int k = 1; k < d; ++k) q[k] = 0;
+        for (;;) {
+            /* incident voxels and dimension of cell q */
+            int dim = 0;
+            for (int k = 0; k < d; ++k) {
+                if (q[k] & 1) {
+                    lo[k] = hi[k] = (q[k] - 1) / 2;
+                    ++dim;
+                } else {
+                    int64_t b = q[k] / 2;
+                    lo[k] = b - 1 < 0 ? 0 : b - 1;
+                    hi[k] = b > j->n[k] - 1 ? j->n[k] - 1 : b;
+                }
+            }
+            /* minimum of f over the incident voxels */
+            uint64_t best = UINT64_MAX;
+            for (int k = 0; k < d; ++k) idx[k] = lo[k];
+            for (;;) {
+                int64_t lin = 0;
+                for (int k = 0; k < d; ++k) lin += idx[k] * j->stride[k];
+                uint64_t v = load(j->img, j->elem, lin);
+                if (v < best) best = v;
+                int k = d - 1;
+                while (k >= 0 && idx[k] == hi[k]) { idx[k] = lo[k]; --k; }
+                if (k < 0) break;
+                ++idx[k];
+            }
+            j->vcec[best] += (dim & 1) ? -1 : 1;
+            /* next cell in this q0 layer */
+            int k = d - 1;
+            while (k >= 1 && q[k] == 2 * j->n[k]) { q[k] = 0; --k; }
+            if (k < 1) break;
+            ++q[k];
+        }
+    }
+}
+
+static void *run_job(void *p) {
+    count_cells((const job_t *)p);
+    return NULL;
+}
+
+static int setup(job_t *base, const void *img, int elem, int d, const int64_t *n, int64_t m) {
+    if (!img || d < 1 || d > MAXD || m < 1 || (elem != 1 && elem != 2 && elem != 4)) return -1;
+    int64_t total = 1;
+    for (int k = d - 1; k >= 0; --k) {
+        if (n[k] < 1) return -1;
+        base->n[k] = n[k];
+        base->stride[k] = total;
+        total *= n[k];
+    }
+    for (int64_t i = 0; i < total; ++i)
+        if (load(img, elem, i) >= (uint64_t)m) return -2;
+    base->img = img; base->elem = elem; base->d = d; base->m = m;
+    return 0;
+}
+
+/* Signed cell counts for cells with q_0 in [q0_lo, q0_hi), added into vcec[0..m). */
+int oracle_vcec_range(const void *img, int elem, int d, const int64_t *n, int64_t m,
+                      int64_t q0_lo, int64_t q0_hi, int64_t *vcec) {
+    job_t j;
+    memset(&j, 0, sizeof j);
+    int rc = setup(&j, img, elem, d, n, m);
+    if (rc) return rc;
+    if (q0_lo < 0) q0_lo = 0;
+    if (q0_hi > 2 * n[0] + 1) q0_hi = 2 * n[0] + 1;
+    j.q0_lo = q0_lo; j.q0_hi = q0_hi; j.vcec = vcec;
+    if (q0_lo < q0_hi) count_cells(&j);
+    return 0;
+}
+
+/* VCEC of the whole image with up to nthreads threads.  Thread count is
+ * lowered so that the private arrays stay within max_bytes. */
+int oracle_vcec(const void *img, int elem, int d, const int64_t *n, int64_t m,
+                int64_t *vcec, int nthreads, int64_t max_bytes) {
+    job_t base;
+    memset(&base, 0, sizeof base);
+    int rc = setup(&base, img, elem, d, n, m);
+    if (rc) return rc;
+    int64_t layers = 2 * n[0] + 1;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if (nthreads > layers) nthreads = (int)layers;
+    if (max_bytes > 0) {
+        int64_t cap = max_bytes / (m * (int64_t)sizeof(int64_t));
+        if (cap < 1) cap = 1;
+        if (nthreads > cap) nthreads = (int)cap;
+    }
+    memset(vcec, 0, (size_t)m * sizeof(int64_t));
+    if (nthreads == 1) {
+        base.q0_lo = 0; base.q0_hi = layers; base.vcec = vcec;
+        count_cells(&base);
+        return 0;
+    }
+    job_t jobs[256];
+    pthread_t th[256];
+    int64_t *priv = (int64_t *)calloc((size_t)m * (size_t)nthreads, sizeof(int64_t));
+    if (!priv) return -3;
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = base;
+        jobs[t].q0_lo = layers * t / nthreads;
+        jobs[t].q0_hi = layers * (t + 1) / nthreads;
+        jobs[t].vcec = priv + (size_t)m * t;
+        pthread_create(&th[t], NULL, run_job, &jobs[t]);
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    for (int t = 0; t < nthreads; ++t)
+        for (int64_t s = 0; s < m; ++s) vcec[s] += priv[(size_t)m * t + s];
+    free(priv);
+    return 0;
+}
+
+/* The curve chi(T_t), t = 0..m-1: prefix sums of the VCEC. */
+int oracle_curve(const void *img, int elem, int d, const int64_t *n, int64_t m,
+                 int64_t *chi, int nthreads, int64_t max_bytes) {
+    int rc = oracle_vcec(img, elem, d, n, m, chi, nthreads, max_bytes);
+    if (rc) return rc;
+    for (int64_t t = 1; t < m; ++t) chi[t] += chi[t - 1];
+    return 0;
+}

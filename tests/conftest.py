@@ -1,0 +1,21 @@
+import pathlib
+import sys
+
+ROOT = pathlib.Path(__file__).resolve().parents[1]
+if str(ROOT) not in sys.path:
+    sys.path.insert(0, str(ROOT))
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X GPU; runs the HIP path through the C ABI")
+
+
+def _ensure_built():
+    """Build the native libraries once if nothing is built (a fresh checkout)."""
+    need = [ROOT / "oracle" / "liboracle.so", ROOT / "gen" / "libeccgen.so"]
+    if not all(p.exists() for p in need):
+        import __graft_entry__
+        __graft_entry__.build_cpu()
+
+
+_ensure_built()

@@ -1,0 +1,211 @@
+"""The oracle pinned to things other than itself.
+
+- golden/: small images whose curves were derived by hand (each file cites the
+  passage its reasoning uses);
+- brute-force Z/2 homology of the closure of {f <= t} (a different construction
+  of T_t), with beta_0 and beta_(d-1) also checked against scipy labelling;
+- textbook reductions: runs in 1-D, components minus holes in 2-D;
+- closed forms: empty complex below the minimum, contractible box at the top,
+  constant images, a single voxel;
+- invariants: flips, axis permutations, strictly increasing relabelling,
+  splitting axis 0 into chunks each read with a one-voxel collar.
+"""
+import itertools
+import pathlib
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+
+import oracle
+from homology import betti
+
+GOLDEN = pathlib.Path(__file__).parent / "golden"
+
+
+def load_fixture(path):
+    rec = {}
+    for line in path.read_text().splitlines():
+        if not line.strip() or line.startswith("#"):
+            continue
+        key, val = line.split(":", 1)
+        rec[key.strip()] = [int(x) for x in val.split()]
+    img = np.array(rec["values"], dtype=np.uint8).reshape(rec["shape"])
+    return img, rec["m"][0], np.array(rec["chi"], dtype=np.int64)
+
+
+@pytest.mark.parametrize("path", sorted(GOLDEN.glob("*.txt")), ids=lambda p: p.stem)
+def test_golden_fixture(path):
+    img, m, chi = load_fixture(path)
+    assert (oracle.curve(img, m=m) == chi).all()
+
+
+def rand_img(rng, shape, m):
+    return rng.integers(0, m, size=shape).astype(np.uint8 if m <= 256 else np.uint16)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5])
+def test_closed_forms(d):
+    rng = np.random.default_rng(d)
+    for _ in range(6):
+        shape = tuple(int(x) for x in rng.integers(1, 6, size=d))
+        m = int(rng.integers(2, 9))
+        img = rand_img(rng, shape, m)
+        chi = oracle.curve(img, m=m)
+        lo, hi = int(img.min()), int(img.max())
+        assert (chi[:lo] == 0).all()          # empty complex below the minimum
+        assert (chi[hi:] == 1).all()          # the full box is contractible
+        c = int(rng.integers(0, m))
+        const = np.full(shape, c, dtype=img.dtype)
+        assert (oracle.curve(const, m=m) == (np.arange(m) >= c)).all()
+
+
+def test_single_voxel_every_dimension():
+    for d in range(1, 7):
+        img = np.full((1,) * d, 2, dtype=np.uint8)
+        assert (oracle.curve(img, m=4) == [0, 0, 1, 1]).all()
+
+
+def _holes(mask):
+    d = mask.ndim
+    comp = np.pad(~mask, 1, constant_values=True)
+    _, k = ndi.label(comp, structure=ndi.generate_binary_structure(d, 1))
+    return k - 1
+
+
+@pytest.mark.parametrize("shape,m,trials", [((8, 8), 4, 12), ((5, 7), 3, 12), ((4, 4, 4), 3, 6),
+                                            ((3, 4, 5), 4, 6), ((9,), 4, 10)])
+def test_homology_brute_force(shape, m, trials):
+    rng = np.random.default_rng(sum(shape) * 31 + m)
+    d = len(shape)
+    for _ in range(trials):
+        img = rand_img(rng, shape, m)
+        chi = oracle.curve(img, m=m)
+        for t in range(m):
+            mask = img <= t
+            beta, n = betti(mask)
+            assert chi[t] == sum((-1) ** k * b for k, b in enumerate(beta))
+            assert chi[t] == sum((-1) ** k * c for k, c in enumerate(n))
+            assert all(b >= 0 for b in beta) and beta[d] == 0
+            _, comps = ndi.label(mask, structure=np.ones((3,) * d))
+            assert beta[0] == comps                    # (3^d - 1)-connectivity
+            if d >= 2:
+                assert beta[d - 1] == _holes(mask)     # Alexander duality
+
+
+def test_1d_runs():
+    rng = np.random.default_rng(11)
+    for _ in range(50):
+        n = int(rng.integers(1, 60))
+        m = int(rng.integers(1, 10))
+        img = rand_img(rng, (n,), m)
+        chi = oracle.curve(img, m=m)
+        for t in range(m):
+            mask = (img <= t).astype(np.int8)
+            runs = int(mask[0]) + int(np.sum((mask[1:] == 1) & (mask[:-1] == 0)))
+            assert chi[t] == runs
+
+
+def test_2d_components_minus_holes():
+    rng = np.random.default_rng(12)
+    import gen
+    imgs = [rand_img(rng, (40, 37), 6) for _ in range(4)]
+    imgs.append(gen.cfg_u8_value_noise((48, 64), seed=4) // 32)
+    for img in imgs:
+        m = int(img.max()) + 1
+        chi = oracle.curve(img.astype(np.uint8), m=m)
+        for t in range(m):
+            mask = img <= t
+            _, comps = ndi.label(mask, structure=np.ones((3, 3)))
+            assert chi[t] == comps - _holes(mask)
+
+
+def test_3d_tunnels_nonnegative():
+    rng = np.random.default_rng(13)
+    for _ in range(3):
+        img = rand_img(rng, (12, 10, 11), 5)
+        chi = oracle.curve(img, m=5)
+        for t in range(5):
+            mask = img <= t
+            _, b0 = ndi.label(mask, structure=np.ones((3, 3, 3)))
+            b2 = _holes(mask)
+            assert b0 + b2 - chi[t] >= 0
+
+
+@pytest.mark.parametrize("d", [2, 3, 4])
+def test_flip_and_permutation_invariance(d):
+    rng = np.random.default_rng(20 + d)
+    shape = tuple(int(x) for x in rng.integers(2, 7, size=d))
+    img = rand_img(rng, shape, 7)
+    ref = oracle.curve(img, m=7)
+    for ax in range(d):
+        assert (oracle.curve(np.flip(img, ax), m=7) == ref).all()
+    for perm in itertools.permutations(range(d)):
+        assert (oracle.curve(np.transpose(img, perm), m=7) == ref).all()
+
+
+def test_monotone_relabel():
+    rng = np.random.default_rng(30)
+    img = rand_img(rng, (9, 8, 7), 10)
+    table = np.cumsum(rng.integers(1, 5, size=10))  # strictly increasing map 0..9 -> ...
+    m2 = int(table[-1]) + 1
+    img2 = table[img].astype(np.uint16)
+    c1 = oracle.curve(img, m=10)
+    c2 = oracle.curve(img2, m=m2)
+    for t in range(10):
+        hi = table[t + 1] if t + 1 < 10 else m2
+        assert (c2[table[t]:hi] == c1[t]).all()
+    assert (c2[: table[0]] == 0).all()
+
+
+@pytest.mark.parametrize("shape", [(10, 6, 5), (7, 9), (6, 3, 4, 3)])
+def test_chunks_with_collar_sum_to_whole(shape):
+    """Each chunk of axis-0 planes, read with a one-voxel collar below it, yields
+    the signed counts of its own cells; the parts add up (Sec. 3, Streaming and
+    Processing one Chunk)."""
+    rng = np.random.default_rng(40)
+    m = 6
+    img = rand_img(rng, shape, m)
+    whole = oracle.vcec(img, m=m)
+    n0 = shape[0]
+    for cuts in [(0, n0), (0, 1, n0), (0, 3, 4, n0), tuple(range(n0 + 1))]:
+        total = np.zeros(m, np.int64)
+        for z0, z1 in zip(cuts[:-1], cuts[1:]):
+            lo = max(z0 - 1, 0)
+            sub = np.ascontiguousarray(img[lo:z1])
+            q_lo = 2 * (z0 - lo)
+            q_hi = 2 * (z1 - lo) + (1 if z1 == n0 else 0)
+            total += oracle.vcec_q0_range(sub, m, q_lo, q_hi)
+        assert (total == whole).all(), cuts
+
+
+def test_threads_do_not_change_result():
+    rng = np.random.default_rng(41)
+    img = rand_img(rng, (17, 13, 11), 50)
+    ref = oracle.curve(img, m=50, nthreads=1)
+    for t in (2, 3, 7, 16):
+        assert (oracle.curve(img, m=50, nthreads=t) == ref).all()
+
+
+def test_value_out_of_range_is_rejected():
+    with pytest.raises(ValueError):
+        oracle.curve(np.array([[0, 5]], dtype=np.uint8), m=5)
+
+
+def test_float_reading_matches_integer_curve():
+    rng = np.random.default_rng(50)
+    img = rand_img(rng, (6, 7, 5), 40)
+    keys, chi = oracle.curve_float(img.astype(np.float32))
+    ref = oracle.curve(img, m=40)
+    assert (keys == np.unique(img).astype(np.float32)).all()
+    assert (chi == ref[np.unique(img)]).all()
+
+
+def test_float_signed_zero_and_nan():
+    img = np.array([[-0.0, 1.0], [0.0, -np.inf]], dtype=np.float32)
+    keys, chi = oracle.curve_float(img)
+    assert list(keys) == [-np.inf, 0.0, 1.0] and not np.signbit(keys[1])
+    # T_{-inf}: one pixel; T_0: three pixels of a 2x2 block (connected); T_1: full
+    assert list(chi) == [1, 1, 1]
+    with pytest.raises(ValueError):
+        oracle.curve_float(np.array([1.0, np.nan], dtype=np.float32))
