@@ -1,0 +1,161 @@
+/*
+ * libecc -- Euler characteristic curves of d-dimensional gray-scale images on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (Heiss & Wagner, arXiv 1705.02045):
+ *   The image is the cubical complex of Sec. 2 ("Consecutive Thresholded
+ *   Images as Sublevel Set Filtrations"): every voxel is a closed unit d-cube
+ *   and the complex holds all voxels and all their faces.  A cell enters the
+ *   filtration at the minimum gray value of the voxels that contain it
+ *   (Sec. 2, "Sublevel Set Filtration").  T_t is the complex of cells with
+ *   value <= t, and the output is chi(T_t) for every threshold t (Sec. 2,
+ *   "Euler Characteristic Curve of an Image"), i.e. the prefix sums of the
+ *   vector of changes a_t = chi(T_t) - chi(T_{t-1}) (Sec. 3, "Tracking the
+ *   Changes" and "Post-Processing").  Counts are exact int64.
+ *
+ * Layout: images are dense, C order, dims[0] slowest (the axis along which
+ * the streaming interface cuts chunks, Sec. 3 "Streaming"), no padding.
+ *
+ * Errors: every function returns an ecc_status.  Nothing aborts or throws.
+ * On failure the caller's output buffers are left unmodified and
+ * ecc_last_error() (thread-local) describes the failure.
+ *
+ * Pointers: "device" means memory the HIP runtime reports as device memory on
+ * the current device; "host" is any other readable memory.  The library never
+ * frees caller memory.  Streams are hipStream_t values passed as void*; NULL
+ * is the null stream.
+ */
+#ifndef ECC_H
+#define ECC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ECC_OK = 0,
+    ECC_E_ARG = -1,              /* null pointer, bad ndim/dims/dtype, size overflow */
+    ECC_E_RANGE = -2,            /* an ECC_U14 value is >= 16384 */
+    ECC_E_NAN = -3,              /* an ECC_F32 image holds a NaN */
+    ECC_E_BUFFER_TOO_SMALL = -4, /* curve capacity too small; count holds the size needed */
+    ECC_E_STATE = -5,            /* streaming call out of order */
+    ECC_E_NOMEM = -6,            /* device or pinned-host allocation failed */
+    ECC_E_HIP = -7,              /* a HIP runtime call failed; message has hipGetErrorString */
+    ECC_E_UNSUPPORTED = -8       /* valid request this build does not implement */
+} ecc_status;
+
+/* Value types.  m is the number of thresholds t = 0..m-1 (Sec. 3, "Range of
+ * Values": values in {0, ..., m-1}). */
+typedef enum {
+    ECC_U8 = 1,   /* uint8,  m = 256 */
+    ECC_U14 = 2,  /* uint16 storage, values < 16384, m = 16384 */
+    ECC_U16 = 3,  /* uint16, m = 65536 */
+    ECC_F32 = 4   /* float32; thresholds are the distinct values (Sec. 3, "Other Ranges of Gray Values") */
+} ecc_dtype;
+
+/* 1 <= ndim <= 4, n[k] >= 1 for k < ndim, n[0] slowest.  Entries past ndim are ignored. */
+typedef struct {
+    int32_t ndim;
+    int64_t n[4];
+} ecc_dims;
+
+/* Output curve.
+ *   capacity: in, entries available in chi (and keys for ECC_F32).
+ *   count:    out, entries written (m, or the number K of distinct values for
+ *             ECC_F32); on ECC_E_BUFFER_TOO_SMALL, the entries needed.
+ *   chi:      out, chi[i] = chi(T_t) for the i-th threshold; host or device.
+ *   keys:     ECC_F32 only: ascending distinct values, -0.0 stored as +0.0;
+ *             host or device.  Ignored for integer types. */
+typedef struct {
+    int64_t capacity;
+    int64_t count;
+    int64_t *chi;
+    float *keys;
+} ecc_curve;
+
+/* Number of thresholds m of an integer dtype (256, 16384, 65536); ECC_E_ARG otherwise. */
+int ecc_threshold_count(ecc_dtype dtype, int64_t *m_out);
+
+/* Euler characteristic curve of an image (Sec. 2 and Sec. 3 as above).
+ *   image: host or device pointer to prod(n) elements of dtype.  Host images
+ *          are copied to the device first.
+ *   curve: capacity >= m (integer types) or >= prod(n) (always enough for
+ *          ECC_F32).  chi/keys may be host or device pointers.
+ *   stream: work is enqueued on it; the call returns after the curve is
+ *          written (it synchronizes that stream).
+ * Errors: ECC_E_ARG, ECC_E_RANGE (U14), ECC_E_NAN (F32),
+ *         ECC_E_BUFFER_TOO_SMALL, ECC_E_NOMEM, ECC_E_HIP, ECC_E_UNSUPPORTED. */
+int ecc_compute(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_curve *curve, void *stream);
+
+/* Stream-ordered form for integer types with device-resident data: enqueues
+ * the whole computation on `stream` and returns without synchronizing.
+ *   image_dev: device pointer, prod(n) elements.
+ *   chi_dev:   device pointer, m int64 entries; written only if the input is
+ *              valid (all U14 values < 16384).
+ *   status_dev: optional device pointer to one uint32; receives 0 on
+ *              success or ECC_STATUS_RANGE_BIT after the work completes.
+ * Scratch memory comes from a per-(device, stream) workspace the library
+ * keeps; concurrent calls on the same stream are ordered by the stream.
+ * Host-side errors: ECC_E_ARG, ECC_E_NOMEM, ECC_E_HIP, ECC_E_UNSUPPORTED. */
+#define ECC_STATUS_RANGE_BIT 1u
+int ecc_compute_async(const void *image_dev, const ecc_dims *dims, ecc_dtype dtype, int64_t *chi_dev,
+                      uint32_t *status_dev, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Streaming (Sec. 3, "Streaming" and "Processing one Chunk"): an image larger
+ * than device memory is pushed as consecutive chunks of whole axis-0 planes.
+ * Each chunk is processed with a one-plane collar taken from its neighbours
+ * (the previous chunk's last plane is kept on the device; each chunk's own
+ * last plane waits for the next chunk); the changes vector stays on the
+ * device and the prefix sum is taken once in ecc_stream_finish.
+ * Integer dtypes only. */
+typedef struct ecc_stream ecc_stream;
+
+/* Starts a stream for an image of full_dims (ndim 1..4).  The handle owns
+ * its device buffers until ecc_stream_finish or ecc_stream_abort.
+ * stream: the HIP stream the work is ordered on (void*, may be NULL).
+ * Errors: ECC_E_ARG, ECC_E_NOMEM, ECC_E_HIP, ECC_E_UNSUPPORTED. */
+int ecc_stream_begin(const ecc_dims *full_dims, ecc_dtype dtype, void *stream, ecc_stream **out);
+
+/* Pushes n_planes consecutive axis-0 planes (n_planes * prod(n[1..]) elements).
+ * Host pointers (pinned or pageable) are copied; the call returns once the
+ * caller may reuse the buffer.  Device pointers are read in place by work on
+ * the stream: the caller must not overwrite them until that work is done
+ * (e.g. by later work on the same stream).
+ * Errors: ECC_E_ARG, ECC_E_STATE (more planes than n[0]), ECC_E_RANGE
+ * (detected for U14 at finish), ECC_E_NOMEM, ECC_E_HIP. */
+int ecc_stream_push_chunk(ecc_stream *st, const void *planes, int64_t n_planes);
+
+/* Processes the last plane, writes the curve and frees the handle (always,
+ * also on error).  Errors: ECC_E_STATE (planes missing), ECC_E_RANGE,
+ * ECC_E_BUFFER_TOO_SMALL, ECC_E_HIP. */
+int ecc_stream_finish(ecc_stream *st, ecc_curve *curve);
+
+/* Frees the handle without producing a curve.  NULL is ignored. */
+void ecc_stream_abort(ecc_stream *st);
+
+/* Kernel timing (measurement support, not needed for results).  While
+ * enabled, every launch of the per-voxel kernels (the integer change-vector
+ * kernel and the float record kernel) is bracketed by two HIP events recorded
+ * on the stream it is launched on.  ecc_profile_read waits for the recorded
+ * events and returns the summed elapsed time in milliseconds and the number
+ * of launches since the last reset.  ecc_profile_enable(0) stops recording;
+ * ecc_profile_reset drops what was recorded.  Process-wide; not for
+ * concurrent use from several threads.  Errors: ECC_E_ARG (NULL output),
+ * ECC_E_HIP. */
+int ecc_profile_enable(int on);
+int ecc_profile_reset(void);
+int ecc_profile_read(double *kernel_ms, int64_t *launches);
+
+/* Thread-local description of the last failure in this thread ("" if none). */
+const char *ecc_last_error(void);
+
+/* Library version string. */
+const char *ecc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ECC_H */

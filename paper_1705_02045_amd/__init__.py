@@ -1,0 +1,217 @@
+"""Euler characteristic curves of gray-scale images on one MI355X.
+
+Thin ctypes binding of ``libecc.so`` (C ABI in ``include/ecc.h``): argument
+marshalling only.  Every step of the computation runs in the library's HIP
+kernels; PyTorch supplies device memory and the current stream.  Importing
+this package fails loudly if the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import pathlib
+
+_HERE = pathlib.Path(__file__).resolve().parent
+_LIBPATH = _HERE / "libecc.so"
+if not _LIBPATH.exists():
+    raise ImportError(f"{_LIBPATH} is missing: build it with __graft_entry__.build() (hipcc, gfx950)")
+_lib = ctypes.CDLL(str(_LIBPATH))
+
+ECC_OK = 0
+ECC_E_ARG = -1
+ECC_E_RANGE = -2
+ECC_E_NAN = -3
+ECC_E_BUFFER_TOO_SMALL = -4
+ECC_E_STATE = -5
+ECC_E_NOMEM = -6
+ECC_E_HIP = -7
+ECC_E_UNSUPPORTED = -8
+STATUS_RANGE_BIT = 1
+
+DTYPES = {"u8": 1, "u14": 2, "u16": 3, "f32": 4}
+THRESHOLDS = {"u8": 256, "u14": 16384, "u16": 65536}
+_ERRNAME = {v: k for k, v in globals().items() if k.startswith("ECC_E_")}
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int64 * 4)]
+
+
+class Curve(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int64), ("count", ctypes.c_int64),
+                ("chi", ctypes.c_void_p), ("keys", ctypes.c_void_p)]
+
+
+_vp = ctypes.c_void_p
+_lib.ecc_compute.restype = ctypes.c_int
+_lib.ecc_compute.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_int, ctypes.POINTER(Curve), _vp]
+_lib.ecc_compute_async.restype = ctypes.c_int
+_lib.ecc_compute_async.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_int, _vp, _vp, _vp]
+_lib.ecc_threshold_count.restype = ctypes.c_int
+_lib.ecc_threshold_count.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
+_lib.ecc_stream_begin.restype = ctypes.c_int
+_lib.ecc_stream_begin.argtypes = [ctypes.POINTER(Dims), ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+_lib.ecc_stream_push_chunk.restype = ctypes.c_int
+_lib.ecc_stream_push_chunk.argtypes = [_vp, _vp, ctypes.c_int64]
+_lib.ecc_stream_finish.restype = ctypes.c_int
+_lib.ecc_stream_finish.argtypes = [_vp, ctypes.POINTER(Curve)]
+_lib.ecc_stream_abort.restype = None
+_lib.ecc_stream_abort.argtypes = [_vp]
+_lib.ecc_profile_enable.restype = ctypes.c_int
+_lib.ecc_profile_enable.argtypes = [ctypes.c_int]
+_lib.ecc_profile_reset.restype = ctypes.c_int
+_lib.ecc_profile_read.restype = ctypes.c_int
+_lib.ecc_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+_lib.ecc_last_error.restype = ctypes.c_char_p
+_lib.ecc_version.restype = ctypes.c_char_p
+
+
+class EccError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.ecc_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {_ERRNAME.get(code, code)} ({code}): {msg}")
+        self.code = code
+
+
+def _check(code: int, where: str):
+    if code != ECC_OK:
+        raise EccError(code, where)
+
+
+def profile_enable(on: bool = True):
+    _check(_lib.ecc_profile_enable(1 if on else 0), "ecc_profile_enable")
+
+
+def profile_reset():
+    _check(_lib.ecc_profile_reset(), "ecc_profile_reset")
+
+
+def profile_read():
+    """(summed milliseconds, launches) of the per-voxel kernels since the last reset."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(_lib.ecc_profile_read(ctypes.byref(ms), ctypes.byref(n)), "ecc_profile_read")
+    return ms.value, n.value
+
+
+def library_path() -> str:
+    return str(_LIBPATH)
+
+
+def version() -> str:
+    return _lib.ecc_version().decode()
+
+
+def make_dims(shape) -> Dims:
+    shape = tuple(int(s) for s in shape)
+    d = Dims()
+    d.ndim = len(shape)
+    for i, s in enumerate(shape[:4]):
+        d.n[i] = s
+    return d
+
+
+def _stream_handle(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dtype_of(t, dtype):
+    import torch
+    if dtype is not None:
+        return dtype
+    return {torch.uint8: "u8", torch.float32: "f32"}.get(t.dtype) or _raise(
+        f"pass dtype= for tensors of {t.dtype} (u14 or u16 for 16-bit data)")
+
+
+def _raise(msg):
+    raise TypeError(msg)
+
+
+def compute(image, dtype: str | None = None):
+    """chi(T_t) for every threshold of a CUDA tensor (int64 tensor on the same device).
+
+    dtype: "u8" (uint8), "u14"/"u16" (16-bit tensors, any 16-bit torch dtype
+    reinterpreted as unsigned), "f32" (returns (keys, chi)).
+    """
+    import torch
+    if not image.is_cuda:
+        raise ValueError("compute() takes a device tensor")
+    dtype = _dtype_of(image, dtype)
+    image = image.contiguous()
+    dims = make_dims(image.shape)
+    dev = image.device
+    with torch.cuda.device(dev):
+        if dtype == "f32":
+            n = image.numel()
+            chi = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+            keys = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+            cv = Curve(capacity=n, count=0, chi=chi.data_ptr(), keys=keys.data_ptr())
+            _check(_lib.ecc_compute(image.data_ptr(), ctypes.byref(dims), DTYPES[dtype], ctypes.byref(cv),
+                                    _stream_handle(dev)), "ecc_compute")
+            return keys[: cv.count], chi[: cv.count]
+        m = THRESHOLDS[dtype]
+        chi = torch.empty(m, dtype=torch.int64, device=dev)
+        cv = Curve(capacity=m, count=0, chi=chi.data_ptr(), keys=None)
+        _check(_lib.ecc_compute(image.data_ptr(), ctypes.byref(dims), DTYPES[dtype], ctypes.byref(cv),
+                                _stream_handle(dev)), "ecc_compute")
+        return chi
+
+
+def compute_async(image, out_chi, dtype: str, status=None, stream=None):
+    """Stream-ordered ecc_compute_async on device tensors (no host synchronisation)."""
+    import torch
+    dims = make_dims(image.shape)
+    s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream_handle(image.device)
+    _check(_lib.ecc_compute_async(image.data_ptr(), ctypes.byref(dims), DTYPES[dtype], out_chi.data_ptr(),
+                                  status.data_ptr() if status is not None else None, s), "ecc_compute_async")
+
+
+def compute_host(array, dtype: str):
+    """ecc_compute on a host numpy array; returns a numpy int64 curve (host output buffer)."""
+    import numpy as np
+    a = np.ascontiguousarray(array)
+    dims = make_dims(a.shape)
+    m = THRESHOLDS[dtype]
+    chi = np.empty(m, dtype=np.int64)
+    cv = Curve(capacity=m, count=0, chi=chi.ctypes.data, keys=None)
+    _check(_lib.ecc_compute(a.ctypes.data, ctypes.byref(dims), DTYPES[dtype], ctypes.byref(cv), None),
+           "ecc_compute")
+    return chi
+
+
+class Stream:
+    """ecc_stream_begin / push_chunk / finish over axis-0 chunks."""
+
+    def __init__(self, shape, dtype: str, stream=None):
+        import torch
+        self.dtype = dtype
+        self._h = ctypes.c_void_p()
+        s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else (
+            _stream_handle(torch.cuda.current_device()) if torch.cuda.is_available() else None)
+        _check(_lib.ecc_stream_begin(ctypes.byref(make_dims(shape)), DTYPES[dtype], s, ctypes.byref(self._h)),
+               "ecc_stream_begin")
+
+    def push(self, planes, n_planes: int | None = None):
+        import numpy as np
+        if isinstance(planes, np.ndarray):
+            planes = np.ascontiguousarray(planes)
+            ptr, n = planes.ctypes.data, planes.shape[0]
+        else:
+            ptr, n = planes.data_ptr(), planes.shape[0]
+        _check(_lib.ecc_stream_push_chunk(self._h, ptr, int(n_planes if n_planes is not None else n)),
+               "ecc_stream_push_chunk")
+        self._keep = planes
+
+    def finish(self, out=None):
+        import numpy as np
+        m = THRESHOLDS[self.dtype]
+        chi = out if out is not None else np.empty(m, dtype=np.int64)
+        ptr = chi.ctypes.data if isinstance(chi, np.ndarray) else chi.data_ptr()
+        cv = Curve(capacity=m, count=0, chi=ptr, keys=None)
+        h, self._h = self._h, ctypes.c_void_p()
+        _check(_lib.ecc_stream_finish(h, ctypes.byref(cv)), "ecc_stream_finish")
+        return chi
+
+    def abort(self):
+        h, self._h = self._h, ctypes.c_void_p()
+        _lib.ecc_stream_abort(h)

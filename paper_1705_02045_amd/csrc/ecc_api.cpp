@@ -1,0 +1,338 @@
+// C ABI of libecc: argument checks, views, workspaces and the resident path.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "ecc_internal.h"
+
+namespace ecc {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    set_error("%s failed: %s", what, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? ECC_E_NOMEM : ECC_E_HIP;
+}
+
+int64_t threshold_count(int dtype) {
+    switch (dtype) {
+    case ECC_U8: return 256;
+    case ECC_U14: return 16384;
+    case ECC_U16: return 65536;
+    default: return -1;
+    }
+}
+
+static size_t elem_bytes(int dtype) {
+    switch (dtype) {
+    case ECC_U8: return 1;
+    case ECC_U14:
+    case ECC_U16: return 2;
+    case ECC_F32: return 4;
+    default: return 0;
+    }
+}
+
+int device_cu_count() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 256;
+    return cus;
+}
+
+int ensure_bytes(void **ptr, size_t *cap, size_t need) {
+    if (*cap >= need && *ptr) return ECC_OK;
+    if (*ptr) {
+        ECC_HIP(hipFree(*ptr));
+        *ptr = nullptr;
+        *cap = 0;
+    }
+    size_t sz = need < 256 ? 256 : need;
+    ECC_HIP(hipMalloc(ptr, sz));
+    *cap = sz;
+    return ECC_OK;
+}
+
+static std::mutex g_ws_mu;
+static std::map<std::pair<int, void *>, Workspace *> g_ws;
+
+int get_workspace(void *stream, Workspace **out) {
+    int dev = 0;
+    ECC_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto key = std::make_pair(dev, stream);
+    auto it = g_ws.find(key);
+    if (it == g_ws.end()) {
+        Workspace *w = new Workspace();
+        w->device = dev;
+        w->stream = stream;
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, 256);
+        if (e != hipSuccess) {
+            delete w;
+            return hip_fail(e, "hipMalloc(status)");
+        }
+        w->status = (uint32_t *)p;
+        it = g_ws.emplace(key, w).first;
+    }
+    *out = it->second;
+    return ECC_OK;
+}
+
+static int check_dims(const ecc_dims *dims, int64_t *total) {
+    if (!dims) {
+        set_error("dims is NULL");
+        return ECC_E_ARG;
+    }
+    if (dims->ndim < 1 || dims->ndim > 4) {
+        set_error("ndim %d outside 1..4", (int)dims->ndim);
+        return ECC_E_ARG;
+    }
+    int64_t t = 1;
+    for (int k = 0; k < dims->ndim; ++k) {
+        if (dims->n[k] < 1) {
+            set_error("n[%d] = %lld < 1", k, (long long)dims->n[k]);
+            return ECC_E_ARG;
+        }
+        if (t > ((int64_t)1 << 62) / dims->n[k]) {
+            set_error("image size overflows");
+            return ECC_E_ARG;
+        }
+        t *= dims->n[k];
+    }
+    *total = t;
+    return ECC_OK;
+}
+
+// Axes of length 1 are dropped: the complex of such an image is the product of
+// the complex of the remaining axes with a closed unit interval, and taking
+// that product changes no Euler characteristic of any threshold.
+bool normalize_int_view(const ecc_dims *dims, IntView *v, int *unsupported) {
+    int64_t ns[4];
+    int k = 0;
+    for (int i = 0; i < dims->ndim; ++i)
+        if (dims->n[i] > 1) ns[k++] = dims->n[i];
+    *unsupported = 0;
+    if (k == 0) ns[k++] = 1;
+    if (k == 1) {
+        v->nin = 1; v->n0 = 1; v->n1 = 1;
+        if (ns[0] > INT32_MAX) { *unsupported = 1; return false; }
+        v->n2 = (int32_t)ns[0];
+    } else if (k == 2) {
+        v->nin = 1; v->n0 = ns[0]; v->n1 = 1;
+        if (ns[1] > INT32_MAX) { *unsupported = 1; return false; }
+        v->n2 = (int32_t)ns[1];
+    } else if (k == 3) {
+        v->nin = 2; v->n0 = ns[0];
+        if (ns[1] > INT32_MAX || ns[2] > INT32_MAX || ns[1] * ns[2] > INT32_MAX) { *unsupported = 1; return false; }
+        v->n1 = (int32_t)ns[1]; v->n2 = (int32_t)ns[2];
+    } else {
+        *unsupported = 1;
+        return false;
+    }
+    if (v->n0 > INT32_MAX - 4) { *unsupported = 1; return false; }
+    return true;
+}
+
+IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
+    IntTiling t{};
+    t.rows = 4;
+    const int cus = device_cu_count();
+    const int wg_per_cu = dtype == ECC_U8 ? 4 : 2;
+    int64_t tiles_xy;
+    if (v.nin == 1) {
+        const int64_t segs = (v.n2 + (int64_t)kWave * t.rows - 1) / ((int64_t)kWave * t.rows);
+        t.wx = (int)(segs < 16 ? segs : 16);
+        t.wy = 1;
+        tiles_xy = (segs + t.wx - 1) / t.wx;
+    } else {
+        const int64_t xs = (v.n2 + kWave - 1) / kWave;
+        t.wx = (int)(xs < 16 ? xs : 16);
+        const int64_t ys = (v.n1 + t.rows - 1) / t.rows;
+        const int64_t wy = 16 / t.wx;
+        t.wy = (int)(ys < wy ? ys : wy);
+        tiles_xy = ((xs + t.wx - 1) / t.wx) * ((ys + t.wy - 1) / t.wy);
+    }
+    const int64_t target = (int64_t)cus * wg_per_cu * 2;
+    int64_t tz = (target + tiles_xy - 1) / tiles_xy;
+    if (tz < 1) tz = 1;
+    if (tz > planes) tz = planes;
+    int64_t zc = (planes + tz - 1) / tz;
+    if (zc < 8 && planes >= 8) zc = 8;
+    t.zc = (int)zc;
+    const int64_t tiles = tiles_xy * ((planes + zc - 1) / zc);
+    int64_t grid = (int64_t)cus * wg_per_cu;
+    if (grid > tiles) grid = tiles;
+    if (grid < 1) grid = 1;
+    t.grid = (int)grid;
+    return t;
+}
+
+// Enqueue the whole integer computation for a device-resident image.
+static int enqueue_int(const void *image_dev, const IntView &v, int dtype, int64_t *chi_dev,
+                       uint32_t *status_out, hipStream_t stream, Workspace *ws) {
+    const int m = (int)threshold_count(dtype);
+    const size_t eb = elem_bytes(dtype);
+    IntTiling tl = choose_int_tiling(v, dtype, v.n0);
+    int rc = ensure_bytes((void **)&ws->partial, &ws->partial_bytes, (size_t)tl.grid * m * sizeof(int32_t));
+    if (rc) return rc;
+    rc = ensure_bytes((void **)&ws->vcec, &ws->vcec_bytes, (size_t)m * sizeof(int64_t));
+    if (rc) return rc;
+    rc = launch_zero(ws->status, 4, stream);
+    if (rc) return rc;
+    IntJob job{};
+    job.src.seg0 = (const uint8_t *)image_dev;
+    job.src.seg1 = (const uint8_t *)image_dev;
+    job.src.seg0_planes = v.n0;
+    job.src.plane_bytes = (int64_t)v.n1 * v.n2 * (int64_t)eb;
+    job.view = v;
+    job.e0 = 0;
+    job.e1 = (int32_t)v.n0;
+    job.lo_inf = 1;
+    job.hi_inf = 1;
+    job.dtype = dtype;
+    rc = launch_int_partial(job, tl, ws->partial, ws->status, stream);
+    if (rc) return rc;
+    rc = launch_reduce_rows(ws->partial, tl.grid, m, ws->vcec, false, stream);
+    if (rc) return rc;
+    return launch_scan(ws->vcec, m, chi_dev, ws->status, status_out, stream);
+}
+
+static bool is_device_ptr(const void *p) {
+    hipPointerAttribute_t attr;
+    memset(&attr, 0, sizeof attr);
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+}  // namespace ecc
+
+using namespace ecc;
+
+extern "C" {
+
+const char *ecc_last_error(void) { return g_err; }
+
+const char *ecc_version(void) { return "libecc 0.1 (gfx950)"; }
+
+int ecc_threshold_count(ecc_dtype dtype, int64_t *m_out) {
+    const int64_t m = threshold_count(dtype);
+    if (m < 0 || !m_out) {
+        set_error("not an integer dtype or NULL output");
+        return ECC_E_ARG;
+    }
+    *m_out = m;
+    return ECC_OK;
+}
+
+int ecc_compute_async(const void *image_dev, const ecc_dims *dims, ecc_dtype dtype, int64_t *chi_dev,
+                      uint32_t *status_dev, void *stream) {
+    g_err[0] = 0;
+    int64_t total = 0;
+    int rc = check_dims(dims, &total);
+    if (rc) return rc;
+    if (!image_dev || !chi_dev) {
+        set_error("NULL image or chi");
+        return ECC_E_ARG;
+    }
+    if (dtype != ECC_U8 && dtype != ECC_U14) {
+        if (dtype == ECC_U16 || dtype == ECC_F32) {
+            set_error("ecc_compute_async: dtype %d not available in this build", (int)dtype);
+            return ECC_E_UNSUPPORTED;
+        }
+        set_error("unknown dtype %d", (int)dtype);
+        return ECC_E_ARG;
+    }
+    IntView v{};
+    int unsup = 0;
+    if (!normalize_int_view(dims, &v, &unsup)) {
+        set_error("integer path: shape not supported (4 axes longer than 1, or an extent beyond 2^31)");
+        return ECC_E_UNSUPPORTED;
+    }
+    Workspace *ws = nullptr;
+    rc = get_workspace(stream, &ws);
+    if (rc) return rc;
+    return enqueue_int(image_dev, v, dtype, chi_dev, status_dev, (hipStream_t)stream, ws);
+}
+
+int ecc_compute(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_curve *curve, void *stream) {
+    g_err[0] = 0;
+    int64_t total = 0;
+    int rc = check_dims(dims, &total);
+    if (rc) return rc;
+    if (!image || !curve || !curve->chi) {
+        set_error("NULL image, curve or curve->chi");
+        return ECC_E_ARG;
+    }
+    if (dtype == ECC_F32 || dtype == ECC_U16) {
+        set_error("ecc_compute: dtype %d not available in this build", (int)dtype);
+        return ECC_E_UNSUPPORTED;
+    }
+    const int64_t m = threshold_count(dtype);
+    if (m < 0) {
+        set_error("unknown dtype %d", (int)dtype);
+        return ECC_E_ARG;
+    }
+    if (curve->capacity < m) {
+        curve->count = m;
+        set_error("curve capacity %lld < %lld", (long long)curve->capacity, (long long)m);
+        return ECC_E_BUFFER_TOO_SMALL;
+    }
+    IntView v{};
+    int unsup = 0;
+    if (!normalize_int_view(dims, &v, &unsup)) {
+        set_error("integer path: shape not supported (4 axes longer than 1, or an extent beyond 2^31)");
+        return ECC_E_UNSUPPORTED;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Workspace *ws = nullptr;
+    rc = get_workspace(stream, &ws);
+    if (rc) return rc;
+    const void *img_dev = image;
+    if (!is_device_ptr(image)) {
+        const size_t bytes = (size_t)total * elem_bytes(dtype);
+        rc = ensure_bytes(&ws->img_tmp, &ws->img_tmp_bytes, bytes);
+        if (rc) return rc;
+        ECC_HIP(hipMemcpyAsync(ws->img_tmp, image, bytes, hipMemcpyHostToDevice, s));
+        img_dev = ws->img_tmp;
+    }
+    const bool chi_dev = is_device_ptr(curve->chi);
+    int64_t *chi_target = curve->chi;
+    if (!chi_dev) {
+        rc = ensure_bytes((void **)&ws->chi_tmp, &ws->chi_tmp_bytes, (size_t)m * sizeof(int64_t));
+        if (rc) return rc;
+        chi_target = ws->chi_tmp;
+    }
+    rc = enqueue_int(img_dev, v, dtype, chi_target, nullptr, s, ws);
+    if (rc) return rc;
+    uint32_t st = 0;
+    ECC_HIP(hipMemcpyAsync(&st, ws->status, 4, hipMemcpyDeviceToHost, s));
+    ECC_HIP(hipStreamSynchronize(s));
+    if (st & kStatusRange) {
+        set_error("a 14-bit image holds a value >= 16384");
+        return ECC_E_RANGE;
+    }
+    if (!chi_dev) {
+        ECC_HIP(hipMemcpyAsync(curve->chi, ws->chi_tmp, (size_t)m * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        ECC_HIP(hipStreamSynchronize(s));
+    }
+    curve->count = m;
+    return ECC_OK;
+}
+
+}  // extern "C"

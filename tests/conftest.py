@@ -12,10 +12,11 @@ def pytest_configure(config):
 
 def _ensure_built():
     """Build the native libraries once if nothing is built (a fresh checkout)."""
-    need = [ROOT / "oracle" / "liboracle.so", ROOT / "gen" / "libeccgen.so"]
+    need = [ROOT / "oracle" / "liboracle.so", ROOT / "gen" / "libeccgen.so",
+            ROOT / "paper_1705_02045_amd" / "libecc.so"]
     if not all(p.exists() for p in need):
         import __graft_entry__
-        __graft_entry__.build_cpu()
+        __graft_entry__.build()
 
 
 _ensure_built()

@@ -1,0 +1,65 @@
+"""The C-ABI library loads without a GPU, exports every symbol include/ecc.h
+declares, and rejects bad arguments before touching the device."""
+import ctypes
+import pathlib
+import re
+
+import pytest
+
+ROOT = pathlib.Path(__file__).resolve().parents[1]
+
+
+def declared_functions():
+    text = (ROOT / "include" / "ecc.h").read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ecc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    import paper_1705_02045_amd as ecc
+    lib = ctypes.CDLL(ecc.library_path())
+    names = declared_functions()
+    assert "ecc_compute" in names and "ecc_stream_push_chunk" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_threshold_counts_and_version():
+    import paper_1705_02045_amd as ecc
+    m = ctypes.c_int64()
+    for name, want in ecc.THRESHOLDS.items():
+        assert ecc._lib.ecc_threshold_count(ecc.DTYPES[name], ctypes.byref(m)) == 0 and m.value == want
+    assert ecc._lib.ecc_threshold_count(ecc.DTYPES["f32"], ctypes.byref(m)) == ecc.ECC_E_ARG
+    assert "gfx950" in ecc.version()
+
+
+@pytest.mark.parametrize("shape", [(), (0,), (3, 0), (1, 2, 3, 4, 5)])
+def test_bad_dims_rejected(shape):
+    import paper_1705_02045_amd as ecc
+    dims = ecc.make_dims(shape[:4]) if shape else ecc.Dims()
+    if len(shape) == 5:
+        dims.ndim = 5
+    buf = (ctypes.c_int64 * 16384)()
+    cv = ecc.Curve(capacity=16384, count=0, chi=ctypes.addressof(buf), keys=None)
+    rc = ecc._lib.ecc_compute(ctypes.addressof(buf), ctypes.byref(dims), ecc.DTYPES["u14"], ctypes.byref(cv), None)
+    assert rc == ecc.ECC_E_ARG
+    assert ecc._lib.ecc_last_error()
+
+
+def test_null_and_dtype_rejected():
+    import paper_1705_02045_amd as ecc
+    dims = ecc.make_dims((4, 4))
+    buf = (ctypes.c_int64 * 256)()
+    cv = ecc.Curve(capacity=256, count=0, chi=ctypes.addressof(buf), keys=None)
+    assert ecc._lib.ecc_compute(None, ctypes.byref(dims), 1, ctypes.byref(cv), None) == ecc.ECC_E_ARG
+    assert ecc._lib.ecc_compute(ctypes.addressof(buf), ctypes.byref(dims), 9, ctypes.byref(cv), None) == ecc.ECC_E_ARG
+    assert ecc._lib.ecc_compute(ctypes.addressof(buf), None, 1, ctypes.byref(cv), None) == ecc.ECC_E_ARG
+
+
+def test_small_capacity_reports_needed_size():
+    import paper_1705_02045_amd as ecc
+    dims = ecc.make_dims((4, 4))
+    buf = (ctypes.c_int64 * 16)()
+    cv = ecc.Curve(capacity=16, count=0, chi=ctypes.addressof(buf), keys=None)
+    rc = ecc._lib.ecc_compute(ctypes.addressof(buf), ctypes.byref(dims), ecc.DTYPES["u8"], ctypes.byref(cv), None)
+    assert rc == ecc.ECC_E_BUFFER_TOO_SMALL and cv.count == 256
