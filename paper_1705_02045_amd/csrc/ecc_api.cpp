@@ -1,6 +1,7 @@
 // C ABI of libecc: argument checks, views, workspaces and the resident path.
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -145,22 +146,30 @@ bool normalize_int_view(const ecc_dims *dims, IntView *v, int *unsupported) {
     return true;
 }
 
+static int env_int(const char *name, int dflt) {
+    const char *s = getenv(name);
+    return (s && *s) ? atoi(s) : dflt;
+}
+
+// Tuning overrides (measurement only): ECC_INT_ROWS, ECC_INT_DBL, ECC_INT_WG_PER_CU, ECC_INT_WAVES.
 IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
     IntTiling t{};
-    t.rows = 4;
+    t.rows = env_int("ECC_INT_ROWS", 4);
+    t.dbl = env_int("ECC_INT_DBL", 0);
     const int cus = device_cu_count();
-    const int wg_per_cu = dtype == ECC_U8 ? 4 : 2;
+    const int wg_per_cu = env_int("ECC_INT_WG_PER_CU", dtype == ECC_U8 ? 4 : 2);
+    const int max_waves = env_int("ECC_INT_WAVES", 16);
     int64_t tiles_xy;
     if (v.nin == 1) {
         const int64_t segs = (v.n2 + (int64_t)kWave * t.rows - 1) / ((int64_t)kWave * t.rows);
-        t.wx = (int)(segs < 16 ? segs : 16);
+        t.wx = (int)(segs < max_waves ? segs : max_waves);
         t.wy = 1;
         tiles_xy = (segs + t.wx - 1) / t.wx;
     } else {
         const int64_t xs = (v.n2 + kWave - 1) / kWave;
-        t.wx = (int)(xs < 16 ? xs : 16);
+        t.wx = (int)(xs < max_waves ? xs : max_waves);
         const int64_t ys = (v.n1 + t.rows - 1) / t.rows;
-        const int64_t wy = 16 / t.wx;
+        const int64_t wy = max_waves / t.wx;
         t.wy = (int)(ys < wy ? ys : wy);
         tiles_xy = ((xs + t.wx - 1) / t.wx) * ((ys + t.wy - 1) / t.wy);
     }
@@ -326,6 +335,10 @@ int ecc_compute(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_cu
     if (st & kStatusRange) {
         set_error("a 14-bit image holds a value >= 16384");
         return ECC_E_RANGE;
+    }
+    if (st != 0) {
+        set_error("internal error: device status 0x%08x", st);
+        return ECC_E_HIP;
     }
     if (!chi_dev) {
         ECC_HIP(hipMemcpyAsync(curve->chi, ws->chi_tmp, (size_t)m * sizeof(int64_t), hipMemcpyDeviceToHost, s));

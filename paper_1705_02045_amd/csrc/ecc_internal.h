@@ -54,6 +54,7 @@ struct IntJob {
 // Tiling of the integer kernel (chosen by the tuner in ecc_tune.cpp).
 struct IntTiling {
     int rows;      // rows (nin == 2) or 64-wide x segments (nin == 1) per wave
+    int dbl;       // per-item update form of the four-item blocks (see ecc_int.hip)
     int wx, wy;    // waves per workgroup along x and along y
     int zc;        // planes per tile
     int grid;      // workgroups (persistent)

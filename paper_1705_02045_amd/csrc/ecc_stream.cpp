@@ -1,28 +1,334 @@
-// Streaming interface (filled in with the chunk pipeline).
+// Streaming interface (Sec. 3, "Streaming", "Parallel Computations" and
+// "Processing one Chunk"): the image arrives as consecutive chunks of whole
+// axis-0 planes.  Each chunk is processed together with the collar planes it
+// needs: the previous chunk's last two planes are kept on the device (the
+// lower collar of the deferred plane and the deferred plane itself), and each
+// chunk's own last plane waits for the next chunk, which holds its upper
+// collar.  Counts accumulate on the device; the prefix sum is taken once.
+//
+// Host chunks go through two device staging buffers filled on a copy stream
+// (hipMemcpyAsync), so the copy of chunk k+1 overlaps the kernels of chunk k.
+// Device chunks are read in place.
+#include <cstring>
+
 #include "ecc_internal.h"
 
+struct ecc_stream {
+    int device = -1;
+    hipStream_t compute = nullptr;  // caller's stream
+    hipStream_t copy = nullptr;     // owned
+    ecc::IntView view{};
+    int dtype = 0;
+    int m = 0;
+    int64_t plane_bytes = 0;
+    int64_t pushed = 0;   // image planes received
+    int64_t emitted = 0;  // image planes whose changes were added
+    // collar: up to two image planes [pushed - ncarry, pushed), double-buffered
+    uint8_t *carry[2] = {nullptr, nullptr};
+    int cur = 0;
+    int ncarry = 0;
+    // staging for host chunks
+    uint8_t *stage[2] = {nullptr, nullptr};
+    size_t stage_cap = 0;
+    hipEvent_t ready[2] = {nullptr, nullptr};
+    hipEvent_t released[2] = {nullptr, nullptr};
+    bool released_recorded[2] = {false, false};
+    int nstaged = 0;
+    // device change vector and per-workgroup rows
+    int32_t *partial = nullptr;
+    size_t partial_bytes = 0;
+    int64_t *vcec = nullptr;
+    uint32_t *status = nullptr;
+};
+
+namespace {
+
 using namespace ecc;
+
+void destroy(ecc_stream *st) {
+    if (!st) return;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (st->device >= 0) (void)hipSetDevice(st->device);
+    if (st->compute) (void)hipStreamSynchronize(st->compute);
+    if (st->copy) (void)hipStreamSynchronize(st->copy);
+    for (int i = 0; i < 2; ++i) {
+        if (st->carry[i]) (void)hipFree(st->carry[i]);
+        if (st->stage[i]) (void)hipFree(st->stage[i]);
+        if (st->ready[i]) (void)hipEventDestroy(st->ready[i]);
+        if (st->released[i]) (void)hipEventDestroy(st->released[i]);
+    }
+    if (st->partial) (void)hipFree(st->partial);
+    if (st->vcec) (void)hipFree(st->vcec);
+    if (st->status) (void)hipFree(st->status);
+    if (st->copy) (void)hipStreamDestroy(st->copy);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    delete st;
+}
+
+bool is_device_ptr(const void *p) {
+    hipPointerAttribute_t attr;
+    memset(&attr, 0, sizeof attr);
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+// Adds the changes of image planes [lo, hi) using the planes held in the
+// carry buffer (image planes [first - ncarry, first)) followed by the chunk
+// (image planes [first, first + nchunk)).
+int run_planes(ecc_stream *st, const uint8_t *chunk, int64_t first, int64_t lo, int64_t hi) {
+    if (hi <= lo) return ECC_OK;
+    const int64_t buf0 = first - st->ncarry;  // image plane of buffer plane 0
+    IntJob job{};
+    job.src.seg0 = st->carry[st->cur];
+    job.src.seg1 = chunk;
+    job.src.seg0_planes = st->ncarry;
+    job.src.plane_bytes = st->plane_bytes;
+    job.view = st->view;
+    job.e0 = (int32_t)(lo - buf0);
+    job.e1 = (int32_t)(hi - buf0);
+    job.lo_inf = lo == 0;
+    job.hi_inf = hi == st->view.n0;
+    job.dtype = st->dtype;
+    IntTiling tl = choose_int_tiling(st->view, st->dtype, hi - lo);
+    int rc = ensure_bytes((void **)&st->partial, &st->partial_bytes, (size_t)tl.grid * st->m * sizeof(int32_t));
+    if (rc) return rc;
+    rc = launch_int_partial(job, tl, st->partial, st->status, st->compute);
+    if (rc) return rc;
+    return launch_reduce_rows(st->partial, tl.grid, st->m, st->vcec, true, st->compute);
+}
+
+// Keeps the last (up to two) planes of carry + chunk as the next carry.
+int update_carry(ecc_stream *st, const uint8_t *chunk, int64_t nchunk) {
+    const int nxt = st->cur ^ 1;
+    const int keep = (int)((st->ncarry + nchunk) < 2 ? (st->ncarry + nchunk) : 2);
+    // planes of the concatenation [carry (ncarry) | chunk (nchunk)], keep the last `keep`
+    const int64_t total = st->ncarry + nchunk;
+    for (int j = 0; j < keep; ++j) {
+        const int64_t b = total - keep + j;
+        const uint8_t *src = b < st->ncarry ? st->carry[st->cur] + b * st->plane_bytes
+                                            : chunk + (b - st->ncarry) * st->plane_bytes;
+        ECC_HIP(hipMemcpyAsync(st->carry[nxt] + (int64_t)j * st->plane_bytes, src, (size_t)st->plane_bytes,
+                               hipMemcpyDeviceToDevice, st->compute));
+    }
+    st->cur = nxt;
+    st->ncarry = keep;
+    return ECC_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
 int ecc_stream_begin(const ecc_dims *full_dims, ecc_dtype dtype, void *stream, ecc_stream **out) {
-    (void)full_dims; (void)dtype; (void)stream; (void)out;
-    set_error("streaming is not available in this build");
-    return ECC_E_UNSUPPORTED;
+    if (!full_dims || !out) {
+        set_error("ecc_stream_begin: NULL argument");
+        return ECC_E_ARG;
+    }
+    *out = nullptr;
+    if (full_dims->ndim < 1 || full_dims->ndim > 4) {
+        set_error("ndim %d outside 1..4", (int)full_dims->ndim);
+        return ECC_E_ARG;
+    }
+    for (int k = 0; k < full_dims->ndim; ++k)
+        if (full_dims->n[k] < 1) {
+            set_error("n[%d] < 1", k);
+            return ECC_E_ARG;
+        }
+    if (dtype != ECC_U8 && dtype != ECC_U14) {
+        if (dtype == ECC_U16 || dtype == ECC_F32) {
+            set_error("streaming: dtype %d not available in this build", (int)dtype);
+            return ECC_E_UNSUPPORTED;
+        }
+        set_error("unknown dtype %d", (int)dtype);
+        return ECC_E_ARG;
+    }
+    // Streaming cuts along axis 0 of the image as given, which stays the
+    // walking axis; in-plane axes of length 1 are dropped (their complex is a
+    // product with a unit interval).
+    IntView v{};
+    int64_t ins[3];
+    int k = 0;
+    for (int i = 1; i < full_dims->ndim; ++i)
+        if (full_dims->n[i] > 1) ins[k++] = full_dims->n[i];
+    if (k == 0) {
+        v.nin = 1; v.n1 = 1; v.n2 = 1;
+    } else if (k == 1 && ins[0] <= INT32_MAX) {
+        v.nin = 1; v.n1 = 1; v.n2 = (int32_t)ins[0];
+    } else if (k == 2 && ins[0] * ins[1] <= INT32_MAX) {
+        v.nin = 2; v.n1 = (int32_t)ins[0]; v.n2 = (int32_t)ins[1];
+    } else {
+        set_error("streaming: plane shape not supported (three in-plane axes, or a plane beyond 2^31 elements)");
+        return ECC_E_UNSUPPORTED;
+    }
+    v.n0 = full_dims->n[0];
+    if (v.n0 > INT32_MAX - 4) {
+        set_error("streaming: too many planes");
+        return ECC_E_UNSUPPORTED;
+    }
+    ecc_stream *st = new ecc_stream();
+    st->compute = (hipStream_t)stream;
+    st->view = v;
+    st->dtype = dtype;
+    st->m = (int)threshold_count(dtype);
+    st->plane_bytes = (int64_t)v.n1 * v.n2 * (dtype == ECC_U8 ? 1 : 2);
+    int rc = ECC_OK;
+    auto fail = [&](int code) {
+        destroy(st);
+        return code;
+    };
+    if (hipGetDevice(&st->device) != hipSuccess) return fail(hip_fail(hipErrorInvalidDevice, "hipGetDevice"));
+    hipError_t e = hipStreamCreateWithFlags(&st->copy, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(hip_fail(e, "hipStreamCreate"));
+    for (int i = 0; i < 2; ++i) {
+        if ((e = hipMalloc(&st->carry[i], (size_t)st->plane_bytes * 2)) != hipSuccess)
+            return fail(hip_fail(e, "hipMalloc(carry)"));
+        if ((e = hipEventCreateWithFlags(&st->ready[i], hipEventDisableTiming)) != hipSuccess)
+            return fail(hip_fail(e, "hipEventCreate"));
+        if ((e = hipEventCreateWithFlags(&st->released[i], hipEventDisableTiming)) != hipSuccess)
+            return fail(hip_fail(e, "hipEventCreate"));
+    }
+    if ((e = hipMalloc(&st->vcec, (size_t)st->m * sizeof(int64_t))) != hipSuccess)
+        return fail(hip_fail(e, "hipMalloc(vcec)"));
+    if ((e = hipMalloc(&st->status, 256)) != hipSuccess) return fail(hip_fail(e, "hipMalloc(status)"));
+    if ((rc = launch_zero(st->vcec, (size_t)st->m * sizeof(int64_t), st->compute))) return fail(rc);
+    if ((rc = launch_zero(st->status, 4, st->compute))) return fail(rc);
+    *out = st;
+    return ECC_OK;
 }
 
 int ecc_stream_push_chunk(ecc_stream *st, const void *planes, int64_t n_planes) {
-    (void)st; (void)planes; (void)n_planes;
-    set_error("streaming is not available in this build");
-    return ECC_E_UNSUPPORTED;
+    if (!st || !planes || n_planes < 1) {
+        set_error("ecc_stream_push_chunk: bad argument");
+        return ECC_E_ARG;
+    }
+    if (st->pushed + n_planes > st->view.n0) {
+        set_error("ecc_stream_push_chunk: %lld planes pushed, image has %lld",
+                  (long long)(st->pushed + n_planes), (long long)st->view.n0);
+        return ECC_E_STATE;
+    }
+    if (n_planes > INT32_MAX / 2) {
+        set_error("ecc_stream_push_chunk: chunk too large");
+        return ECC_E_ARG;
+    }
+    int prev = -1;
+    ECC_HIP(hipGetDevice(&prev));
+    if (prev != st->device) ECC_HIP(hipSetDevice(st->device));
+    const size_t bytes = (size_t)n_planes * (size_t)st->plane_bytes;
+    const uint8_t *chunk = (const uint8_t *)planes;
+    int rc = ECC_OK;
+    if (!is_device_ptr(planes)) {
+        // Host chunk: copy into staging buffer k % 2 on the copy stream, after
+        // the kernels that last read that buffer are done.
+        const int k = st->nstaged & 1;
+        if (bytes > st->stage_cap) {
+            ECC_HIP(hipStreamSynchronize(st->compute));
+            ECC_HIP(hipStreamSynchronize(st->copy));
+            for (int i = 0; i < 2; ++i) {
+                if (st->stage[i]) ECC_HIP(hipFree(st->stage[i]));
+                st->stage[i] = nullptr;
+                st->released_recorded[i] = false;
+            }
+            st->stage_cap = 0;
+            for (int i = 0; i < 2; ++i) ECC_HIP(hipMalloc(&st->stage[i], bytes));
+            st->stage_cap = bytes;
+        }
+        if (st->released_recorded[k]) ECC_HIP(hipStreamWaitEvent(st->copy, st->released[k], 0));
+        ECC_HIP(hipMemcpyAsync(st->stage[k], planes, bytes, hipMemcpyHostToDevice, st->copy));
+        ECC_HIP(hipEventRecord(st->ready[k], st->copy));
+        ECC_HIP(hipStreamWaitEvent(st->compute, st->ready[k], 0));
+        chunk = st->stage[k];
+        st->nstaged++;
+        const int64_t first = st->pushed;
+        const int64_t hi = (first + n_planes == st->view.n0) ? st->view.n0 : first + n_planes - 1;
+        rc = run_planes(st, chunk, first, st->emitted, hi);
+        if (!rc) rc = update_carry(st, chunk, n_planes);
+        if (!rc) {
+            ECC_HIP(hipEventRecord(st->released[k], st->compute));
+            st->released_recorded[k] = true;
+            // the caller's buffer may be reused once its copy is done
+            ECC_HIP(hipEventSynchronize(st->ready[k]));
+            st->emitted = hi;
+            st->pushed = first + n_planes;
+        }
+    } else {
+        const int64_t first = st->pushed;
+        const int64_t hi = (first + n_planes == st->view.n0) ? st->view.n0 : first + n_planes - 1;
+        rc = run_planes(st, chunk, first, st->emitted, hi);
+        if (!rc) rc = update_carry(st, chunk, n_planes);
+        if (!rc) {
+            st->emitted = hi;
+            st->pushed = first + n_planes;
+        }
+    }
+    if (prev != st->device) (void)hipSetDevice(prev);
+    return rc;
 }
 
 int ecc_stream_finish(ecc_stream *st, ecc_curve *curve) {
-    (void)st; (void)curve;
-    set_error("streaming is not available in this build");
-    return ECC_E_UNSUPPORTED;
+    if (!st) {
+        set_error("ecc_stream_finish: NULL stream");
+        return ECC_E_ARG;
+    }
+    int rc = ECC_OK;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(st->device);
+    do {
+        if (!curve || !curve->chi) {
+            set_error("ecc_stream_finish: NULL curve");
+            rc = ECC_E_ARG;
+            break;
+        }
+        if (st->pushed != st->view.n0) {
+            set_error("ecc_stream_finish: %lld of %lld planes pushed", (long long)st->pushed,
+                      (long long)st->view.n0);
+            rc = ECC_E_STATE;
+            break;
+        }
+        if (curve->capacity < st->m) {
+            curve->count = st->m;
+            set_error("curve capacity %lld < %d", (long long)curve->capacity, st->m);
+            rc = ECC_E_BUFFER_TOO_SMALL;
+            break;
+        }
+        int64_t *tmp = nullptr;
+        hipError_t e = hipMalloc(&tmp, (size_t)st->m * sizeof(int64_t));
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "hipMalloc(curve)");
+            break;
+        }
+        rc = launch_scan(st->vcec, st->m, tmp, st->status, nullptr, st->compute);
+        uint32_t stv = 0;
+        if (!rc) {
+            e = hipMemcpyAsync(&stv, st->status, 4, hipMemcpyDeviceToHost, st->compute);
+            if (e == hipSuccess) e = hipStreamSynchronize(st->compute);
+            if (e != hipSuccess) rc = hip_fail(e, "status read");
+        }
+        if (!rc && (stv & kStatusRange)) {
+            set_error("a 14-bit image holds a value >= 16384");
+            rc = ECC_E_RANGE;
+        } else if (!rc && stv != 0) {
+            set_error("internal error: device status 0x%08x", stv);
+            rc = ECC_E_HIP;
+        }
+        if (!rc) {
+            e = hipMemcpyAsync(curve->chi, tmp, (size_t)st->m * sizeof(int64_t), hipMemcpyDefault, st->compute);
+            if (e == hipSuccess) e = hipStreamSynchronize(st->compute);
+            if (e != hipSuccess) rc = hip_fail(e, "curve copy");
+            else curve->count = st->m;
+        }
+        (void)hipFree(tmp);
+    } while (0);
+    destroy(st);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return rc;
 }
 
-void ecc_stream_abort(ecc_stream *st) { (void)st; }
+void ecc_stream_abort(ecc_stream *st) { destroy(st); }
 
-}
+}  // extern "C"

@@ -63,3 +63,16 @@ def test_small_capacity_reports_needed_size():
     cv = ecc.Curve(capacity=16, count=0, chi=ctypes.addressof(buf), keys=None)
     rc = ecc._lib.ecc_compute(ctypes.addressof(buf), ctypes.byref(dims), ecc.DTYPES["u8"], ctypes.byref(cv), None)
     assert rc == ecc.ECC_E_BUFFER_TOO_SMALL and cv.count == 256
+
+
+def test_stream_argument_errors():
+    import paper_1705_02045_amd as ecc
+    h = ctypes.c_void_p()
+    dims = ecc.make_dims((4, 5, 6))
+    assert ecc._lib.ecc_stream_begin(None, ecc.DTYPES["u14"], None, ctypes.byref(h)) == ecc.ECC_E_ARG
+    assert ecc._lib.ecc_stream_begin(ctypes.byref(dims), 9, None, ctypes.byref(h)) == ecc.ECC_E_ARG
+    bad = ecc.make_dims((4, 0, 6))
+    assert ecc._lib.ecc_stream_begin(ctypes.byref(bad), ecc.DTYPES["u8"], None, ctypes.byref(h)) == ecc.ECC_E_ARG
+    assert ecc._lib.ecc_stream_push_chunk(None, None, 1) == ecc.ECC_E_ARG
+    assert ecc._lib.ecc_stream_finish(None, None) == ecc.ECC_E_ARG
+    ecc._lib.ecc_stream_abort(None)

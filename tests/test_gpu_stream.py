@@ -1,0 +1,95 @@
+"""Streaming through the C ABI (ecc_stream_begin / push_chunk / finish): any
+split of axis 0 into chunks gives the oracle's curve exactly (Sec. 3,
+"Streaming": chunks are independent and their change vectors add up)."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ecc():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1705_02045_amd as ecc
+    return ecc
+
+
+def stream_curve(ecc, img, dtype, cuts, kind):
+    st = ecc.Stream(img.shape, dtype)
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        part = np.ascontiguousarray(img[a:b])
+        if kind == "pageable":
+            st.push(part)
+        elif kind == "pinned":
+            t = torch.from_numpy(part.view(np.int16) if part.dtype == np.uint16 else part).pin_memory()
+            st.push(t)
+        else:
+            t = torch.from_numpy(part.view(np.int16) if part.dtype == np.uint16 else part).cuda()
+            st.push(t)
+            torch.cuda.synchronize()
+    return st.finish()
+
+
+SPLITS = {
+    "whole": lambda n: [0, n],
+    "every_plane": lambda n: list(range(n + 1)),
+    "ones_then_rest": lambda n: [0, 1, 2, n],
+    "uneven": lambda n: sorted({0, n, *[int(x) for x in np.linspace(0, n, 5)[1:-1] + np.array([1, -1, 2])]}),
+}
+
+
+@pytest.mark.parametrize("kind", ["pageable", "pinned", "device"])
+@pytest.mark.parametrize("split", list(SPLITS))
+def test_stream_3d_u14(ecc, kind, split):
+    img = gen.cfg_u14_value_noise((13, 70, 90), seed=21)
+    cuts = SPLITS[split](img.shape[0])
+    print(f"\n[gpu] stream u14 {img.shape} {kind} cuts={cuts}", flush=True)
+    got = stream_curve(ecc, img, "u14", cuts, kind)
+    assert (got == oracle.curve(img, m=16384)).all()
+
+
+@pytest.mark.parametrize("shape", [(9, 130), (1, 50, 60), (6, 1, 1), (7, 5), (5, 3, 1, 4)])
+def test_stream_shapes_u8(ecc, shape):
+    img = gen.iid(shape, 8, seed=3)
+    cuts = SPLITS["every_plane"](shape[0]) if shape[0] < 10 else SPLITS["uneven"](shape[0])
+    print(f"\n[gpu] stream u8 {shape} cuts={cuts}", flush=True)
+    got = stream_curve(ecc, img, "u8", cuts, "pageable")
+    assert (got == oracle.curve(img, m=256)).all()
+
+
+def test_stream_matches_resident(ecc):
+    img = gen.cfg_u14_value_noise((64, 128, 200), seed=22)
+    t = torch.from_numpy(img.view(np.int16)).cuda()
+    res = ecc.compute(t, dtype="u14").cpu().numpy()
+    got = stream_curve(ecc, img, "u14", [0, 10, 11, 40, 64], "device")
+    assert (got == res).all()
+
+
+def test_stream_state_errors(ecc):
+    img = gen.cfg_u14_value_noise((6, 20, 30), seed=23)
+    st = ecc.Stream(img.shape, "u14")
+    st.push(img[:4])
+    with pytest.raises(ecc.EccError) as ei:
+        st.push(img[:3])
+    assert ei.value.code == ecc.ECC_E_STATE
+    with pytest.raises(ecc.EccError) as ei:
+        st.finish()
+    assert ei.value.code == ecc.ECC_E_STATE
+    st2 = ecc.Stream(img.shape, "u14")
+    st2.push(img[:2])
+    st2.abort()
+
+
+def test_stream_range_error(ecc):
+    img = gen.cfg_u14_value_noise((6, 20, 30), seed=24)
+    img[4, 3, 3] = 20000
+    st = ecc.Stream(img.shape, "u14")
+    st.push(img[:3])
+    st.push(img[3:])
+    with pytest.raises(ecc.EccError) as ei:
+        st.finish()
+    assert ei.value.code == ecc.ECC_E_RANGE
