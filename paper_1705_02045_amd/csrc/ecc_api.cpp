@@ -79,12 +79,18 @@ int get_workspace(void *stream, Workspace **out) {
         w->device = dev;
         w->stream = stream;
         void *p = nullptr;
-        hipError_t e = hipMalloc(&p, 256);
+        hipError_t e = hipMalloc(&p, 1024);
         if (e != hipSuccess) {
             delete w;
             return hip_fail(e, "hipMalloc(status)");
         }
         w->status = (uint32_t *)p;
+        int rc = launch_zero(p, 1024, (hipStream_t)stream);
+        if (rc) {
+            (void)hipFree(p);
+            delete w;
+            return rc;
+        }
         it = g_ws.emplace(key, w).first;
     }
     *out = it->second;
@@ -151,14 +157,16 @@ static int env_int(const char *name, int dflt) {
     return (s && *s) ? atoi(s) : dflt;
 }
 
-// Tuning overrides (measurement only): ECC_INT_ROWS, ECC_INT_DBL, ECC_INT_WG_PER_CU, ECC_INT_WAVES.
+// Tuning overrides (measurement only): ECC_INT_ROWS, ECC_INT_MODE, ECC_INT_PD,
+// ECC_INT_WAVES, ECC_INT_TILES_PER_CU.
 IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
     IntTiling t{};
-    t.rows = env_int("ECC_INT_ROWS", 4);
-    t.dbl = env_int("ECC_INT_DBL", 0);
+    t.rows = env_int("ECC_INT_ROWS", 2);
+    t.mode = env_int("ECC_INT_MODE", 0);
+    t.pd = env_int("ECC_INT_PD", 1);
     const int cus = device_cu_count();
-    const int wg_per_cu = env_int("ECC_INT_WG_PER_CU", dtype == ECC_U8 ? 4 : 2);
     const int max_waves = env_int("ECC_INT_WAVES", 16);
+    const int tiles_per_cu = env_int("ECC_INT_TILES_PER_CU", 4);
     int64_t tiles_xy;
     if (v.nin == 1) {
         const int64_t segs = (v.n2 + (int64_t)kWave * t.rows - 1) / ((int64_t)kWave * t.rows);
@@ -173,18 +181,16 @@ IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
         t.wy = (int)(ys < wy ? ys : wy);
         tiles_xy = ((xs + t.wx - 1) / t.wx) * ((ys + t.wy - 1) / t.wy);
     }
-    const int64_t target = (int64_t)cus * wg_per_cu * 2;
+    // one tile per workgroup: split axis 0 until there are about
+    // tiles_per_cu tiles per CU (a multiple of 8 keeps the XCD permutation)
+    const int64_t target = (int64_t)cus * tiles_per_cu;
     int64_t tz = (target + tiles_xy - 1) / tiles_xy;
     if (tz < 1) tz = 1;
     if (tz > planes) tz = planes;
     int64_t zc = (planes + tz - 1) / tz;
     if (zc < 8 && planes >= 8) zc = 8;
     t.zc = (int)zc;
-    const int64_t tiles = tiles_xy * ((planes + zc - 1) / zc);
-    int64_t grid = (int64_t)cus * wg_per_cu;
-    if (grid > tiles) grid = tiles;
-    if (grid < 1) grid = 1;
-    t.grid = (int)grid;
+    t.grid = (int)(tiles_xy * ((planes + zc - 1) / zc));
     return t;
 }
 
@@ -198,12 +204,8 @@ static int enqueue_int(const void *image_dev, const IntView &v, int dtype, int64
     if (rc) return rc;
     rc = ensure_bytes((void **)&ws->vcec, &ws->vcec_bytes, (size_t)m * sizeof(int64_t));
     if (rc) return rc;
-    rc = launch_zero(ws->status, 4, stream);
-    if (rc) return rc;
     IntJob job{};
-    job.src.seg0 = (const uint8_t *)image_dev;
-    job.src.seg1 = (const uint8_t *)image_dev;
-    job.src.seg0_planes = v.n0;
+    job.src.base = (const uint8_t *)image_dev;
     job.src.plane_bytes = (int64_t)v.n1 * v.n2 * (int64_t)eb;
     job.view = v;
     job.e0 = 0;
@@ -211,11 +213,13 @@ static int enqueue_int(const void *image_dev, const IntView &v, int dtype, int64
     job.lo_inf = 1;
     job.hi_inf = 1;
     job.dtype = dtype;
-    rc = launch_int_partial(job, tl, ws->partial, ws->status, stream);
+    rc = ensure_bytes((void **)&ws->stage, &ws->stage_bytes,
+                      (size_t)merge_stage_rows(tl.grid) * m * sizeof(int64_t));
     if (rc) return rc;
-    rc = launch_reduce_rows(ws->partial, tl.grid, m, ws->vcec, false, stream);
+    rc = launch_int_partial(job, tl, ws->partial, ws->status, nullptr, stream);
     if (rc) return rc;
-    return launch_scan(ws->vcec, m, chi_dev, ws->status, status_out, stream);
+    return launch_merge(ws->partial, tl.grid, m, ws->stage, ws->vcec, false, true, chi_dev, ws->status, status_out,
+                        stream);
 }
 
 static bool is_device_ptr(const void *p) {
@@ -327,10 +331,10 @@ int ecc_compute(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_cu
         if (rc) return rc;
         chi_target = ws->chi_tmp;
     }
-    rc = enqueue_int(img_dev, v, dtype, chi_target, nullptr, s, ws);
+    rc = enqueue_int(img_dev, v, dtype, chi_target, ws->status + 2, s, ws);
     if (rc) return rc;
     uint32_t st = 0;
-    ECC_HIP(hipMemcpyAsync(&st, ws->status, 4, hipMemcpyDeviceToHost, s));
+    ECC_HIP(hipMemcpyAsync(&st, ws->status + 2, 4, hipMemcpyDeviceToHost, s));
     ECC_HIP(hipStreamSynchronize(s));
     if (st & kStatusRange) {
         set_error("a 14-bit image holds a value >= 16384");

@@ -43,12 +43,8 @@ struct KParams {
     int32_t wx, wy;
     int32_t *partial;
     uint32_t *status;
+    int64_t *zero_vcec;  // cleared by workgroup 0 when not null
 };
-
-__device__ __forceinline__ const uint8_t *plane_ptr(const PlaneSrc &s, int32_t p) {
-    return p < (int32_t)s.seg0_planes ? s.seg0 + (int64_t)p * s.plane_bytes
-                                      : s.seg1 + (int64_t)(p - (int32_t)s.seg0_planes) * s.plane_bytes;
-}
 
 // Fourth word of a raw buffer resource on gfx9-family parts (32-bit data format).
 constexpr int kBufferWord3 = 0x00020000;
@@ -88,65 +84,70 @@ __device__ __forceinline__ uint32_t load_elem(__amdgpu_buffer_rsrc_t rs, uint32_
 __device__ __forceinline__ uint64_t ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
 
 // ----------------------------------------------------------------------------
-// Histogram updates of four (row, field) items at once.  For item i the lanes
-// whose ownership flag flips between planes (p_i != c_i) add
-// e = (p_i ? s_i : -s_i) at byte offset g_i.  The block sets EXEC directly
-// from the two lane masks and restores it before returning, so the compiler
-// never sees a modified EXEC.  Per item either
-//   CND: one v_cndmask builds +-1 and one ds_add covers both directions, or
-//   DBL: two masked ds_adds with the constant registers +1 / -1 (no VALU).
-// The histogram is the kernel's only LDS object, at LDS address 0, so the bin
-// offsets are LDS addresses.  The scalar ops of the block write SCC, which is
-// therefore declared clobbered: the compiler must not keep a comparison
-// result in SCC across the block.
-#define ECC_CND(i, NEG, POS)                                                                   \
-    "s_xor_b64 exec, %[c" #i "], %[p" #i "]\n\t"                                               \
-    "v_cndmask_b32_e64 %[t" #i "], " NEG ", " POS ", %[p" #i "]\n\t"                           \
-    "ds_add_u32 %[g" #i "], %[t" #i "]\n\t"
-#define ECC_DBL(i, PFLIP, CFLIP)                                                              \
-    "s_andn2_b64 exec, %[p" #i "], %[c" #i "]\n\t"                                             \
-    "ds_add_u32 %[g" #i "], %[" PFLIP "]\n\t"                                                  \
-    "s_andn2_b64 exec, %[c" #i "], %[p" #i "]\n\t"                                             \
-    "ds_add_u32 %[g" #i "], %[" CFLIP "]\n\t"
-// sign +1: p=1,c=0 -> +1 ; sign -1: p=1,c=0 -> -1
-#define ECC_CNDP(i) ECC_CND(i, "-1", "1")
-#define ECC_CNDM(i) ECC_CND(i, "1", "-1")
-#define ECC_DBLP(i) ECC_DBL(i, "one", "mone")
-#define ECC_DBLM(i) ECC_DBL(i, "mone", "one")
-
-#define ECC_UPD_ASM(BODY)                                                                      \
-    asm volatile("s_mov_b64 %[sv], exec\n\t" BODY "s_mov_b64 exec, %[sv]"                      \
-                 : [sv] "=&s"(sv), [t0] "=&v"(t0), [t1] "=&v"(t1), [t2] "=&v"(t2), [t3] "=&v"(t3) \
-                 : [g0] "v"(g0), [g1] "v"(g1), [g2] "v"(g2), [g3] "v"(g3), [c0] "s"(c0), [c1] "s"(c1), \
-                   [c2] "s"(c2), [c3] "s"(c3), [p0] "s"(p0), [p1] "s"(p1), [p2] "s"(p2), [p3] "s"(p3),  \
-                   [one] "v"(one), [mone] "v"(mone)                                             \
+// Histogram updates of four (row, field) items at once.  Item i adds at byte
+// offset g_i on the lanes whose ownership flag flips between planes
+// (p_i != c_i): +s_i where it falls (p_i set, c_i clear) and -s_i where it
+// rises.  Two forms per item, chosen at compile time (bit i of DM):
+//  - select (bit clear): one add of e_i = (p_i ? s_i : -s_i) on the lanes of
+//    p_i ^ c_i; e_i is built beforehand with full EXEC (it depends only on the
+//    previous plane's mask, so it is off the critical path);
+//  - split (bit set): an add of the constant +-1 on p_i & ~c_i and one of the
+//    opposite constant on c_i & ~p_i: no vector select, but two LDS
+//    instructions.
+// The block sets EXEC directly from the lane masks and restores it before
+// returning, so the compiler never sees a modified EXEC.  The histogram is the
+// kernel's only LDS object, at LDS address 0, so the bin offsets are LDS
+// addresses.  The scalar ops of the block write SCC, which is therefore
+// declared clobbered: the compiler must not keep a comparison result in SCC
+// across the block.  SG: bit i set = item i has sign -1.
+#define ECC_SEL(i) "s_xor_b64 exec, %[c" #i "], %[p" #i "]\n\tds_add_u32 %[g" #i "], %[e" #i "]\n\t"
+#define ECC_SPL(i, FALL, RISE)                                                   \
+    "s_andn2_b64 exec, %[p" #i "], %[c" #i "]\n\tds_add_u32 %[g" #i "], %[" FALL \
+    "]\n\ts_andn2_b64 exec, %[c" #i "], %[p" #i "]\n\tds_add_u32 %[g" #i "], %[" RISE "]\n\t"
+#define ECC_SPP(i) ECC_SPL(i, "one", "mone")
+#define ECC_SPM(i) ECC_SPL(i, "mone", "one")
+#define ECC_UPD(A, B, C, D)                                                                                       \
+    asm volatile("s_mov_b64 %[sv], exec\n\t" A(0) B(1) C(2) D(3) "s_mov_b64 exec, %[sv]"                        \
+                 : [sv] "=&s"(sv)                                                                                 \
+                 : [g0] "v"(g0), [g1] "v"(g1), [g2] "v"(g2), [g3] "v"(g3), [e0] "v"(e0), [e1] "v"(e1),          \
+                   [e2] "v"(e2), [e3] "v"(e3), [c0] "s"(c0), [c1] "s"(c1), [c2] "s"(c2), [c3] "s"(c3),          \
+                   [p0] "s"(p0), [p1] "s"(p1), [p2] "s"(p2), [p3] "s"(p3), [one] "v"(one), [mone] "v"(mone) \
                  : "memory", "scc")
 
-// SIGNS: bit i set = item i has sign -1.  DBL: bit i set = item i uses DBL.
-template <int SIGNS, int DBL>
+template <int SG, int DM>
 __device__ __forceinline__ void update4(uint32_t g0, uint32_t g1, uint32_t g2, uint32_t g3, uint64_t c0, uint64_t c1,
                                         uint64_t c2, uint64_t c3, uint64_t p0, uint64_t p1, uint64_t p2, uint64_t p3,
-                                        uint32_t one, uint32_t mone) {
+                                        uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3, uint32_t one,
+                                        uint32_t mone) {
     uint64_t sv;
-    uint32_t t0, t1, t2, t3;
-    // NIN == 2 signs (+,-,-,+) = 0b0110; NIN == 1 signs (-,+,-,+) = 0b0101.
-    if constexpr (SIGNS == 0b0110 && DBL == 0b0000) {
-        ECC_UPD_ASM(ECC_CNDP(0) ECC_CNDM(1) ECC_CNDM(2) ECC_CNDP(3));
-    } else if constexpr (SIGNS == 0b0110 && DBL == 0b0110) {
-        ECC_UPD_ASM(ECC_CNDP(0) ECC_DBLM(1) ECC_DBLM(2) ECC_CNDP(3));
-    } else if constexpr (SIGNS == 0b0110 && DBL == 0b1001) {
-        ECC_UPD_ASM(ECC_DBLP(0) ECC_CNDM(1) ECC_CNDM(2) ECC_DBLP(3));
-    } else if constexpr (SIGNS == 0b0110 && DBL == 0b1111) {
-        ECC_UPD_ASM(ECC_DBLP(0) ECC_DBLM(1) ECC_DBLM(2) ECC_DBLP(3));
-    } else if constexpr (SIGNS == 0b0101 && DBL == 0b0000) {
-        ECC_UPD_ASM(ECC_CNDM(0) ECC_CNDP(1) ECC_CNDM(2) ECC_CNDP(3));
-    } else if constexpr (SIGNS == 0b0101 && DBL == 0b1111) {
-        ECC_UPD_ASM(ECC_DBLM(0) ECC_DBLP(1) ECC_DBLM(2) ECC_DBLP(3));
-    } else if constexpr (SIGNS == 0b0101 && DBL == 0b0101) {
-        ECC_UPD_ASM(ECC_DBLM(0) ECC_CNDP(1) ECC_DBLM(2) ECC_CNDP(3));
-    } else {
-        static_assert(SIGNS < 0, "update4: combination not instantiated");
-    }
+    if constexpr (DM == 0) ECC_UPD(ECC_SEL, ECC_SEL, ECC_SEL, ECC_SEL);
+    else if constexpr (SG == 0b0110 && DM == 0b0110) ECC_UPD(ECC_SEL, ECC_SPM, ECC_SPM, ECC_SEL);
+    else if constexpr (SG == 0b0110 && DM == 0b1001) ECC_UPD(ECC_SPP, ECC_SEL, ECC_SEL, ECC_SPP);
+    else if constexpr (SG == 0b0110 && DM == 0b1111) ECC_UPD(ECC_SPP, ECC_SPM, ECC_SPM, ECC_SPP);
+    else if constexpr (SG == 0b0101 && DM == 0b0101) ECC_UPD(ECC_SPM, ECC_SEL, ECC_SPM, ECC_SEL);
+    else if constexpr (SG == 0b0101 && DM == 0b1010) ECC_UPD(ECC_SEL, ECC_SPP, ECC_SEL, ECC_SPP);
+    else if constexpr (SG == 0b0101 && DM == 0b1111) ECC_UPD(ECC_SPM, ECC_SPP, ECC_SPM, ECC_SPP);
+    else static_assert(DM < 0, "update4: form not instantiated");
+}
+#undef ECC_UPD
+#undef ECC_SPM
+#undef ECC_SPP
+#undef ECC_SPL
+#undef ECC_SEL
+
+// +-1 of an item from the previous plane's ownership mask p (lane bit set:
+// the vertex below was owned by this edge, so a flip removes it: +s).
+__device__ __forceinline__ uint32_t flip_value(uint64_t p, int s) {
+    return __builtin_amdgcn_inverse_ballot_w64(p) ? (uint32_t)s : (uint32_t)(-s);
+}
+
+// Update forms per group of four items (DM of update4).  Mode 0: all select;
+// 1: split on the items of sign -1 (nin == 2) or of the vertex field
+// (nin == 1); 2: split on the others; 3: all split.
+template <int NIN, int MODE>
+constexpr int group_dm() {
+    constexpr int half = (NIN == 2) ? 0b0110 : 0b0101;
+    return MODE == 0 ? 0 : MODE == 1 ? half : MODE == 2 ? (0b1111 ^ half) : 0b1111;
 }
 
 template <int NIN, int R>
@@ -189,7 +190,10 @@ struct Walker {
         for (int i = 0; i < NI; ++i) g[i] = kInf;
     }
 
-    static constexpr int kSigns = (NIN == 2) ? 0b0110 : 0b0101;
+    // sign (-1)^(in-plane interval axes) of item i = r*K + k, k's bits = singleton axes
+    static constexpr int sign(int i) { return (((NIN - __builtin_popcount(i % K)) & 1) ? -1 : 1); }
+    // sign bits of a group of four items (bit j set: item j has sign -1)
+    static constexpr int kGroupSigns = (NIN == 2) ? 0b0110 : 0b0101;
 };
 
 // Validity on the far edges of the in-plane axes (see the boundary rule at the
@@ -223,28 +227,36 @@ __device__ __forceinline__ uint64_t edge_mask(const EdgeMasks &em, int i) {
 
 // One wave walks the planes [zs, ze) of its rows.  FULL: no position of this
 // wave lies on a far edge, so the comparison masks need no validity mask.
-template <typename T, int NIN, int R, int DBL, bool FULL>
-__device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uint32_t (&voff)[2][R + 1],
-                                     const uint32_t (&soff)[R + 1], const EdgeMasks &em, uint32_t &orv) {
+// PD: planes of raw loads kept in flight ahead of the plane being compared.
+// The plane loop is unrolled by lcm(2, PD+1) so that every register buffer is
+// addressed with a compile-time index (plane p of the tile uses raw buffer
+// (p - zs) mod (PD+1) and field buffer (p - zs) mod 2).
+template <typename T, int NIN, int R, int MODE, bool FULL, int PD>
+__device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uint32_t (&vx)[R + 1],
+                                     const uint32_t (&vxl)[R + 1], const uint32_t (&soff)[R + 1], const EdgeMasks &em,
+                                     uint32_t &orv) {
     using W = Walker<NIN, R>;
     constexpr int NR = W::NR;
     constexpr int NI = W::NI;
     constexpr int ESZ = sizeof(T);
-    const int32_t pbytes = (int32_t)P.src.plane_bytes;
-    const uint32_t one = 1u, mone = 0xFFFFFFFFu;
+    constexpr int NB = PD + 1;
+    constexpr int U = (NB % 2 == 0) ? NB : 2 * NB;
+    const int64_t pb = P.src.plane_bytes;
+    const int32_t pbytes = (int32_t)pb;
     // planes zs-1 and ze are +inf outside the image
     const bool lo_real = !(zs == P.e0 && P.lo_inf);
     const bool hi_real = !(ze == P.e1 && P.hi_inf);
+    auto real = [&](int p) { return p < ze || (p == ze && hi_real); };  // for p >= zs
 
-    auto load_plane = [&](int p, uint32_t (&a)[NR], uint32_t (&b)[NR]) {
-        const uint8_t *pp = plane_ptr(P.src, p);
+    auto load_at = [&](const uint8_t *pp, uint32_t (&a)[NR], uint32_t (&b)[NR]) {
         __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)pp, (short)0, pbytes, kBufferWord3);
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) {
-            a[rr] = load_elem(rs, voff[0][rr], soff[rr], ESZ);
-            b[rr] = load_elem(rs, voff[1][rr], soff[rr], ESZ);
+            a[rr] = load_elem(rs, vx[rr], soff[rr], ESZ);
+            b[rr] = load_elem(rs, vxl[rr], soff[rr], ESZ);
         }
     };
+    auto load_plane = [&](int p, uint32_t (&a)[NR], uint32_t (&b)[NR]) { load_at(P.src.base + p * pb, a, b); };
     auto range_acc = [&](const uint32_t (&a)[NR]) {
         // rows owned by this wave (the collar row is checked by its owner)
 #pragma unroll
@@ -256,87 +268,99 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
         else return c & edge_mask<NIN>(em, i);
     };
     // Compare plane z+1 (gn) with plane z (gc) and add the changes of plane z.
+    constexpr int DM = group_dm<NIN, MODE>();
+    const uint32_t one = 1u, mone = 0xFFFFFFFFu;
     auto step = [&](const uint32_t (&gc)[NI], const uint32_t (&gn)[NI], uint64_t (&cp)[NI]) {
 #pragma unroll
         for (int i = 0; i < NI; i += 4) {
+            uint32_t e[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) e[j] = ((DM >> j) & 1) ? one : flip_value(cp[i + j], W::sign(i + j));
             const uint64_t c0 = cmp(gn[i], gc[i], i), c1 = cmp(gn[i + 1], gc[i + 1], i + 1);
             const uint64_t c2 = cmp(gn[i + 2], gc[i + 2], i + 2), c3 = cmp(gn[i + 3], gc[i + 3], i + 3);
-            update4<W::kSigns, DBL>(gc[i], gc[i + 1], gc[i + 2], gc[i + 3], c0, c1, c2, c3, cp[i], cp[i + 1],
-                                    cp[i + 2], cp[i + 3], one, mone);
+            update4<W::kGroupSigns, DM>(gc[i], gc[i + 1], gc[i + 2], gc[i + 3], c0, c1, c2, c3, cp[i], cp[i + 1],
+                                        cp[i + 2], cp[i + 3], e[0], e[1], e[2], e[3], one, mone);
             cp[i] = c0;
             cp[i + 1] = c1;
             cp[i + 2] = c2;
             cp[i + 3] = c3;
         }
     };
-    // fields of plane p from raw (a, b), or +inf for the plane past the end
-    auto next_fields = [&](int p, const uint32_t (&a)[NR], const uint32_t (&b)[NR], uint32_t (&g)[NI]) {
-        if (p < ze || hi_real) {
-            W::fields(a, b, g);
-            if (p < ze) range_acc(a);
-        } else {
-            W::set_inf(g);
-        }
-    };
 
-    uint32_t g0[NI], g1[NI];
+    uint32_t ra[NB][NR], rb[NB][NR];
+    uint32_t g[2][NI];
     uint64_t cp[NI];
-    uint32_t a0[NR], b0[NR], a1[NR], b1[NR];
 
-    // g1 <- plane zs-1 (or +inf), g0 <- plane zs, cp <- [g0 < g1]
+    // g[1] <- plane zs-1 (or +inf), g[0] <- plane zs, cp <- [g0 < g1]
     if (lo_real) {
-        load_plane(zs - 1, a0, b0);
-        W::fields(a0, b0, g1);
+        load_plane(zs - 1, ra[NB - 1], rb[NB - 1]);
+        W::fields(ra[NB - 1], rb[NB - 1], g[1]);
     } else {
-        W::set_inf(g1);
+        W::set_inf(g[1]);
     }
-    load_plane(zs, a1, b1);
-    W::fields(a1, b1, g0);
-    range_acc(a1);
+    load_plane(zs, ra[0], rb[0]);
+    W::fields(ra[0], rb[0], g[0]);
+    range_acc(ra[0]);
 #pragma unroll
-    for (int i = 0; i < NI; ++i) cp[i] = cmp(g0[i], g1[i], i);
+    for (int i = 0; i < NI; ++i) cp[i] = cmp(g[0][i], g[1][i], i);
+#pragma unroll
+    for (int j = 1; j <= PD; ++j)
+        if (real(zs + j)) load_plane(zs + j, ra[j], rb[j]);
 
-    // Invariant at the top of each iteration: g0 holds plane z, a0/b0 hold
-    // the raw values of plane z+1.  Two planes per iteration so that the roles
-    // of (g0, a0/b0) and (g1, a1/b1) alternate without register copies.  The
-    // steady-state loop runs while planes z+1..z+3 are inside the tile, so it
-    // has no boundary tests; the last planes are done after it.
-    if (zs + 1 < ze || hi_real) load_plane(zs + 1, a0, b0);
+    // Phase u of a block handles plane z+u: start the load of plane z+u+1+PD
+    // into the buffer that held plane z+u, turn plane z+u+1 into fields and
+    // compare.  `nxt` points at the next plane to load.  Steady state: every
+    // plane touched lies inside the tile.
+    const uint8_t *nxt = P.src.base + (zs + 1 + PD) * pb;
     int z = zs;
-    for (; z + 3 < ze; z += 2) {
-        load_plane(z + 2, a1, b1);
-        W::fields(a0, b0, g1);
-        range_acc(a0);
-        step(g0, g1, cp);
-        load_plane(z + 3, a0, b0);
-        W::fields(a1, b1, g0);
-        range_acc(a1);
-        step(g1, g0, cp);
+    for (; z + U + PD < ze; z += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            load_at(nxt, ra[u % NB], rb[u % NB]);
+            nxt += pb;
+            W::fields(ra[(u + 1) % NB], rb[(u + 1) % NB], g[(u + 1) & 1]);
+            range_acc(ra[(u + 1) % NB]);
+            step(g[u & 1], g[(u + 1) & 1], cp);
+        }
     }
-    // at most three planes left: z, z+1, z+2 (< ze)
-    if (z < ze) {
-        if (z + 2 < ze || (z + 2 == ze && hi_real)) load_plane(z + 2, a1, b1);
-        next_fields(z + 1, a0, b0, g1);
-        step(g0, g1, cp);
-        ++z;
-        if (z < ze) {
-            if (z + 2 < ze || (z + 2 == ze && hi_real)) load_plane(z + 2, a0, b0);
-            next_fields(z + 1, a1, b1, g0);
-            step(g1, g0, cp);
-            ++z;
-            if (z < ze) {
-                next_fields(z + 1, a0, b0, g1);
-                step(g0, g1, cp);
+    // Last planes, with boundary tests.
+    while (z < ze) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int zz = z + u;
+            if (zz < ze) {
+                if (real(zz + 1 + PD)) load_at(nxt, ra[u % NB], rb[u % NB]);
+                nxt += pb;
+                if (real(zz + 1)) {
+                    W::fields(ra[(u + 1) % NB], rb[(u + 1) % NB], g[(u + 1) & 1]);
+                    if (zz + 1 < ze) range_acc(ra[(u + 1) % NB]);
+                } else {
+                    W::set_inf(g[(u + 1) & 1]);
+                }
+                step(g[u & 1], g[(u + 1) & 1], cp);
             }
         }
+        z += U;
     }
 }
 
-template <typename T, int M, int NIN, int R, int DBL>
-__global__ void __launch_bounds__(1024) int_vcec_kernel(KParams P) {
+// One tile per workgroup.  Workgroups are dispatched round-robin over the 8
+// XCDs; the tile index is permuted so that the workgroups of one XCD take
+// neighbouring tiles, which share collar rows and planes through its L2.
+// Occupancy the register budget is fitted to (waves per SIMD).  The LDS
+// histogram allows two 16-wave workgroups per CU: R == 2 is fitted to both
+// (8 waves per SIMD, 64 registers), R == 4 to one (4 waves per SIMD), which
+// leaves room for deep load pipelines instead.
+template <int NIN, int R, int PD>
+constexpr int kWavesPerEU() {
+    return (R <= 2) ? 8 : 4;
+}
+
+template <typename T, int M, int NIN, int R, int MODE, int PD>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<NIN, R, PD>())))
+int_vcec_kernel(KParams P) {
     using W = Walker<NIN, R>;
     constexpr int NR = W::NR;
-    constexpr int NI = W::NI;
     constexpr int ESZ = sizeof(T);
     __shared__ int32_t hist[M];
 
@@ -347,7 +371,13 @@ __global__ void __launch_bounds__(1024) int_vcec_kernel(KParams P) {
         if (tid == 0) atomicOr(P.status, 0x80000000u);
         return;
     }
-    for (int i = tid; i < M; i += blockDim.x) hist[i] = 0;
+    // (loops with a uniform trip count: a thread-dependent one makes the
+    // compiler treat later lane masks as divergent)
+    for (int i0 = 0; i0 < M; i0 += (int)blockDim.x)
+        if (i0 + tid < M) hist[i0 + tid] = 0;
+    if (P.zero_vcec && blockIdx.x == 0)
+        for (int i0 = 0; i0 < M; i0 += (int)blockDim.x)
+            if (i0 + tid < M) P.zero_vcec[i0 + tid] = 0;
     __syncthreads();
 
     const int lane = tid & (kWave - 1);
@@ -356,63 +386,48 @@ __global__ void __launch_bounds__(1024) int_vcec_kernel(KParams P) {
     const int wyi = wave / P.wx;
     const int32_t n1 = P.n1, n2 = P.n2;
 
-    // Tiles handed out so that the workgroups resident on one XCD (blockIdx
-    // mod 8 under round-robin dispatch) work on neighbouring tiles, which share
-    // collar rows and planes through that XCD's L2.
-    const int ntiles = P.tiles_x * P.tiles_y * P.tiles_z;
-    int t0, tstep, tend;
-    if ((gridDim.x & 7) == 0 && ntiles >= (int)gridDim.x) {
-        const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3, per = gridDim.x >> 3;
-        t0 = (int)((int64_t)ntiles * xcd / 8) + j;
-        tend = (int)((int64_t)ntiles * (xcd + 1) / 8);
-        tstep = per;
-    } else {
-        t0 = blockIdx.x;
-        tend = ntiles;
-        tstep = gridDim.x;
-    }
+    const int G = gridDim.x;
+    const int b = blockIdx.x;
+    const int t = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+    const int tx = t % P.tiles_x;
+    const int ty = (t / P.tiles_x) % P.tiles_y;
+    const int tz = t / (P.tiles_x * P.tiles_y);
+    const int zs = P.e0 + tz * P.zc;
+    const int ze = min(zs + P.zc, P.e1);
 
     uint32_t orv = 0;
-    for (int t = t0; t < tend; t += tstep) {
-        const int tx = t % P.tiles_x;
-        const int ty = (t / P.tiles_x) % P.tiles_y;
-        const int tz = t / (P.tiles_x * P.tiles_y);
-        const int zs = P.e0 + tz * P.zc;
-        const int ze = min(zs + P.zc, P.e1);
-        if (zs >= ze) continue;
-
-        // Byte offsets of x and of x-1 (clamped into the row) per loaded row,
-        // the row's byte offset within a plane, and the edge masks.
-        uint32_t voff[2][R + 1] = {};
-        uint32_t soff[R + 1] = {};
-        EdgeMasks em{};
-        bool full, any;
-        if constexpr (NIN == 1) {
-            const int32_t seg0 = (tx * P.wx + wxi) * R;
-            any = seg0 * kWave < n2;
-            full = (seg0 + R) * kWave - 1 <= n2 - 2;
+    // Per loaded row: byte offsets of x and of x-1 (clamped into the row) and
+    // the row's byte offset within a plane.  NIN == 1: row r is the 64-wide
+    // x-segment seg0 + r of the single in-plane axis.
+    uint32_t vx[R + 1] = {}, vxl[R + 1] = {}, soff[R + 1] = {};
+    EdgeMasks em{};
+    bool full = false, any = false;
+    if constexpr (NIN == 1) {
+        const int32_t seg0 = (tx * P.wx + wxi) * R;
+        any = seg0 * kWave < n2;
+        full = (seg0 + R) * kWave - 1 <= n2 - 2;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int32_t x = (seg0 + r) * kWave + lane;
-                const int32_t xcl = min(x, n2 - 1);
-                voff[0][r] = (uint32_t)xcl * ESZ;
-                voff[1][r] = (uint32_t)(xcl > 0 ? xcl - 1 : 0) * ESZ;
-                soff[r] = 0;
-            }
-        } else {
-            const int32_t x0 = (tx * P.wx + wxi) * kWave;
-            const int32_t x = x0 + lane;
-            const int32_t y0 = (ty * P.wy + wyi) * R;
-            any = x0 < n2 && y0 < n1;
-            full = (x0 + kWave - 1 <= n2 - 2) && (y0 + R - 1 <= n1 - 2);
-            const int32_t xcl = min(x, n2 - 1);
+        for (int r = 0; r < R; ++r) {
+            const int32_t xcl = min((seg0 + r) * kWave + lane, n2 - 1);
+            vx[r] = (uint32_t)xcl * ESZ;
+            vxl[r] = (uint32_t)(xcl > 0 ? xcl - 1 : 0) * ESZ;
+        }
+    } else {
+        const int32_t x0 = (tx * P.wx + wxi) * kWave;
+        const int32_t x = x0 + lane;
+        const int32_t y0 = (ty * P.wy + wyi) * R;
+        any = x0 < n2 && y0 < n1;
+        full = (x0 + kWave - 1 <= n2 - 2) && (y0 + R - 1 <= n1 - 2);
+        const int32_t xcl = min(x, n2 - 1);
+        const uint32_t ox = (uint32_t)xcl * ESZ, oxl = (uint32_t)(xcl > 0 ? xcl - 1 : 0) * ESZ;
 #pragma unroll
-            for (int rr = 0; rr < NR; ++rr) {
-                voff[0][rr] = (uint32_t)xcl * ESZ;
-                voff[1][rr] = (uint32_t)(xcl > 0 ? xcl - 1 : 0) * ESZ;
-                const int32_t y = min(max(y0 + rr - 1, 0), n1 - 1);
-                soff[rr] = (uint32_t)y * (uint32_t)n2 * ESZ;
-            }
+        for (int rr = 0; rr < NR; ++rr) {
+            vx[rr] = ox;
+            vxl[rr] = oxl;
+            const int32_t y = min(max(y0 + rr - 1, 0), n1 - 1);
+            soff[rr] = (uint32_t)y * (uint32_t)n2 * ESZ;
+        }
+        if (!full) {
             em.lx_int = ballot(x <= n2 - 2);
             em.lx_any = ballot(x < n2);
 #pragma unroll
@@ -421,15 +436,17 @@ __global__ void __launch_bounds__(1024) int_vcec_kernel(KParams P) {
                 em.ry_any |= (uint32_t)(y0 + r < n1) << r;
             }
         }
-        if (!any) continue;
+    }
+    if (any && zs < ze) {
         if (full) {
-            walk<T, NIN, R, DBL, true>(P, zs, ze, voff, soff, em, orv);
+            walk<T, NIN, R, MODE, true, PD>(P, zs, ze, vx, vxl, soff, em, orv);
         } else if constexpr (NIN == 1) {
             // An edge group of segments is walked as pairs of segments, each
-            // with its own lane masks.
+            // pair with its own lane masks.
+            const int32_t seg0 = (tx * P.wx + wxi) * R;
 #pragma unroll
             for (int r = 0; r < R; r += 2) {
-                const int32_t xs = ((tx * P.wx + wxi) * R + r) * kWave;
+                const int32_t xs = (seg0 + r) * kWave;
                 if (xs >= n2) break;
                 const int32_t xa = xs + lane, xb = xs + kWave + lane;
                 EdgeMasks e2{};
@@ -437,12 +454,12 @@ __global__ void __launch_bounds__(1024) int_vcec_kernel(KParams P) {
                 e2.lx_any = ballot(xa < n2);
                 e2.lx_int2 = ballot(xb <= n2 - 2);
                 e2.lx_any2 = ballot(xb < n2);
-                const uint32_t vo[2][3] = {{voff[0][r], voff[0][r + 1], 0u}, {voff[1][r], voff[1][r + 1], 0u}};
-                const uint32_t so[3] = {0u, 0u, 0u};
-                walk<T, 1, 2, DBL, false>(P, zs, ze, vo, so, e2, orv);
+                const uint32_t v2[3] = {vx[r], vx[r + 1], 0u}, vl2[3] = {vxl[r], vxl[r + 1], 0u};
+                const uint32_t s2[3] = {0u, 0u, 0u};
+                walk<T, 1, 2, MODE, false, 1>(P, zs, ze, v2, vl2, s2, e2, orv);
             }
         } else {
-            walk<T, NIN, R, DBL, false>(P, zs, ze, voff, soff, em, orv);
+            walk<T, NIN, R, MODE, false, PD>(P, zs, ze, vx, vxl, soff, em, orv);
         }
     }
 
@@ -452,48 +469,52 @@ __global__ void __launch_bounds__(1024) int_vcec_kernel(KParams P) {
     // the update blocks' LDS adds are not tracked by the compiler's counters
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     __syncthreads();
-    int32_t *dst = P.partial + (size_t)blockIdx.x * M;
-    for (int i = tid; i < M; i += blockDim.x) dst[i] = hist[i];
+    int32_t *dst = P.partial + (size_t)b * M;
+    for (int i0 = 0; i0 < M; i0 += (int)blockDim.x)
+        if (i0 + tid < M) dst[i0 + tid] = hist[i0 + tid];
 }
 
-template <typename T, int M, int NIN, int R, int DBL>
+template <typename T, int M, int NIN, int R, int MODE, int PD>
 static int launch_one(const KParams &p, const IntTiling &tl, hipStream_t stream) {
     const int threads = kWave * tl.wx * tl.wy;
     void *tok = nullptr;
     int rc = profile_begin(stream, &tok);
     if (rc) return rc;
-    hipLaunchKernelGGL((int_vcec_kernel<T, M, NIN, R, DBL>), dim3(tl.grid), dim3(threads), 0, stream, p);
+    hipLaunchKernelGGL((int_vcec_kernel<T, M, NIN, R, MODE, PD>), dim3(tl.grid), dim3(threads), 0, stream, p);
     ECC_HIP(hipGetLastError());
     return profile_end(stream, tok);
 }
 
-template <typename T, int M, int NIN, int R>
-static int launch_dbl(const KParams &p, const IntTiling &tl, hipStream_t stream) {
-    if constexpr (NIN == 2) {
-        switch (tl.dbl) {
-        case 0b0000: return launch_one<T, M, NIN, R, 0b0000>(p, tl, stream);
-        case 0b0110: return launch_one<T, M, NIN, R, 0b0110>(p, tl, stream);
-        case 0b1001: return launch_one<T, M, NIN, R, 0b1001>(p, tl, stream);
-        case 0b1111: return launch_one<T, M, NIN, R, 0b1111>(p, tl, stream);
-        default: break;
-        }
-    } else {
-        switch (tl.dbl) {
-        case 0b0000: return launch_one<T, M, NIN, R, 0b0000>(p, tl, stream);
-        case 0b0101: return launch_one<T, M, NIN, R, 0b0101>(p, tl, stream);
-        case 0b1111: return launch_one<T, M, NIN, R, 0b1111>(p, tl, stream);
-        default: break;
-        }
+template <typename T, int M, int NIN, int R, int MODE>
+static int launch_pd(const KParams &p, const IntTiling &tl, hipStream_t stream) {
+    switch (tl.pd) {
+    case 1: return launch_one<T, M, NIN, R, MODE, 1>(p, tl, stream);
+    case 2: return launch_one<T, M, NIN, R, MODE, 2>(p, tl, stream);
+    case 3: return launch_one<T, M, NIN, R, MODE, 3>(p, tl, stream);
+    default: break;
     }
-    set_error("integer kernel: update mode %d not built", tl.dbl);
+    set_error("integer kernel: prefetch depth %d not built", tl.pd);
+    return ECC_E_UNSUPPORTED;
+}
+
+template <typename T, int M, int NIN, int R>
+static int launch_mode(const KParams &p, const IntTiling &tl, hipStream_t stream) {
+    switch (tl.mode) {
+    case 0: return launch_pd<T, M, NIN, R, 0>(p, tl, stream);
+    case 1: return launch_pd<T, M, NIN, R, 1>(p, tl, stream);
+    case 2: return launch_pd<T, M, NIN, R, 2>(p, tl, stream);
+    case 3: return launch_pd<T, M, NIN, R, 3>(p, tl, stream);
+    default: break;
+    }
+    set_error("integer kernel: update mode %d not built", tl.mode);
     return ECC_E_UNSUPPORTED;
 }
 
 template <typename T, int M, int NIN>
 static int launch_rows(const KParams &p, const IntTiling &tl, hipStream_t stream) {
     switch (tl.rows) {
-    case 2: return launch_dbl<T, M, NIN, 2>(p, tl, stream);
-    case 4: return launch_dbl<T, M, NIN, 4>(p, tl, stream);
+    case 2: return launch_mode<T, M, NIN, 2>(p, tl, stream);
+    case 4: return launch_mode<T, M, NIN, 4>(p, tl, stream);
     default: break;
     }
     set_error("integer kernel: %d rows per wave not built", tl.rows);
@@ -501,7 +522,7 @@ static int launch_rows(const KParams &p, const IntTiling &tl, hipStream_t stream
 }
 
 int launch_int_partial(const IntJob &job, const IntTiling &tl, int32_t *partial, uint32_t *status,
-                       hipStream_t stream) {
+                       int64_t *zero_vcec, hipStream_t stream) {
     KParams p{};
     p.src = job.src;
     p.n1 = job.view.n1;
@@ -520,6 +541,7 @@ int launch_int_partial(const IntJob &job, const IntTiling &tl, int32_t *partial,
     p.tiles_z = (job.e1 - job.e0 + tl.zc - 1) / tl.zc;
     p.partial = partial;
     p.status = status;
+    p.zero_vcec = zero_vcec;
     if (job.dtype == ECC_U8)
         return nin == 1 ? launch_rows<uint8_t, 256, 1>(p, tl, stream) : launch_rows<uint8_t, 256, 2>(p, tl, stream);
     if (job.dtype == ECC_U14)

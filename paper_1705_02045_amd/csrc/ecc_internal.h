@@ -23,13 +23,11 @@ int hip_fail(hipError_t e, const char *what);
         if (_e != hipSuccess) return hip_fail(_e, #call); \
     } while (0)
 
-// Source of axis-0 planes for one launch: planes [0, seg0_planes) live at
-// seg0, the following planes at seg1.  Lets a chunk be read together with the
-// collar planes kept from the previous chunk without copying either.
+// Source of axis-0 planes for one launch: plane p starts at
+// base + p * plane_bytes (one contiguous buffer, so the kernel advances a
+// plane pointer instead of recomputing it).
 struct PlaneSrc {
-    const uint8_t *seg0;
-    const uint8_t *seg1;
-    int64_t seg0_planes;
+    const uint8_t *base;
     int64_t plane_bytes;
 };
 
@@ -54,10 +52,11 @@ struct IntJob {
 // Tiling of the integer kernel (chosen by the tuner in ecc_tune.cpp).
 struct IntTiling {
     int rows;      // rows (nin == 2) or 64-wide x segments (nin == 1) per wave
-    int dbl;       // per-item update form of the four-item blocks (see ecc_int.hip)
+    int mode;      // update form of the four-item groups (0..3, see ecc_int.hip)
+    int pd;        // planes of raw loads in flight ahead of the compared plane
     int wx, wy;    // waves per workgroup along x and along y
     int zc;        // planes per tile
-    int grid;      // workgroups (persistent)
+    int grid;      // workgroups = tiles (one tile per workgroup)
 };
 
 // Device scratch of one (device, stream) pair.
@@ -68,7 +67,9 @@ struct Workspace {
     size_t partial_bytes = 0;
     int64_t *vcec = nullptr;     // [m] changes vector
     size_t vcec_bytes = 0;
-    uint32_t *status = nullptr;  // device status word
+    uint32_t *status = nullptr;  // device words: [0] status, [2] status copy
+    int64_t *stage = nullptr;    // merge stage rows
+    size_t stage_bytes = 0;
     int64_t *chi_tmp = nullptr;  // [m] curve staging for host outputs
     size_t chi_tmp_bytes = 0;
     void *img_tmp = nullptr;     // device copy of a host image
@@ -84,13 +85,17 @@ int device_cu_count();
 IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes);
 
 // Kernels (ecc_int.hip / ecc_scan.hip).  All enqueue on `stream`.
+// zero_vcec: when not null, workgroup 0 clears m int64 entries there first.
 int launch_int_partial(const IntJob &job, const IntTiling &tl, int32_t *partial, uint32_t *status,
-                       hipStream_t stream);
+                       int64_t *zero_vcec, hipStream_t stream);
 int launch_zero(void *p, size_t bytes, hipStream_t stream);
-int launch_reduce_rows(const int32_t *partial, int rows, int m, int64_t *vcec, bool accumulate,
-                       hipStream_t stream);
-int launch_scan(const int64_t *vcec, int m, int64_t *chi, const uint32_t *status, uint32_t *status_out,
-                hipStream_t stream);
+// Column sums of the per-workgroup rows into vcec through int64 stage rows
+// ([merge_stage_rows(rows)][m]) and, with do_scan, the prefix sum of vcec into
+// chi (ecc_scan.hip).  The scan copies the status word to status_out (when
+// not null) and clears it.
+int merge_stage_rows(int rows);
+int launch_merge(const int32_t *partial, int rows, int m, int64_t *stage, int64_t *vcec, bool accumulate,
+                 bool do_scan, int64_t *chi, uint32_t *status, uint32_t *status_out, hipStream_t stream);
 
 bool normalize_int_view(const ecc_dims *dims, IntView *v, int *err_ndim_dropped);
 

@@ -25,52 +25,26 @@ int launch_zero(void *p, size_t bytes, hipStream_t stream) {
     return ECC_OK;
 }
 
-// Column sums of the [rows][m] int32 table into int64 vcec.  Block (bx, by)
-// sums rows by, by + gridDim.y, ... of columns bx*256 .. bx*256+255, then adds
-// its partial sum with one 64-bit atomic per column.
-__global__ void reduce_rows_kernel(const int32_t *__restrict__ partial, int rows, int m,
-                                   unsigned long long *vcec) {
-    const int col = blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= m) return;
-    int64_t s = 0;
-    for (int r = blockIdx.y; r < rows; r += gridDim.y) s += partial[(size_t)r * m + col];
-    if (s != 0) atomicAdd(&vcec[col], (unsigned long long)s);
-}
-
-int launch_reduce_rows(const int32_t *partial, int rows, int m, int64_t *vcec, bool accumulate,
-                       hipStream_t stream) {
-    if (!accumulate) {
-        int rc = launch_zero(vcec, (size_t)m * sizeof(int64_t), stream);
-        if (rc) return rc;
-    }
-    const int threads = 256;
-    const int bx = (m + threads - 1) / threads;
-    int by = 1;
-    while (by < 32 && bx * by < 512 && by * 8 <= rows) by *= 2;
-    hipLaunchKernelGGL(reduce_rows_kernel, dim3(bx, by), dim3(threads), 0, stream, partial, rows, m,
-                       (unsigned long long *)vcec);
-    ECC_HIP(hipGetLastError());
-    return ECC_OK;
-}
-
-// Inclusive prefix sum of m int64 values by one workgroup of 1024 threads.
-// The curve is written only if the status word reports a valid input; the
-// status is copied to status_out when that is given.
-__global__ void __launch_bounds__(1024) scan_kernel(const int64_t *__restrict__ vcec, int m, int64_t *chi,
-                                                   const uint32_t *status, uint32_t *status_out) {
+// Inclusive prefix sum of m int64 values by one workgroup: chunks of
+// blockDim*16 values, each thread scanning 16 consecutive values of a chunk,
+// the thread totals scanned across the block, a running carry between chunks.
+__device__ void block_scan_write(const int64_t *__restrict__ in, int m, int64_t *out) {
     __shared__ int64_t wsum[16];
     __shared__ int64_t carry_s;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const uint32_t st = status ? *status : 0u;
-    if (status_out && tid == 0) *status_out = st;
-    if (st != 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nwaves = blockDim.x >> 6;
     if (tid == 0) carry_s = 0;
     __syncthreads();
-    for (int base = 0; base < m; base += 1024) {
-        const int i = base + tid;
-        int64_t v = i < m ? vcec[i] : 0;
-        // wave-level inclusive scan
+    for (int c0 = 0; c0 < m; c0 += (int)blockDim.x * 16) {
+        const int base = c0 + tid * 16;
+        int64_t loc[16];
+        int64_t run = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            run += (base + j < m) ? in[base + j] : 0;
+            loc[j] = run;
+        }
+        int64_t v = run;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const int64_t u = __shfl_up(v, off, 64);
@@ -79,28 +53,124 @@ __global__ void __launch_bounds__(1024) scan_kernel(const int64_t *__restrict__ 
         if (lane == 63) wsum[wave] = v;
         __syncthreads();
         if (wave == 0) {
-            int64_t w = lane < 16 ? wsum[lane] : 0;
+            int64_t w = lane < nwaves ? wsum[lane] : 0;
 #pragma unroll
             for (int off = 1; off < 16; off <<= 1) {
                 const int64_t u = __shfl_up(w, off, 64);
                 if (lane >= off) w += u;
             }
-            if (lane < 16) wsum[lane] = w;  // inclusive totals of waves 0..lane
+            if (lane < nwaves) wsum[lane] = w;
         }
         __syncthreads();
-        const int64_t carry = carry_s;
-        const int64_t before = wave > 0 ? wsum[wave - 1] : 0;
-        if (i < m) chi[i] = carry + before + v;
+        const int64_t offset = carry_s + (v - run) + (wave > 0 ? wsum[wave - 1] : 0);
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (base + j < m) out[base + j] = offset + loc[j];
         __syncthreads();
-        if (tid == 0) carry_s = carry + wsum[15];
+        if (tid == 0) carry_s += wsum[nwaves - 1];
         __syncthreads();
     }
 }
 
-int launch_scan(const int64_t *vcec, int m, int64_t *chi, const uint32_t *status, uint32_t *status_out,
-                hipStream_t stream) {
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, vcec, m, chi, status, status_out);
-    ECC_HIP(hipGetLastError());
+// Merge of the per-workgroup rows [rows][m] (int32) into the int64 change
+// vector, in kernels that follow each other on the stream (the kernel
+// boundary orders their memory; no fences or counters):
+//  1. colsum_kernel, block (bx, by): rows by, by+BY, ... of columns
+//     bx*1024 .. +1023 (256 threads x 4 columns, 16-byte loads), written to
+//     stage[by][column], or, with BY == 1, straight into vcec;
+//  2. fold_kernel (BY > 1): the BY stage rows of each column into vcec;
+//  3. scan_kernel (one block): the curve is the prefix sum of vcec, written
+//     if the status word is clear; the status is copied and cleared.
+// vcec is overwritten, or added to with `accumulate`.
+__global__ void __launch_bounds__(256) colsum_kernel(const int32_t *__restrict__ partial, int rows, int m,
+                                                     int64_t *__restrict__ dst, int accumulate) {
+    const int BY = gridDim.y;
+    const int c0 = blockIdx.x * 1024 + threadIdx.x * 4;
+    if (c0 >= m) return;
+    int64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    const int4 *p = reinterpret_cast<const int4 *>(partial);
+    const size_t stride4 = (size_t)m / 4;
+    int r = blockIdx.y;
+    for (; r + 3 * BY < rows; r += 4 * BY) {
+        int4 a[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[j] = p[(size_t)(r + j * BY) * stride4 + c0 / 4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            s0 += a[j].x;
+            s1 += a[j].y;
+            s2 += a[j].z;
+            s3 += a[j].w;
+        }
+    }
+    for (; r < rows; r += BY) {
+        const int4 a = p[(size_t)r * stride4 + c0 / 4];
+        s0 += a.x;
+        s1 += a.y;
+        s2 += a.z;
+        s3 += a.w;
+    }
+    int64_t *d = dst + (size_t)blockIdx.y * m + c0;
+    if (accumulate) {
+        s0 += d[0];
+        s1 += d[1];
+        s2 += d[2];
+        s3 += d[3];
+    }
+    d[0] = s0;
+    d[1] = s1;
+    d[2] = s2;
+    d[3] = s3;
+}
+
+__global__ void __launch_bounds__(256) fold_kernel(const int64_t *__restrict__ stage, int by, int m,
+                                                   int64_t *__restrict__ vcec, int accumulate) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= m) return;
+    int64_t t = accumulate ? vcec[c] : 0;
+    for (int y = 0; y < by; ++y) t += stage[(size_t)y * m + c];
+    vcec[c] = t;
+}
+
+__global__ void __launch_bounds__(1024) scan_kernel(const int64_t *__restrict__ vcec, int m, int64_t *chi,
+                                                    uint32_t *status, uint32_t *status_out) {
+    const uint32_t stv = *status;
+    if (stv == 0) block_scan_write(vcec, m, chi);
+    if (threadIdx.x == 0) {
+        if (status_out) *status_out = stv;
+        *status = 0u;
+    }
+}
+
+int merge_stage_rows(int rows) {
+    int by = 1;
+    while (by < 32 && by * 8 <= rows) by *= 2;
+    return by;
+}
+
+int launch_merge(const int32_t *partial, int rows, int m, int64_t *stage, int64_t *vcec, bool accumulate,
+                 bool do_scan, int64_t *chi, uint32_t *status, uint32_t *status_out, hipStream_t stream) {
+    if (m % 4 != 0 || m > 65536) {
+        set_error("launch_merge: m = %d not supported", m);
+        return ECC_E_ARG;
+    }
+    if (rows > 0) {
+        const int bx = (m + 1023) / 1024;
+        const int by = merge_stage_rows(rows);
+        hipLaunchKernelGGL(colsum_kernel, dim3(bx, by), dim3(256), 0, stream, partial, rows, m,
+                           by == 1 ? vcec : stage, (by == 1 && accumulate) ? 1 : 0);
+        ECC_HIP(hipGetLastError());
+        if (by > 1) {
+            hipLaunchKernelGGL(fold_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, (const int64_t *)stage, by,
+                               m, vcec, accumulate ? 1 : 0);
+            ECC_HIP(hipGetLastError());
+        }
+    }
+    if (do_scan) {
+        hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, (const int64_t *)vcec, m, chi, status,
+                           status_out);
+        ECC_HIP(hipGetLastError());
+    }
     return ECC_OK;
 }
 

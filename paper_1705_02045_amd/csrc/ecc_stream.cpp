@@ -1,10 +1,15 @@
 // Streaming interface (Sec. 3, "Streaming", "Parallel Computations" and
 // "Processing one Chunk"): the image arrives as consecutive chunks of whole
-// axis-0 planes.  Each chunk is processed together with the collar planes it
-// needs: the previous chunk's last two planes are kept on the device (the
-// lower collar of the deferred plane and the deferred plane itself), and each
-// chunk's own last plane waits for the next chunk, which holds its upper
-// collar.  Counts accumulate on the device; the prefix sum is taken once.
+// axis-0 planes.  Each chunk's last plane waits for the next chunk, which
+// holds its upper collar.  The changes of a plane need the planes on either
+// side of it, so a chunk [f, f+n) is split in two launches over contiguous
+// buffers:
+//  - the seam: the deferred plane f-1 and plane f, read from a small device
+//    buffer holding the last two planes of the previous chunk followed by
+//    copies of the chunk's first two planes;
+//  - the body: planes [f+1, f+n-1) (to the end of the image on the last
+//    chunk), read from the chunk itself.
+// Counts accumulate on the device; the prefix sum is taken once.
 //
 // Host chunks go through two device staging buffers filled on a copy stream
 // (hipMemcpyAsync), so the copy of chunk k+1 overlaps the kernels of chunk k.
@@ -23,8 +28,9 @@ struct ecc_stream {
     int64_t plane_bytes = 0;
     int64_t pushed = 0;   // image planes received
     int64_t emitted = 0;  // image planes whose changes were added
-    // collar: up to two image planes [pushed - ncarry, pushed), double-buffered
-    uint8_t *carry[2] = {nullptr, nullptr};
+    // seam buffers of four planes: [0, ncarry) hold image planes
+    // [pushed - ncarry, pushed); a push appends the chunk's first planes
+    uint8_t *seam[2] = {nullptr, nullptr};
     int cur = 0;
     int ncarry = 0;
     // staging for host chunks
@@ -37,6 +43,8 @@ struct ecc_stream {
     // device change vector and per-workgroup rows
     int32_t *partial = nullptr;
     size_t partial_bytes = 0;
+    int64_t *mstage = nullptr;  // merge stage rows
+    size_t mstage_bytes = 0;
     int64_t *vcec = nullptr;
     uint32_t *status = nullptr;
 };
@@ -53,12 +61,13 @@ void destroy(ecc_stream *st) {
     if (st->compute) (void)hipStreamSynchronize(st->compute);
     if (st->copy) (void)hipStreamSynchronize(st->copy);
     for (int i = 0; i < 2; ++i) {
-        if (st->carry[i]) (void)hipFree(st->carry[i]);
+        if (st->seam[i]) (void)hipFree(st->seam[i]);
         if (st->stage[i]) (void)hipFree(st->stage[i]);
         if (st->ready[i]) (void)hipEventDestroy(st->ready[i]);
         if (st->released[i]) (void)hipEventDestroy(st->released[i]);
     }
     if (st->partial) (void)hipFree(st->partial);
+    if (st->mstage) (void)hipFree(st->mstage);
     if (st->vcec) (void)hipFree(st->vcec);
     if (st->status) (void)hipFree(st->status);
     if (st->copy) (void)hipStreamDestroy(st->copy);
@@ -77,44 +86,72 @@ bool is_device_ptr(const void *p) {
     return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
-// Adds the changes of image planes [lo, hi) using the planes held in the
-// carry buffer (image planes [first - ncarry, first)) followed by the chunk
-// (image planes [first, first + nchunk)).
-int run_planes(ecc_stream *st, const uint8_t *chunk, int64_t first, int64_t lo, int64_t hi) {
-    if (hi <= lo) return ECC_OK;
-    const int64_t buf0 = first - st->ncarry;  // image plane of buffer plane 0
-    IntJob job{};
-    job.src.seg0 = st->carry[st->cur];
-    job.src.seg1 = chunk;
-    job.src.seg0_planes = st->ncarry;
-    job.src.plane_bytes = st->plane_bytes;
-    job.view = st->view;
-    job.e0 = (int32_t)(lo - buf0);
-    job.e1 = (int32_t)(hi - buf0);
-    job.lo_inf = lo == 0;
-    job.hi_inf = hi == st->view.n0;
-    job.dtype = st->dtype;
-    IntTiling tl = choose_int_tiling(st->view, st->dtype, hi - lo);
-    int rc = ensure_bytes((void **)&st->partial, &st->partial_bytes, (size_t)tl.grid * st->m * sizeof(int32_t));
-    if (rc) return rc;
-    rc = launch_int_partial(job, tl, st->partial, st->status, st->compute);
-    if (rc) return rc;
-    return launch_reduce_rows(st->partial, tl.grid, st->m, st->vcec, true, st->compute);
-}
+int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
 
-// Keeps the last (up to two) planes of carry + chunk as the next carry.
-int update_carry(ecc_stream *st, const uint8_t *chunk, int64_t nchunk) {
-    const int nxt = st->cur ^ 1;
-    const int keep = (int)((st->ncarry + nchunk) < 2 ? (st->ncarry + nchunk) : 2);
-    // planes of the concatenation [carry (ncarry) | chunk (nchunk)], keep the last `keep`
-    const int64_t total = st->ncarry + nchunk;
-    for (int j = 0; j < keep; ++j) {
-        const int64_t b = total - keep + j;
-        const uint8_t *src = b < st->ncarry ? st->carry[st->cur] + b * st->plane_bytes
-                                            : chunk + (b - st->ncarry) * st->plane_bytes;
-        ECC_HIP(hipMemcpyAsync(st->carry[nxt] + (int64_t)j * st->plane_bytes, src, (size_t)st->plane_bytes,
-                               hipMemcpyDeviceToDevice, st->compute));
+// Adds the changes of image planes [lo, hi) of `chunk` (image planes
+// [f, f + n)) and of the seam, and keeps the last two planes for the next push.
+int run_chunk(ecc_stream *st, const uint8_t *chunk, int64_t f, int64_t n, int64_t hi) {
+    const int64_t pb = st->plane_bytes;
+    const int64_t n0 = st->view.n0;
+    const int a = st->ncarry;
+    const int64_t k2 = min64(n, 2);
+    uint8_t *seam = st->seam[st->cur];
+    ECC_HIP(hipMemcpyAsync(seam + a * pb, chunk, (size_t)(k2 * pb), hipMemcpyDeviceToDevice, st->compute));
+
+    const int64_t lo = st->emitted;
+    const int64_t body_lo = f == 0 ? 0 : min64(f + 1, hi);
+    IntJob jobs[2];
+    IntTiling tl[2];
+    int njobs = 0;
+    if (lo < body_lo) {  // seam buffer plane j is image plane f - a + j
+        IntJob &j = jobs[njobs];
+        j = IntJob{};
+        j.src.base = seam;
+        j.e0 = (int32_t)(lo - (f - a));
+        j.e1 = (int32_t)(body_lo - (f - a));
+        j.lo_inf = lo == 0;
+        j.hi_inf = body_lo == n0;
+        tl[njobs++] = choose_int_tiling(st->view, st->dtype, body_lo - lo);
     }
+    if (body_lo < hi) {  // chunk plane j is image plane f + j
+        IntJob &j = jobs[njobs];
+        j = IntJob{};
+        j.src.base = chunk;
+        j.e0 = (int32_t)(body_lo - f);
+        j.e1 = (int32_t)(hi - f);
+        j.lo_inf = body_lo == 0;
+        j.hi_inf = hi == n0;
+        tl[njobs++] = choose_int_tiling(st->view, st->dtype, hi - body_lo);
+    }
+    int rows = 0;
+    for (int i = 0; i < njobs; ++i) rows += tl[i].grid;
+    if (rows > 0) {
+        int rc = ensure_bytes((void **)&st->partial, &st->partial_bytes, (size_t)rows * st->m * sizeof(int32_t));
+        if (rc) return rc;
+        rc = ensure_bytes((void **)&st->mstage, &st->mstage_bytes,
+                          (size_t)merge_stage_rows(rows) * st->m * sizeof(int64_t));
+        if (rc) return rc;
+        int row0 = 0;
+        for (int i = 0; i < njobs; ++i) {
+            jobs[i].src.plane_bytes = pb;
+            jobs[i].view = st->view;
+            jobs[i].dtype = st->dtype;
+            rc = launch_int_partial(jobs[i], tl[i], st->partial + (size_t)row0 * st->m, st->status, nullptr,
+                                    st->compute);
+            if (rc) return rc;
+            row0 += tl[i].grid;
+        }
+        rc = launch_merge(st->partial, rows, st->m, st->mstage, st->vcec, true, false, nullptr, st->status, nullptr,
+                          st->compute);
+        if (rc) return rc;
+    }
+
+    // next carry: the last min(a + n, 2) image planes, from the chunk when it
+    // has two planes, else from the seam (which then holds all of them)
+    const int nxt = st->cur ^ 1;
+    const int keep = (int)min64(a + n, 2);
+    const uint8_t *src = n >= 2 ? chunk + (n - 2) * pb : seam + (a + k2 - keep) * pb;
+    ECC_HIP(hipMemcpyAsync(st->seam[nxt], src, (size_t)(keep * pb), hipMemcpyDeviceToDevice, st->compute));
     st->cur = nxt;
     st->ncarry = keep;
     return ECC_OK;
@@ -185,8 +222,8 @@ int ecc_stream_begin(const ecc_dims *full_dims, ecc_dtype dtype, void *stream, e
     hipError_t e = hipStreamCreateWithFlags(&st->copy, hipStreamNonBlocking);
     if (e != hipSuccess) return fail(hip_fail(e, "hipStreamCreate"));
     for (int i = 0; i < 2; ++i) {
-        if ((e = hipMalloc(&st->carry[i], (size_t)st->plane_bytes * 2)) != hipSuccess)
-            return fail(hip_fail(e, "hipMalloc(carry)"));
+        if ((e = hipMalloc(&st->seam[i], (size_t)st->plane_bytes * 4)) != hipSuccess)
+            return fail(hip_fail(e, "hipMalloc(seam)"));
         if ((e = hipEventCreateWithFlags(&st->ready[i], hipEventDisableTiming)) != hipSuccess)
             return fail(hip_fail(e, "hipEventCreate"));
         if ((e = hipEventCreateWithFlags(&st->released[i], hipEventDisableTiming)) != hipSuccess)
@@ -194,9 +231,9 @@ int ecc_stream_begin(const ecc_dims *full_dims, ecc_dtype dtype, void *stream, e
     }
     if ((e = hipMalloc(&st->vcec, (size_t)st->m * sizeof(int64_t))) != hipSuccess)
         return fail(hip_fail(e, "hipMalloc(vcec)"));
-    if ((e = hipMalloc(&st->status, 256)) != hipSuccess) return fail(hip_fail(e, "hipMalloc(status)"));
+    if ((e = hipMalloc(&st->status, 1024)) != hipSuccess) return fail(hip_fail(e, "hipMalloc(status)"));
     if ((rc = launch_zero(st->vcec, (size_t)st->m * sizeof(int64_t), st->compute))) return fail(rc);
-    if ((rc = launch_zero(st->status, 4, st->compute))) return fail(rc);
+    if ((rc = launch_zero(st->status, 1024, st->compute))) return fail(rc);
     *out = st;
     return ECC_OK;
 }
@@ -245,8 +282,7 @@ int ecc_stream_push_chunk(ecc_stream *st, const void *planes, int64_t n_planes) 
         st->nstaged++;
         const int64_t first = st->pushed;
         const int64_t hi = (first + n_planes == st->view.n0) ? st->view.n0 : first + n_planes - 1;
-        rc = run_planes(st, chunk, first, st->emitted, hi);
-        if (!rc) rc = update_carry(st, chunk, n_planes);
+        rc = run_chunk(st, chunk, first, n_planes, hi);
         if (!rc) {
             ECC_HIP(hipEventRecord(st->released[k], st->compute));
             st->released_recorded[k] = true;
@@ -258,8 +294,7 @@ int ecc_stream_push_chunk(ecc_stream *st, const void *planes, int64_t n_planes) 
     } else {
         const int64_t first = st->pushed;
         const int64_t hi = (first + n_planes == st->view.n0) ? st->view.n0 : first + n_planes - 1;
-        rc = run_planes(st, chunk, first, st->emitted, hi);
-        if (!rc) rc = update_carry(st, chunk, n_planes);
+        rc = run_chunk(st, chunk, first, n_planes, hi);
         if (!rc) {
             st->emitted = hi;
             st->pushed = first + n_planes;
@@ -302,10 +337,11 @@ int ecc_stream_finish(ecc_stream *st, ecc_curve *curve) {
             rc = hip_fail(e, "hipMalloc(curve)");
             break;
         }
-        rc = launch_scan(st->vcec, st->m, tmp, st->status, nullptr, st->compute);
+        rc = launch_merge(nullptr, 0, st->m, nullptr, st->vcec, true, true, tmp, st->status, st->status + 2,
+                          st->compute);
         uint32_t stv = 0;
         if (!rc) {
-            e = hipMemcpyAsync(&stv, st->status, 4, hipMemcpyDeviceToHost, st->compute);
+            e = hipMemcpyAsync(&stv, st->status + 2, 4, hipMemcpyDeviceToHost, st->compute);
             if (e == hipSuccess) e = hipStreamSynchronize(st->compute);
             if (e != hipSuccess) rc = hip_fail(e, "status read");
         }
