@@ -79,13 +79,13 @@ int get_workspace(void *stream, Workspace **out) {
         w->device = dev;
         w->stream = stream;
         void *p = nullptr;
-        hipError_t e = hipMalloc(&p, 1024);
+        hipError_t e = hipMalloc(&p, kStatusBytes);
         if (e != hipSuccess) {
             delete w;
             return hip_fail(e, "hipMalloc(status)");
         }
         w->status = (uint32_t *)p;
-        int rc = launch_zero(p, 1024, (hipStream_t)stream);
+        int rc = launch_zero(p, kStatusBytes, (hipStream_t)stream);
         if (rc) {
             (void)hipFree(p);
             delete w;
@@ -157,13 +157,14 @@ static int env_int(const char *name, int dflt) {
     return (s && *s) ? atoi(s) : dflt;
 }
 
-// Tuning overrides (measurement only): ECC_INT_ROWS, ECC_INT_MODE, ECC_INT_PD,
+// Tuning overrides (measurement only): ECC_INT_ROWS, ECC_INT_MODE, ECC_INT_PD, ECC_INT_KPF,
 // ECC_INT_WAVES, ECC_INT_TILES_PER_CU.
 IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
     IntTiling t{};
     t.rows = env_int("ECC_INT_ROWS", 2);
     t.mode = env_int("ECC_INT_MODE", 0);
     t.pd = env_int("ECC_INT_PD", 1);
+    t.kpf = env_int("ECC_INT_KPF", 0);
     const int cus = device_cu_count();
     const int max_waves = env_int("ECC_INT_WAVES", 16);
     const int tiles_per_cu = env_int("ECC_INT_TILES_PER_CU", 4);
@@ -233,6 +234,92 @@ static bool is_device_ptr(const void *p) {
     return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Float images: records -> sort -> per-key running sums (ecc_float.hip,
+// ecc_sort.hip).  Synchronous: the number of distinct values is only known
+// at the end.
+static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc_curve *curve, hipStream_t s) {
+    if (!curve->keys) {
+        set_error("ECC_F32 needs curve->keys");
+        return ECC_E_ARG;
+    }
+    Workspace *ws = nullptr;
+    int rc = get_workspace(s, &ws);
+    if (rc) return rc;
+    const float *img_dev = (const float *)image;
+    if (!is_device_ptr(image)) {
+        const size_t bytes = (size_t)n * 4;
+        rc = ensure_bytes(&ws->img_tmp, &ws->img_tmp_bytes, bytes);
+        if (rc) return rc;
+        ECC_HIP(hipMemcpyAsync(ws->img_tmp, image, bytes, hipMemcpyHostToDevice, s));
+        img_dev = (const float *)ws->img_tmp;
+    }
+    // carve the float scratch
+    const int64_t segs = radix_segments(n);
+    const int64_t ft = float_tiles(n);
+    size_t off[9], total = 0;
+    const size_t sz[9] = {(size_t)n * 4, (size_t)n * 4, (size_t)n, (size_t)n,
+                          (size_t)(256 * segs) * 4, (size_t)radix_scan_tiles(256 * segs) * 4,
+                          (size_t)ft * 8, (size_t)ft * 8, 8};
+    for (int i = 0; i < 9; ++i) {
+        off[i] = total;
+        total += align256(sz[i]);
+    }
+    // curve staging unless the caller's buffers are device memory that holds
+    // any possible count (n entries)
+    const bool direct = curve->capacity >= n && is_device_ptr(curve->chi) && is_device_ptr(curve->keys);
+    const size_t out_k = total, out_c = out_k + align256((size_t)n * 4);
+    if (!direct) total = out_c + align256((size_t)n * 8);
+    rc = ensure_bytes(&ws->fbuf, &ws->fbuf_bytes, total);
+    if (rc) return rc;
+    uint8_t *b = (uint8_t *)ws->fbuf;
+    uint32_t *k[2] = {(uint32_t *)(b + off[0]), (uint32_t *)(b + off[1])};
+    int8_t *v[2] = {(int8_t *)(b + off[2]), (int8_t *)(b + off[3])};
+    uint32_t *counts = (uint32_t *)(b + off[4]);
+    uint32_t *sums = (uint32_t *)(b + off[5]);
+    int64_t *tile_chg = (int64_t *)(b + off[6]);
+    int64_t *tile_last = (int64_t *)(b + off[7]);
+    int64_t *count_dev = (int64_t *)(b + off[8]);
+    float *out_keys = direct ? curve->keys : (float *)(b + out_k);
+    int64_t *out_chi = direct ? curve->chi : (int64_t *)(b + out_c);
+
+    rc = launch_float_change(img_dev, dims, k[0], v[0], ws->status, s);
+    if (rc) return rc;
+    rc = radix_sort_records(k, v, n, counts, sums, s);
+    if (rc) return rc;
+    rc = launch_float_curve(k[0], v[0], n, tile_chg, tile_last, count_dev, out_keys, out_chi, s);
+    if (rc) return rc;
+    uint32_t st = 0;
+    int64_t kcount = 0;
+    ECC_HIP(hipMemcpyAsync(&st, ws->status, 4, hipMemcpyDeviceToHost, s));
+    ECC_HIP(hipMemcpyAsync(&kcount, count_dev, 8, hipMemcpyDeviceToHost, s));
+    ECC_HIP(hipStreamSynchronize(s));
+    if (st != 0) {
+        rc = launch_zero(ws->status, 4, s);
+        if (rc) return rc;
+        ECC_HIP(hipStreamSynchronize(s));
+        if (st & kStatusNaN) {
+            set_error("a float image holds a NaN");
+            return ECC_E_NAN;
+        }
+        set_error("internal error: device status 0x%08x", st);
+        return ECC_E_HIP;
+    }
+    if (kcount > curve->capacity) {
+        curve->count = kcount;
+        set_error("curve capacity %lld < %lld distinct values", (long long)curve->capacity, (long long)kcount);
+        return ECC_E_BUFFER_TOO_SMALL;
+    }
+    if (!direct) {
+        ECC_HIP(hipMemcpyAsync(curve->keys, out_keys, (size_t)kcount * 4, hipMemcpyDefault, s));
+        ECC_HIP(hipMemcpyAsync(curve->chi, out_chi, (size_t)kcount * 8, hipMemcpyDefault, s));
+        ECC_HIP(hipStreamSynchronize(s));
+    }
+    curve->count = kcount;
+    return ECC_OK;
+}
+
 }  // namespace ecc
 
 using namespace ecc;
@@ -292,7 +379,8 @@ int ecc_compute(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_cu
         set_error("NULL image, curve or curve->chi");
         return ECC_E_ARG;
     }
-    if (dtype == ECC_F32 || dtype == ECC_U16) {
+    if (dtype == ECC_F32) return compute_float(image, dims, total, curve, (hipStream_t)stream);
+    if (dtype == ECC_U16) {
         set_error("ecc_compute: dtype %d not available in this build", (int)dtype);
         return ECC_E_UNSUPPORTED;
     }

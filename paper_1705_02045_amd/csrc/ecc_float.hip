@@ -1,0 +1,379 @@
+// Float32 images (Sec. 3, "Floating Point Values"): the values are not known
+// in advance, so every voxel emits a record (key, change) and the records
+// are sorted by key, summed per distinct key and prefix-summed.
+//
+// The change of a voxel v is the signed count of the cells of the cubical
+// complex that v introduces (Sec. 3, Algorithm 1: a cell enters with the
+// first of its incident voxels in the order "smaller value first, ties broken
+// by position").  A cell of the closed voxel v is named by a direction
+// s in {-1,0,1}^D (s_i = 0: the cell spans v along axis i; s_i = +-1: it is
+// the face on that side); it has dimension #{i : s_i = 0}.  Its other
+// incident voxels are v + delta with delta_i in {0, s_i}, delta != 0, so v
+// introduces it iff none of those precedes v.  With U_s = OR of "precedes"
+// over that box, U_s = prec(s) | OR_{i : s_i != 0} U_{s with s_i = 0}, and
+//     change(v) = sum_s (-1)^dim(s) [U_s = 0] = 1 - sum_{s != 0} (-1)^dim(s) U_s
+// (the first sum over all s is prod_i (2 - 1) = 1).
+//
+// On the GPU a wave holds 64 consecutive voxels of one line of the last axis;
+// "precedes" for each of the 3^D - 1 neighbour directions is one ballot, the
+// recursion for U_s runs on those wave-wide masks in scalar registers, and
+// each U_s is accumulated per lane with one add-with-carry.
+//
+// Keys: the canonical float (-0 folded into +0) mapped to an unsigned integer
+// with the same order (sign bit set: all bits flipped; else the sign bit set).
+
+#include "ecc_internal.h"
+
+namespace ecc {
+
+__device__ __forceinline__ uint32_t f32_key(uint32_t u) {
+    if ((u & 0x7FFFFFFFu) == 0u) u = 0u;  // -0 -> +0
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float key_to_f32(uint32_t k) {
+    const uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+    return __uint_as_float(u);
+}
+
+constexpr int pow3(int d) { return d == 0 ? 1 : 3 * pow3(d - 1); }
+// base-3 digit k of a direction code: 0 -> -1, 1 -> 0, 2 -> +1
+constexpr int digit3(int t, int k) { return (t / pow3(k)) % 3; }
+template <int D>
+constexpr int nonzeros(int t) {
+    int c = 0;
+    for (int k = 0; k < D; ++k) c += digit3(t, k) != 1;
+    return c;
+}
+// delta earlier than v in C order: its first non-zero component (axis 0 is
+// the most significant, digit D-1-k holds axis k) is negative
+template <int D>
+constexpr bool earlier(int t) {
+    for (int a = 0; a < D; ++a) {
+        const int dg = digit3(t, D - 1 - a);
+        if (dg != 1) return dg == 0;
+    }
+    return false;
+}
+
+__device__ __forceinline__ uint64_t ballot64(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+
+// acc += lane bit of m  /  acc -= lane bit of m  (one VALU op each: the mask is
+// the carry-in; the carry-out goes to a scratch scalar pair)
+__device__ __forceinline__ void add_bit(int32_t &acc, uint64_t m) {
+    uint64_t co;
+    asm("v_addc_co_u32_e64 %0, %1, %0, 0, %2" : "+v"(acc), "=&s"(co) : "s"(m));
+}
+__device__ __forceinline__ void sub_bit(int32_t &acc, uint64_t m) {
+    uint64_t co;
+    asm("v_subb_co_u32_e64 %0, %1, %0, 0, %2" : "+v"(acc), "=&s"(co) : "s"(m));
+}
+
+struct FloatView {
+    int32_t n[4];       // extents, axis 0 slowest, padded in front with 1
+    uint32_t stride[4]; // element strides
+    int32_t bpr;        // blocks per line of the last axis
+};
+
+// One thread per voxel.  D = number of axes after dropping axes of extent 1
+// (the complex of the others times unit intervals has the same curve).
+template <int D>
+__global__ void __launch_bounds__(256) float_change_kernel(const float *__restrict__ img, uint32_t img_bytes,
+                                                           FloatView v, uint32_t *__restrict__ keys,
+                                                           int8_t *__restrict__ chg, uint32_t *status) {
+    constexpr int P = pow3(D);
+    constexpr int C = (P - 1) / 2;  // code of the zero direction
+    const int32_t nx = v.n[3];
+    const int64_t line = blockIdx.x / v.bpr;
+    const int32_t x = (int32_t)(blockIdx.x % v.bpr) * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+    // lanes past the end of the line stay in step (no early exit keeps the
+    // ballots and the scalar mask arithmetic in uniform control flow)
+    const bool act = x < nx;
+    // coordinates of the line (uniform): axes 4-D .. 2 of the padded view
+    int32_t c[4];
+    {
+        // (readfirstlane: the compiler must see these as wave-uniform, so that
+        // the per-direction tests below stay scalar branches)
+        int32_t r = __builtin_amdgcn_readfirstlane((int32_t)line);
+#pragma unroll
+        for (int k = 2; k >= 4 - D; --k) {
+            c[k] = __builtin_amdgcn_readfirstlane(r % v.n[k]);
+            r = __builtin_amdgcn_readfirstlane(r / v.n[k]);
+        }
+    }
+    uint32_t base = (uint32_t)x;  // element index of v
+#pragma unroll
+    for (int k = 4 - D; k <= 2; ++k) base += (uint32_t)c[k] * v.stride[k];
+    __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)img, (short)0, (int)img_bytes, 0x00020000);
+    // Every load below is unconditional, at a clamped address when its
+    // result is not used (offsets past the buffer read 0), so that no branch
+    // surrounds the ballots.
+    const uint32_t own_bits = __builtin_amdgcn_raw_buffer_load_b32(rs, base * 4u, 0, 0);
+    const uint32_t k0 = f32_key(own_bits);
+    const float f0 = __uint_as_float(own_bits);
+
+    // prec[t]: the neighbour in direction t exists and precedes v
+    uint64_t prec[P];
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+        prec[t] = 0;
+        if (t == C) continue;  // compile-time
+        // axes other than the last: uniform validity
+        bool ok = true;
+        int32_t off = 0;
+#pragma unroll
+        for (int j = 1; j < D; ++j) {  // digit j <-> padded axis 3 - j
+            const int k = 3 - j;
+            const int dg = digit3(t, j);
+            if (dg == 0) ok = ok && c[k] > 0;
+            if (dg == 2) ok = ok && c[k] < v.n[k] - 1;
+            off += (dg - 1) * (int32_t)v.stride[k];
+        }
+        const int dx = digit3(t, 0) - 1;
+        const bool lane_ok = ok && act && ((dx == 0) || (dx < 0 ? x > 0 : x < nx - 1));
+        const uint32_t idx = lane_ok ? base + (uint32_t)(off + dx) : base;
+        // IEEE comparisons: -0 == +0, infinities are ordinary values (a NaN
+        // anywhere fails the whole call)
+        const float fn = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, idx * 4u, 0, 0));
+        const bool p = earlier<D>(t) ? (fn <= f0) : (fn < f0);
+        prec[t] = ballot64(lane_ok && p);
+    }
+    // U_s over increasing numbers of non-zero components, then the signed sum
+    uint64_t U[P];
+    U[C] = 0;  // the zero direction: empty box
+    int32_t acc = 0;
+#pragma unroll
+    for (int lvl = 1; lvl <= D; ++lvl) {
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+            if (nonzeros<D>(t) != lvl) continue;
+            uint64_t u = prec[t];
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+                if (digit3(t, j) != 1) u |= U[t + (1 - digit3(t, j)) * pow3(j)];
+            U[t] = u;
+            // (-1)^dim, dim = D - lvl: subtract for even dim, add for odd
+            if (((D - lvl) & 1) == 0) add_bit(acc, u);
+            else sub_bit(acc, u);
+        }
+    }
+    if (ballot64(act && (own_bits & 0x7FFFFFFFu) > 0x7F800000u) != 0 && (threadIdx.x & (kWave - 1)) == 0)
+        atomicOr(status, kStatusNaN);
+    if (act) {
+        keys[base] = k0;
+        chg[base] = (int8_t)(1 - acc);
+    }
+}
+
+int launch_float_change(const float *img_dev, const ecc_dims *dims, uint32_t *keys, int8_t *chg, uint32_t *status,
+                        hipStream_t stream) {
+    // drop axes of extent 1, pad in front to four axes
+    int32_t ext[4];
+    int d = 0;
+    int64_t total = 1;
+    for (int i = 0; i < dims->ndim; ++i) {
+        total *= dims->n[i];
+        if (dims->n[i] > 1) ext[d++] = (int32_t)dims->n[i];
+    }
+    if (total * 4 > (int64_t)UINT32_MAX) {
+        set_error("float images are limited to 2^30 elements in this build");
+        return ECC_E_UNSUPPORTED;
+    }
+    FloatView v{};
+    const int D = d == 0 ? 1 : d;
+    if (d == 0) ext[d++] = 1;
+    for (int k = 0; k < 4; ++k) v.n[k] = 1;
+    for (int i = 0; i < D; ++i) v.n[4 - D + i] = ext[i];
+    uint32_t s = 1;
+    for (int k = 3; k >= 0; --k) {
+        v.stride[k] = s;
+        s *= (uint32_t)v.n[k];
+    }
+    const int nx = v.n[3];
+    const int threads = nx >= 256 ? 256 : ((nx + 63) / 64) * 64;
+    v.bpr = (nx + threads - 1) / threads;
+    const int64_t lines = total / nx;
+    const int64_t grid = lines * v.bpr;
+    if (grid > INT32_MAX) {
+        set_error("float image: too many lines");
+        return ECC_E_UNSUPPORTED;
+    }
+    const uint32_t bytes = (uint32_t)(total * 4);
+    switch (D) {
+    case 1: hipLaunchKernelGGL(float_change_kernel<1>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, keys, chg, status); break;
+    case 2: hipLaunchKernelGGL(float_change_kernel<2>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, keys, chg, status); break;
+    case 3: hipLaunchKernelGGL(float_change_kernel<3>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, keys, chg, status); break;
+    default: hipLaunchKernelGGL(float_change_kernel<4>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, keys, chg, status); break;
+    }
+    ECC_HIP(hipGetLastError());
+    return ECC_OK;
+}
+
+// ----------------------------------------------------------------------------
+// After sorting: chi after each distinct key = running sum of the changes up
+// to and including the last record with that key.  Records are taken in tiles
+// of kFTile; pass 1 sums each tile (changes, and the number of last-of-key
+// positions), pass 2 scans the tile sums in one workgroup, pass 3 writes
+// (key, chi) at the rank of each last-of-key position.
+
+constexpr int kFThreads = 256;
+constexpr int kFItems = 16;
+constexpr int kFTile = kFThreads * kFItems;
+
+__device__ __forceinline__ bool last_of_key(const uint32_t *keys, int64_t i, int64_t n) {
+    return i == n - 1 || keys[i] != keys[i + 1];
+}
+
+template <typename T>
+__device__ T block_sum(T v, T *sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    T t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+    __syncthreads();
+    return t;
+}
+
+__global__ void __launch_bounds__(kFThreads) fsum_tiles_kernel(const uint32_t *__restrict__ keys,
+                                                              const int8_t *__restrict__ chg, int64_t n,
+                                                              int64_t *__restrict__ tile_chg,
+                                                              int64_t *__restrict__ tile_last) {
+    __shared__ int64_t sh[4];
+    const int64_t t0 = (int64_t)blockIdx.x * kFTile;
+    int64_t s = 0, l = 0;
+#pragma unroll
+    for (int j = 0; j < kFItems; ++j) {
+        const int64_t i = t0 + (int64_t)j * kFThreads + threadIdx.x;
+        if (i < n) {
+            s += chg[i];
+            l += last_of_key(keys, i, n);
+        }
+    }
+    s = block_sum(s, sh);
+    l = block_sum(l, sh);
+    if (threadIdx.x == 0) {
+        tile_chg[blockIdx.x] = s;
+        tile_last[blockIdx.x] = l;
+    }
+}
+
+// Exclusive scan in place of two int64 arrays of length nt by one workgroup;
+// total_last receives the sum of the second (the number of distinct keys).
+__global__ void __launch_bounds__(1024) fscan_tiles_kernel(int64_t *a, int64_t *b, int64_t nt, int64_t *total_last) {
+    __shared__ int64_t wa[16], wb[16];
+    __shared__ int64_t carry_a, carry_b;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) carry_a = carry_b = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nt; c0 += 1024) {
+        const int64_t i = c0 + tid;
+        const int64_t va = i < nt ? a[i] : 0, vb = i < nt ? b[i] : 0;
+        int64_t xa = va, xb = vb;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t ua = __shfl_up(xa, off, 64), ub = __shfl_up(xb, off, 64);
+            if (lane >= off) {
+                xa += ua;
+                xb += ub;
+            }
+        }
+        if (lane == 63) {
+            wa[wave] = xa;
+            wb[wave] = xb;
+        }
+        __syncthreads();
+        int64_t pa = carry_a, pb = carry_b;
+        for (int w = 0; w < wave; ++w) {
+            pa += wa[w];
+            pb += wb[w];
+        }
+        if (i < nt) {
+            a[i] = pa + xa - va;
+            b[i] = pb + xb - vb;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int w = 0; w < 16; ++w) {
+                carry_a += wa[w];
+                carry_b += wb[w];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *total_last = carry_b;
+}
+
+__global__ void __launch_bounds__(kFThreads) fwrite_kernel(const uint32_t *__restrict__ keys,
+                                                          const int8_t *__restrict__ chg, int64_t n,
+                                                          const int64_t *__restrict__ tile_chg,
+                                                          const int64_t *__restrict__ tile_last,
+                                                          float *__restrict__ out_keys, int64_t *__restrict__ out_chi) {
+    __shared__ int64_t wc[4], wl[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // each thread takes kFItems consecutive records of the tile
+    const int64_t i0 = (int64_t)blockIdx.x * kFTile + (int64_t)tid * kFItems;
+    int64_t c[kFItems];
+    bool last[kFItems];
+    int64_t sc = 0, sl = 0;
+#pragma unroll
+    for (int j = 0; j < kFItems; ++j) {
+        const int64_t i = i0 + j;
+        const bool in = i < n;
+        sc += in ? chg[i] : 0;
+        c[j] = sc;
+        last[j] = in && last_of_key(keys, i, n);
+        sl += last[j];
+    }
+    int64_t xc = sc, xl = sl;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t uc = __shfl_up(xc, off, 64), ul = __shfl_up(xl, off, 64);
+        if (lane >= off) {
+            xc += uc;
+            xl += ul;
+        }
+    }
+    if (lane == 63) {
+        wc[wave] = xc;
+        wl[wave] = xl;
+    }
+    __syncthreads();
+    int64_t bc = tile_chg[blockIdx.x] + xc - sc, bl = tile_last[blockIdx.x] + xl - sl;
+    for (int w = 0; w < wave; ++w) {
+        bc += wc[w];
+        bl += wl[w];
+    }
+#pragma unroll
+    for (int j = 0; j < kFItems; ++j) {
+        if (last[j]) {
+            out_keys[bl] = key_to_f32(keys[i0 + j]);
+            out_chi[bl] = bc + c[j];
+            ++bl;
+        }
+    }
+}
+
+int launch_float_curve(const uint32_t *keys, const int8_t *chg, int64_t n, int64_t *tile_chg, int64_t *tile_last,
+                       int64_t *total_last, float *out_keys, int64_t *out_chi, hipStream_t stream) {
+    const int64_t nt = (n + kFTile - 1) / kFTile;
+    if (nt > INT32_MAX) {
+        set_error("float curve: too many records");
+        return ECC_E_UNSUPPORTED;
+    }
+    hipLaunchKernelGGL(fsum_tiles_kernel, dim3((unsigned)nt), dim3(kFThreads), 0, stream, keys, chg, n, tile_chg,
+                       tile_last);
+    ECC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(fscan_tiles_kernel, dim3(1), dim3(1024), 0, stream, tile_chg, tile_last, nt, total_last);
+    ECC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(fwrite_kernel, dim3((unsigned)nt), dim3(kFThreads), 0, stream, keys, chg, n, tile_chg,
+                       tile_last, out_keys, out_chi);
+    ECC_HIP(hipGetLastError());
+    return ECC_OK;
+}
+
+int64_t float_tiles(int64_t n) { return (n + kFTile - 1) / kFTile; }
+
+}  // namespace ecc

@@ -13,6 +13,12 @@ namespace ecc {
 
 constexpr int kWave = 64;
 constexpr uint32_t kStatusRange = ECC_STATUS_RANGE_BIT;
+constexpr uint32_t kStatusNaN = 2u;  // a float image holds a NaN
+// Device status block (1024 bytes per workspace or stream): word 0 status,
+// word 1 its copy taken by the scan, word 2 the copy handed to the host,
+// bytes [kStatusTotalsOffset, +512) the scan's group totals.
+constexpr size_t kStatusBytes = 1024;
+constexpr size_t kStatusTotalsOffset = 128;
 
 void set_error(const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
@@ -54,6 +60,7 @@ struct IntTiling {
     int rows;      // rows (nin == 2) or 64-wide x segments (nin == 1) per wave
     int mode;      // update form of the four-item groups (0..3, see ecc_int.hip)
     int pd;        // planes of raw loads in flight ahead of the compared plane
+    int kpf;       // distance in planes of the L2 prefetch (0: none)
     int wx, wy;    // waves per workgroup along x and along y
     int zc;        // planes per tile
     int grid;      // workgroups = tiles (one tile per workgroup)
@@ -67,13 +74,15 @@ struct Workspace {
     size_t partial_bytes = 0;
     int64_t *vcec = nullptr;     // [m] changes vector
     size_t vcec_bytes = 0;
-    uint32_t *status = nullptr;  // device words: [0] status, [2] status copy
+    uint32_t *status = nullptr;  // device status block (kStatusBytes)
     int64_t *stage = nullptr;    // merge stage rows
     size_t stage_bytes = 0;
     int64_t *chi_tmp = nullptr;  // [m] curve staging for host outputs
     size_t chi_tmp_bytes = 0;
     void *img_tmp = nullptr;     // device copy of a host image
     size_t img_tmp_bytes = 0;
+    void *fbuf = nullptr;        // float path: records, sort scratch, curve staging
+    size_t fbuf_bytes = 0;
 };
 
 int get_workspace(void *stream, Workspace **out);
@@ -98,6 +107,17 @@ int launch_merge(const int32_t *partial, int rows, int m, int64_t *stage, int64_
                  bool do_scan, int64_t *chi, uint32_t *status, uint32_t *status_out, hipStream_t stream);
 
 bool normalize_int_view(const ecc_dims *dims, IntView *v, int *err_ndim_dropped);
+
+// Float path (ecc_float.hip, ecc_sort.hip).
+int launch_float_change(const float *img_dev, const ecc_dims *dims, uint32_t *keys, int8_t *chg, uint32_t *status,
+                        hipStream_t stream);
+int64_t radix_segments(int64_t n);
+int64_t radix_scan_tiles(int64_t entries);
+int radix_sort_records(uint32_t *k[2], int8_t *v[2], int64_t n, uint32_t *counts, uint32_t *sums,
+                       hipStream_t stream);
+int64_t float_tiles(int64_t n);
+int launch_float_curve(const uint32_t *keys, const int8_t *chg, int64_t n, int64_t *tile_chg, int64_t *tile_last,
+                       int64_t *total_last, float *out_keys, int64_t *out_chi, hipStream_t stream);
 
 // Optional event timing of the per-voxel kernels (ecc_profile.cpp).
 int profile_begin(hipStream_t s, void **token);

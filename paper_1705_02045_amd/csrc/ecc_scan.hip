@@ -25,62 +25,17 @@ int launch_zero(void *p, size_t bytes, hipStream_t stream) {
     return ECC_OK;
 }
 
-// Inclusive prefix sum of m int64 values by one workgroup: chunks of
-// blockDim*16 values, each thread scanning 16 consecutive values of a chunk,
-// the thread totals scanned across the block, a running carry between chunks.
-__device__ void block_scan_write(const int64_t *__restrict__ in, int m, int64_t *out) {
-    __shared__ int64_t wsum[16];
-    __shared__ int64_t carry_s;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nwaves = blockDim.x >> 6;
-    if (tid == 0) carry_s = 0;
-    __syncthreads();
-    for (int c0 = 0; c0 < m; c0 += (int)blockDim.x * 16) {
-        const int base = c0 + tid * 16;
-        int64_t loc[16];
-        int64_t run = 0;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            run += (base + j < m) ? in[base + j] : 0;
-            loc[j] = run;
-        }
-        int64_t v = run;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int64_t u = __shfl_up(v, off, 64);
-            if (lane >= off) v += u;
-        }
-        if (lane == 63) wsum[wave] = v;
-        __syncthreads();
-        if (wave == 0) {
-            int64_t w = lane < nwaves ? wsum[lane] : 0;
-#pragma unroll
-            for (int off = 1; off < 16; off <<= 1) {
-                const int64_t u = __shfl_up(w, off, 64);
-                if (lane >= off) w += u;
-            }
-            if (lane < nwaves) wsum[lane] = w;
-        }
-        __syncthreads();
-        const int64_t offset = carry_s + (v - run) + (wave > 0 ? wsum[wave - 1] : 0);
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-            if (base + j < m) out[base + j] = offset + loc[j];
-        __syncthreads();
-        if (tid == 0) carry_s += wsum[nwaves - 1];
-        __syncthreads();
-    }
-}
-
 // Merge of the per-workgroup rows [rows][m] (int32) into the int64 change
 // vector, in kernels that follow each other on the stream (the kernel
 // boundary orders their memory; no fences or counters):
 //  1. colsum_kernel, block (bx, by): rows by, by+BY, ... of columns
 //     bx*1024 .. +1023 (256 threads x 4 columns, 16-byte loads), written to
 //     stage[by][column], or, with BY == 1, straight into vcec;
-//  2. fold_kernel (BY > 1): the BY stage rows of each column into vcec;
-//  3. scan_kernel (one block): the curve is the prefix sum of vcec, written
-//     if the status word is clear; the status is copied and cleared.
+//  2. fold_scan_kernel: the BY stage rows of each column into vcec (BY > 1)
+//     and, with do_scan, the prefix sums of column groups of 1024;
+//  3. scan_offsets_kernel (do_scan): adds the totals of the preceding groups;
+//     the curve is written only if the status word is clear, and the status
+//     is copied out and cleared.
 // vcec is overwritten, or added to with `accumulate`.
 __global__ void __launch_bounds__(256) colsum_kernel(const int32_t *__restrict__ partial, int rows, int m,
                                                      int64_t *__restrict__ dst, int accumulate) {
@@ -123,22 +78,74 @@ __global__ void __launch_bounds__(256) colsum_kernel(const int32_t *__restrict__
     d[3] = s3;
 }
 
-__global__ void __launch_bounds__(256) fold_kernel(const int64_t *__restrict__ stage, int by, int m,
-                                                   int64_t *__restrict__ vcec, int accumulate) {
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= m) return;
-    int64_t t = accumulate ? vcec[c] : 0;
-    for (int y = 0; y < by; ++y) t += stage[(size_t)y * m + c];
-    vcec[c] = t;
+// Column group bx (1024 columns, 4 per thread): the BY stage rows are folded
+// into vcec (when stage is not null) and, with do_scan and a clear status
+// word, the group's inclusive prefix sum is written to chi and its total to
+// totals[bx].  Block 0 copies the status word to status[1] for the offsets
+// kernel.
+__global__ void __launch_bounds__(256) fold_scan_kernel(const int64_t *__restrict__ stage, int by, int m,
+                                                        int64_t *__restrict__ vcec, int accumulate, int do_scan,
+                                                        int64_t *__restrict__ chi, uint32_t *status,
+                                                        int64_t *__restrict__ totals) {
+    __shared__ int64_t wsum[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c0 = blockIdx.x * 1024 + tid * 4;
+    int64_t v[4] = {0, 0, 0, 0};
+    if (c0 < m) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = (stage == nullptr || accumulate) ? vcec[c0 + j] : 0;
+        if (stage != nullptr) {
+            for (int y = 0; y < by; ++y) {
+                const int64_t *st = stage + (size_t)y * m + c0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j] += st[j];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) vcec[c0 + j] = v[j];
+        }
+    }
+    if (!do_scan) return;
+    const uint32_t stv = *status;
+    if (blockIdx.x == 0 && tid == 0) status[1] = stv;
+    if (stv != 0) return;
+    // inclusive scan: within the thread, across the wave, across the 4 waves
+    v[1] += v[0];
+    v[2] += v[1];
+    v[3] += v[2];
+    int64_t x = v[3];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t u = __shfl_up(x, off, 64);
+        if (lane >= off) x += u;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    int64_t base = x - v[3];
+    for (int w = 0; w < wave; ++w) base += wsum[w];
+    if (c0 < m) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) chi[c0 + j] = base + v[j];
+    }
+    if (tid == 0) totals[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
-__global__ void __launch_bounds__(1024) scan_kernel(const int64_t *__restrict__ vcec, int m, int64_t *chi,
-                                                    uint32_t *status, uint32_t *status_out) {
-    const uint32_t stv = *status;
-    if (stv == 0) block_scan_write(vcec, m, chi);
-    if (threadIdx.x == 0) {
+// Adds the totals of the preceding column groups to chi (when the status
+// copied by fold_scan_kernel is clear); block 0 copies the status out and
+// clears the status word.
+__global__ void __launch_bounds__(256) scan_offsets_kernel(int m, int64_t *__restrict__ chi, uint32_t *status,
+                                                           uint32_t *status_out, const int64_t *__restrict__ totals) {
+    const uint32_t stv = status[1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (status_out) *status_out = stv;
-        *status = 0u;
+        status[0] = 0u;
+    }
+    if (stv != 0 || blockIdx.x == 0) return;
+    int64_t off = 0;
+    for (int j = 0; j < (int)blockIdx.x; ++j) off += totals[j];
+    const int c0 = blockIdx.x * 1024 + threadIdx.x * 4;
+    if (c0 < m) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) chi[c0 + j] += off;
     }
 }
 
@@ -154,22 +161,24 @@ int launch_merge(const int32_t *partial, int rows, int m, int64_t *stage, int64_
         set_error("launch_merge: m = %d not supported", m);
         return ECC_E_ARG;
     }
+    const int groups = (m + 1023) / 1024;
+    int by = 0;
     if (rows > 0) {
-        const int bx = (m + 1023) / 1024;
-        const int by = merge_stage_rows(rows);
-        hipLaunchKernelGGL(colsum_kernel, dim3(bx, by), dim3(256), 0, stream, partial, rows, m,
+        by = merge_stage_rows(rows);
+        hipLaunchKernelGGL(colsum_kernel, dim3(groups, by), dim3(256), 0, stream, partial, rows, m,
                            by == 1 ? vcec : stage, (by == 1 && accumulate) ? 1 : 0);
         ECC_HIP(hipGetLastError());
-        if (by > 1) {
-            hipLaunchKernelGGL(fold_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, (const int64_t *)stage, by,
-                               m, vcec, accumulate ? 1 : 0);
+    }
+    if (by > 1 || do_scan) {
+        int64_t *totals = reinterpret_cast<int64_t *>(status) + kStatusTotalsOffset / 8;
+        hipLaunchKernelGGL(fold_scan_kernel, dim3(groups), dim3(256), 0, stream, by > 1 ? (const int64_t *)stage : nullptr,
+                           by, m, vcec, accumulate ? 1 : 0, do_scan ? 1 : 0, chi, status, totals);
+        ECC_HIP(hipGetLastError());
+        if (do_scan) {
+            hipLaunchKernelGGL(scan_offsets_kernel, dim3(groups), dim3(256), 0, stream, m, chi, status, status_out,
+                               (const int64_t *)totals);
             ECC_HIP(hipGetLastError());
         }
-    }
-    if (do_scan) {
-        hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, (const int64_t *)vcec, m, chi, status,
-                           status_out);
-        ECC_HIP(hipGetLastError());
     }
     return ECC_OK;
 }

@@ -231,9 +231,9 @@ int ecc_stream_begin(const ecc_dims *full_dims, ecc_dtype dtype, void *stream, e
     }
     if ((e = hipMalloc(&st->vcec, (size_t)st->m * sizeof(int64_t))) != hipSuccess)
         return fail(hip_fail(e, "hipMalloc(vcec)"));
-    if ((e = hipMalloc(&st->status, 1024)) != hipSuccess) return fail(hip_fail(e, "hipMalloc(status)"));
+    if ((e = hipMalloc(&st->status, kStatusBytes)) != hipSuccess) return fail(hip_fail(e, "hipMalloc(status)"));
     if ((rc = launch_zero(st->vcec, (size_t)st->m * sizeof(int64_t), st->compute))) return fail(rc);
-    if ((rc = launch_zero(st->status, 1024, st->compute))) return fail(rc);
+    if ((rc = launch_zero(st->status, kStatusBytes, st->compute))) return fail(rc);
     *out = st;
     return ECC_OK;
 }
