@@ -192,3 +192,33 @@ def cfg_u8_value_noise(shape, seed: int) -> np.ndarray:
 def cfg_f32_value_noise(shape=(128, 128, 128, 128), seed: int = 3, sigma: float = 0.01, **kw) -> np.ndarray:
     """float32 value noise: lattice 8, values in [0,1), Gaussian jitter of standard deviation sigma."""
     return value_noise_f32(shape, sigma, seed, lshift=3, **kw)
+
+
+def serving_requests(count: int, seed: int = 4, side_scale: float = 1.0):
+    """Mixed request stream: request i draws h = hash(seed, 3, i); the low bit
+    picks 2-D uint8 value noise (sides uniform in 32..2048) or 3-D 14-bit value
+    noise (sides uniform in 16..256); further 16-bit fields of h pick the
+    sides, and the request's image seed is h >> 32.  side_scale < 1 shrinks the
+    side ranges proportionally (small test streams).  Returns a list of
+    (dtype, shape, image_seed)."""
+    h = hash_np(seed, 3, np.arange(count, dtype=np.uint64))
+    out = []
+    for i in range(count):
+        v = int(h[i])
+        f = [(v >> (8 + 16 * k)) & 0xFFFF for k in range(3)]
+        if v & 1:
+            lo, hi = 16, max(16, int(256 * side_scale))
+            shape = tuple(lo + (x * (hi - lo + 1) >> 16) for x in f)
+            out.append(("u14", shape, v >> 32))
+        else:
+            lo, hi = 32, max(32, int(2048 * side_scale))
+            shape = tuple(lo + (x * (hi - lo + 1) >> 16) for x in f[:2])
+            out.append(("u8", shape, v >> 32))
+    return out
+
+
+def serving_image(dtype: str, shape, image_seed: int) -> np.ndarray:
+    """The image of one serving request (see serving_requests)."""
+    if dtype == "u14":
+        return cfg_u14_value_noise(shape, seed=image_seed)
+    return cfg_u8_value_noise(shape, seed=image_seed)

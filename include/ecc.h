@@ -136,6 +136,51 @@ int ecc_stream_finish(ecc_stream *st, ecc_curve *curve);
 /* Frees the handle without producing a curve.  NULL is ignored. */
 void ecc_stream_abort(ecc_stream *st);
 
+/* ---------------------------------------------------------------------------
+ * Batches of independent images (integer dtypes).  Curves of unrelated images
+ * never merge, so one launch can carry the tiles of many images (Sec. 3,
+ * "Parallel Computations": the work splits into parts whose changes vectors
+ * are summed; here each image sums only its own parts). */
+typedef struct {
+    const void *image; /* device pointer, prod(dims.n) elements of dtype */
+    ecc_dims dims;     /* as for ecc_compute */
+    int32_t dtype;     /* ECC_U8 or ECC_U14 */
+    int64_t *chi;      /* device pointer, m int64 entries (written only if the image is valid) */
+} ecc_job;
+
+typedef struct ecc_batch ecc_batch;
+
+/* A batch context bound to the current device and `stream` (void*, may be
+ * NULL).  It owns device scratch and pinned descriptor tables, reused by
+ * later runs.  Errors: ECC_E_ARG, ECC_E_HIP. */
+int ecc_batch_create(void *stream, ecc_batch **out);
+
+/* Enqueues the curves of n_jobs images on the context's stream and returns
+ * without waiting for them.  status_dev: optional device array of n_jobs
+ * uint32; entry j receives 0 or ECC_STATUS_RANGE_BIT for image j.  Runs on
+ * one context are ordered by its stream; a context is not for concurrent use
+ * from several host threads.  The images and chi buffers must stay valid
+ * until the work is done.  Errors: ECC_E_ARG (bad job), ECC_E_UNSUPPORTED
+ * (shape or dtype the integer path does not take), ECC_E_NOMEM, ECC_E_HIP. */
+int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *status_dev);
+
+/* Waits for the context's work and frees it.  NULL is ignored. */
+void ecc_batch_destroy(ecc_batch *b);
+
+/* Serving replay for measurement: request i (jobs[i], device-resident image;
+ * its chi field is ignored) becomes available at arrival_s[i] seconds after
+ * the call starts (ascending).  Continuous batching (one_launch_per_image =
+ * 0): whenever fewer than two batches are in flight, everything that has
+ * arrived (at most max_batch requests) goes into the next ecc_batch_run.
+ * Otherwise every request is one ecc_compute_async launch as soon as it
+ * arrives.  Each request's curve is copied to host memory at chi_host +
+ * (sum of the m of the requests before it); latency_s[i] receives the time
+ * from its arrival until that copy was seen complete.  Blocks until all
+ * requests are done.  Errors: ECC_E_ARG, ECC_E_UNSUPPORTED, ECC_E_NOMEM,
+ * ECC_E_HIP. */
+int ecc_serve_simulate(ecc_batch *b, int32_t n, const ecc_job *jobs, const double *arrival_s, int32_t max_batch,
+                       int32_t one_launch_per_image, int64_t *chi_host, double *latency_s);
+
 /* Kernel timing (measurement support, not needed for results).  While
  * enabled, every launch of the per-voxel kernels (the integer change-vector
  * kernel and the float record kernel) is bracketed by two HIP events recorded

@@ -36,6 +36,11 @@ class Dims(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int64 * 4)]
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("image", ctypes.c_void_p), ("dims", Dims), ("dtype", ctypes.c_int32),
+                ("chi", ctypes.c_void_p)]
+
+
 class Curve(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int64), ("count", ctypes.c_int64),
                 ("chi", ctypes.c_void_p), ("keys", ctypes.c_void_p)]
@@ -59,6 +64,14 @@ _lib.ecc_stream_abort.argtypes = [_vp]
 _lib.ecc_profile_enable.restype = ctypes.c_int
 _lib.ecc_profile_enable.argtypes = [ctypes.c_int]
 _lib.ecc_profile_reset.restype = ctypes.c_int
+_lib.ecc_batch_create.restype = ctypes.c_int
+_lib.ecc_batch_create.argtypes = [_vp, ctypes.POINTER(_vp)]
+_lib.ecc_batch_run.restype = ctypes.c_int
+_lib.ecc_batch_run.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
+_lib.ecc_batch_destroy.restype = None
+_lib.ecc_batch_destroy.argtypes = [_vp]
+_lib.ecc_serve_simulate.restype = ctypes.c_int
+_lib.ecc_serve_simulate.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
 _lib.ecc_profile_read.restype = ctypes.c_int
 _lib.ecc_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
 _lib.ecc_last_error.restype = ctypes.c_char_p
@@ -215,3 +228,54 @@ class Stream:
     def abort(self):
         h, self._h = self._h, ctypes.c_void_p()
         _lib.ecc_stream_abort(h)
+
+
+def _jobs_array(images, dtypes, chis=None):
+    n = len(images)
+    arr = (Job * n)()
+    for i, img in enumerate(images):
+        arr[i].image = img.data_ptr()
+        arr[i].dims = make_dims(img.shape)
+        arr[i].dtype = DTYPES[dtypes[i]]
+        arr[i].chi = chis[i].data_ptr() if chis is not None else None
+    return arr
+
+
+class Batch:
+    """ecc_batch_create / run / destroy: curves of many device images per launch."""
+
+    def __init__(self, stream=None):
+        import torch
+        s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream_handle(torch.cuda.current_device())
+        self._h = ctypes.c_void_p()
+        _check(_lib.ecc_batch_create(s, ctypes.byref(self._h)), "ecc_batch_create")
+
+    def run(self, images, dtypes, chis, status=None):
+        """Enqueue; images and chis are device tensors (chis int64 of m entries each)."""
+        arr = _jobs_array(images, dtypes, chis)
+        _check(_lib.ecc_batch_run(self._h, len(images), ctypes.cast(arr, _vp),
+                                  status.data_ptr() if status is not None else None), "ecc_batch_run")
+
+    def serve(self, images, dtypes, arrival_s, max_batch: int, one_launch_per_image: bool = False):
+        """ecc_serve_simulate: returns (latency seconds per request, host curves concatenated)."""
+        import numpy as np
+        arr = _jobs_array(images, dtypes)
+        arrival = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        total = sum(THRESHOLDS[d] for d in dtypes)
+        chi = np.empty(total, dtype=np.int64)
+        lat = np.empty(len(images), dtype=np.float64)
+        _check(_lib.ecc_serve_simulate(self._h, len(images), ctypes.cast(arr, _vp), arrival.ctypes.data,
+                                       int(max_batch), int(bool(one_launch_per_image)), chi.ctypes.data,
+                                       lat.ctypes.data), "ecc_serve_simulate")
+        return lat, chi
+
+    def close(self):
+        h, self._h = self._h, ctypes.c_void_p()
+        if h:
+            _lib.ecc_batch_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -20,6 +20,8 @@ void set_error(const char *fmt, ...) {
     va_end(ap);
 }
 
+void g_err_clear() { g_err[0] = 0; }
+
 int hip_fail(hipError_t e, const char *what) {
     set_error("%s failed: %s", what, hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? ECC_E_NOMEM : ECC_E_HIP;
@@ -34,7 +36,7 @@ int64_t threshold_count(int dtype) {
     }
 }
 
-static size_t elem_bytes(int dtype) {
+size_t elem_bytes(int dtype) {
     switch (dtype) {
     case ECC_U8: return 1;
     case ECC_U14:
@@ -97,7 +99,7 @@ int get_workspace(void *stream, Workspace **out) {
     return ECC_OK;
 }
 
-static int check_dims(const ecc_dims *dims, int64_t *total) {
+int check_dims(const ecc_dims *dims, int64_t *total) {
     if (!dims) {
         set_error("dims is NULL");
         return ECC_E_ARG;

@@ -199,6 +199,9 @@ int launch_float_change(const float *img_dev, const ecc_dims *dims, uint32_t *ke
         return ECC_E_UNSUPPORTED;
     }
     const uint32_t bytes = (uint32_t)(total * 4);
+    void *tok = nullptr;
+    int rc = profile_begin(stream, &tok);
+    if (rc) return rc;
     switch (D) {
     case 1: hipLaunchKernelGGL(float_change_kernel<1>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, keys, chg, status); break;
     case 2: hipLaunchKernelGGL(float_change_kernel<2>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, keys, chg, status); break;
@@ -206,7 +209,7 @@ int launch_float_change(const float *img_dev, const ecc_dims *dims, uint32_t *ke
     default: hipLaunchKernelGGL(float_change_kernel<4>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, keys, chg, status); break;
     }
     ECC_HIP(hipGetLastError());
-    return ECC_OK;
+    return profile_end(stream, tok);
 }
 
 // ----------------------------------------------------------------------------

@@ -29,6 +29,8 @@
 // R x-segments (nin == 1) and walks the planes of its tile.  Field values are
 // kept pre-multiplied by 4 so they are LDS byte offsets of their bins.
 
+#include <cstring>
+
 #include "ecc_internal.h"
 
 namespace ecc {
@@ -392,13 +394,13 @@ constexpr int kWavesPerEU() {
     return (R <= 2) ? 8 : 4;
 }
 
+// One tile of one image: b = the workgroup's index among the image's G
+// tiles.  Writes the tile's counts to row b of P.partial.
 template <typename T, int M, int NIN, int R, int MODE, int PD, int KPF>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<NIN, R, PD>())))
-int_vcec_kernel(KParams P) {
+__device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const int b, const int G) {
     using W = Walker<NIN, R>;
     constexpr int NR = W::NR;
     constexpr int ESZ = sizeof(T);
-    __shared__ int32_t hist[M];
 
     const int tid = threadIdx.x;
     // The update blocks address bins by their LDS byte offset: the histogram
@@ -411,7 +413,7 @@ int_vcec_kernel(KParams P) {
     // compiler treat later lane masks as divergent)
     for (int i0 = 0; i0 < M; i0 += (int)blockDim.x)
         if (i0 + tid < M) hist[i0 + tid] = 0;
-    if (P.zero_vcec && blockIdx.x == 0)
+    if (P.zero_vcec && b == 0)
         for (int i0 = 0; i0 < M; i0 += (int)blockDim.x)
             if (i0 + tid < M) P.zero_vcec[i0 + tid] = 0;
     __syncthreads();
@@ -420,10 +422,10 @@ int_vcec_kernel(KParams P) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wxi = wave % P.wx;
     const int wyi = wave / P.wx;
+    // (batched launches use a fixed workgroup size: waves past wx * wy idle)
+    const bool wave_in = wave < P.wx * P.wy;
     const int32_t n1 = P.n1, n2 = P.n2;
 
-    const int G = gridDim.x;
-    const int b = blockIdx.x;
     const int t = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
     const int tx = t % P.tiles_x;
     const int ty = (t / P.tiles_x) % P.tiles_y;
@@ -440,7 +442,7 @@ int_vcec_kernel(KParams P) {
     bool full = false, any = false;
     if constexpr (NIN == 1) {
         const int32_t seg0 = (tx * P.wx + wxi) * R;
-        any = seg0 * kWave < n2;
+        any = wave_in && seg0 * kWave < n2;
         full = (seg0 + R) * kWave - 1 <= n2 - 2;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -452,7 +454,7 @@ int_vcec_kernel(KParams P) {
         const int32_t x0 = (tx * P.wx + wxi) * kWave;
         const int32_t x = x0 + lane;
         const int32_t y0 = (ty * P.wy + wyi) * R;
-        any = x0 < n2 && y0 < n1;
+        any = wave_in && x0 < n2 && y0 < n1;
         full = (x0 + kWave - 1 <= n2 - 2) && (y0 + R - 1 <= n1 - 2);
         const int32_t xcl = min(x, n2 - 1);
         const uint32_t ox = (uint32_t)xcl * ESZ, oxl = (uint32_t)(xcl > 0 ? xcl - 1 : 0) * ESZ;
@@ -528,6 +530,32 @@ int_vcec_kernel(KParams P) {
 }
 
 template <typename T, int M, int NIN, int R, int MODE, int PD, int KPF>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<NIN, R, PD>())))
+int_vcec_kernel(KParams P) {
+    __shared__ int32_t hist[M];
+    tile_body<T, M, NIN, R, MODE, PD, KPF>(P, hist, blockIdx.x, gridDim.x);
+}
+
+// Batched form: the tiles of many images in one launch.  Image j owns
+// workgroups [tile_begin[j], tile_begin[j+1]); its parameters are jobs[j].
+template <typename T, int M, int NIN>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<NIN, 2, 1>())))
+int_vcec_batch_kernel(const KParams *__restrict__ jobs, const int32_t *__restrict__ tile_begin, int njobs) {
+    __shared__ int32_t hist[M];
+    const int b = blockIdx.x;
+    int lo = 0, hi = njobs - 1;  // last j with tile_begin[j] <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile_begin[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const KParams P = jobs[lo];
+    const int b0 = tile_begin[lo];
+    tile_body<T, M, NIN, 2, 0, 1, 0>(P, hist, b - b0, tile_begin[lo + 1] - b0);
+}
+
+template <typename T, int M, int NIN, int R, int MODE, int PD, int KPF>
 static int launch_one(const KParams &p, const IntTiling &tl, hipStream_t stream) {
     const int threads = kWave * tl.wx * tl.wy;
     void *tok = nullptr;
@@ -572,8 +600,8 @@ static int launch_rows(const KParams &p, const IntTiling &tl, hipStream_t stream
     return ECC_E_UNSUPPORTED;
 }
 
-int launch_int_partial(const IntJob &job, const IntTiling &tl, int32_t *partial, uint32_t *status,
-                       int64_t *zero_vcec, hipStream_t stream) {
+static KParams make_params(const IntJob &job, const IntTiling &tl, int32_t *partial, uint32_t *status,
+                           int64_t *zero_vcec) {
     KParams p{};
     p.src = job.src;
     p.n1 = job.view.n1;
@@ -593,6 +621,13 @@ int launch_int_partial(const IntJob &job, const IntTiling &tl, int32_t *partial,
     p.partial = partial;
     p.status = status;
     p.zero_vcec = zero_vcec;
+    return p;
+}
+
+int launch_int_partial(const IntJob &job, const IntTiling &tl, int32_t *partial, uint32_t *status,
+                       int64_t *zero_vcec, hipStream_t stream) {
+    const KParams p = make_params(job, tl, partial, status, zero_vcec);
+    const int nin = job.view.nin;
     if (job.dtype == ECC_U8)
         return nin == 1 ? launch_rows<uint8_t, 256, 1>(p, tl, stream) : launch_rows<uint8_t, 256, 2>(p, tl, stream);
     if (job.dtype == ECC_U14)
@@ -600,6 +635,29 @@ int launch_int_partial(const IntJob &job, const IntTiling &tl, int32_t *partial,
                         : launch_rows<uint16_t, 16384, 2>(p, tl, stream);
     set_error("integer kernel: unsupported dtype %d", job.dtype);
     return ECC_E_UNSUPPORTED;
+}
+
+size_t kparams_bytes() { return sizeof(KParams); }
+
+void fill_kparams(void *dst, const IntJob &job, const IntTiling &tl, int32_t *partial, uint32_t *status) {
+    const KParams p = make_params(job, tl, partial, status, nullptr);
+    memcpy(dst, &p, sizeof p);
+}
+
+int launch_int_batch(int dtype, int nin, const void *jobs_dev, const int32_t *tile_begin_dev, int njobs, int tiles,
+                     hipStream_t stream) {
+    if (njobs <= 0 || tiles <= 0) return ECC_OK;
+    const KParams *j = (const KParams *)jobs_dev;
+    if (dtype == ECC_U8 && nin == 1)
+        hipLaunchKernelGGL((int_vcec_batch_kernel<uint8_t, 256, 1>), dim3(tiles), dim3(1024), 0, stream, j, tile_begin_dev, njobs);
+    else if (dtype == ECC_U8)
+        hipLaunchKernelGGL((int_vcec_batch_kernel<uint8_t, 256, 2>), dim3(tiles), dim3(1024), 0, stream, j, tile_begin_dev, njobs);
+    else if (nin == 1)
+        hipLaunchKernelGGL((int_vcec_batch_kernel<uint16_t, 16384, 1>), dim3(tiles), dim3(1024), 0, stream, j, tile_begin_dev, njobs);
+    else
+        hipLaunchKernelGGL((int_vcec_batch_kernel<uint16_t, 16384, 2>), dim3(tiles), dim3(1024), 0, stream, j, tile_begin_dev, njobs);
+    ECC_HIP(hipGetLastError());
+    return ECC_OK;
 }
 
 }  // namespace ecc

@@ -21,6 +21,7 @@ constexpr size_t kStatusBytes = 1024;
 constexpr size_t kStatusTotalsOffset = 128;
 
 void set_error(const char *fmt, ...);
+void g_err_clear();
 int hip_fail(hipError_t e, const char *what);
 
 #define ECC_HIP(call)                                  \
@@ -107,6 +108,26 @@ int launch_merge(const int32_t *partial, int rows, int m, int64_t *stage, int64_
                  bool do_scan, int64_t *chi, uint32_t *status, uint32_t *status_out, hipStream_t stream);
 
 bool normalize_int_view(const ecc_dims *dims, IntView *v, int *err_ndim_dropped);
+int check_dims(const ecc_dims *dims, int64_t *total);
+size_t elem_bytes(int dtype);
+
+// Batched integer path (ecc_int.hip, ecc_scan.hip, ecc_batch.cpp).  The
+// per-image kernel parameters are opaque to the host code: kparams_bytes()
+// bytes each, filled by fill_kparams().
+size_t kparams_bytes();
+void fill_kparams(void *dst, const IntJob &job, const IntTiling &tl, int32_t *partial, uint32_t *status);
+int launch_int_batch(int dtype, int nin, const void *jobs_dev, const int32_t *tile_begin_dev, int njobs, int tiles,
+                     hipStream_t stream);
+struct MergeJob {
+    const int32_t *partial;  // [rows][m]
+    int32_t rows;
+    int32_t m;
+    int64_t *vcec;           // [m] scratch
+    int64_t *chi;            // [m] output
+    uint32_t *status;        // device status word of the image (cleared here)
+    uint32_t *status_out;    // optional copy for the caller
+};
+int launch_batch_merge(const MergeJob *jobs_dev, int njobs, int max_m, hipStream_t stream);
 
 // Float path (ecc_float.hip, ecc_sort.hip).
 int launch_float_change(const float *img_dev, const ecc_dims *dims, uint32_t *keys, int8_t *chg, uint32_t *status,

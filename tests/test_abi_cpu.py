@@ -76,3 +76,21 @@ def test_stream_argument_errors():
     assert ecc._lib.ecc_stream_push_chunk(None, None, 1) == ecc.ECC_E_ARG
     assert ecc._lib.ecc_stream_finish(None, None) == ecc.ECC_E_ARG
     ecc._lib.ecc_stream_abort(None)
+
+
+def test_batch_argument_errors():
+    import paper_1705_02045_amd as ecc
+    assert ecc._lib.ecc_batch_create(None, None) == ecc.ECC_E_ARG
+    assert ecc._lib.ecc_batch_run(None, 1, None, None) == ecc.ECC_E_ARG
+    lat = (ctypes.c_double * 1)()
+    arr = (ctypes.c_double * 1)()
+    chi = (ctypes.c_int64 * 256)()
+    assert ecc._lib.ecc_serve_simulate(None, 1, None, arr, 1, 0, chi, lat) == ecc.ECC_E_ARG
+    ecc._lib.ecc_batch_destroy(None)
+
+
+def test_job_struct_layout():
+    import paper_1705_02045_amd as ecc
+    # image, dims (int32 + pad + 4 x int64), dtype (+ pad), chi
+    assert ctypes.sizeof(ecc.Job) == 8 + 40 + 8 + 8
+    assert ecc.Job.chi.offset == 56

@@ -1,0 +1,101 @@
+"""GPU parity of the batched integer path and of the serving replay: every
+image's curve must equal the oracle's exactly."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ecc():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1705_02045_amd as ecc
+    return ecc
+
+
+def dev(img):
+    return torch.from_numpy(img.view(np.int16) if img.dtype == np.uint16 else img).cuda()
+
+
+MIXED = [("u8", (32, 32)), ("u14", (16, 16, 16)), ("u8", (300, 70)), ("u14", (9, 17, 129)), ("u8", (1, 1)),
+         ("u14", (3, 1, 300)), ("u8", (200,)), ("u14", (70, 130, 66)), ("u8", (5, 2, 300)), ("u14", (2, 2)),
+         ("u8", (129, 2049)), ("u14", (100, 64, 64))]
+
+
+def run_batch(ecc, b, specs, seed0=0, status=None):
+    imgs = [gen.serving_image(d, s, seed0 + i) for i, (d, s) in enumerate(specs)]
+    dimgs = [dev(a) for a in imgs]
+    chis = [torch.full((ecc.THRESHOLDS[d],), -7, dtype=torch.int64, device="cuda") for d, _ in specs]
+    b.run(dimgs, [d for d, _ in specs], chis, status)
+    torch.cuda.synchronize()
+    return imgs, [c.cpu().numpy() for c in chis]
+
+
+def test_batch_mixed(ecc):
+    b = ecc.Batch()
+    imgs, got = run_batch(ecc, b, MIXED)
+    for (d, s), img, g in zip(MIXED, imgs, got):
+        ref = oracle.curve(img, m=ecc.THRESHOLDS[d])
+        assert (g == ref).all(), f"{d} {s}"
+    # a second, smaller batch on the same context reuses its scratch
+    imgs, got = run_batch(ecc, b, MIXED[3:6], seed0=50)
+    for (d, s), img, g in zip(MIXED[3:6], imgs, got):
+        assert (g == oracle.curve(img, m=ecc.THRESHOLDS[d])).all(), f"{d} {s}"
+    b.close()
+
+
+def test_batch_range_error_is_per_image(ecc):
+    b = ecc.Batch()
+    specs = [("u14", (5, 40, 70)), ("u14", (6, 30, 65)), ("u8", (40, 70))]
+    imgs = [gen.serving_image(d, s, 7 + i) for i, (d, s) in enumerate(specs)]
+    imgs[1][2, 3, 4] = 20000
+    chis = [torch.full((ecc.THRESHOLDS[d],), -7, dtype=torch.int64, device="cuda") for d, _ in specs]
+    status = torch.full((3,), 99, dtype=torch.int32, device="cuda")
+    b.run([dev(a) for a in imgs], [d for d, _ in specs], chis, status)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    assert list(st) == [0, ecc.STATUS_RANGE_BIT, 0]
+    assert (chis[1].cpu().numpy() == -7).all()
+    for i in (0, 2):
+        assert (chis[i].cpu().numpy() == oracle.curve(imgs[i], m=ecc.THRESHOLDS[specs[i][0]])).all()
+    # the flagged image's status does not leak into the next run
+    imgs2, got2 = run_batch(ecc, b, specs[:2], seed0=30)
+    for (d, s), img, g in zip(specs[:2], imgs2, got2):
+        assert (g == oracle.curve(img, m=ecc.THRESHOLDS[d])).all()
+    b.close()
+
+
+@pytest.mark.parametrize("one_launch", [False, True], ids=["batched", "per_image"])
+def test_serve_replay(ecc, one_launch):
+    reqs = gen.serving_requests(48, seed=4, side_scale=0.25)
+    imgs = [gen.serving_image(*r) for r in reqs]
+    dimgs = [dev(a) for a in imgs]
+    dtypes = [r[0] for r in reqs]
+    arrival = np.cumsum(np.random.default_rng(1).exponential(2e-4, size=len(reqs)))
+    b = ecc.Batch()
+    lat, chi = b.serve(dimgs, dtypes, arrival, max_batch=16, one_launch_per_image=one_launch)
+    b.close()
+    assert (lat > 0).all()
+    off = 0
+    for (d, s, _), img in zip(reqs, imgs):
+        m = ecc.THRESHOLDS[d]
+        assert (chi[off:off + m] == oracle.curve(img, m=m)).all(), f"{d} {s}"
+        off += m
+
+
+def test_serving_stream_sample_full_sides(ecc):
+    # requests of the full-size mix (sides up to 2048 / 256), a sample of them
+    reqs = gen.serving_requests(4096, seed=4)[:24]
+    imgs = [gen.serving_image(*r) for r in reqs]
+    b = ecc.Batch()
+    chis = [torch.empty(ecc.THRESHOLDS[r[0]], dtype=torch.int64, device="cuda") for r in reqs]
+    b.run([dev(a) for a in imgs], [r[0] for r in reqs], chis)
+    torch.cuda.synchronize()
+    for r, img, c in zip(reqs, imgs, chis):
+        assert (c.cpu().numpy() == oracle.curve(img, m=ecc.THRESHOLDS[r[0]])).all(), f"{r}"
+    b.close()
