@@ -9,7 +9,10 @@ i.e. every kernel of the path: change-vector kernel, merge, prefix sum.
 Prints ONE JSON line: GVoxel/s over the timed steps, the roofline of the
 dominant kernel (HBM bytes it must read / its measured average duration, HIP
 events on its launch stream) and the CPU oracle timed on a bounded sample of
-the same volume on this host.
+the same volume on this host.  Under "legs": the other workloads of the path
+(serving mix at a p99 latency bound, 4-D float32, host-staged streaming
+against the measured host-to-device copy rate, the 2-D 256^2 uint8 latency),
+each timed after the headline steps.
 """
 from __future__ import annotations
 
@@ -71,6 +74,133 @@ def cpu_baseline(img, target_s: float):
             "sample": f"planes 0..{planes - 1} of the {n0}x{n1}x{n2} volume ({vox} voxels, {dt:.1f} s)"}
 
 
+def leg_serving(n_req: int, slo_ms: float):
+    """Serving mix (50/50 2-D uint8 sides 32..2048 / 3-D 14-bit sides 16..256,
+    value noise, seeded): highest Poisson arrival rate whose p99 latency
+    (arrival -> curve in host memory) stays within slo_ms, for continuous
+    batching and for one launch per image."""
+    import numpy as np
+    import torch
+    import gen
+    import paper_1705_02045_amd as ecc
+    reqs = gen.serving_requests(n_req, seed=4)
+    imgs = []
+    for r in reqs:
+        a = gen.serving_image(*r)
+        imgs.append(torch.from_numpy(a.view(np.int16) if a.dtype == np.uint16 else a).cuda())
+    dtypes = [r[0] for r in reqs]
+    vox = sum(int(np.prod(r[1])) for r in reqs)
+    b = ecc.Batch()
+    b.serve(imgs[:64], dtypes[:64], np.zeros(64), max_batch=64)
+    b.serve(imgs[:64], dtypes[:64], np.zeros(64), max_batch=1, one_launch_per_image=True)
+    rng = np.random.default_rng(4)
+
+    def run(arr, single):
+        lat, _ = b.serve(imgs, dtypes, arr, max_batch=256, one_launch_per_image=single)
+        return float(np.percentile(lat, 99)) * 1e3, float(np.percentile(lat, 50)) * 1e3, float(np.max(arr + lat))
+
+    out = {}
+    for name, single in (("batched", False), ("one_launch_per_image", True)):
+        _, _, span = run(np.zeros(n_req), single)
+        sat = n_req / span
+        best = None
+        for f in (0.3, 0.5, 0.7, 0.8, 0.9, 0.95):
+            lam = f * sat
+            arr = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
+            arr -= arr[0]
+            p99, p50, _ = run(arr, single)
+            if p99 <= slo_ms:
+                best = {"rate_img_per_s": round(lam, 1), "p50_ms": round(p50, 3), "p99_ms": round(p99, 3)}
+        out[name] = {"saturation_img_per_s": round(sat, 1), "saturation_gvoxel_per_s": round(vox / span / 1e9, 2),
+                     "at_slo": best}
+    b.close()
+    rb = (out["batched"]["at_slo"] or {}).get("rate_img_per_s")
+    rs = (out["one_launch_per_image"]["at_slo"] or {}).get("rate_img_per_s")
+    out.update({"requests": n_req, "voxels": vox, "slo_p99_ms": slo_ms,
+                "speedup_at_slo": round(rb / rs, 2) if rb and rs else None})
+    return out
+
+
+def leg_float(reps: int):
+    """4-D 128^4 float32 value noise (lattice 8, sigma 0.01, seed 3), device-resident: whole float path."""
+    import numpy as np
+    import torch
+    import gen
+    import paper_1705_02045_amd as ecc
+    img = gen.cfg_f32_value_noise((128, 128, 128, 128), seed=3)
+    t = torch.from_numpy(img).cuda()
+    keys, chi = ecc.compute(t, "f32")
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        keys, chi = ecc.compute(t, "f32")
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ms = float(np.median(times)) * 1e3
+    return {"shape": [128, 128, 128, 128], "distinct_values": int(keys.numel()), "ms": round(ms, 3),
+            "gvoxel_per_s": round(img.size / ms / 1e6, 3)}
+
+
+def leg_stream_host(planes_per_chunk: int, chunks: int, side: int):
+    """Host-staged streaming: pinned chunks of side x side 14-bit planes pushed
+    through ecc_stream_push_chunk, against the hipMemcpyAsync host-to-device
+    rate of the same pinned chunk measured in the same run."""
+    import numpy as np
+    import torch
+    import gen
+    import paper_1705_02045_amd as ecc
+    chunk = gen.cfg_u14_value_noise((planes_per_chunk, side, side), seed=2)
+    pinned = torch.from_numpy(chunk.view(np.int16)).pin_memory()
+    dst = torch.empty_like(pinned, device="cuda")
+    dst.copy_(pinned, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(chunks):
+        dst.copy_(pinned, non_blocking=True)
+    torch.cuda.synchronize()
+    h2d = chunks * pinned.numel() * 2 / (time.perf_counter() - t0)
+    del dst
+    host = pinned.numpy()
+    shape = (planes_per_chunk * chunks, side, side)
+    st = ecc.Stream(shape, "u14")
+    st.push(host[:1])
+    st.abort()
+    t0 = time.perf_counter()
+    st = ecc.Stream(shape, "u14")
+    for _ in range(chunks):
+        st.push(host)
+    chi = st.finish()
+    dt = time.perf_counter() - t0
+    rate = chunks * pinned.numel() * 2 / dt
+    return {"shape": list(shape), "chunk_planes": planes_per_chunk, "chunk_bytes": int(pinned.numel() * 2),
+            "stream_gb_per_s": round(rate / 1e9, 2), "h2d_gb_per_s": round(h2d / 1e9, 2),
+            "pcie_frac": round(rate / h2d, 4), "gvoxel_per_s": round(rate / 2e9, 2), "chi_last": int(chi[-1])}
+
+
+def leg_small_2d(reps: int):
+    """2-D 256x256 uint8 i.i.d. (seed 0): latency of one synchronous ecc_compute
+    (device image, device curve) and the oracle on the same image."""
+    import numpy as np
+    import torch
+    import gen
+    import oracle
+    import paper_1705_02045_amd as ecc
+    img = gen.cfg_2d_u8_iid((256, 256), seed=0)
+    t = torch.from_numpy(img).cuda()
+    ecc.compute(t, "u8")
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        ecc.compute(t, "u8")
+        times.append(time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    oracle.curve(img, m=256)
+    cpu_ms = (time.perf_counter() - t0) * 1e3
+    return {"shape": [256, 256], "p50_us": round(float(np.median(times)) * 1e6, 1),
+            "p99_us": round(float(np.percentile(times, 99)) * 1e6, 1), "oracle_ms": round(cpu_ms, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +208,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, default=1024, help="edge of the cubic volume")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget; 0 skips it")
+    ap.add_argument("--legs", default="serving,float,stream_host,small_2d",
+                    help="further workloads reported under 'legs' (comma list, or 'none')")
+    ap.add_argument("--serve-requests", type=int, default=1024)
+    ap.add_argument("--serve-slo-ms", type=float, default=10.0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -141,6 +275,22 @@ def main():
         log("[bench] CPU oracle baseline ...")
         cpu = cpu_baseline(img, args.cpu_seconds)
 
+    legs = {}
+    for leg in [x for x in args.legs.split(",") if x and x != "none"]:
+        log(f"[bench] leg {leg} ...")
+        t0 = time.perf_counter()
+        if leg == "serving":
+            legs[leg] = leg_serving(args.serve_requests, args.serve_slo_ms)
+        elif leg == "float":
+            legs[leg] = leg_float(5)
+        elif leg == "stream_host":
+            legs[leg] = leg_stream_host(8, 4, 8192)
+        elif leg == "small_2d":
+            legs[leg] = leg_small_2d(200)
+        else:
+            raise SystemExit(f"unknown leg {leg}")
+        log(f"[bench] leg {leg}: {time.perf_counter() - t0:.1f} s")
+
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -159,6 +309,7 @@ def main():
                    "shape": list(shape), "thresholds": 16384, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "legs": legs,
     }
     print(json.dumps(out), flush=True)
     return 0

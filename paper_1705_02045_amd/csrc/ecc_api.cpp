@@ -159,7 +159,7 @@ static int env_int(const char *name, int dflt) {
     return (s && *s) ? atoi(s) : dflt;
 }
 
-// Tuning overrides (measurement only): ECC_INT_ROWS, ECC_INT_MODE, ECC_INT_PD, ECC_INT_KPF,
+// Tuning overrides (measurement only): ECC_INT_ROWS, ECC_INT_MODE, ECC_INT_PD, ECC_INT_KPF, ECC_INT_WX,
 // ECC_INT_WAVES, ECC_INT_TILES_PER_CU.
 IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
     IntTiling t{};
@@ -178,7 +178,8 @@ IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
         tiles_xy = (segs + t.wx - 1) / t.wx;
     } else {
         const int64_t xs = (v.n2 + kWave - 1) / kWave;
-        t.wx = (int)(xs < max_waves ? xs : max_waves);
+        const int wx_cap = env_int("ECC_INT_WX", 16);
+        t.wx = (int)(xs < wx_cap ? xs : wx_cap);
         const int64_t ys = (v.n1 + t.rows - 1) / t.rows;
         const int64_t wy = max_waves / t.wx;
         t.wy = (int)(ys < wy ? ys : wy);
