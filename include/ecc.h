@@ -173,9 +173,10 @@ void ecc_batch_destroy(ecc_batch *b);
  * 0): whenever fewer than two batches are in flight, everything that has
  * arrived (at most max_batch requests) goes into the next ecc_batch_run.
  * Otherwise every request is one ecc_compute_async launch as soon as it
- * arrives.  Each request's curve is copied to host memory at chi_host +
- * (sum of the m of the requests before it); latency_s[i] receives the time
- * from its arrival until that copy was seen complete.  Blocks until all
+ * arrives.  Each request's curve is copied to pinned host memory owned by
+ * the call; latency_s[i] receives the time from its arrival until that copy
+ * was seen complete.  At the end all curves are copied to chi_host, request
+ * i's at chi_host + (sum of the m of the requests before it).  Blocks until all
  * requests are done.  Errors: ECC_E_ARG, ECC_E_UNSUPPORTED, ECC_E_NOMEM,
  * ECC_E_HIP. */
 int ecc_serve_simulate(ecc_batch *b, int32_t n, const ecc_job *jobs, const double *arrival_s, int32_t max_batch,

@@ -159,14 +159,13 @@ static int env_int(const char *name, int dflt) {
     return (s && *s) ? atoi(s) : dflt;
 }
 
-// Tuning overrides (measurement only): ECC_INT_ROWS, ECC_INT_MODE, ECC_INT_PD, ECC_INT_KPF, ECC_INT_WX,
+// Tuning overrides (measurement only): ECC_INT_ROWS, ECC_INT_MODE, ECC_INT_PD, ECC_INT_WX,
 // ECC_INT_WAVES, ECC_INT_TILES_PER_CU.
 IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
     IntTiling t{};
     t.rows = env_int("ECC_INT_ROWS", 2);
     t.mode = env_int("ECC_INT_MODE", 0);
     t.pd = env_int("ECC_INT_PD", 1);
-    t.kpf = env_int("ECC_INT_KPF", 0);
     const int cus = device_cu_count();
     const int max_waves = env_int("ECC_INT_WAVES", 16);
     const int tiles_per_cu = env_int("ECC_INT_TILES_PER_CU", 4);

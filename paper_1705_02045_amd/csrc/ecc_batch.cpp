@@ -55,7 +55,6 @@ IntTiling batch_tiling(const IntView &v) {
     t.rows = 2;
     t.mode = 0;
     t.pd = 1;
-    t.kpf = 0;
     const int max_waves = 16;
     int64_t tiles_xy;
     if (v.nin == 1) {
@@ -317,9 +316,14 @@ int ecc_serve_simulate(ecc_batch *b, int32_t n, const ecc_job *jobs, const doubl
     int prev = -1;
     ECC_HIP(hipGetDevice(&prev));
     if (prev != b->device) ECC_HIP(hipSetDevice(b->device));
-    int64_t *chi_dev = nullptr;
+    // curves land in pinned host memory (a copy into pageable memory would
+    // block the host thread until the stream drains) and are copied to
+    // chi_host at the end
+    int64_t *chi_dev = nullptr, *chi_pin = nullptr;
     hipError_t e = hipMalloc(&chi_dev, (size_t)off[n] * 8);
+    if (e == hipSuccess) e = hipHostMalloc(&chi_pin, (size_t)off[n] * 8, hipHostMallocDefault);
     if (e != hipSuccess) {
+        if (chi_dev) (void)hipFree(chi_dev);
         if (prev != b->device) (void)hipSetDevice(prev);
         return hip_fail(e, "ecc_serve_simulate: curve staging");
     }
@@ -348,7 +352,7 @@ int ecc_serve_simulate(ecc_batch *b, int32_t n, const ecc_job *jobs, const doubl
                 rc = ecc_batch_run(b, k, js.data() + next, nullptr);
             }
             if (rc) break;
-            e = hipMemcpyAsync(chi_host + off[next], chi_dev + off[next], (size_t)(off[next + k] - off[next]) * 8,
+            e = hipMemcpyAsync(chi_pin + off[next], chi_dev + off[next], (size_t)(off[next + k] - off[next]) * 8,
                                hipMemcpyDeviceToHost, b->stream);
             hipEvent_t ev = nullptr;
             if (e == hipSuccess) {
@@ -384,6 +388,8 @@ int ecc_serve_simulate(ecc_batch *b, int32_t n, const ecc_job *jobs, const doubl
     (void)hipStreamSynchronize(b->stream);
     for (auto &f : flight) (void)hipEventDestroy(f.ev);
     for (auto ev : pool) (void)hipEventDestroy(ev);
+    if (!rc) memcpy(chi_host, chi_pin, (size_t)off[n] * 8);
+    (void)hipHostFree(chi_pin);
     (void)hipFree(chi_dev);
     if (prev != b->device) (void)hipSetDevice(prev);
     return rc;

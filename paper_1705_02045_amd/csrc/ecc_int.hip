@@ -237,36 +237,22 @@ constexpr int lcm(int a, int b) {
     return a / x * b;
 }
 
-// Dword loads that cover the owned voxels of one plane of a wave (R rows or
-// segments of 64 elements).
-template <typename T, int R>
-constexpr int kPrefetchLoads() {
-    return (R * (int)sizeof(T) + 3) / 4;
-}
-
 // One wave walks the planes [zs, ze) of its rows.  FULL: no position of this
 // wave lies on a far edge, so the comparison masks need no validity mask.
 // PD: planes of raw loads kept in flight ahead of the plane being compared.
-// KPF (FULL walks only): distance in planes of a cache prefetch, one dword
-// per lane covering the wave's owned voxels (byte offsets pfo), whose result
-// is only waited for KPF planes later; it brings the plane into L2 so that
-// the raw loads PD planes ahead hit there instead of waiting on HBM.
-// The plane loop is unrolled by lcm(2, PD+1, KPF) so that every register
-// buffer is addressed with a compile-time index (plane p of the tile uses raw
-// buffer (p - zs) mod (PD+1) and field buffer (p - zs) mod 2).
-template <typename T, int NIN, int R, int MODE, bool FULL, int PD, int KPF>
+// The plane loop is unrolled by lcm(2, PD+1) so that every register buffer is
+// addressed with a compile-time index (plane p of the tile uses raw buffer
+// (p - zs) mod (PD+1) and field buffer (p - zs) mod 2).
+template <typename T, int NIN, int R, int MODE, bool FULL, int PD>
 __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uint32_t (&vx)[R + 1],
                                      const uint32_t (&vxl)[R + 1], const uint32_t (&soff)[R + 1], const EdgeMasks &em,
-                                     const uint32_t (&pfo)[2], uint32_t &orv) {
+                                     uint32_t &orv) {
     using W = Walker<NIN, R>;
     constexpr int NR = W::NR;
     constexpr int NI = W::NI;
     constexpr int ESZ = sizeof(T);
     constexpr int NB = PD + 1;
-    static_assert(KPF == 0 || (FULL && KPF >= PD), "prefetch only on full walks, beyond the raw loads");
-    constexpr int U = lcm(lcm(2, NB), KPF > 0 ? KPF : 1);
-    constexpr int KD = KPF > PD ? KPF : PD;  // farthest plane touched ahead
-    constexpr int NPF = kPrefetchLoads<T, R>();
+    constexpr int U = lcm(2, NB);
     const int64_t pb = P.src.plane_bytes;
     const int32_t pbytes = (int32_t)pb;
     // planes zs-1 and ze are +inf outside the image
@@ -338,22 +324,10 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
     // compare.  `nxt` points at the next plane to load.  Steady state: every
     // plane touched lies inside the tile.
     const uint8_t *nxt = P.src.base + (zs + 1 + PD) * pb;
-    uint32_t pf[KPF > 0 ? KPF : 1][NPF] = {};
     int z = zs;
-    for (; z + U + KD < ze; z += U) {
+    for (; z + U + PD < ze; z += U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if constexpr (KPF > 0) {
-                // wait for the prefetch issued KPF planes ago, then issue
-                // the one of plane z+u+1+KPF into its registers
-                __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc(
-                    (void *)(nxt + (KPF - PD) * pb), (short)0, pbytes, kBufferWord3);
-#pragma unroll
-                for (int j = 0; j < NPF; ++j) {
-                    asm volatile("" ::"v"(pf[u % KPF][j]));
-                    pf[u % KPF][j] = __builtin_amdgcn_raw_buffer_load_b32(rp, pfo[j], 0, 0);
-                }
-            }
             load_at(nxt, ra[u % NB], rb[u % NB]);
             nxt += pb;
             W::fields(ra[(u + 1) % NB], rb[(u + 1) % NB], g[(u + 1) & 1]);
@@ -396,7 +370,7 @@ constexpr int kWavesPerEU() {
 
 // One tile of one image: b = the workgroup's index among the image's G
 // tiles.  Writes the tile's counts to row b of P.partial.
-template <typename T, int M, int NIN, int R, int MODE, int PD, int KPF>
+template <typename T, int M, int NIN, int R, int MODE, int PD>
 __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const int b, const int G) {
     using W = Walker<NIN, R>;
     constexpr int NR = W::NR;
@@ -477,22 +451,7 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
     }
     if (any && zs < ze) {
         if (full) {
-            uint32_t pfo[2] = {0u, 0u};
-            if constexpr (KPF > 0) {
-                // lane -> (owned row or segment, dword within its 64 elements)
-                constexpr int lpr = 16 * ESZ;  // dwords per 64 elements
-#pragma unroll
-                for (int j = 0; j < kPrefetchLoads<T, R>(); ++j) {
-                    const int rr = min(j * (kWave / lpr) + lane / lpr, R - 1);
-                    const uint32_t d = (uint32_t)(lane % lpr) * 4u;
-                    if constexpr (NIN == 1) {
-                        pfo[j] = (uint32_t)((tx * P.wx + wxi) * R + rr) * kWave * ESZ + d;
-                    } else {
-                        pfo[j] = soff[rr + 1] + (uint32_t)((tx * P.wx + wxi) * kWave) * ESZ + d;
-                    }
-                }
-            }
-            walk<T, NIN, R, MODE, true, PD, KPF>(P, zs, ze, vx, vxl, soff, em, pfo, orv);
+            walk<T, NIN, R, MODE, true, PD>(P, zs, ze, vx, vxl, soff, em, orv);
         } else if constexpr (NIN == 1) {
             // An edge group of segments is walked as pairs of segments, each
             // pair with its own lane masks.
@@ -509,12 +468,10 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
                 e2.lx_any2 = ballot(xb < n2);
                 const uint32_t v2[3] = {vx[r], vx[r + 1], 0u}, vl2[3] = {vxl[r], vxl[r + 1], 0u};
                 const uint32_t s2[3] = {0u, 0u, 0u};
-                const uint32_t pf2[2] = {0u, 0u};
-                walk<T, 1, 2, MODE, false, 1, 0>(P, zs, ze, v2, vl2, s2, e2, pf2, orv);
+                walk<T, 1, 2, MODE, false, 1>(P, zs, ze, v2, vl2, s2, e2, orv);
             }
         } else {
-            const uint32_t pf2[2] = {0u, 0u};
-            walk<T, NIN, R, MODE, false, PD, 0>(P, zs, ze, vx, vxl, soff, em, pf2, orv);
+            walk<T, NIN, R, MODE, false, PD>(P, zs, ze, vx, vxl, soff, em, orv);
         }
     }
 
@@ -529,11 +486,11 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
         if (i0 + tid < M) dst[i0 + tid] = hist[i0 + tid];
 }
 
-template <typename T, int M, int NIN, int R, int MODE, int PD, int KPF>
+template <typename T, int M, int NIN, int R, int MODE, int PD>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<NIN, R, PD>())))
 int_vcec_kernel(KParams P) {
     __shared__ int32_t hist[M];
-    tile_body<T, M, NIN, R, MODE, PD, KPF>(P, hist, blockIdx.x, gridDim.x);
+    tile_body<T, M, NIN, R, MODE, PD>(P, hist, blockIdx.x, gridDim.x);
 }
 
 // Batched form: the tiles of many images in one launch.  Image j owns
@@ -552,29 +509,25 @@ int_vcec_batch_kernel(const KParams *__restrict__ jobs, const int32_t *__restric
     lo = __builtin_amdgcn_readfirstlane(lo);
     const KParams P = jobs[lo];
     const int b0 = tile_begin[lo];
-    tile_body<T, M, NIN, 2, 0, 1, 0>(P, hist, b - b0, tile_begin[lo + 1] - b0);
+    tile_body<T, M, NIN, 2, 0, 1>(P, hist, b - b0, tile_begin[lo + 1] - b0);
 }
 
-template <typename T, int M, int NIN, int R, int MODE, int PD, int KPF>
+template <typename T, int M, int NIN, int R, int MODE, int PD>
 static int launch_one(const KParams &p, const IntTiling &tl, hipStream_t stream) {
     const int threads = kWave * tl.wx * tl.wy;
     void *tok = nullptr;
     int rc = profile_begin(stream, &tok);
     if (rc) return rc;
-    hipLaunchKernelGGL((int_vcec_kernel<T, M, NIN, R, MODE, PD, KPF>), dim3(tl.grid), dim3(threads), 0, stream, p);
+    hipLaunchKernelGGL((int_vcec_kernel<T, M, NIN, R, MODE, PD>), dim3(tl.grid), dim3(threads), 0, stream, p);
     ECC_HIP(hipGetLastError());
     return profile_end(stream, tok);
 }
 
-// (prefetch depth, cache prefetch distance) pairs that are built
 template <typename T, int M, int NIN, int R, int MODE>
 static int launch_pd(const KParams &p, const IntTiling &tl, hipStream_t stream) {
-    if (tl.pd == 1 && tl.kpf == 0) return launch_one<T, M, NIN, R, MODE, 1, 0>(p, tl, stream);
-    if (tl.pd == 1 && tl.kpf == 2) return launch_one<T, M, NIN, R, MODE, 1, 2>(p, tl, stream);
-    if (tl.pd == 1 && tl.kpf == 4) return launch_one<T, M, NIN, R, MODE, 1, 4>(p, tl, stream);
-    if (tl.pd == 1 && tl.kpf == 6) return launch_one<T, M, NIN, R, MODE, 1, 6>(p, tl, stream);
-    if (tl.pd == 2 && tl.kpf == 0) return launch_one<T, M, NIN, R, MODE, 2, 0>(p, tl, stream);
-    set_error("integer kernel: prefetch depth %d with cache prefetch %d not built", tl.pd, tl.kpf);
+    if (tl.pd == 1) return launch_one<T, M, NIN, R, MODE, 1>(p, tl, stream);
+    if (tl.pd == 2) return launch_one<T, M, NIN, R, MODE, 2>(p, tl, stream);
+    set_error("integer kernel: prefetch depth %d not built", tl.pd);
     return ECC_E_UNSUPPORTED;
 }
 

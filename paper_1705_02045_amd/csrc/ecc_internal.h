@@ -61,7 +61,6 @@ struct IntTiling {
     int rows;      // rows (nin == 2) or 64-wide x segments (nin == 1) per wave
     int mode;      // update form of the four-item groups (0..3, see ecc_int.hip)
     int pd;        // planes of raw loads in flight ahead of the compared plane
-    int kpf;       // distance in planes of the L2 prefetch (0: none)
     int wx, wy;    // waves per workgroup along x and along y
     int zc;        // planes per tile
     int grid;      // workgroups = tiles (one tile per workgroup)
