@@ -257,14 +257,14 @@ static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc
         ECC_HIP(hipMemcpyAsync(ws->img_tmp, image, bytes, hipMemcpyHostToDevice, s));
         img_dev = (const float *)ws->img_tmp;
     }
-    // carve the float scratch
-    const int64_t segs = radix_segments(n);
+    // carve the float scratch: two record buffers, the digit table and its
+    // scan sums, the curve's tile sums and the distinct-value count
+    const int64_t tiles = radix_tiles(n);
     const int64_t ft = float_tiles(n);
-    size_t off[9], total = 0;
-    const size_t sz[9] = {(size_t)n * 4, (size_t)n * 4, (size_t)n, (size_t)n,
-                          (size_t)(256 * segs) * 4, (size_t)radix_scan_tiles(256 * segs) * 4,
-                          (size_t)ft * 8, (size_t)ft * 8, 8};
-    for (int i = 0; i < 9; ++i) {
+    size_t off[7], total = 0;
+    const size_t sz[7] = {(size_t)n * 8, (size_t)n * 8, (size_t)(256 * tiles) * 4,
+                          (size_t)radix_scan_tiles(256 * tiles) * 4, (size_t)ft * 8, (size_t)ft * 8, 8};
+    for (int i = 0; i < 7; ++i) {
         off[i] = total;
         total += align256(sz[i]);
     }
@@ -276,21 +276,20 @@ static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc
     rc = ensure_bytes(&ws->fbuf, &ws->fbuf_bytes, total);
     if (rc) return rc;
     uint8_t *b = (uint8_t *)ws->fbuf;
-    uint32_t *k[2] = {(uint32_t *)(b + off[0]), (uint32_t *)(b + off[1])};
-    int8_t *v[2] = {(int8_t *)(b + off[2]), (int8_t *)(b + off[3])};
-    uint32_t *counts = (uint32_t *)(b + off[4]);
-    uint32_t *sums = (uint32_t *)(b + off[5]);
-    int64_t *tile_chg = (int64_t *)(b + off[6]);
-    int64_t *tile_last = (int64_t *)(b + off[7]);
-    int64_t *count_dev = (int64_t *)(b + off[8]);
+    uint64_t *rec[2] = {(uint64_t *)(b + off[0]), (uint64_t *)(b + off[1])};
+    uint32_t *counts = (uint32_t *)(b + off[2]);
+    uint32_t *sums = (uint32_t *)(b + off[3]);
+    int64_t *tile_chg = (int64_t *)(b + off[4]);
+    int64_t *tile_last = (int64_t *)(b + off[5]);
+    int64_t *count_dev = (int64_t *)(b + off[6]);
     float *out_keys = direct ? curve->keys : (float *)(b + out_k);
     int64_t *out_chi = direct ? curve->chi : (int64_t *)(b + out_c);
 
-    rc = launch_float_change(img_dev, dims, k[0], v[0], ws->status, s);
+    rc = launch_float_change(img_dev, dims, rec[0], ws->status, s);
     if (rc) return rc;
-    rc = radix_sort_records(k, v, n, counts, sums, s);
+    rc = radix_sort_records(rec, n, counts, sums, s);
     if (rc) return rc;
-    rc = launch_float_curve(k[0], v[0], n, tile_chg, tile_last, count_dev, out_keys, out_chi, s);
+    rc = launch_float_curve(rec[0], n, tile_chg, tile_last, count_dev, out_keys, out_chi, s);
     if (rc) return rc;
     uint32_t st = 0;
     int64_t kcount = 0;

@@ -21,6 +21,7 @@
 //
 // Keys: the canonical float (-0 folded into +0) mapped to an unsigned integer
 // with the same order (sign bit set: all bits flipped; else the sign bit set).
+// A record is one 64-bit word: key in bits 8..39, change (int8) in bits 0..7.
 
 #include "ecc_internal.h"
 
@@ -79,8 +80,8 @@ struct FloatView {
 // (the complex of the others times unit intervals has the same curve).
 template <int D>
 __global__ void __launch_bounds__(256) float_change_kernel(const float *__restrict__ img, uint32_t img_bytes,
-                                                           FloatView v, uint32_t *__restrict__ keys,
-                                                           int8_t *__restrict__ chg, uint32_t *status) {
+                                                           FloatView v, uint64_t *__restrict__ rec,
+                                                           uint32_t *status) {
     constexpr int P = pow3(D);
     constexpr int C = (P - 1) / 2;  // code of the zero direction
     const int32_t nx = v.n[3];
@@ -159,13 +160,10 @@ __global__ void __launch_bounds__(256) float_change_kernel(const float *__restri
     }
     if (ballot64(act && (own_bits & 0x7FFFFFFFu) > 0x7F800000u) != 0 && (threadIdx.x & (kWave - 1)) == 0)
         atomicOr(status, kStatusNaN);
-    if (act) {
-        keys[base] = k0;
-        chg[base] = (int8_t)(1 - acc);
-    }
+    if (act) rec[base] = ((uint64_t)k0 << 8) | (uint8_t)(int8_t)(1 - acc);
 }
 
-int launch_float_change(const float *img_dev, const ecc_dims *dims, uint32_t *keys, int8_t *chg, uint32_t *status,
+int launch_float_change(const float *img_dev, const ecc_dims *dims, uint64_t *rec, uint32_t *status,
                         hipStream_t stream) {
     // drop axes of extent 1, pad in front to four axes
     int32_t ext[4];
@@ -203,10 +201,10 @@ int launch_float_change(const float *img_dev, const ecc_dims *dims, uint32_t *ke
     int rc = profile_begin(stream, &tok);
     if (rc) return rc;
     switch (D) {
-    case 1: hipLaunchKernelGGL(float_change_kernel<1>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, keys, chg, status); break;
-    case 2: hipLaunchKernelGGL(float_change_kernel<2>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, keys, chg, status); break;
-    case 3: hipLaunchKernelGGL(float_change_kernel<3>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, keys, chg, status); break;
-    default: hipLaunchKernelGGL(float_change_kernel<4>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, keys, chg, status); break;
+    case 1: hipLaunchKernelGGL(float_change_kernel<1>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, rec, status); break;
+    case 2: hipLaunchKernelGGL(float_change_kernel<2>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, rec, status); break;
+    case 3: hipLaunchKernelGGL(float_change_kernel<3>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, rec, status); break;
+    default: hipLaunchKernelGGL(float_change_kernel<4>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, rec, status); break;
     }
     ECC_HIP(hipGetLastError());
     return profile_end(stream, tok);
@@ -223,8 +221,10 @@ constexpr int kFThreads = 256;
 constexpr int kFItems = 16;
 constexpr int kFTile = kFThreads * kFItems;
 
-__device__ __forceinline__ bool last_of_key(const uint32_t *keys, int64_t i, int64_t n) {
-    return i == n - 1 || keys[i] != keys[i + 1];
+__device__ __forceinline__ uint32_t rec_key(uint64_t r) { return (uint32_t)(r >> 8); }
+__device__ __forceinline__ int32_t rec_chg(uint64_t r) { return (int32_t)(int8_t)(uint8_t)(r & 0xFFu); }
+__device__ __forceinline__ bool last_of_key(const uint64_t *rec, int64_t i, int64_t n) {
+    return i == n - 1 || rec_key(rec[i]) != rec_key(rec[i + 1]);
 }
 
 template <typename T>
@@ -240,8 +240,7 @@ __device__ T block_sum(T v, T *sh) {
     return t;
 }
 
-__global__ void __launch_bounds__(kFThreads) fsum_tiles_kernel(const uint32_t *__restrict__ keys,
-                                                              const int8_t *__restrict__ chg, int64_t n,
+__global__ void __launch_bounds__(kFThreads) fsum_tiles_kernel(const uint64_t *__restrict__ rec, int64_t n,
                                                               int64_t *__restrict__ tile_chg,
                                                               int64_t *__restrict__ tile_last) {
     __shared__ int64_t sh[4];
@@ -251,8 +250,8 @@ __global__ void __launch_bounds__(kFThreads) fsum_tiles_kernel(const uint32_t *_
     for (int j = 0; j < kFItems; ++j) {
         const int64_t i = t0 + (int64_t)j * kFThreads + threadIdx.x;
         if (i < n) {
-            s += chg[i];
-            l += last_of_key(keys, i, n);
+            s += rec_chg(rec[i]);
+            l += last_of_key(rec, i, n);
         }
     }
     s = block_sum(s, sh);
@@ -309,8 +308,7 @@ __global__ void __launch_bounds__(1024) fscan_tiles_kernel(int64_t *a, int64_t *
     if (tid == 0) *total_last = carry_b;
 }
 
-__global__ void __launch_bounds__(kFThreads) fwrite_kernel(const uint32_t *__restrict__ keys,
-                                                          const int8_t *__restrict__ chg, int64_t n,
+__global__ void __launch_bounds__(kFThreads) fwrite_kernel(const uint64_t *__restrict__ rec, int64_t n,
                                                           const int64_t *__restrict__ tile_chg,
                                                           const int64_t *__restrict__ tile_last,
                                                           float *__restrict__ out_keys, int64_t *__restrict__ out_chi) {
@@ -325,9 +323,9 @@ __global__ void __launch_bounds__(kFThreads) fwrite_kernel(const uint32_t *__res
     for (int j = 0; j < kFItems; ++j) {
         const int64_t i = i0 + j;
         const bool in = i < n;
-        sc += in ? chg[i] : 0;
+        sc += in ? rec_chg(rec[i]) : 0;
         c[j] = sc;
-        last[j] = in && last_of_key(keys, i, n);
+        last[j] = in && last_of_key(rec, i, n);
         sl += last[j];
     }
     int64_t xc = sc, xl = sl;
@@ -352,26 +350,26 @@ __global__ void __launch_bounds__(kFThreads) fwrite_kernel(const uint32_t *__res
 #pragma unroll
     for (int j = 0; j < kFItems; ++j) {
         if (last[j]) {
-            out_keys[bl] = key_to_f32(keys[i0 + j]);
+            out_keys[bl] = key_to_f32(rec_key(rec[i0 + j]));
             out_chi[bl] = bc + c[j];
             ++bl;
         }
     }
 }
 
-int launch_float_curve(const uint32_t *keys, const int8_t *chg, int64_t n, int64_t *tile_chg, int64_t *tile_last,
+int launch_float_curve(const uint64_t *rec, int64_t n, int64_t *tile_chg, int64_t *tile_last,
                        int64_t *total_last, float *out_keys, int64_t *out_chi, hipStream_t stream) {
     const int64_t nt = (n + kFTile - 1) / kFTile;
     if (nt > INT32_MAX) {
         set_error("float curve: too many records");
         return ECC_E_UNSUPPORTED;
     }
-    hipLaunchKernelGGL(fsum_tiles_kernel, dim3((unsigned)nt), dim3(kFThreads), 0, stream, keys, chg, n, tile_chg,
+    hipLaunchKernelGGL(fsum_tiles_kernel, dim3((unsigned)nt), dim3(kFThreads), 0, stream, rec, n, tile_chg,
                        tile_last);
     ECC_HIP(hipGetLastError());
     hipLaunchKernelGGL(fscan_tiles_kernel, dim3(1), dim3(1024), 0, stream, tile_chg, tile_last, nt, total_last);
     ECC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(fwrite_kernel, dim3((unsigned)nt), dim3(kFThreads), 0, stream, keys, chg, n, tile_chg,
+    hipLaunchKernelGGL(fwrite_kernel, dim3((unsigned)nt), dim3(kFThreads), 0, stream, rec, n, tile_chg,
                        tile_last, out_keys, out_chi);
     ECC_HIP(hipGetLastError());
     return ECC_OK;

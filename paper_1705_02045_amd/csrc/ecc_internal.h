@@ -129,14 +129,15 @@ struct MergeJob {
 int launch_batch_merge(const MergeJob *jobs_dev, int njobs, int max_m, hipStream_t stream);
 
 // Float path (ecc_float.hip, ecc_sort.hip).
-int launch_float_change(const float *img_dev, const ecc_dims *dims, uint32_t *keys, int8_t *chg, uint32_t *status,
+// Records: one 64-bit word per voxel, order-preserving key in bits 8..39,
+// change (int8) in bits 0..7.
+int launch_float_change(const float *img_dev, const ecc_dims *dims, uint64_t *rec, uint32_t *status,
                         hipStream_t stream);
-int64_t radix_segments(int64_t n);
+int64_t radix_tiles(int64_t n);
 int64_t radix_scan_tiles(int64_t entries);
-int radix_sort_records(uint32_t *k[2], int8_t *v[2], int64_t n, uint32_t *counts, uint32_t *sums,
-                       hipStream_t stream);
+int radix_sort_records(uint64_t *rec[2], int64_t n, uint32_t *counts, uint32_t *sums, hipStream_t stream);
 int64_t float_tiles(int64_t n);
-int launch_float_curve(const uint32_t *keys, const int8_t *chg, int64_t n, int64_t *tile_chg, int64_t *tile_last,
+int launch_float_curve(const uint64_t *rec, int64_t n, int64_t *tile_chg, int64_t *tile_last,
                        int64_t *total_last, float *out_keys, int64_t *out_chi, hipStream_t stream);
 
 // Optional event timing of the per-voxel kernels (ecc_profile.cpp).

@@ -1,80 +1,135 @@
-// Stable LSD radix sort of float records (32-bit key, 8-bit change), 8-bit
-// digits, four passes (Sec. 3, "Floating Point Values": the values are
-// sorted before the running sum).
+// Stable LSD radix sort of float records (Sec. 3, "Floating Point Values":
+// the values are sorted before the running sum).  A record is one 64-bit word:
+// the 32-bit order-preserving key in bits 8..39 and the voxel's change (int8)
+// in bits 0..7.  Four passes of 8-bit digits.
 //
-// Each wave owns a segment of kSegRecords consecutive records.  A pass:
-//  1. digit counts per (digit, segment), digit-major, from a per-wave LDS
-//     histogram;
+// A workgroup owns a tile of kTile consecutive records.  A pass:
+//  1. radix_count_kernel: digit counts per (digit, tile), digit-major;
 //  2. exclusive scan of that table: the output position of the first record
-//     of each digit in each segment;
-//  3. the wave walks its segment in order, 64 records at a time; the lanes
-//     with equal digits find each other with eight ballots, take ranks by
-//     lane order, and the leader advances the digit's running position.
-// Records keep their order within a digit, so every pass is stable.
+//     of each digit of each tile;
+//  3. radix_scatter_kernel: the tile is ranked stably in LDS (per round of
+//     1024 records, lanes with equal digits find each other with eight
+//     ballots; the waves' counts are prefixed per digit), reordered by digit
+//     in LDS, and written out: records of one digit leave a tile as one
+//     contiguous run, so the stores coalesce.
 
 #include "ecc_internal.h"
 
 namespace ecc {
 
-constexpr int kSortThreads = 256;  // four waves
-constexpr int kSegRounds = 256;
-constexpr int64_t kSegRecords = (int64_t)kSegRounds * kWave;
+constexpr int kSortThreads = 1024;
+constexpr int kSortWaves = kSortThreads / kWave;
+constexpr int kItems = 8;
+constexpr int64_t kTile = (int64_t)kSortThreads * kItems;
 
-__global__ void __launch_bounds__(kSortThreads) radix_count_kernel(const uint32_t *__restrict__ keys, int64_t n,
-                                                                   int shift, int64_t segs,
+__device__ __forceinline__ uint32_t digit_of(uint64_t r, int shift) { return (uint32_t)(r >> shift) & 255u; }
+
+__global__ void __launch_bounds__(kSortThreads) radix_count_kernel(const uint64_t *__restrict__ rec, int64_t n,
+                                                                   int shift, int64_t tiles,
                                                                    uint32_t *__restrict__ counts) {
-    __shared__ uint32_t cnt[kSortThreads / kWave][256];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
-    for (int d = lane; d < 256; d += kWave) cnt[wave][d] = 0;
+    __shared__ uint32_t cnt[256];
+    const int tid = threadIdx.x;
+    if (tid < 256) cnt[tid] = 0;
     __syncthreads();
-    const int64_t seg = (int64_t)blockIdx.x * (kSortThreads / kWave) + wave;
-    if (seg < segs) {
-        const int64_t i0 = seg * kSegRecords;
-        for (int r = 0; r < kSegRounds; ++r) {
-            const int64_t i = i0 + (int64_t)r * kWave + lane;
-            if (i < n) atomicAdd(&cnt[wave][(keys[i] >> shift) & 255u], 1u);
-        }
+    const int64_t t0 = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int64_t i = t0 + (int64_t)j * kSortThreads + tid;
+        if (i < n) atomicAdd(&cnt[digit_of(rec[i], shift)], 1u);
     }
     __syncthreads();
-    if (seg < segs)
-        for (int d = lane; d < 256; d += kWave) counts[(int64_t)d * segs + seg] = cnt[wave][d];
+    if (tid < 256) counts[(int64_t)tid * tiles + blockIdx.x] = cnt[tid];
 }
 
-__global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const uint32_t *__restrict__ keys_in,
-                                                                     const int8_t *__restrict__ vals_in, int64_t n,
-                                                                     int shift, int64_t segs,
+__global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const uint64_t *__restrict__ in, int64_t n,
+                                                                     int shift, int64_t tiles,
                                                                      const uint32_t *__restrict__ offsets,
-                                                                     uint32_t *__restrict__ keys_out,
-                                                                     int8_t *__restrict__ vals_out) {
-    __shared__ uint32_t pos[kSortThreads / kWave][256];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
-    const int64_t seg = (int64_t)blockIdx.x * (kSortThreads / kWave) + wave;
-    if (seg >= segs) return;  // whole wave (no block barriers below)
-    for (int d = lane; d < 256; d += kWave) pos[wave][d] = offsets[(int64_t)d * segs + seg];
+                                                                     uint64_t *__restrict__ out) {
+    __shared__ uint64_t buf[kTile];
+    __shared__ uint32_t wcnt[2][kSortWaves][256];  // per round (alternating): waves' digit counts
+    __shared__ uint32_t run[256];                  // records of each digit ranked so far
+    __shared__ uint32_t start[256];                // first LDS slot of each digit
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+    const int64_t t0 = (int64_t)blockIdx.x * kTile;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t i0 = seg * kSegRecords;
-    for (int r = 0; r < kSegRounds; ++r) {
-        const int64_t i = i0 + (int64_t)r * kWave + lane;
-        if (i0 + (int64_t)r * kWave >= n) break;  // uniform
-        const bool in = i < n;
-        const uint32_t k = in ? keys_in[i] : 0u;
-        const int8_t v = in ? vals_in[i] : (int8_t)0;
-        const uint32_t d = (k >> shift) & 255u;
-        uint64_t peers = __builtin_amdgcn_ballot_w64(in);
+    if (tid < 256) {
+        run[tid] = 0;
+        for (int w = 0; w < kSortWaves; ++w) wcnt[0][w][tid] = 0;
+    }
+    __syncthreads();
+
+    uint64_t r[kItems];
+    uint32_t rank[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int64_t i = t0 + (int64_t)j * kSortThreads + tid;
+        r[j] = i < n ? in[i] : ~0ull;  // past the end: digit 255, never written
+    }
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        // round j: records t0 + j*1024 .. +1023, in thread order.  Table
+        // j & 1 was cleared before this round; the prefix step clears the
+        // other one for the next round (its last readers passed the barrier
+        // at the start of this round's prefix step).
+        const int B = j & 1;
+        const uint32_t d = digit_of(r[j], shift);
+        uint64_t peers = ~0ull;
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
             const uint64_t m = __builtin_amdgcn_ballot_w64((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
-        const uint32_t rank = (uint32_t)__builtin_popcountll(peers & lt);
-        const uint32_t p = pos[wave][d] + rank;
-        if (in) {
-            keys_out[p] = k;
-            vals_out[p] = v;
+        const uint32_t rw = (uint32_t)__builtin_popcountll(peers & lt);
+        if (rw == 0) wcnt[B][wave][d] = (uint32_t)__builtin_popcountll(peers);
+        __syncthreads();
+        if (tid < 256) {  // prefix over the waves, per digit
+            uint32_t acc = run[tid];
+            for (int w = 0; w < kSortWaves; ++w) {
+                const uint32_t c = wcnt[B][w][tid];
+                wcnt[B][w][tid] = acc;
+                acc += c;
+                wcnt[B ^ 1][w][tid] = 0;
+            }
+            run[tid] = acc;
         }
-        // the lowest lane of each digit group advances the group's position
-        // (every lane has read it above: one wave, program order)
-        if (in && rank == 0) pos[wave][d] += (uint32_t)__builtin_popcountll(peers);
+        __syncthreads();
+        rank[j] = wcnt[B][wave][d] + rw;
+    }
+    // first slot of each digit: exclusive scan of run[] (256 values, one wave
+    // of 64 lanes, four digits per lane)
+    if (tid < kWave) {
+        uint32_t v[4], s = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[q] = run[tid * 4 + q];
+            s += v[q];
+        }
+        uint32_t x = s;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t u = __shfl_up(x, off, 64);
+            if (lane >= off) x += u;
+        }
+        uint32_t p = x - s;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            start[tid * 4 + q] = p;
+            p += v[q];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) buf[start[digit_of(r[j], shift)] + rank[j]] = r[j];
+    __syncthreads();
+    const int64_t valid = (n - t0) < kTile ? (n - t0) : kTile;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int s = j * kSortThreads + tid;
+        if (s < valid) {
+            const uint64_t v = buf[s];
+            const uint32_t d = digit_of(v, shift);
+            out[(int64_t)offsets[(int64_t)d * tiles + blockIdx.x] + (s - start[d])] = v;
+        }
     }
 }
 
@@ -176,32 +231,29 @@ static int exclusive_scan_u32(uint32_t *a, int64_t n, uint32_t *sums, hipStream_
     return ECC_OK;
 }
 
-int64_t radix_segments(int64_t n) { return (n + kSegRecords - 1) / kSegRecords; }
+int64_t radix_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
 int64_t radix_scan_tiles(int64_t entries) { return (entries + kScanTile - 1) / kScanTile; }
 
-// Sorts (k[0], v[0]) into (k[0], v[0]) using (k[1], v[1]) as the other buffer
-// (four passes: the result ends where it started).  counts: 256 * segs
-// entries; sums: radix_scan_tiles(256 * segs) entries.
-int radix_sort_records(uint32_t *k[2], int8_t *v[2], int64_t n, uint32_t *counts, uint32_t *sums,
-                       hipStream_t stream) {
+// Sorts rec[0] in place, rec[1] being the other buffer (four passes: the
+// result ends where it started).  counts: 256 * radix_tiles(n) entries;
+// sums: radix_scan_tiles(256 * radix_tiles(n)) entries.
+int radix_sort_records(uint64_t *rec[2], int64_t n, uint32_t *counts, uint32_t *sums, hipStream_t stream) {
     if (n <= 1) return ECC_OK;
     if (n > (int64_t)UINT32_MAX) {
         set_error("radix sort: too many records");
         return ECC_E_UNSUPPORTED;
     }
-    const int64_t segs = radix_segments(n);
-    const int64_t blocks = (segs + (kSortThreads / kWave) - 1) / (kSortThreads / kWave);
+    const int64_t tiles = radix_tiles(n);
     int cur = 0;
     for (int pass = 0; pass < 4; ++pass) {
-        const int shift = 8 * pass;
-        hipLaunchKernelGGL(radix_count_kernel, dim3((unsigned)blocks), dim3(kSortThreads), 0, stream,
-                           (const uint32_t *)k[cur], n, shift, segs, counts);
+        const int shift = 8 + 8 * pass;  // key bits 8..39
+        hipLaunchKernelGGL(radix_count_kernel, dim3((unsigned)tiles), dim3(kSortThreads), 0, stream,
+                           (const uint64_t *)rec[cur], n, shift, tiles, counts);
         ECC_HIP(hipGetLastError());
-        int rc = exclusive_scan_u32(counts, 256 * segs, sums, stream);
+        int rc = exclusive_scan_u32(counts, 256 * tiles, sums, stream);
         if (rc) return rc;
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)blocks), dim3(kSortThreads), 0, stream,
-                           (const uint32_t *)k[cur], (const int8_t *)v[cur], n, shift, segs,
-                           (const uint32_t *)counts, k[cur ^ 1], v[cur ^ 1]);
+        hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)tiles), dim3(kSortThreads), 0, stream,
+                           (const uint64_t *)rec[cur], n, shift, tiles, (const uint32_t *)counts, rec[cur ^ 1]);
         ECC_HIP(hipGetLastError());
         cur ^= 1;
     }
