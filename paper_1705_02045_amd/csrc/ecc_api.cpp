@@ -184,8 +184,9 @@ IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
         t.wy = (int)(ys < wy ? ys : wy);
         tiles_xy = ((xs + t.wx - 1) / t.wx) * ((ys + t.wy - 1) / t.wy);
     }
-    // one tile per workgroup: split axis 0 until there are about
-    // tiles_per_cu tiles per CU (a multiple of 8 keeps the XCD permutation)
+    // split axis 0 until there are about tiles_per_cu tiles per CU; planes
+    // with more tiles than that get several consecutive tiles per workgroup,
+    // so the per-workgroup rows stay about tiles_per_cu per CU
     const int64_t target = (int64_t)cus * tiles_per_cu;
     int64_t tz = (target + tiles_xy - 1) / tiles_xy;
     if (tz < 1) tz = 1;
@@ -193,7 +194,10 @@ IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
     int64_t zc = (planes + tz - 1) / tz;
     if (zc < 8 && planes >= 8) zc = 8;
     t.zc = (int)zc;
-    t.grid = (int)(tiles_xy * ((planes + zc - 1) / zc));
+    const int64_t tiles = tiles_xy * ((planes + zc - 1) / zc);
+    const int64_t per = tiles > target ? (tiles + target - 1) / target : 1;
+    t.per_wg = (int)per;
+    t.grid = (int)((tiles + per - 1) / per);
     return t;
 }
 

@@ -72,6 +72,7 @@ IntTiling batch_tiling(const IntView &v) {
     int64_t zc = std::max<int64_t>(64, (v.n0 + 3) / 4);
     if (zc > v.n0) zc = v.n0;
     t.zc = (int)zc;
+    t.per_wg = 1;
     t.grid = (int)(tiles_xy * ((v.n0 + zc - 1) / zc));
     return t;
 }

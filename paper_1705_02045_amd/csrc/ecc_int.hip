@@ -42,6 +42,7 @@ struct KParams {
     int32_t lo_inf, hi_inf;
     int32_t zc;
     int32_t tiles_x, tiles_y, tiles_z;
+    int32_t per_wg;  // consecutive tiles walked by one workgroup into one histogram
     int32_t wx, wy;
     int32_t *partial;
     uint32_t *status;
@@ -368,8 +369,9 @@ constexpr int kWavesPerEU() {
     return (R <= 2) ? 8 : 4;
 }
 
-// One tile of one image: b = the workgroup's index among the image's G
-// tiles.  Writes the tile's counts to row b of P.partial.
+// The tiles of one workgroup of one image: b = the workgroup's index among
+// the image's G workgroups.  Writes the counts of its tiles to row b of
+// P.partial.
 template <typename T, int M, int NIN, int R, int MODE, int PD>
 __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const int b, const int G) {
     using W = Walker<NIN, R>;
@@ -400,14 +402,20 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
     const bool wave_in = wave < P.wx * P.wy;
     const int32_t n1 = P.n1, n2 = P.n2;
 
-    const int t = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+    // workgroup b (permuted: the workgroups of one XCD take neighbouring
+    // ranges) walks tiles [t0, t1) into its histogram
+    const int bp = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+    const int ntiles = P.tiles_x * P.tiles_y * P.tiles_z;
+    const int t0 = bp * P.per_wg;
+    const int t1 = min(t0 + P.per_wg, ntiles);
+    uint32_t orv = 0;
+    for (int t = t0; t < t1; ++t) {
     const int tx = t % P.tiles_x;
     const int ty = (t / P.tiles_x) % P.tiles_y;
     const int tz = t / (P.tiles_x * P.tiles_y);
     const int zs = P.e0 + tz * P.zc;
     const int ze = min(zs + P.zc, P.e1);
 
-    uint32_t orv = 0;
     // Per loaded row: byte offsets of x and of x-1 (clamped into the row) and
     // the row's byte offset within a plane.  NIN == 1: row r is the 64-wide
     // x-segment seg0 + r of the single in-plane axis.
@@ -474,6 +482,7 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
             walk<T, NIN, R, MODE, false, PD>(P, zs, ze, vx, vxl, soff, em, orv);
         }
     }
+    }  // tiles
 
     if constexpr (M != 256) {
         if (orv >= (uint32_t)M) atomicOr(P.status, kStatusRange);
@@ -571,6 +580,7 @@ static KParams make_params(const IntJob &job, const IntTiling &tl, int32_t *part
     p.tiles_x = (int32_t)((job.view.n2 + xw - 1) / xw);
     p.tiles_y = nin == 1 ? 1 : (int32_t)((job.view.n1 + (int64_t)tl.rows * tl.wy - 1) / ((int64_t)tl.rows * tl.wy));
     p.tiles_z = (job.e1 - job.e0 + tl.zc - 1) / tl.zc;
+    p.per_wg = tl.per_wg > 0 ? tl.per_wg : 1;
     p.partial = partial;
     p.status = status;
     p.zero_vcec = zero_vcec;

@@ -63,7 +63,8 @@ struct IntTiling {
     int pd;        // planes of raw loads in flight ahead of the compared plane
     int wx, wy;    // waves per workgroup along x and along y
     int zc;        // planes per tile
-    int grid;      // workgroups = tiles (one tile per workgroup)
+    int per_wg;    // tiles walked by one workgroup (consecutive, one histogram)
+    int grid;      // workgroups = ceil(tiles / per_wg)
 };
 
 // Device scratch of one (device, stream) pair.

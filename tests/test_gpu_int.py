@@ -125,6 +125,18 @@ def test_repeated_calls_reuse_workspace(ecc):
         check(ecc, gen.cfg_u14_value_noise(shape, seed=11), "u14")
 
 
+@pytest.mark.parametrize("shape,dtype", [((3, 5000, 700), "u14"), ((4, 2048, 2048), "u8"), ((20, 3000, 1000), "u14"),
+                                         ((3, 2100000), "u8")], ids=str)
+def test_several_tiles_per_workgroup(ecc, shape, dtype):
+    """Planes with more tiles than the device holds workgroups: each workgroup
+    walks a run of consecutive tiles into one histogram (2500 tiles in runs of
+    3 with a short last run; 2048 in runs of 2 over a permuted grid; 1500 in
+    runs of 2 over an unpermuted grid; a 2-D image of 1026 row segments)."""
+    print(f"\n[gpu] several tiles per workgroup {shape} {dtype}", flush=True)
+    img = gen.cfg_u14_value_noise(shape, seed=12) if dtype == "u14" else gen.iid(shape, 8, seed=12)
+    check(ecc, img, dtype)
+
+
 def test_full_size_1024_cubed_u14(ecc):
     """The 3-D 14-bit value-noise volume of 1024^3 voxels (seed 1), compared in full."""
     print("\n[gpu] 1024^3 u14 value noise seed 1: generating", flush=True)
