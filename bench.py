@@ -10,9 +10,10 @@ Prints ONE JSON line: GVoxel/s over the timed steps, the roofline of the
 dominant kernel (HBM bytes it must read / its measured average duration, HIP
 events on its launch stream) and the CPU oracle timed on a bounded sample of
 the same volume on this host.  Under "legs": the other workloads of the path
-(serving mix at a p99 latency bound, 4-D float32, host-staged streaming
-against the measured host-to-device copy rate, the 2-D 256^2 uint8 latency),
-each timed after the headline steps.
+(serving mix at a p99 latency bound, 4-D float32, host-staged streaming of
+8192^2 x 1024 against the measured host-to-device copy rate, the
+2600 x 14450^2 volume made and streamed slab by slab on the device, the 2-D
+256^2 uint8 latency), each timed after the headline steps.
 """
 from __future__ import annotations
 
@@ -143,40 +144,118 @@ def leg_float(reps: int):
             "gvoxel_per_s": round(img.size / ms / 1e6, 3)}
 
 
-def leg_stream_host(planes_per_chunk: int, chunks: int, side: int):
-    """Host-staged streaming: pinned chunks of side x side 14-bit planes pushed
-    through ecc_stream_push_chunk, against the hipMemcpyAsync host-to-device
-    rate of the same pinned chunk measured in the same run."""
+def leg_stream_host(planes: int, side: int, chunk_planes: int, ring: int):
+    """Host-staged streaming of the 3-D 14-bit value-noise volume of
+    planes x side x side voxels (seed 2): chunks of chunk_planes planes in
+    pinned host memory pushed through ecc_stream_push_chunk (double-buffered
+    hipMemcpyAsync inside the library), against the host-to-device copy rate
+    of the same pinned chunks measured in the same run.  The host bytes are
+    made by the device generator and copied down into a ring of `ring` pinned
+    chunks; each refill happens outside the timed intervals, which cover the
+    pushes of one ring and the completion of their kernels."""
     import numpy as np
     import torch
     import gen
     import paper_1705_02045_amd as ecc
-    chunk = gen.cfg_u14_value_noise((planes_per_chunk, side, side), seed=2)
-    pinned = torch.from_numpy(chunk.view(np.int16)).pin_memory()
-    dst = torch.empty_like(pinned, device="cuda")
-    dst.copy_(pinned, non_blocking=True)
+    shape = (planes, side, side)
+    chunk_bytes = chunk_planes * side * side * 2
+    pinned = [torch.empty((chunk_planes, side, side), dtype=torch.int16).pin_memory() for _ in range(ring)]
+    dev = torch.empty((chunk_planes, side, side), dtype=torch.int16, device="cuda")
+    ent = max(gen.dev_table_entries(shape, z0, min(z0 + chunk_planes, planes)) for z0 in range(0, planes, chunk_planes))
+    table = torch.empty(ent, dtype=torch.int16, device="cuda")
+    cs = torch.cuda.current_stream().cuda_stream
+    # host-to-device rate of the pinned chunks
+    for p in pinned:
+        dev.copy_(p, non_blocking=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(chunks):
-        dst.copy_(pinned, non_blocking=True)
+    for _ in range(2):
+        for p in pinned:
+            dev.copy_(p, non_blocking=True)
     torch.cuda.synchronize()
-    h2d = chunks * pinned.numel() * 2 / (time.perf_counter() - t0)
-    del dst
-    host = pinned.numpy()
-    shape = (planes_per_chunk * chunks, side, side)
+    h2d = 2 * ring * chunk_bytes / (time.perf_counter() - t0)
     st = ecc.Stream(shape, "u14")
-    st.push(host[:1])
-    st.abort()
+    timed = 0.0
+    for r0 in range(0, planes, ring * chunk_planes):
+        spans = []
+        for k in range(ring):
+            z0 = r0 + k * chunk_planes
+            if z0 >= planes:
+                break
+            z1 = min(z0 + chunk_planes, planes)
+            gen.cfg_u14_value_noise_dev(dev.data_ptr(), shape, 2, z0, z1, table.data_ptr(), ent, stream=cs)
+            pinned[k][: z1 - z0].copy_(dev[: z1 - z0])
+            spans.append(z1 - z0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k, n in enumerate(spans):
+            st.push(pinned[k], n)
+        torch.cuda.synchronize()
+        timed += time.perf_counter() - t0
     t0 = time.perf_counter()
-    st = ecc.Stream(shape, "u14")
-    for _ in range(chunks):
-        st.push(host)
     chi = st.finish()
-    dt = time.perf_counter() - t0
-    rate = chunks * pinned.numel() * 2 / dt
-    return {"shape": list(shape), "chunk_planes": planes_per_chunk, "chunk_bytes": int(pinned.numel() * 2),
+    timed += time.perf_counter() - t0
+    total = planes * side * side * 2
+    rate = total / timed
+    return {"shape": list(shape), "seed": 2, "chunk_planes": chunk_planes, "chunk_bytes": chunk_bytes,
+            "pinned_ring_chunks": ring, "bytes": total, "timed_s": round(timed, 3),
             "stream_gb_per_s": round(rate / 1e9, 2), "h2d_gb_per_s": round(h2d / 1e9, 2),
             "pcie_frac": round(rate / h2d, 4), "gvoxel_per_s": round(rate / 2e9, 2), "chi_last": int(chi[-1])}
+
+
+def leg_stream_device(shape, slab: int):
+    """The 3-D 14-bit value-noise volume of shape (seed 2) made slab by slab in
+    device memory by the device generator and streamed through
+    ecc_stream_push_chunk (device chunks, read in place), all on one stream.
+    HIP events around each push time the ECC work alone; the whole loop
+    (generation included) gives the end-to-end rate."""
+    import torch
+    import gen
+    import paper_1705_02045_amd as ecc
+    planes = shape[0]
+    plane = shape[1] * shape[2]
+    ent = max(gen.dev_table_entries(shape, z0, min(z0 + slab, planes)) for z0 in range(0, planes, slab))
+    table = torch.empty(ent, dtype=torch.int16, device="cuda")
+    bufs = [torch.empty((slab,) + tuple(shape[1:]), dtype=torch.int16, device="cuda") for _ in range(2)]
+    stream = torch.cuda.current_stream()
+    cs = stream.cuda_stream
+    # first slab once, untimed: library and allocator set-up
+    gen.cfg_u14_value_noise_dev(bufs[0].data_ptr(), shape, 2, 0, slab, table.data_ptr(), ent, stream=cs)
+    st = ecc.Stream(shape, "u14")
+    st.push(bufs[0], 1)
+    st.abort()
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    st = ecc.Stream(shape, "u14")
+    last = time.perf_counter()
+    for k, z0 in enumerate(range(0, planes, slab)):
+        z1 = min(z0 + slab, planes)
+        b = bufs[k % 2]
+        gen.cfg_u14_value_noise_dev(b.data_ptr(), shape, 2, z0, z1, table.data_ptr(), ent, stream=cs)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        st.push(b, z1 - z0)
+        e1.record(stream)
+        evs.append((e0, e1))
+        if time.perf_counter() - last > 20:
+            log(f"[bench] stream_device: planes {z1}/{planes}")
+            last = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    chi = st.finish()
+    e1 = torch.cuda.Event(enable_timing=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    evs.append((e0, e1))
+    ecc_s = sum(a.elapsed_time(b) for a, b in evs) / 1e3
+    vox = planes * plane
+    return {"shape": list(shape), "seed": 2, "slab_planes": slab, "voxels": vox, "bytes": 2 * vox,
+            "ecc_s": round(ecc_s, 4), "end_to_end_s": round(wall, 4),
+            "gvoxel_per_s": round(vox / ecc_s / 1e9, 2), "hbm_frac": round(2 * vox / ecc_s / (HBM_PEAK_GBS * 1e9), 4),
+            "end_to_end_gvoxel_per_s": round(vox / wall / 1e9, 2), "chi_last": int(chi[-1])}
 
 
 def leg_small_2d(reps: int):
@@ -209,7 +288,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, default=1024, help="edge of the cubic volume")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget; 0 skips it")
-    ap.add_argument("--legs", default="serving,float,stream_host,small_2d",
+    ap.add_argument("--legs", default="serving,float,stream_host,stream_device,small_2d",
                     help="further workloads reported under 'legs' (comma list, or 'none')")
     ap.add_argument("--serve-requests", type=int, default=1024)
     ap.add_argument("--serve-slo-ms", type=float, default=10.0)
@@ -285,7 +364,9 @@ def main():
         elif leg == "float":
             legs[leg] = leg_float(5)
         elif leg == "stream_host":
-            legs[leg] = leg_stream_host(8, 4, 8192)
+            legs[leg] = leg_stream_host(1024, 8192, 16, 4)
+        elif leg == "stream_device":
+            legs[leg] = leg_stream_device((2600, 14450, 14450), 64)
         elif leg == "small_2d":
             legs[leg] = leg_small_2d(200)
         else:

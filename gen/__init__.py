@@ -94,6 +94,54 @@ def value_noise_f32(shape, sigma: float, seed: int, lshift: int = 3, z0: int = 0
     return out
 
 
+# ------------------------------------------------------ device generator
+_DEV = None
+
+
+def dev_lib() -> ctypes.CDLL:
+    """libeccgen_dev.so: the integer value noise made in device memory (same bytes)."""
+    global _DEV
+    if _DEV is None:
+        path = _HERE / "libeccgen_dev.so"
+        if not path.exists():
+            raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(str(path))
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.eccgen_dev_table_entries.restype = ctypes.c_int
+        L.eccgen_dev_table_entries.argtypes = [ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                               i64p]
+        L.eccgen_dev_value_noise.restype = ctypes.c_int
+        L.eccgen_dev_value_noise.argtypes = [ctypes.c_uint64, ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                             ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+        _DEV = L
+    return _DEV
+
+
+def dev_table_entries(shape, z0: int, z1: int, lshift: int = 4) -> int:
+    """uint16 entries of the lattice table for planes [z0, z1) of a 3-D image."""
+    n = ctypes.c_int64(0)
+    if dev_lib().eccgen_dev_table_entries(len(shape), _dims(shape), lshift, z0, z1, ctypes.byref(n)):
+        raise ValueError("eccgen_dev_table_entries: bad arguments")
+    return n.value
+
+
+def value_noise_dev(out_ptr: int, shape, bits: int, amp: int, seed: int, z0: int, z1: int, table_ptr: int,
+                    table_entries: int, lshift: int = 4, elem: int = 2, stream: int = 0) -> None:
+    """Enqueues planes [z0, z1) of the 3-D integer value noise into device
+    memory at out_ptr (the bytes value_noise() makes), on HIP stream `stream`."""
+    rc = dev_lib().eccgen_dev_value_noise(seed, len(shape), _dims(shape), lshift, bits, amp, z0, z1, out_ptr, elem,
+                                          table_ptr, table_entries, stream or None)
+    if rc:
+        raise ValueError(f"eccgen_dev_value_noise failed ({rc})")
+
+
+def cfg_u14_value_noise_dev(out_ptr: int, shape, seed: int, z0: int, z1: int, table_ptr: int, table_entries: int,
+                            stream: int = 0) -> None:
+    """Device-made planes [z0, z1) of cfg_u14_value_noise(shape, seed)."""
+    value_noise_dev(out_ptr, shape, 14, 64, seed, z0, z1, table_ptr, table_entries, lshift=4, elem=2, stream=stream)
+
+
 # ------------------------------------------------------ numpy restatements
 def mix64_np(z: np.ndarray) -> np.ndarray:
     z = np.asarray(z, dtype=np.uint64)

@@ -47,3 +47,18 @@ def test_ranges_and_statistics():
     assert u.shape == (256, 256) and u.dtype == np.uint8 and u.min() == 0 and u.max() == 255
     f = gen.cfg_f32_value_noise((16, 16, 16, 16))
     assert f.dtype == np.float32 and -0.2 < f.min() and f.max() < 1.2
+
+
+def test_device_generator_library_exports():
+    """libeccgen_dev.so loads here (no GPU needed) and sizes its lattice table:
+    node planes z0 >> 4 .. ((z1 - 1) >> 4) + 1, each ((n1 - 1) >> 4) + 2 by
+    ((n2 - 1) >> 4) + 2 nodes."""
+    L = gen.dev_lib()
+    assert hasattr(L, "eccgen_dev_value_noise")
+    assert gen.dev_table_entries((2600, 14450, 14450), 0, 64) == 5 * 905 * 905
+    assert gen.dev_table_entries((2600, 14450, 14450), 100, 200) == (12 - 6 + 2) * 905 * 905
+    assert gen.dev_table_entries((5, 1, 1), 4, 5) == 2 * 2 * 2
+    with pytest.raises(ValueError):
+        gen.dev_table_entries((5, 6), 0, 5)  # 3-D only
+    with pytest.raises(ValueError):
+        gen.dev_table_entries((5, 6, 7), 3, 3)  # empty range
