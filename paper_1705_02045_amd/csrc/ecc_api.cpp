@@ -160,15 +160,25 @@ static int env_int(const char *name, int dflt) {
 }
 
 // Tuning overrides (measurement only): ECC_INT_ROWS, ECC_INT_MODE, ECC_INT_PD, ECC_INT_WX,
-// ECC_INT_WAVES, ECC_INT_TILES_PER_CU.
+// ECC_INT_WAVES, ECC_INT_TILES_PER_CU, ECC_INT_TILE_STRIDE.
 IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
     IntTiling t{};
-    t.rows = env_int("ECC_INT_ROWS", 2);
+    // Launch size picks rows per wave and tiles per CU (measured on MI355X):
+    // below 256 MiB four tiles per CU are fastest, above it eight.  From
+    // 4 GiB on (e.g. 62 planes of 8192^2 or of 14450^2) four rows per wave
+    // run at about 2.8 TB/s where two rows reach 2.0-2.4; below 2 GiB two
+    // rows are faster.  Likely cause: four rows keep half as many workgroups
+    // in flight, so fewer distinct 2 MiB pages per plane step need
+    // translating once a plane spans many pages.
+    const int64_t launch_bytes = planes * (int64_t)v.n1 * v.n2 * (dtype == ECC_U8 ? 1 : 2);
+    const bool big = launch_bytes >= ((int64_t)4 << 30);
+    t.rows = env_int("ECC_INT_ROWS", big ? 4 : 2);
     t.mode = env_int("ECC_INT_MODE", 0);
     t.pd = env_int("ECC_INT_PD", 1);
     const int cus = device_cu_count();
     const int max_waves = env_int("ECC_INT_WAVES", 16);
-    const int tiles_per_cu = env_int("ECC_INT_TILES_PER_CU", 4);
+    const int tiles_per_cu =
+        env_int("ECC_INT_TILES_PER_CU", launch_bytes < ((int64_t)256 << 20) ? 4 : (t.rows == 4 ? 16 : 8));
     int64_t tiles_xy;
     if (v.nin == 1) {
         const int64_t segs = (v.n2 + (int64_t)kWave * t.rows - 1) / ((int64_t)kWave * t.rows);
@@ -185,8 +195,9 @@ IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
         tiles_xy = ((xs + t.wx - 1) / t.wx) * ((ys + t.wy - 1) / t.wy);
     }
     // split axis 0 until there are about tiles_per_cu tiles per CU; planes
-    // with more tiles than that get several consecutive tiles per workgroup,
-    // so the per-workgroup rows stay about tiles_per_cu per CU
+    // with more tiles than that get several tiles per workgroup (strided, so
+    // the resident workgroups hold neighbouring tiles), so the per-workgroup
+    // rows stay about tiles_per_cu per CU
     const int64_t target = (int64_t)cus * tiles_per_cu;
     int64_t tz = (target + tiles_xy - 1) / tiles_xy;
     if (tz < 1) tz = 1;
@@ -197,6 +208,7 @@ IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
     const int64_t tiles = tiles_xy * ((planes + zc - 1) / zc);
     const int64_t per = tiles > target ? (tiles + target - 1) / target : 1;
     t.per_wg = (int)per;
+    t.tile_stride = env_int("ECC_INT_TILE_STRIDE", 0);
     t.grid = (int)((tiles + per - 1) / per);
     return t;
 }
@@ -213,6 +225,7 @@ static int enqueue_int(const void *image_dev, const IntView &v, int dtype, int64
     if (rc) return rc;
     IntJob job{};
     job.src.base = (const uint8_t *)image_dev;
+    job.src.lo_base = job.src.base;
     job.src.plane_bytes = (int64_t)v.n1 * v.n2 * (int64_t)eb;
     job.view = v;
     job.e0 = 0;

@@ -248,6 +248,7 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
             }
             IntJob job{};
             job.src.base = (const uint8_t *)jobs[j].image;
+            job.src.lo_base = job.src.base;
             job.src.plane_bytes = (int64_t)P.view.n1 * P.view.n2 * (int64_t)elem_bytes(jobs[j].dtype);
             job.view = P.view;
             job.e0 = 0;

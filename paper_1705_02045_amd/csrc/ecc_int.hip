@@ -42,7 +42,8 @@ struct KParams {
     int32_t lo_inf, hi_inf;
     int32_t zc;
     int32_t tiles_x, tiles_y, tiles_z;
-    int32_t per_wg;  // consecutive tiles walked by one workgroup into one histogram
+    int32_t per_wg;       // tiles per workgroup (at most)
+    int32_t tile_stride;  // 0: consecutive runs of per_wg tiles; 1: strided by the grid
     int32_t wx, wy;
     int32_t *partial;
     uint32_t *status;
@@ -269,7 +270,8 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
             b[rr] = load_elem(rs, vxl[rr], soff[rr], ESZ);
         }
     };
-    auto load_plane = [&](int p, uint32_t (&a)[NR], uint32_t (&b)[NR]) { load_at(P.src.base + p * pb, a, b); };
+    auto plane_ptr = [&](int p) { return (p < 0 ? P.src.lo_base : P.src.base) + p * pb; };
+    auto load_plane = [&](int p, uint32_t (&a)[NR], uint32_t (&b)[NR]) { load_at(plane_ptr(p), a, b); };
     auto range_acc = [&](const uint32_t (&a)[NR]) {
         // rows owned by this wave (the collar row is checked by its owner)
 #pragma unroll
@@ -324,7 +326,7 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
     // into the buffer that held plane z+u, turn plane z+u+1 into fields and
     // compare.  `nxt` points at the next plane to load.  Steady state: every
     // plane touched lies inside the tile.
-    const uint8_t *nxt = P.src.base + (zs + 1 + PD) * pb;
+    const uint8_t *nxt = plane_ptr(zs + 1 + PD);  // zs >= -1, so this plane is in `base`
     int z = zs;
     for (; z + U + PD < ze; z += U) {
 #pragma unroll
@@ -370,8 +372,8 @@ constexpr int kWavesPerEU() {
 }
 
 // The tiles of one workgroup of one image: b = the workgroup's index among
-// the image's G workgroups.  Writes the counts of its tiles to row b of
-// P.partial.
+// the image's G workgroups (G <= tiles).  Writes the counts of its tiles to
+// row b of P.partial.
 template <typename T, int M, int NIN, int R, int MODE, int PD>
 __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const int b, const int G) {
     using W = Walker<NIN, R>;
@@ -403,13 +405,15 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
     const int32_t n1 = P.n1, n2 = P.n2;
 
     // workgroup b (permuted: the workgroups of one XCD take neighbouring
-    // ranges) walks tiles [t0, t1) into its histogram
+    // indices) walks its tiles into one histogram: a run of per_wg
+    // consecutive tiles, or (tile_stride) tiles bp, bp + G, bp + 2G, ...
     const int bp = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
     const int ntiles = P.tiles_x * P.tiles_y * P.tiles_z;
-    const int t0 = bp * P.per_wg;
-    const int t1 = min(t0 + P.per_wg, ntiles);
+    const int tstep = P.tile_stride ? G : 1;
+    const int t0 = P.tile_stride ? bp : bp * P.per_wg;
+    const int t1 = P.tile_stride ? ntiles : min(t0 + P.per_wg, ntiles);
     uint32_t orv = 0;
-    for (int t = t0; t < t1; ++t) {
+    for (int t = t0; t < t1; t += tstep) {
     const int tx = t % P.tiles_x;
     const int ty = (t / P.tiles_x) % P.tiles_y;
     const int tz = t / (P.tiles_x * P.tiles_y);
@@ -581,6 +585,7 @@ static KParams make_params(const IntJob &job, const IntTiling &tl, int32_t *part
     p.tiles_y = nin == 1 ? 1 : (int32_t)((job.view.n1 + (int64_t)tl.rows * tl.wy - 1) / ((int64_t)tl.rows * tl.wy));
     p.tiles_z = (job.e1 - job.e0 + tl.zc - 1) / tl.zc;
     p.per_wg = tl.per_wg > 0 ? tl.per_wg : 1;
+    p.tile_stride = tl.tile_stride;
     p.partial = partial;
     p.status = status;
     p.zero_vcec = zero_vcec;

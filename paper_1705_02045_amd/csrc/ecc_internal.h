@@ -33,8 +33,13 @@ int hip_fail(hipError_t e, const char *what);
 // Source of axis-0 planes for one launch: plane p starts at
 // base + p * plane_bytes (one contiguous buffer, so the kernel advances a
 // plane pointer instead of recomputing it).
+// Plane p of a launch (buffer coordinates) is read at base + p * plane_bytes
+// for p >= 0 and at lo_base + p * plane_bytes for p < 0: a launch can start in
+// a second buffer that holds the planes just before `base` (the carried
+// planes of a stream).  lo_base = base when there is no such buffer.
 struct PlaneSrc {
     const uint8_t *base;
+    const uint8_t *lo_base;
     int64_t plane_bytes;
 };
 
@@ -63,7 +68,8 @@ struct IntTiling {
     int pd;        // planes of raw loads in flight ahead of the compared plane
     int wx, wy;    // waves per workgroup along x and along y
     int zc;        // planes per tile
-    int per_wg;    // tiles walked by one workgroup (consecutive, one histogram)
+    int per_wg;    // tiles walked by one workgroup into one histogram (at most)
+    int tile_stride;  // 0: a workgroup walks per_wg consecutive tiles; 1: tiles strided by the grid
     int grid;      // workgroups = ceil(tiles / per_wg)
 };
 

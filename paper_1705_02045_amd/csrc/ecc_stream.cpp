@@ -2,13 +2,10 @@
 // "Processing one Chunk"): the image arrives as consecutive chunks of whole
 // axis-0 planes.  Each chunk's last plane waits for the next chunk, which
 // holds its upper collar.  The changes of a plane need the planes on either
-// side of it, so a chunk [f, f+n) is split in two launches over contiguous
-// buffers:
-//  - the seam: the deferred plane f-1 and plane f, read from a small device
-//    buffer holding the last two planes of the previous chunk followed by
-//    copies of the chunk's first two planes;
-//  - the body: planes [f+1, f+n-1) (to the end of the image on the last
-//    chunk), read from the chunk itself.
+// side of it, so the launch of a chunk [f, f+n) covers planes [f-1, f+n-1)
+// (to the end of the image on the last chunk) and reads planes f-2 and f-1
+// from a two-plane carry buffer (the previous push's last planes), the rest
+// from the chunk itself.
 // Counts accumulate on the device; the prefix sum is taken once.
 //
 // Host chunks go through two device staging buffers filled on a copy stream
@@ -28,9 +25,9 @@ struct ecc_stream {
     int64_t plane_bytes = 0;
     int64_t pushed = 0;   // image planes received
     int64_t emitted = 0;  // image planes whose changes were added
-    // seam buffers of four planes: [0, ncarry) hold image planes
-    // [pushed - ncarry, pushed); a push appends the chunk's first planes
-    uint8_t *seam[2] = {nullptr, nullptr};
+    // carry buffers of two planes: [0, ncarry) hold image planes
+    // [pushed - ncarry, pushed)
+    uint8_t *carry_buf[2] = {nullptr, nullptr};
     int cur = 0;
     int ncarry = 0;
     // staging for host chunks
@@ -61,7 +58,7 @@ void destroy(ecc_stream *st) {
     if (st->compute) (void)hipStreamSynchronize(st->compute);
     if (st->copy) (void)hipStreamSynchronize(st->copy);
     for (int i = 0; i < 2; ++i) {
-        if (st->seam[i]) (void)hipFree(st->seam[i]);
+        if (st->carry_buf[i]) (void)hipFree(st->carry_buf[i]);
         if (st->stage[i]) (void)hipFree(st->stage[i]);
         if (st->ready[i]) (void)hipEventDestroy(st->ready[i]);
         if (st->released[i]) (void)hipEventDestroy(st->released[i]);
@@ -88,70 +85,52 @@ bool is_device_ptr(const void *p) {
 
 int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
 
-// Adds the changes of image planes [lo, hi) of `chunk` (image planes
-// [f, f + n)) and of the seam, and keeps the last two planes for the next push.
+// Adds the changes of image planes [emitted, hi) of a push whose chunk holds
+// image planes [f, f + n), in one launch: buffer plane p is image plane f + p,
+// read from the chunk for p >= 0 and from the carry buffer (the previous
+// image planes [f - a, f)) for p < 0.  Then keeps the last two image planes
+// for the next push.
 int run_chunk(ecc_stream *st, const uint8_t *chunk, int64_t f, int64_t n, int64_t hi) {
     const int64_t pb = st->plane_bytes;
     const int64_t n0 = st->view.n0;
     const int a = st->ncarry;
-    const int64_t k2 = min64(n, 2);
-    uint8_t *seam = st->seam[st->cur];
-    ECC_HIP(hipMemcpyAsync(seam + a * pb, chunk, (size_t)(k2 * pb), hipMemcpyDeviceToDevice, st->compute));
-
-    const int64_t lo = st->emitted;
-    const int64_t body_lo = f == 0 ? 0 : min64(f + 1, hi);
-    IntJob jobs[2];
-    IntTiling tl[2];
-    int njobs = 0;
-    if (lo < body_lo) {  // seam buffer plane j is image plane f - a + j
-        IntJob &j = jobs[njobs];
-        j = IntJob{};
-        j.src.base = seam;
-        j.e0 = (int32_t)(lo - (f - a));
-        j.e1 = (int32_t)(body_lo - (f - a));
-        j.lo_inf = lo == 0;
-        j.hi_inf = body_lo == n0;
-        tl[njobs++] = choose_int_tiling(st->view, st->dtype, body_lo - lo);
-    }
-    if (body_lo < hi) {  // chunk plane j is image plane f + j
-        IntJob &j = jobs[njobs];
-        j = IntJob{};
+    uint8_t *carry = st->carry_buf[st->cur];
+    const int64_t lo = st->emitted;  // f - 1, or 0 on the first push
+    if (lo < hi) {
+        IntJob j{};
         j.src.base = chunk;
-        j.e0 = (int32_t)(body_lo - f);
+        j.src.lo_base = carry + a * pb;
+        j.src.plane_bytes = pb;
+        j.view = st->view;
+        j.dtype = st->dtype;
+        j.e0 = (int32_t)(lo - f);
         j.e1 = (int32_t)(hi - f);
-        j.lo_inf = body_lo == 0;
-        j.hi_inf = hi == n0;
-        tl[njobs++] = choose_int_tiling(st->view, st->dtype, hi - body_lo);
-    }
-    int rows = 0;
-    for (int i = 0; i < njobs; ++i) rows += tl[i].grid;
-    if (rows > 0) {
-        int rc = ensure_bytes((void **)&st->partial, &st->partial_bytes, (size_t)rows * st->m * sizeof(int32_t));
+        j.lo_inf = lo == 0;  // else plane lo - 1 = f - 2 is carry plane a - 2 (a == 2)
+        j.hi_inf = hi == n0;  // else plane hi = f + n - 1 is the chunk's last plane
+        const IntTiling tl = choose_int_tiling(st->view, st->dtype, hi - lo);
+        int rc = ensure_bytes((void **)&st->partial, &st->partial_bytes, (size_t)tl.grid * st->m * sizeof(int32_t));
         if (rc) return rc;
         rc = ensure_bytes((void **)&st->mstage, &st->mstage_bytes,
-                          (size_t)merge_stage_rows(rows) * st->m * sizeof(int64_t));
+                          (size_t)merge_stage_rows(tl.grid) * st->m * sizeof(int64_t));
         if (rc) return rc;
-        int row0 = 0;
-        for (int i = 0; i < njobs; ++i) {
-            jobs[i].src.plane_bytes = pb;
-            jobs[i].view = st->view;
-            jobs[i].dtype = st->dtype;
-            rc = launch_int_partial(jobs[i], tl[i], st->partial + (size_t)row0 * st->m, st->status, nullptr,
-                                    st->compute);
-            if (rc) return rc;
-            row0 += tl[i].grid;
-        }
-        rc = launch_merge(st->partial, rows, st->m, st->mstage, st->vcec, true, false, nullptr, st->status, nullptr,
-                          st->compute);
+        rc = launch_int_partial(j, tl, st->partial, st->status, nullptr, st->compute);
+        if (rc) return rc;
+        rc = launch_merge(st->partial, tl.grid, st->m, st->mstage, st->vcec, true, false, nullptr, st->status,
+                          nullptr, st->compute);
         if (rc) return rc;
     }
 
-    // next carry: the last min(a + n, 2) image planes, from the chunk when it
-    // has two planes, else from the seam (which then holds all of them)
+    // next carry: image planes [f + n - keep, f + n), keep = min(a + n, 2)
     const int nxt = st->cur ^ 1;
     const int keep = (int)min64(a + n, 2);
-    const uint8_t *src = n >= 2 ? chunk + (n - 2) * pb : seam + (a + k2 - keep) * pb;
-    ECC_HIP(hipMemcpyAsync(st->seam[nxt], src, (size_t)(keep * pb), hipMemcpyDeviceToDevice, st->compute));
+    uint8_t *dst = st->carry_buf[nxt];
+    if (n >= 2) {
+        ECC_HIP(hipMemcpyAsync(dst, chunk + (n - 2) * pb, (size_t)(2 * pb), hipMemcpyDeviceToDevice, st->compute));
+    } else {  // n == 1: the last carried plane (if any), then the chunk's plane
+        if (keep == 2)
+            ECC_HIP(hipMemcpyAsync(dst, carry + (a - 1) * pb, (size_t)pb, hipMemcpyDeviceToDevice, st->compute));
+        ECC_HIP(hipMemcpyAsync(dst + (keep - 1) * pb, chunk, (size_t)pb, hipMemcpyDeviceToDevice, st->compute));
+    }
     st->cur = nxt;
     st->ncarry = keep;
     return ECC_OK;
@@ -222,8 +201,8 @@ int ecc_stream_begin(const ecc_dims *full_dims, ecc_dtype dtype, void *stream, e
     hipError_t e = hipStreamCreateWithFlags(&st->copy, hipStreamNonBlocking);
     if (e != hipSuccess) return fail(hip_fail(e, "hipStreamCreate"));
     for (int i = 0; i < 2; ++i) {
-        if ((e = hipMalloc(&st->seam[i], (size_t)st->plane_bytes * 4)) != hipSuccess)
-            return fail(hip_fail(e, "hipMalloc(seam)"));
+        if ((e = hipMalloc(&st->carry_buf[i], (size_t)st->plane_bytes * 2)) != hipSuccess)
+            return fail(hip_fail(e, "hipMalloc(carry)"));
         if ((e = hipEventCreateWithFlags(&st->ready[i], hipEventDisableTiming)) != hipSuccess)
             return fail(hip_fail(e, "hipEventCreate"));
         if ((e = hipEventCreateWithFlags(&st->released[i], hipEventDisableTiming)) != hipSuccess)

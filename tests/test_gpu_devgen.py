@@ -57,19 +57,22 @@ def test_device_generator_matches_host_full_width(ecc, z0, z1):
     assert bool((got == torch.from_numpy(want.view(np.int16)).cuda()).all())
 
 
-def stream_device(ecc, shape, seed, slab, planes=None):
+def stream_device(ecc, shape, seed, slab, planes=None, cuts=None):
     """Streams planes [0, planes) of the value-noise volume of `shape` from
-    device-made slabs; returns (curve, smallest value seen)."""
+    device-made slabs (of `slab` planes, or between the given cuts); returns
+    (curve, smallest value seen)."""
     planes = shape[0] if planes is None else planes
     full = (planes,) + tuple(shape[1:])
-    ent = max(gen.dev_table_entries(shape, z0, min(z0 + slab, planes)) for z0 in range(0, planes, slab))
+    cuts = list(range(0, planes, slab)) + [planes] if cuts is None else cuts
+    spans = list(zip(cuts[:-1], cuts[1:]))
+    ent = max(gen.dev_table_entries(shape, z0, z1) for z0, z1 in spans)
+    width = max(z1 - z0 for z0, z1 in spans)
     table = torch.empty(ent, dtype=torch.int16, device="cuda")
-    bufs = [torch.empty((slab,) + tuple(shape[1:]), dtype=torch.int16, device="cuda") for _ in range(2)]
+    bufs = [torch.empty((width,) + tuple(shape[1:]), dtype=torch.int16, device="cuda") for _ in range(2)]
     s = torch.cuda.current_stream().cuda_stream
     st = ecc.Stream(full, "u14")
     lo = None
-    for k, z0 in enumerate(range(0, planes, slab)):
-        z1 = min(z0 + slab, planes)
+    for k, (z0, z1) in enumerate(spans):
         b = bufs[k % 2]
         gen.cfg_u14_value_noise_dev(b.data_ptr(), shape, seed, z0, z1, table.data_ptr(), table.numel(), stream=s)
         m = b[: z1 - z0].amin()  # 14-bit values: the int16 view is non-negative
@@ -79,15 +82,26 @@ def stream_device(ecc, shape, seed, slab, planes=None):
 
 
 def test_stream_device_slabs_first_planes_vs_oracle(ecc):
-    """Planes [0, 9) of the 1.09 TB volume (1.88 G voxels) streamed from
-    device-made slabs of 4 planes, against the oracle on the host bytes."""
-    planes = 9
-    print("\n[gpu] streamed device slabs, first 9 planes of the TB volume", flush=True)
-    got, _ = stream_device(ecc, TB_SHAPE, TB_SEED, 4, planes)
+    """Planes [0, 11) of the 1.09 TB volume (2.3 G voxels, 4.6 GB) against the
+    oracle on the host bytes: resident (one launch of more than 4 GiB, four
+    rows per wave), streamed as 1 + 10 planes (the second launch reads its
+    first planes from the carry buffer, four rows per wave) and in slabs of
+    4 planes (two rows per wave)."""
+    planes = 11
+    print("\n[gpu] first 11 planes of the TB volume: streamed 1 + 10", flush=True)
+    got_a, _ = stream_device(ecc, TB_SHAPE, TB_SEED, 0, planes, cuts=[0, 1, planes])
+    print("[gpu] streamed in slabs of 4", flush=True)
+    got_b, _ = stream_device(ecc, TB_SHAPE, TB_SEED, 4, planes)
+    print("[gpu] resident", flush=True)
+    vol = dev_planes(TB_SHAPE, TB_SEED, 0, planes)
+    got_c = ecc.compute(vol, "u14").cpu().numpy()
+    del vol
     img = gen.cfg_u14_value_noise(TB_SHAPE, seed=TB_SEED, z0=0, z1=planes)
     print("[gpu] oracle ...", flush=True)
     ref = oracle.curve(img, m=16384)
-    assert (got == ref).all()
+    assert (got_a == ref).all()
+    assert (got_b == ref).all()
+    assert (got_c == ref).all()
     assert ref[-1] == 1
 
 
