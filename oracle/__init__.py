@@ -11,6 +11,10 @@ minimum over the voxels that contain it (sublevel set filtration), and
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` use this package.  The GPU library never imports it.
 
+``curve_max_entry`` computes the other convention for a cell's value, the
+maximum over its voxels (the literal "largest gray value" reading), by the
+same cell enumeration.
+
 Floating-point images (Section 3, "Other Ranges of Gray Values"): the curve is
 a step function over the distinct values.  NaN is rejected; -0.0 and +0.0 are
 one value (IEEE equality).  The output lists every distinct value in ascending
@@ -40,7 +44,7 @@ def lib() -> ctypes.CDLL:
             raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
         L = ctypes.CDLL(str(path))
         i64p = ctypes.POINTER(ctypes.c_int64)
-        for name in ("oracle_vcec", "oracle_curve"):
+        for name in ("oracle_vcec", "oracle_curve", "oracle_curve_max"):
             fn = getattr(L, name)
             fn.restype = ctypes.c_int
             fn.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, i64p, ctypes.c_int64,
@@ -99,6 +103,21 @@ def curve(img: np.ndarray, m: int | None = None, nthreads: int | None = None,
     rc = lib().oracle_curve(img.ctypes.data, _ELEM[img.dtype], img.ndim, dims, m,
                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                             nthreads or default_threads(), max_bytes)
+    _check(rc)
+    return out
+
+
+def curve_max_entry(img: np.ndarray, m: int | None = None, nthreads: int | None = None,
+                    max_bytes: int = 8 << 30) -> np.ndarray:
+    """The "largest value" convention: each cell's value is the maximum of f
+    over the voxels containing it; returns sum_{c: value(c) <= t} (-1)^dim c
+    for t = 0..m-1 (int64).  These cell sets are not complexes."""
+    img, dims = _prep(img)
+    m = int(m if m is not None else DEFAULT_M[img.dtype])
+    out = np.zeros(m, dtype=np.int64)
+    rc = lib().oracle_curve_max(img.ctypes.data, _ELEM[img.dtype], img.ndim, dims, m,
+                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                nthreads or default_threads(), max_bytes)
     _check(rc)
     return out
 

@@ -31,6 +31,13 @@
  * into a private int64 array, and the arrays are summed at the end.
  *
  * Element types: 1 = uint8, 2 = uint16, 4 = uint32.  Every value must be < m.
+ *
+ * Second convention (the *_max entry points): a cell's value is the MAXIMUM
+ * of f over the voxels containing it -- the literal "largest gray value among
+ * its voxels" reading of the entry value, the alternative to Sec. 2's
+ * minimum.  Its cell sets are not complexes (a face can enter after a cell it
+ * bounds), so the "curve" is the signed cell count sum_{c: value(c) <= t}
+ * (-1)^dim c, computed the same way with max in place of min.
  */
 #include <pthread.h>
 #include <stdint.h>
@@ -45,6 +52,7 @@ typedef struct {
     int64_t n[MAXD], stride[MAXD];
     int64_t m;
     int64_t q0_lo, q0_hi;
+    int use_max;                /* 0: minimum over incident voxels, 1: maximum */
     int64_t *vcec;
 } job_t;
 
@@ -77,14 +85,14 @@ static void count_cells(const job_t *j) {
                     hi[k] = b > j->n[k] - 1 ? j->n[k] - 1 : b;
                 }
             }
-            /* minimum of f over the incident voxels */
-            uint64_t best = UINT64_MAX;
+            /* minimum (or maximum) of f over the incident voxels */
+            uint64_t best = j->use_max ? 0 : UINT64_MAX;
             for (int k = 0; k < d; ++k) idx[k] = lo[k];
             for (;;) {
                 int64_t lin = 0;
                 for (int k = 0; k < d; ++k) lin += idx[k] * j->stride[k];
                 uint64_t v = load(j->img, j->elem, lin);
-                if (v < best) best = v;
+                if (j->use_max ? v > best : v < best) best = v;
                 int k = d - 1;
                 while (k >= 0 && idx[k] == hi[k]) { idx[k] = lo[k]; --k; }
                 if (k < 0) break;
@@ -134,14 +142,13 @@ int oracle_vcec_range(const void *img, int elem, int d, const int64_t *n, int64_
     return 0;
 }
 
-/* VCEC of the whole image with up to nthreads threads.  Thread count is
- * lowered so that the private arrays stay within max_bytes. */
-int oracle_vcec(const void *img, int elem, int d, const int64_t *n, int64_t m,
-                int64_t *vcec, int nthreads, int64_t max_bytes) {
+static int vcec_rule(const void *img, int elem, int d, const int64_t *n, int64_t m, int use_max,
+                     int64_t *vcec, int nthreads, int64_t max_bytes) {
     job_t base;
     memset(&base, 0, sizeof base);
     int rc = setup(&base, img, elem, d, n, m);
     if (rc) return rc;
+    base.use_max = use_max;
     int64_t layers = 2 * n[0] + 1;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
@@ -175,10 +182,26 @@ int oracle_vcec(const void *img, int elem, int d, const int64_t *n, int64_t m,
     return 0;
 }
 
+/* VCEC of the whole image with up to nthreads threads.  Thread count is
+ * lowered so that the private arrays stay within max_bytes. */
+int oracle_vcec(const void *img, int elem, int d, const int64_t *n, int64_t m,
+                int64_t *vcec, int nthreads, int64_t max_bytes) {
+    return vcec_rule(img, elem, d, n, m, 0, vcec, nthreads, max_bytes);
+}
+
 /* The curve chi(T_t), t = 0..m-1: prefix sums of the VCEC. */
 int oracle_curve(const void *img, int elem, int d, const int64_t *n, int64_t m,
                  int64_t *chi, int nthreads, int64_t max_bytes) {
     int rc = oracle_vcec(img, elem, d, n, m, chi, nthreads, max_bytes);
+    if (rc) return rc;
+    for (int64_t t = 1; t < m; ++t) chi[t] += chi[t - 1];
+    return 0;
+}
+
+/* The same with each cell's value the maximum over its voxels. */
+int oracle_curve_max(const void *img, int elem, int d, const int64_t *n, int64_t m,
+                     int64_t *chi, int nthreads, int64_t max_bytes) {
+    int rc = vcec_rule(img, elem, d, n, m, 1, chi, nthreads, max_bytes);
     if (rc) return rc;
     for (int64_t t = 1; t < m; ++t) chi[t] += chi[t - 1];
     return 0;

@@ -24,20 +24,45 @@ GOLDEN = pathlib.Path(__file__).parent / "golden"
 
 
 def load_fixture(path):
-    rec = {}
+    rec = {"rule": "min"}
     for line in path.read_text().splitlines():
         if not line.strip() or line.startswith("#"):
             continue
         key, val = line.split(":", 1)
-        rec[key.strip()] = [int(x) for x in val.split()]
+        key = key.strip()
+        rec[key] = val.strip() if key == "rule" else [int(x) for x in val.split()]
     img = np.array(rec["values"], dtype=np.uint8).reshape(rec["shape"])
-    return img, rec["m"][0], np.array(rec["chi"], dtype=np.int64)
+    return img, rec["m"][0], np.array(rec["chi"], dtype=np.int64), rec["rule"]
 
 
 @pytest.mark.parametrize("path", sorted(GOLDEN.glob("*.txt")), ids=lambda p: p.stem)
 def test_golden_fixture(path):
-    img, m, chi = load_fixture(path)
-    assert (oracle.curve(img, m=m) == chi).all()
+    img, m, chi, rule = load_fixture(path)
+    got = oracle.curve(img, m=m) if rule == "min" else oracle.curve_max_entry(img, m=m)
+    assert (got == chi).all()
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_max_entry_identity_and_closed_forms(d):
+    """Largest-value convention against the minimum one: min(M - f) = M - max f
+    over every cell's voxels, so the max-convention count up to t is the
+    complement, within the whole box (chi = 1), of the min-convention
+    complex of M - f at M - t - 1:  max_f(t) = 1 - min_{M-f}(M - t - 1)."""
+    rng = np.random.default_rng(40 + d)
+    for _ in range(6):
+        shape = tuple(int(x) for x in rng.integers(1, 6, size=d))
+        m = int(rng.integers(2, 9))
+        img = rand_img(rng, shape, m)
+        got = oracle.curve_max_entry(img, m=m)
+        inv = oracle.curve((m - 1 - img.astype(np.int64)).astype(img.dtype), m=m)
+        want = 1 - np.concatenate([inv[::-1][1:], [0]])  # want[t] = 1 - inv[M - t - 1], inv[-1] = 0
+        assert (got == want).all()
+        lo, hi = int(img.min()), int(img.max())
+        assert (got[:lo] == 0).all()
+        assert (got[hi:] == 1).all()
+        c = int(rng.integers(0, m))
+        const = np.full(shape, c, dtype=img.dtype)
+        assert (oracle.curve_max_entry(const, m=m) == (np.arange(m) >= c)).all()
 
 
 def rand_img(rng, shape, m):
