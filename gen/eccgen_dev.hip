@@ -18,7 +18,7 @@
  * Neither the node index nor i depends on n_0, so planes [z0, z1) of an image
  * are the same bytes whatever its number of planes.
  *
- * Layout: 3-D only.  Two kernels per call:
+ * Layout: 3-D only, bits + 2 * lshift <= 24.  Two kernels per call:
  *   lattice: the U values of the node planes that [z0, z1) touches, as a
  *            uint16 table [nzn][N1][N2] (caller's device buffer);
  *   voxels:  each thread makes two x-neighbours of one row (same lattice
@@ -48,9 +48,22 @@ __global__ void __launch_bounds__(256) lattice_kernel(uint64_t key1, int shift, 
         table[i] = (uint16_t)(mix64(key1 + (node0 + (uint64_t)i + 1) * GAMMA) >> shift);
 }
 
+// High 32 bits of mix64(z): only they feed the jitter.  The last product is
+// formed for its high word only: (z ^ (z >> 31)) >> 32 = h ^ (h >> 31) with
+// h = (z >> 32).
+__device__ inline uint32_t mix64_hi(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = z ^ (z >> 27);
+    const uint32_t lo = (uint32_t)z, hi = (uint32_t)(z >> 32);
+    const uint32_t h = __umulhi(lo, 0x133111EBu) + lo * 0x94D049BBu + hi * 0x133111EBu;
+    return h ^ (h >> 31);
+}
+
 struct VoxArgs {
     const uint16_t *table;
     uint64_t key2;
+    uint64_t row_step;  // GAMMA * n2 * gridDim.y: jitter counter advance per row iteration
+    int32_t dq, dr;     // gridDim.y = dq * n1 + dr
     int64_t z0;      // first generated plane
     int64_t zn0;     // first node plane held by the table
     int64_t rows;    // (z1 - z0) * n1
@@ -61,12 +74,12 @@ struct VoxArgs {
     int32_t maxv;
 };
 
+// ctr = key2 + (i + 1) * GAMMA for the voxel's C-order index i
 template <typename T>
-__device__ inline T finish_voxel(uint32_t acc, const VoxArgs &a, uint64_t gidx) {
+__device__ inline T finish_voxel(uint32_t acc, const VoxArgs &a, uint64_t ctr) {
     const int dl = 3 * a.lshift;
     const int32_t bv = (int32_t)((acc + (1u << (dl - 1))) >> dl);
-    const uint64_t hj = mix64(a.key2 + (gidx + 1) * GAMMA);
-    const int32_t jit = (int32_t)(((hj >> 32) * (uint64_t)(2 * a.amp + 1)) >> 32) - a.amp;
+    const int32_t jit = (int32_t)__umulhi(mix64_hi(ctr), (uint32_t)(2 * a.amp + 1)) - a.amp;
     int32_t v = bv + jit;
     v = v < 0 ? 0 : (v > a.maxv ? a.maxv : v);
     return (T)v;
@@ -81,9 +94,20 @@ __global__ void __launch_bounds__(256) voxel_kernel(VoxArgs a, T *__restrict__ o
     const int32_t xn = x >> a.lshift, rx = x & (L - 1);
     const bool two = x + 1 < a.n2;
     const int64_t plane_nodes = (int64_t)a.N1 * a.N2;
-    for (int64_t row = blockIdx.y; row < a.rows; row += gridDim.y) {
-        const int64_t zr = row / a.n1;
-        const int32_t y = (int32_t)(row - zr * a.n1);
+    // jitter counter of voxel (row, x): key2 + ((z0 * n1 + row) * n2 + x + 1) * GAMMA (mod 2^64)
+    uint64_t ctr = a.key2 + (((uint64_t)a.z0 * (uint64_t)a.n1 + blockIdx.y) * (uint64_t)a.n2 + (uint64_t)x + 1) * GAMMA;
+    // row = zr * n1 + y, advanced by gridDim.y = dq * n1 + dr per iteration
+    int64_t zr = blockIdx.y / a.n1;
+    int32_t y = (int32_t)(blockIdx.y % a.n1);
+    for (int64_t row = blockIdx.y; row < a.rows; row += gridDim.y, ctr += a.row_step) {
+        if (row != blockIdx.y) {
+            zr += a.dq;
+            y += a.dr;
+            if (y >= a.n1) {
+                y -= a.n1;
+                ++zr;
+            }
+        }
         const int64_t z = a.z0 + zr;
         const int64_t zn = z >> a.lshift;
         const uint32_t rz = (uint32_t)(z & (L - 1));
@@ -93,16 +117,18 @@ __global__ void __launch_bounds__(256) voxel_kernel(VoxArgs a, T *__restrict__ o
         const uint16_t *t01 = t00 + a.N2;
         const uint16_t *t10 = t00 + plane_nodes;
         const uint16_t *t11 = t10 + a.N2;
+        // every factor below is < 2^24 (values < 2^bits, weights <= 2^lshift,
+        // bits + 2 * lshift <= 24), so the 24-bit multiplier gives the exact
+        // 32-bit products
         const uint32_t wz0 = (uint32_t)L - rz, wz1 = rz, wy0 = (uint32_t)L - ry, wy1 = ry;
-        const uint32_t s0 = ((uint32_t)t00[0] * wy0 + (uint32_t)t01[0] * wy1) * wz0 +
-                            ((uint32_t)t10[0] * wy0 + (uint32_t)t11[0] * wy1) * wz1;
-        const uint32_t s1 = ((uint32_t)t00[1] * wy0 + (uint32_t)t01[1] * wy1) * wz0 +
-                            ((uint32_t)t10[1] * wy0 + (uint32_t)t11[1] * wy1) * wz1;
-        const uint64_t gidx = ((uint64_t)z * (uint64_t)a.n1 + (uint64_t)y) * (uint64_t)a.n2 + (uint64_t)x;
-        const T v0 = finish_voxel<T>(s0 * (uint32_t)(L - rx) + s1 * (uint32_t)rx, a, gidx);
+        const uint32_t s0 = __umul24(__umul24(t00[0], wy0) + __umul24(t01[0], wy1), wz0) +
+                            __umul24(__umul24(t10[0], wy0) + __umul24(t11[0], wy1), wz1);
+        const uint32_t s1 = __umul24(__umul24(t00[1], wy0) + __umul24(t01[1], wy1), wz0) +
+                            __umul24(__umul24(t10[1], wy0) + __umul24(t11[1], wy1), wz1);
+        const T v0 = finish_voxel<T>(__umul24(s0, L - rx) + __umul24(s1, rx), a, ctr);
         T *o = out + row * a.n2 + x;
         if (two) {
-            const T v1 = finish_voxel<T>(s0 * (uint32_t)(L - rx - 1) + s1 * (uint32_t)(rx + 1), a, gidx + 1);
+            const T v1 = finish_voxel<T>(__umul24(s0, L - rx - 1) + __umul24(s1, rx + 1), a, ctr + GAMMA);
             if constexpr (PAIRED_STORE) {
                 if constexpr (sizeof(T) == 2) {
                     *(uint32_t *)o = (uint32_t)v0 | ((uint32_t)v1 << 16);
@@ -157,7 +183,7 @@ int eccgen_dev_value_noise(uint64_t seed, int d, const int64_t *dims, int lshift
     int64_t zn0, nzn, N1, N2;
     if (!out || !table || !table_shape(d, dims, lshift, z0, z1, &zn0, &nzn, &N1, &N2)) return -1;
     if ((elem != 1 && elem != 2) || bits < 1 || bits > 8 * elem || amp < 0 || amp > (1 << 16)) return -1;
-    if (3 * lshift + bits > 32) return -1;  // corner sums stay in 32 bits
+    if (2 * lshift + bits > 24) return -1;  // interpolation factors fit the 24-bit multiplier
     const int64_t count = nzn * N1 * N2;
     if (table_entries < count) return -1;
     hipStream_t s = (hipStream_t)stream;
@@ -183,6 +209,9 @@ int eccgen_dev_value_noise(uint64_t seed, int d, const int64_t *dims, int lshift
     a.maxv = (int32_t)((1u << bits) - 1);
     const int64_t pairs = (dims[2] + 1) / 2;
     const dim3 grid((unsigned)((pairs + 255) / 256), (unsigned)(a.rows < 65535 ? a.rows : 65535));
+    a.row_step = (uint64_t)grid.y * (uint64_t)dims[2] * GAMMA;
+    a.dq = (int32_t)(grid.y / dims[1]);
+    a.dr = (int32_t)(grid.y % dims[1]);
     const bool paired = dims[2] % 2 == 0 && (uintptr_t)out % (2 * elem) == 0;
     if (elem == 2) {
         if (paired)
