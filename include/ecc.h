@@ -89,6 +89,19 @@ int ecc_threshold_count(ecc_dtype dtype, int64_t *m_out);
  *         ECC_E_BUFFER_TOO_SMALL, ECC_E_NOMEM, ECC_E_HIP, ECC_E_UNSUPPORTED. */
 int ecc_compute(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_curve *curve, void *stream);
 
+/* The other convention for a cell's entry value: the MAXIMUM of the image
+ * over the voxels containing the cell (a literal "largest gray value among
+ * its voxels" reading, in place of Sec. 2's minimum, "Sublevel Set
+ * Filtration").  chi[t] = sum of (-1)^dim c over the cells c whose maximum is
+ * <= t, for t = 0..m-1.  These cell sets are not complexes in general (a face
+ * can enter after the cell it bounds); chi[m-1] = 1 (the whole box).
+ * Computed as the change vector of m-1-v read back reversed: the cells whose
+ * maximum is t are those whose minimum of m-1-v is m-1-t.
+ * Integer dtypes only; arguments, synchronisation and errors as
+ * ecc_compute (ECC_E_UNSUPPORTED for ECC_F32 and ECC_U16). */
+int ecc_compute_max_entry(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_curve *curve,
+                          void *stream);
+
 /* Stream-ordered form for integer types with device-resident data: enqueues
  * the whole computation on `stream` and returns without synchronizing.
  *   image_dev: device pointer, prod(n) elements.

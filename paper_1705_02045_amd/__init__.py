@@ -49,6 +49,8 @@ class Curve(ctypes.Structure):
 _vp = ctypes.c_void_p
 _lib.ecc_compute.restype = ctypes.c_int
 _lib.ecc_compute.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_int, ctypes.POINTER(Curve), _vp]
+_lib.ecc_compute_max_entry.restype = ctypes.c_int
+_lib.ecc_compute_max_entry.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_int, ctypes.POINTER(Curve), _vp]
 _lib.ecc_compute_async.restype = ctypes.c_int
 _lib.ecc_compute_async.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_int, _vp, _vp, _vp]
 _lib.ecc_threshold_count.restype = ctypes.c_int
@@ -167,6 +169,24 @@ def compute(image, dtype: str | None = None):
         cv = Curve(capacity=m, count=0, chi=chi.data_ptr(), keys=None)
         _check(_lib.ecc_compute(image.data_ptr(), ctypes.byref(dims), DTYPES[dtype], ctypes.byref(cv),
                                 _stream_handle(dev)), "ecc_compute")
+        return chi
+
+
+def compute_max_entry(image, dtype: str):
+    """ecc_compute_max_entry on a CUDA tensor (integer dtypes): each cell's value
+    is the maximum over its voxels.  Returns the int64 curve on the same device."""
+    import torch
+    if not image.is_cuda:
+        raise ValueError("compute_max_entry() takes a device tensor")
+    image = image.contiguous()
+    dims = make_dims(image.shape)
+    dev = image.device
+    with torch.cuda.device(dev):
+        m = THRESHOLDS.get(dtype, 1)  # the library rejects non-integer dtypes
+        chi = torch.empty(m, dtype=torch.int64, device=dev)
+        cv = Curve(capacity=m, count=0, chi=chi.data_ptr(), keys=None)
+        _check(_lib.ecc_compute_max_entry(image.data_ptr(), ctypes.byref(dims), DTYPES[dtype], ctypes.byref(cv),
+                                          _stream_handle(dev)), "ecc_compute_max_entry")
         return chi
 
 

@@ -215,7 +215,7 @@ IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
 
 // Enqueue the whole integer computation for a device-resident image.
 static int enqueue_int(const void *image_dev, const IntView &v, int dtype, int64_t *chi_dev,
-                       uint32_t *status_out, hipStream_t stream, Workspace *ws) {
+                       uint32_t *status_out, hipStream_t stream, Workspace *ws, bool max_entry = false) {
     const int m = (int)threshold_count(dtype);
     const size_t eb = elem_bytes(dtype);
     IntTiling tl = choose_int_tiling(v, dtype, v.n0);
@@ -233,13 +233,14 @@ static int enqueue_int(const void *image_dev, const IntView &v, int dtype, int64
     job.lo_inf = 1;
     job.hi_inf = 1;
     job.dtype = dtype;
+    job.invert = max_entry ? 1 : 0;
     rc = ensure_bytes((void **)&ws->stage, &ws->stage_bytes,
                       (size_t)merge_stage_rows(tl.grid) * m * sizeof(int64_t));
     if (rc) return rc;
     rc = launch_int_partial(job, tl, ws->partial, ws->status, nullptr, stream);
     if (rc) return rc;
     return launch_merge(ws->partial, tl.grid, m, ws->stage, ws->vcec, false, true, chi_dev, ws->status, status_out,
-                        stream);
+                        stream, max_entry);
 }
 
 static bool is_device_ptr(const void *p) {
@@ -258,6 +259,70 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 // Float images: records -> sort -> per-key running sums (ecc_float.hip,
 // ecc_sort.hip).  Synchronous: the number of distinct values is only known
 // at the end.
+// Synchronous integer curve: host or device image and curve.  max_entry:
+// each cell's value is the maximum over its voxels (the kernel reads M-1-v
+// and the merge writes the rows reversed).
+static int compute_int(const void *image, const ecc_dims *dims, int64_t total, ecc_dtype dtype, ecc_curve *curve,
+                       hipStream_t s, bool max_entry) {
+    if (dtype == ECC_U16) {
+        set_error("dtype %d not available in this build", (int)dtype);
+        return ECC_E_UNSUPPORTED;
+    }
+    const int64_t m = threshold_count(dtype);
+    if (m < 0) {
+        set_error("unknown dtype %d", (int)dtype);
+        return ECC_E_ARG;
+    }
+    if (curve->capacity < m) {
+        curve->count = m;
+        set_error("curve capacity %lld < %lld", (long long)curve->capacity, (long long)m);
+        return ECC_E_BUFFER_TOO_SMALL;
+    }
+    IntView v{};
+    int unsup = 0;
+    if (!normalize_int_view(dims, &v, &unsup)) {
+        set_error("integer path: shape not supported (4 axes longer than 1, or an extent beyond 2^31)");
+        return ECC_E_UNSUPPORTED;
+    }
+    Workspace *ws = nullptr;
+    int rc = get_workspace(s, &ws);
+    if (rc) return rc;
+    const void *img_dev = image;
+    if (!is_device_ptr(image)) {
+        const size_t bytes = (size_t)total * elem_bytes(dtype);
+        rc = ensure_bytes(&ws->img_tmp, &ws->img_tmp_bytes, bytes);
+        if (rc) return rc;
+        ECC_HIP(hipMemcpyAsync(ws->img_tmp, image, bytes, hipMemcpyHostToDevice, s));
+        img_dev = ws->img_tmp;
+    }
+    const bool chi_dev = is_device_ptr(curve->chi);
+    int64_t *chi_target = curve->chi;
+    if (!chi_dev) {
+        rc = ensure_bytes((void **)&ws->chi_tmp, &ws->chi_tmp_bytes, (size_t)m * sizeof(int64_t));
+        if (rc) return rc;
+        chi_target = ws->chi_tmp;
+    }
+    rc = enqueue_int(img_dev, v, dtype, chi_target, ws->status + 2, s, ws, max_entry);
+    if (rc) return rc;
+    uint32_t st = 0;
+    ECC_HIP(hipMemcpyAsync(&st, ws->status + 2, 4, hipMemcpyDeviceToHost, s));
+    ECC_HIP(hipStreamSynchronize(s));
+    if (st & kStatusRange) {
+        set_error("a 14-bit image holds a value >= 16384");
+        return ECC_E_RANGE;
+    }
+    if (st != 0) {
+        set_error("internal error: device status 0x%08x", st);
+        return ECC_E_HIP;
+    }
+    if (!chi_dev) {
+        ECC_HIP(hipMemcpyAsync(curve->chi, ws->chi_tmp, (size_t)m * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        ECC_HIP(hipStreamSynchronize(s));
+    }
+    curve->count = m;
+    return ECC_OK;
+}
+
 static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc_curve *curve, hipStream_t s) {
     if (!curve->keys) {
         set_error("ECC_F32 needs curve->keys");
@@ -398,64 +463,24 @@ int ecc_compute(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_cu
         return ECC_E_ARG;
     }
     if (dtype == ECC_F32) return compute_float(image, dims, total, curve, (hipStream_t)stream);
-    if (dtype == ECC_U16) {
-        set_error("ecc_compute: dtype %d not available in this build", (int)dtype);
-        return ECC_E_UNSUPPORTED;
-    }
-    const int64_t m = threshold_count(dtype);
-    if (m < 0) {
-        set_error("unknown dtype %d", (int)dtype);
+    return compute_int(image, dims, total, dtype, curve, (hipStream_t)stream, false);
+}
+
+int ecc_compute_max_entry(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_curve *curve,
+                          void *stream) {
+    g_err[0] = 0;
+    int64_t total = 0;
+    int rc = check_dims(dims, &total);
+    if (rc) return rc;
+    if (!image || !curve || !curve->chi) {
+        set_error("NULL image, curve or curve->chi");
         return ECC_E_ARG;
     }
-    if (curve->capacity < m) {
-        curve->count = m;
-        set_error("curve capacity %lld < %lld", (long long)curve->capacity, (long long)m);
-        return ECC_E_BUFFER_TOO_SMALL;
-    }
-    IntView v{};
-    int unsup = 0;
-    if (!normalize_int_view(dims, &v, &unsup)) {
-        set_error("integer path: shape not supported (4 axes longer than 1, or an extent beyond 2^31)");
+    if (dtype == ECC_F32) {
+        set_error("ecc_compute_max_entry: integer dtypes only");
         return ECC_E_UNSUPPORTED;
     }
-    hipStream_t s = (hipStream_t)stream;
-    Workspace *ws = nullptr;
-    rc = get_workspace(stream, &ws);
-    if (rc) return rc;
-    const void *img_dev = image;
-    if (!is_device_ptr(image)) {
-        const size_t bytes = (size_t)total * elem_bytes(dtype);
-        rc = ensure_bytes(&ws->img_tmp, &ws->img_tmp_bytes, bytes);
-        if (rc) return rc;
-        ECC_HIP(hipMemcpyAsync(ws->img_tmp, image, bytes, hipMemcpyHostToDevice, s));
-        img_dev = ws->img_tmp;
-    }
-    const bool chi_dev = is_device_ptr(curve->chi);
-    int64_t *chi_target = curve->chi;
-    if (!chi_dev) {
-        rc = ensure_bytes((void **)&ws->chi_tmp, &ws->chi_tmp_bytes, (size_t)m * sizeof(int64_t));
-        if (rc) return rc;
-        chi_target = ws->chi_tmp;
-    }
-    rc = enqueue_int(img_dev, v, dtype, chi_target, ws->status + 2, s, ws);
-    if (rc) return rc;
-    uint32_t st = 0;
-    ECC_HIP(hipMemcpyAsync(&st, ws->status + 2, 4, hipMemcpyDeviceToHost, s));
-    ECC_HIP(hipStreamSynchronize(s));
-    if (st & kStatusRange) {
-        set_error("a 14-bit image holds a value >= 16384");
-        return ECC_E_RANGE;
-    }
-    if (st != 0) {
-        set_error("internal error: device status 0x%08x", st);
-        return ECC_E_HIP;
-    }
-    if (!chi_dev) {
-        ECC_HIP(hipMemcpyAsync(curve->chi, ws->chi_tmp, (size_t)m * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        ECC_HIP(hipStreamSynchronize(s));
-    }
-    curve->count = m;
-    return ECC_OK;
+    return compute_int(image, dims, total, dtype, curve, (hipStream_t)stream, true);
 }
 
 }  // extern "C"

@@ -245,7 +245,7 @@ constexpr int lcm(int a, int b) {
 // The plane loop is unrolled by lcm(2, PD+1) so that every register buffer is
 // addressed with a compile-time index (plane p of the tile uses raw buffer
 // (p - zs) mod (PD+1) and field buffer (p - zs) mod 2).
-template <typename T, int NIN, int R, int MODE, bool FULL, int PD>
+template <typename T, int NIN, int R, int MODE, bool FULL, int PD, bool INV>
 __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uint32_t (&vx)[R + 1],
                                      const uint32_t (&vxl)[R + 1], const uint32_t (&soff)[R + 1], const EdgeMasks &em,
                                      uint32_t &orv) {
@@ -253,6 +253,7 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
     constexpr int NR = W::NR;
     constexpr int NI = W::NI;
     constexpr int ESZ = sizeof(T);
+    constexpr uint32_t kInvMask = ESZ == 1 ? 255u : 16383u;
     constexpr int NB = PD + 1;
     constexpr int U = lcm(2, NB);
     const int64_t pb = P.src.plane_bytes;
@@ -268,6 +269,10 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
         for (int rr = 0; rr < NR; ++rr) {
             a[rr] = load_elem(rs, vx[rr], soff[rr], ESZ);
             b[rr] = load_elem(rs, vxl[rr], soff[rr], ESZ);
+            if constexpr (INV) {  // M-1-v (M a power of two); bits >= log2 M stay for the range check
+                a[rr] ^= kInvMask;
+                b[rr] ^= kInvMask;
+            }
         }
     };
     auto plane_ptr = [&](int p) { return (p < 0 ? P.src.lo_base : P.src.base) + p * pb; };
@@ -374,7 +379,7 @@ constexpr int kWavesPerEU() {
 // The tiles of one workgroup of one image: b = the workgroup's index among
 // the image's G workgroups (G <= tiles).  Writes the counts of its tiles to
 // row b of P.partial.
-template <typename T, int M, int NIN, int R, int MODE, int PD>
+template <typename T, int M, int NIN, int R, int MODE, int PD, bool INV = false>
 __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const int b, const int G) {
     using W = Walker<NIN, R>;
     constexpr int NR = W::NR;
@@ -463,7 +468,7 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
     }
     if (any && zs < ze) {
         if (full) {
-            walk<T, NIN, R, MODE, true, PD>(P, zs, ze, vx, vxl, soff, em, orv);
+            walk<T, NIN, R, MODE, true, PD, INV>(P, zs, ze, vx, vxl, soff, em, orv);
         } else if constexpr (NIN == 1) {
             // An edge group of segments is walked as pairs of segments, each
             // pair with its own lane masks.
@@ -480,10 +485,10 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
                 e2.lx_any2 = ballot(xb < n2);
                 const uint32_t v2[3] = {vx[r], vx[r + 1], 0u}, vl2[3] = {vxl[r], vxl[r + 1], 0u};
                 const uint32_t s2[3] = {0u, 0u, 0u};
-                walk<T, 1, 2, MODE, false, 1>(P, zs, ze, v2, vl2, s2, e2, orv);
+                walk<T, 1, 2, MODE, false, 1, INV>(P, zs, ze, v2, vl2, s2, e2, orv);
             }
         } else {
-            walk<T, NIN, R, MODE, false, PD>(P, zs, ze, vx, vxl, soff, em, orv);
+            walk<T, NIN, R, MODE, false, PD, INV>(P, zs, ze, vx, vxl, soff, em, orv);
         }
     }
     }  // tiles
@@ -499,11 +504,14 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
         if (i0 + tid < M) dst[i0 + tid] = hist[i0 + tid];
 }
 
-template <typename T, int M, int NIN, int R, int MODE, int PD>
+// INV: every loaded value v is replaced by M-1-v, so the histogram counts
+// each cell at M-1 minus the maximum over its voxels (the largest-value
+// convention, read back reversed by the merge).
+template <typename T, int M, int NIN, int R, int MODE, int PD, bool INV = false>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<NIN, R, PD>())))
 int_vcec_kernel(KParams P) {
     __shared__ int32_t hist[M];
-    tile_body<T, M, NIN, R, MODE, PD>(P, hist, blockIdx.x, gridDim.x);
+    tile_body<T, M, NIN, R, MODE, PD, INV>(P, hist, blockIdx.x, gridDim.x);
 }
 
 // Batched form: the tiles of many images in one launch.  Image j owns
@@ -525,13 +533,13 @@ int_vcec_batch_kernel(const KParams *__restrict__ jobs, const int32_t *__restric
     tile_body<T, M, NIN, 2, 0, 1>(P, hist, b - b0, tile_begin[lo + 1] - b0);
 }
 
-template <typename T, int M, int NIN, int R, int MODE, int PD>
+template <typename T, int M, int NIN, int R, int MODE, int PD, bool INV = false>
 static int launch_one(const KParams &p, const IntTiling &tl, hipStream_t stream) {
     const int threads = kWave * tl.wx * tl.wy;
     void *tok = nullptr;
     int rc = profile_begin(stream, &tok);
     if (rc) return rc;
-    hipLaunchKernelGGL((int_vcec_kernel<T, M, NIN, R, MODE, PD>), dim3(tl.grid), dim3(threads), 0, stream, p);
+    hipLaunchKernelGGL((int_vcec_kernel<T, M, NIN, R, MODE, PD, INV>), dim3(tl.grid), dim3(threads), 0, stream, p);
     ECC_HIP(hipGetLastError());
     return profile_end(stream, tok);
 }
@@ -560,6 +568,19 @@ static int launch_rows(const KParams &p, const IntTiling &tl, hipStream_t stream
     switch (tl.rows) {
     case 2: return launch_mode<T, M, NIN, 2>(p, tl, stream);
     case 4: return launch_mode<T, M, NIN, 4>(p, tl, stream);
+    default: break;
+    }
+    set_error("integer kernel: %d rows per wave not built", tl.rows);
+    return ECC_E_UNSUPPORTED;
+}
+
+// Inverted values (largest-value convention): walking mode 0, one plane of
+// look-ahead.
+template <typename T, int M, int NIN>
+static int launch_inverted(const KParams &p, const IntTiling &tl, hipStream_t stream) {
+    switch (tl.rows) {
+    case 2: return launch_one<T, M, NIN, 2, 0, 1, true>(p, tl, stream);
+    case 4: return launch_one<T, M, NIN, 4, 0, 1, true>(p, tl, stream);
     default: break;
     }
     set_error("integer kernel: %d rows per wave not built", tl.rows);
@@ -596,6 +617,14 @@ int launch_int_partial(const IntJob &job, const IntTiling &tl, int32_t *partial,
                        int64_t *zero_vcec, hipStream_t stream) {
     const KParams p = make_params(job, tl, partial, status, zero_vcec);
     const int nin = job.view.nin;
+    if (job.invert) {
+        if (job.dtype == ECC_U8)
+            return nin == 1 ? launch_inverted<uint8_t, 256, 1>(p, tl, stream)
+                            : launch_inverted<uint8_t, 256, 2>(p, tl, stream);
+        if (job.dtype == ECC_U14)
+            return nin == 1 ? launch_inverted<uint16_t, 16384, 1>(p, tl, stream)
+                            : launch_inverted<uint16_t, 16384, 2>(p, tl, stream);
+    }
     if (job.dtype == ECC_U8)
         return nin == 1 ? launch_rows<uint8_t, 256, 1>(p, tl, stream) : launch_rows<uint8_t, 256, 2>(p, tl, stream);
     if (job.dtype == ECC_U14)

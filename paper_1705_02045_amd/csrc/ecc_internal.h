@@ -59,9 +59,10 @@ struct IntJob {
     int32_t lo_inf;       // plane e0-1 lies outside the image
     int32_t hi_inf;       // plane e1 lies outside the image
     int dtype;            // ECC_U8 or ECC_U14
+    int invert;           // values read as M-1-v (largest-value convention)
 };
 
-// Tiling of the integer kernel (chosen by the tuner in ecc_tune.cpp).
+// Tiling of the integer kernel (chosen by choose_int_tiling in ecc_api.cpp).
 struct IntTiling {
     int rows;      // rows (nin == 2) or 64-wide x segments (nin == 1) per wave
     int mode;      // update form of the four-item groups (0..3, see ecc_int.hip)
@@ -111,7 +112,8 @@ int launch_zero(void *p, size_t bytes, hipStream_t stream);
 // not null) and clears it.
 int merge_stage_rows(int rows);
 int launch_merge(const int32_t *partial, int rows, int m, int64_t *stage, int64_t *vcec, bool accumulate,
-                 bool do_scan, int64_t *chi, uint32_t *status, uint32_t *status_out, hipStream_t stream);
+                 bool do_scan, int64_t *chi, uint32_t *status, uint32_t *status_out, hipStream_t stream,
+                 bool reverse = false);
 
 bool normalize_int_view(const ecc_dims *dims, IntView *v, int *err_ndim_dropped);
 int check_dims(const ecc_dims *dims, int64_t *total);

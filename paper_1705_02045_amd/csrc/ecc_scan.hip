@@ -36,9 +36,11 @@ int launch_zero(void *p, size_t bytes, hipStream_t stream) {
 //  3. scan_offsets_kernel (do_scan): adds the totals of the preceding groups;
 //     the curve is written only if the status word is clear, and the status
 //     is copied out and cleared.
+// With `reverse`, colsum_kernel writes column c of the rows at m-1-c (the
+// largest-value convention: the kernel counted at m-1-value).
 // vcec is overwritten, or added to with `accumulate`.
 __global__ void __launch_bounds__(256) colsum_kernel(const int32_t *__restrict__ partial, int rows, int m,
-                                                     int64_t *__restrict__ dst, int accumulate) {
+                                                     int64_t *__restrict__ dst, int accumulate, int reverse) {
     const int BY = gridDim.y;
     const int c0 = blockIdx.x * 1024 + threadIdx.x * 4;
     if (c0 >= m) return;
@@ -65,7 +67,22 @@ __global__ void __launch_bounds__(256) colsum_kernel(const int32_t *__restrict__
         s2 += a.z;
         s3 += a.w;
     }
-    int64_t *d = dst + (size_t)blockIdx.y * m + c0;
+    int64_t *row = dst + (size_t)blockIdx.y * m;
+    if (reverse) {  // column c lands at m-1-c
+        int64_t *d = row + (m - 1 - c0);
+        if (accumulate) {
+            s0 += d[0];
+            s1 += d[-1];
+            s2 += d[-2];
+            s3 += d[-3];
+        }
+        d[0] = s0;
+        d[-1] = s1;
+        d[-2] = s2;
+        d[-3] = s3;
+        return;
+    }
+    int64_t *d = row + c0;
     if (accumulate) {
         s0 += d[0];
         s1 += d[1];
@@ -234,7 +251,8 @@ int merge_stage_rows(int rows) {
 }
 
 int launch_merge(const int32_t *partial, int rows, int m, int64_t *stage, int64_t *vcec, bool accumulate,
-                 bool do_scan, int64_t *chi, uint32_t *status, uint32_t *status_out, hipStream_t stream) {
+                 bool do_scan, int64_t *chi, uint32_t *status, uint32_t *status_out, hipStream_t stream,
+                 bool reverse) {
     if (m % 4 != 0 || m > 65536) {
         set_error("launch_merge: m = %d not supported", m);
         return ECC_E_ARG;
@@ -244,7 +262,7 @@ int launch_merge(const int32_t *partial, int rows, int m, int64_t *stage, int64_
     if (rows > 0) {
         by = merge_stage_rows(rows);
         hipLaunchKernelGGL(colsum_kernel, dim3(groups, by), dim3(256), 0, stream, partial, rows, m,
-                           by == 1 ? vcec : stage, (by == 1 && accumulate) ? 1 : 0);
+                           by == 1 ? vcec : stage, (by == 1 && accumulate) ? 1 : 0, reverse ? 1 : 0);
         ECC_HIP(hipGetLastError());
     }
     if (by > 1 || do_scan) {
