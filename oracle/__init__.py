@@ -13,7 +13,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 
 ``curve_max_entry`` computes the other convention for a cell's value, the
 maximum over its voxels (the literal "largest gray value" reading), by the
-same cell enumeration.
+same cell enumeration.  ``curve_dual`` enumerates the dual complex (voxels as
+vertices, each cell at the maximum over its vertices).
 
 Floating-point images (Section 3, "Other Ranges of Gray Values"): the curve is
 a step function over the distinct values.  NaN is rejected; -0.0 and +0.0 are
@@ -44,7 +45,7 @@ def lib() -> ctypes.CDLL:
             raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
         L = ctypes.CDLL(str(path))
         i64p = ctypes.POINTER(ctypes.c_int64)
-        for name in ("oracle_vcec", "oracle_curve", "oracle_curve_max"):
+        for name in ("oracle_vcec", "oracle_curve", "oracle_curve_max", "oracle_curve_dual"):
             fn = getattr(L, name)
             fn.restype = ctypes.c_int
             fn.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, i64p, ctypes.c_int64,
@@ -118,6 +119,21 @@ def curve_max_entry(img: np.ndarray, m: int | None = None, nthreads: int | None 
     rc = lib().oracle_curve_max(img.ctypes.data, _ELEM[img.dtype], img.ndim, dims, m,
                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                 nthreads or default_threads(), max_bytes)
+    _check(rc)
+    return out
+
+
+def curve_dual(img: np.ndarray, m: int | None = None, nthreads: int | None = None,
+               max_bytes: int = 8 << 30) -> np.ndarray:
+    """The dual complex (voxels as vertices, edges between voxels sharing a
+    (d-1)-face, squares and cubes of such neighbours): every cell enters at
+    the maximum over its vertices.  chi(T_t) for t = 0..m-1 (int64)."""
+    img, dims = _prep(img)
+    m = int(m if m is not None else DEFAULT_M[img.dtype])
+    out = np.zeros(m, dtype=np.int64)
+    rc = lib().oracle_curve_dual(img.ctypes.data, _ELEM[img.dtype], img.ndim, dims, m,
+                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 nthreads or default_threads(), max_bytes)
     _check(rc)
     return out
 

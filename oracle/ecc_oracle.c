@@ -32,6 +32,16 @@
  *
  * Element types: 1 = uint8, 2 = uint16, 4 = uint32.  Every value must be < m.
  *
+ * Dual complex (oracle_curve_dual; the construction the paper's footnote
+ * to Sec. 2 "Consecutive Thresholded Images" sets against its own, with
+ * voxels as vertices): the vertices are the voxels, and a cell is a product
+ * of factors each either one voxel index {a} or a pair {a, a+1} of
+ * neighbours along that axis -- doubled coordinates p in prod_k
+ * [0, 2 (n_k - 1)], even p_k = 2a the index a, odd p_k = 2a+1 the pair;
+ * dimension = number of pairs.  A cell enters when all its vertices have
+ * (lower-star filtration): value = MAXIMUM of f over its vertices.  Edges join
+ * voxels that share a (d-1)-face only (2d-connectivity).
+ *
  * Second convention (the *_max entry points): a cell's value is the MAXIMUM
  * of f over the voxels containing it -- the literal "largest gray value among
  * its voxels" reading of the entry value, the alternative to Sec. 2's
@@ -53,6 +63,7 @@ typedef struct {
     int64_t m;
     int64_t q0_lo, q0_hi;
     int use_max;                /* 0: minimum over incident voxels, 1: maximum */
+    int dual;                   /* 1: cells of the dual complex (voxels as vertices) */
     int64_t *vcec;
 } job_t;
 
@@ -76,7 +87,11 @@ static void count_cells(const job_t *j) {
             /* incident voxels and dimension of cell q */
             int dim = 0;
             for (int k = 0; k < d; ++k) {
-                if (q[k] & 1) {
+                if (j->dual) {  /* even: one voxel; odd: the pair (a, a+1) */
+                    lo[k] = q[k] / 2;
+                    hi[k] = (q[k] + 1) / 2;
+                    dim += (int)(q[k] & 1);
+                } else if (q[k] & 1) {
                     lo[k] = hi[k] = (q[k] - 1) / 2;
                     ++dim;
                 } else {
@@ -101,7 +116,7 @@ static void count_cells(const job_t *j) {
             j->vcec[best] += (dim & 1) ? -1 : 1;
             /* next cell in this q0 layer */
             int k = d - 1;
-            while (k >= 1 && q[k] == 2 * j->n[k]) { q[k] = 0; --k; }
+            while (k >= 1 && q[k] == 2 * j->n[k] - (j->dual ? 2 : 0)) { q[k] = 0; --k; }
             if (k < 1) break;
             ++q[k];
         }
@@ -142,14 +157,15 @@ int oracle_vcec_range(const void *img, int elem, int d, const int64_t *n, int64_
     return 0;
 }
 
-static int vcec_rule(const void *img, int elem, int d, const int64_t *n, int64_t m, int use_max,
+static int vcec_rule(const void *img, int elem, int d, const int64_t *n, int64_t m, int use_max, int dual,
                      int64_t *vcec, int nthreads, int64_t max_bytes) {
     job_t base;
     memset(&base, 0, sizeof base);
     int rc = setup(&base, img, elem, d, n, m);
     if (rc) return rc;
     base.use_max = use_max;
-    int64_t layers = 2 * n[0] + 1;
+    base.dual = dual;
+    int64_t layers = dual ? 2 * n[0] - 1 : 2 * n[0] + 1;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
     if (nthreads > layers) nthreads = (int)layers;
@@ -186,7 +202,7 @@ static int vcec_rule(const void *img, int elem, int d, const int64_t *n, int64_t
  * lowered so that the private arrays stay within max_bytes. */
 int oracle_vcec(const void *img, int elem, int d, const int64_t *n, int64_t m,
                 int64_t *vcec, int nthreads, int64_t max_bytes) {
-    return vcec_rule(img, elem, d, n, m, 0, vcec, nthreads, max_bytes);
+    return vcec_rule(img, elem, d, n, m, 0, 0, vcec, nthreads, max_bytes);
 }
 
 /* The curve chi(T_t), t = 0..m-1: prefix sums of the VCEC. */
@@ -201,7 +217,16 @@ int oracle_curve(const void *img, int elem, int d, const int64_t *n, int64_t m,
 /* The same with each cell's value the maximum over its voxels. */
 int oracle_curve_max(const void *img, int elem, int d, const int64_t *n, int64_t m,
                      int64_t *chi, int nthreads, int64_t max_bytes) {
-    int rc = vcec_rule(img, elem, d, n, m, 1, chi, nthreads, max_bytes);
+    int rc = vcec_rule(img, elem, d, n, m, 1, 0, chi, nthreads, max_bytes);
+    if (rc) return rc;
+    for (int64_t t = 1; t < m; ++t) chi[t] += chi[t - 1];
+    return 0;
+}
+
+/* Curve of the dual complex (voxels as vertices, value = max over vertices). */
+int oracle_curve_dual(const void *img, int elem, int d, const int64_t *n, int64_t m,
+                      int64_t *chi, int nthreads, int64_t max_bytes) {
+    int rc = vcec_rule(img, elem, d, n, m, 1, 1, chi, nthreads, max_bytes);
     if (rc) return rc;
     for (int64_t t = 1; t < m; ++t) chi[t] += chi[t - 1];
     return 0;

@@ -1,7 +1,8 @@
 """Brute-force Z/2 homology of thresholded images (test helper, tiny inputs only).
 
 T_t is built here as the CLOSURE of the voxels with value <= t: every face of
-every such voxel cube.  This is a different construction from the oracle's
+every such voxel cube.  For the dual complex (voxels as vertices) the cells
+spanned by the vertices with value <= t are built directly.  This is a different construction from the oracle's
 (which gives each cell the minimum value of its incident voxels); the two
 agree only if the sublevel sets of Sec. 2 are exactly these closures.
 Betti numbers come from ranks of boundary matrices over GF(2), computed by
@@ -50,10 +51,28 @@ def gf2_rank(rows):
     return rank
 
 
+def dual_cells(mask: np.ndarray):
+    """Cells of the dual complex spanned by the voxels where mask is True: the
+    voxels are vertices; doubled coordinate p_k even = voxel index p_k/2, odd =
+    the pair of neighbours (p_k-1)/2, (p_k+1)/2; a cell is present iff all its
+    vertices are."""
+    d = mask.ndim
+    cells = set()
+    for p in itertools.product(*[range(2 * n - 1) for n in mask.shape]):
+        verts = itertools.product(*[(q // 2,) if q % 2 == 0 else (q // 2, q // 2 + 1) for q in p])
+        if all(mask[v] for v in verts):
+            cells.add(p)
+    return cells
+
+
 def betti(mask: np.ndarray):
     """(betti numbers beta_0..beta_d, cell counts n_0..n_d) of the closure of mask."""
-    d = mask.ndim
-    cells = closure_cells(mask)
+    return betti_cells(closure_cells(mask), mask.ndim)
+
+
+def betti_cells(cells, d: int):
+    """(betti numbers, cell counts) of a cubical complex given by its cells in
+    doubled coordinates (odd coordinate = interval factor)."""
     by_dim = [[] for _ in range(d + 1)]
     for c in cells:
         by_dim[sum(q % 2 for q in c)].append(c)
@@ -64,7 +83,7 @@ def betti(mask: np.ndarray):
         for c in by_dim[k]:
             bits = 0
             for f in boundary(c):
-                assert f in index[k - 1], "closure is not a complex"
+                assert f in index[k - 1], "the cells are not a complex"
                 bits ^= 1 << index[k - 1][f]
             rows.append(bits)
         ranks[k] = gf2_rank(rows)

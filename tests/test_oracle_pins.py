@@ -18,7 +18,7 @@ import pytest
 import scipy.ndimage as ndi
 
 import oracle
-from homology import betti
+from homology import betti, betti_cells, dual_cells
 
 GOLDEN = pathlib.Path(__file__).parent / "golden"
 
@@ -38,8 +38,8 @@ def load_fixture(path):
 @pytest.mark.parametrize("path", sorted(GOLDEN.glob("*.txt")), ids=lambda p: p.stem)
 def test_golden_fixture(path):
     img, m, chi, rule = load_fixture(path)
-    got = oracle.curve(img, m=m) if rule == "min" else oracle.curve_max_entry(img, m=m)
-    assert (got == chi).all()
+    fn = {"min": oracle.curve, "max": oracle.curve_max_entry, "dual": oracle.curve_dual}[rule]
+    assert (fn(img, m=m) == chi).all()
 
 
 @pytest.mark.parametrize("d", [1, 2, 3, 4])
@@ -234,3 +234,60 @@ def test_float_signed_zero_and_nan():
     assert list(chi) == [1, 1, 1]
     with pytest.raises(ValueError):
         oracle.curve_float(np.array([1.0, np.nan], dtype=np.float32))
+
+
+@pytest.mark.parametrize("shape,m,trials", [((8, 8), 4, 10), ((5, 7), 3, 10), ((4, 4, 4), 3, 5),
+                                            ((3, 4, 5), 4, 5), ((9,), 4, 10), ((1, 6), 3, 5)])
+def test_dual_homology_brute_force(shape, m, trials):
+    """Dual complex (voxels as vertices): Z/2 homology of the cells spanned by
+    {f <= t}; beta_0 = components under 2d-connectivity (scipy's default
+    structuring element), beta_(d-1) = bounded components of the complement
+    under full (3^d - 1) connectivity (the dual adjacency pair)."""
+    rng = np.random.default_rng(sum(shape) * 37 + m)
+    d = len(shape)
+    for _ in range(trials):
+        img = rand_img(rng, shape, m)
+        chi = oracle.curve_dual(img, m=m)
+        for t in range(m):
+            mask = img <= t
+            beta, n = betti_cells(dual_cells(mask), d)
+            assert chi[t] == sum((-1) ** k * b for k, b in enumerate(beta))
+            assert chi[t] == sum((-1) ** k * c for k, c in enumerate(n))
+            assert all(b >= 0 for b in beta) and beta[d] == 0
+            _, comps = ndi.label(mask, structure=ndi.generate_binary_structure(d, 1))
+            assert beta[0] == comps
+            if d >= 2:
+                comp = np.pad(~mask, 1, constant_values=True)
+                _, k = ndi.label(comp, structure=np.ones((3,) * d))
+                assert beta[d - 1] == k - 1
+
+
+def box_faces(shape):
+    """Every face of the box of voxel indices: (codimension, index per axis or
+    None for a free axis); fixed axes take the first or the last index."""
+    d = len(shape)
+    for fixed in itertools.product((None, 0, 1), repeat=d):
+        yield sum(f is not None for f in fixed), tuple(
+            None if f is None else (0 if f == 0 else shape[k] - 1) for k, f in enumerate(fixed))
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_dual_from_max_entry_of_faces(d):
+    """The dual complex's cells are the largest-value convention's cells away
+    from the box's outer boundary, with dimension d - dim; inclusion-exclusion
+    over the box's faces: dual(f) = (-1)^d sum_F (-1)^codim(F) max_entry(f|F)
+    (a 0-dimensional face contributes [f(corner) <= t])."""
+    rng = np.random.default_rng(60 + d)
+    for _ in range(5):
+        shape = tuple(int(x) for x in rng.integers(1, 6, size=d))
+        m = int(rng.integers(2, 9))
+        img = rand_img(rng, shape, m)
+        acc = np.zeros(m, dtype=np.int64)
+        for codim, idx in box_faces(shape):
+            sub = img[tuple(slice(None) if i is None else i for i in idx)]
+            if sub.ndim == 0:
+                a = (np.arange(m) >= int(sub)).astype(np.int64)
+            else:
+                a = oracle.curve_max_entry(np.ascontiguousarray(sub), m=m)
+            acc += (-1) ** codim * a
+        assert (oracle.curve_dual(img, m=m) == (-1) ** d * acc).all()
