@@ -12,8 +12,9 @@ events on its launch stream) and the CPU oracle timed on a bounded sample of
 the same volume on this host.  Under "legs": the other workloads of the path
 (serving mix at a p99 latency bound, 4-D float32, host-staged streaming of
 8192^2 x 1024 against the measured host-to-device copy rate, the
-2600 x 14450^2 volume made and streamed slab by slab on the device, the 2-D
-256^2 uint8 latency), each timed after the headline steps.
+2600 x 14450^2 volume made and streamed slab by slab on the device, the
+largest-value and dual constructions on the headline volume, the 2-D 256^2
+uint8 latency), each timed after the headline steps.
 """
 from __future__ import annotations
 
@@ -281,6 +282,26 @@ def leg_stream_device(shape, slab: int):
             "end_to_end_gvoxel_per_s": round(vox / overlap_s / 1e9, 2), "chi_last": int(chi[-1])}
 
 
+def leg_conventions(vol, reps: int):
+    """The other constructions on the headline volume (device image, device
+    curve, synchronous calls): each cell at the maximum over its voxels
+    (ecc_compute_max_entry), and the dual complex with the lower-star
+    filtration (ecc_compute_dual: the volume and its 26 box faces)."""
+    import numpy as np
+    import paper_1705_02045_amd as ecc
+    out = {}
+    for name, fn in (("max_entry", ecc.compute_max_entry), ("dual", ecc.compute_dual)):
+        fn(vol, "u14")
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn(vol, "u14")
+            times.append(time.perf_counter() - t0)
+        ms = float(np.median(times)) * 1e3
+        out[name] = {"ms": round(ms, 4), "gvoxel_per_s": round(vol.numel() / ms / 1e6, 2)}
+    return out
+
+
 def leg_small_2d(reps: int):
     """2-D 256x256 uint8 i.i.d. (seed 0): latency of one synchronous ecc_compute
     (device image, device curve) and the oracle on the same image."""
@@ -311,7 +332,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, default=1024, help="edge of the cubic volume")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget; 0 skips it")
-    ap.add_argument("--legs", default="serving,float,stream_host,stream_device,small_2d",
+    ap.add_argument("--legs", default="serving,float,stream_host,stream_device,conventions,small_2d",
                     help="further workloads reported under 'legs' (comma list, or 'none')")
     ap.add_argument("--serve-requests", type=int, default=1024)
     ap.add_argument("--serve-slo-ms", type=float, default=10.0)
@@ -399,6 +420,8 @@ def main():
             legs[leg] = leg_stream_host(1024, 8192, 16, 4)
         elif leg == "stream_device":
             legs[leg] = leg_stream_device((2600, 14450, 14450), 64)
+        elif leg == "conventions":
+            legs[leg] = leg_conventions(vol, 20)
         elif leg == "small_2d":
             legs[leg] = leg_small_2d(200)
         else:

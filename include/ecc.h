@@ -102,6 +102,21 @@ int ecc_compute(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_cu
 int ecc_compute_max_entry(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_curve *curve,
                           void *stream);
 
+/* The dual complex of the image (the alternative the footnote to Sec. 2,
+ * "Consecutive Thresholded Images as Sublevel Set Filtrations", names:
+ * voxels become vertices, with the lower-star filtration).  Vertices are the
+ * voxels; a cell is a product, per axis, of one index or a pair of
+ * neighbouring indices (edges join voxels that share a (d-1)-face:
+ * 4-connectivity in 2-D, 6 in 3-D); a cell enters at the maximum of the
+ * image over its vertices.  chi[t] = chi of the cells with value <= t, for
+ * t = 0..m-1.  Axes of length 1 are dropped; at most three may remain.
+ * Computed from the largest-value convention of the image and of every face
+ * of its box (inclusion-exclusion over the faces, (-1)^codim).
+ * Integer dtypes u8 and u14; arguments, synchronisation and errors as
+ * ecc_compute (ECC_E_UNSUPPORTED for ECC_F32, ECC_U16, or more than three
+ * axes longer than 1). */
+int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_curve *curve, void *stream);
+
 /* Stream-ordered form for integer types with device-resident data: enqueues
  * the whole computation on `stream` and returns without synchronizing.
  *   image_dev: device pointer, prod(n) elements.

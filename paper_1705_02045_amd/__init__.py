@@ -49,6 +49,8 @@ class Curve(ctypes.Structure):
 _vp = ctypes.c_void_p
 _lib.ecc_compute.restype = ctypes.c_int
 _lib.ecc_compute.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_int, ctypes.POINTER(Curve), _vp]
+_lib.ecc_compute_dual.restype = ctypes.c_int
+_lib.ecc_compute_dual.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_int, ctypes.POINTER(Curve), _vp]
 _lib.ecc_compute_max_entry.restype = ctypes.c_int
 _lib.ecc_compute_max_entry.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_int, ctypes.POINTER(Curve), _vp]
 _lib.ecc_compute_async.restype = ctypes.c_int
@@ -172,12 +174,10 @@ def compute(image, dtype: str | None = None):
         return chi
 
 
-def compute_max_entry(image, dtype: str):
-    """ecc_compute_max_entry on a CUDA tensor (integer dtypes): each cell's value
-    is the maximum over its voxels.  Returns the int64 curve on the same device."""
+def _compute_int_variant(fn, name, image, dtype):
     import torch
     if not image.is_cuda:
-        raise ValueError("compute_max_entry() takes a device tensor")
+        raise ValueError(f"{name}() takes a device tensor")
     image = image.contiguous()
     dims = make_dims(image.shape)
     dev = image.device
@@ -185,9 +185,21 @@ def compute_max_entry(image, dtype: str):
         m = THRESHOLDS.get(dtype, 1)  # the library rejects non-integer dtypes
         chi = torch.empty(m, dtype=torch.int64, device=dev)
         cv = Curve(capacity=m, count=0, chi=chi.data_ptr(), keys=None)
-        _check(_lib.ecc_compute_max_entry(image.data_ptr(), ctypes.byref(dims), DTYPES[dtype], ctypes.byref(cv),
-                                          _stream_handle(dev)), "ecc_compute_max_entry")
+        _check(fn(image.data_ptr(), ctypes.byref(dims), DTYPES[dtype], ctypes.byref(cv), _stream_handle(dev)),
+               f"ecc_{name}")
         return chi
+
+
+def compute_max_entry(image, dtype: str):
+    """ecc_compute_max_entry on a CUDA tensor (integer dtypes): each cell's value
+    is the maximum over its voxels.  Returns the int64 curve on the same device."""
+    return _compute_int_variant(_lib.ecc_compute_max_entry, "compute_max_entry", image, dtype)
+
+
+def compute_dual(image, dtype: str):
+    """ecc_compute_dual on a CUDA tensor (u8, u14): the dual complex, voxels as
+    vertices with the lower-star filtration.  Returns the int64 curve."""
+    return _compute_int_variant(_lib.ecc_compute_dual, "compute_dual", image, dtype)
 
 
 def compute_async(image, out_chi, dtype: str, status=None, stream=None):

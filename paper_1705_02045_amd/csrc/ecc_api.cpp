@@ -483,4 +483,130 @@ int ecc_compute_max_entry(const void *image, const ecc_dims *dims, ecc_dtype dty
     return compute_int(image, dims, total, dtype, curve, (hipStream_t)stream, true);
 }
 
+// Dual complex (voxels as vertices, lower-star filtration).  Its cells are
+// the cells of the voxel complex away from the box's outer boundary, with
+// dimension d - dim and value the maximum over their voxels, so by
+// inclusion-exclusion over the faces F of the box (every axis free, or fixed
+// at its first or last index):
+//   dual(f)(t) = (-1)^d sum_F (-1)^codim(F) max_entry(f|F)(t).
+// Axes of length 1 are dropped first (a product with a point).
+int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_curve *curve, void *stream) {
+    g_err[0] = 0;
+    int64_t total = 0;
+    int rc = check_dims(dims, &total);
+    if (rc) return rc;
+    if (!image || !curve || !curve->chi) {
+        set_error("NULL image, curve or curve->chi");
+        return ECC_E_ARG;
+    }
+    if (dtype != ECC_U8 && dtype != ECC_U14) {
+        if (dtype == ECC_F32 || dtype == ECC_U16) {
+            set_error("ecc_compute_dual: integer dtypes u8 and u14 only");
+            return ECC_E_UNSUPPORTED;
+        }
+        set_error("unknown dtype %d", (int)dtype);
+        return ECC_E_ARG;
+    }
+    const int64_t m = threshold_count(dtype);
+    if (curve->capacity < m) {
+        curve->count = m;
+        set_error("curve capacity %lld < %lld", (long long)curve->capacity, (long long)m);
+        return ECC_E_BUFFER_TOO_SMALL;
+    }
+    int64_t n[4];
+    int d = 0;
+    for (int k = 0; k < dims->ndim; ++k)
+        if (dims->n[k] > 1) n[d++] = dims->n[k];
+    if (d > 3) {
+        set_error("ecc_compute_dual: at most three axes longer than 1");
+        return ECC_E_UNSUPPORTED;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Workspace *ws = nullptr;
+    rc = get_workspace(s, &ws);
+    if (rc) return rc;
+    const size_t eb = elem_bytes(dtype);
+    const void *img_dev = image;
+    if (!is_device_ptr(image)) {
+        rc = ensure_bytes(&ws->img_tmp, &ws->img_tmp_bytes, (size_t)total * eb);
+        if (rc) return rc;
+        ECC_HIP(hipMemcpyAsync(ws->img_tmp, image, (size_t)total * eb, hipMemcpyHostToDevice, s));
+        img_dev = ws->img_tmp;
+    }
+    int nf = 1;
+    for (int k = 0; k < d; ++k) nf *= 3;
+    int64_t st[3] = {1, 1, 1};  // element strides of the kept axes
+    for (int k = d - 2; k >= 0; --k) st[k] = st[k + 1] * n[k + 1];
+    int64_t face_max = 1;  // the largest face of codimension >= 1
+    for (int k = 0; k < d; ++k)
+        if (total / n[k] > face_max) face_max = total / n[k];
+    // dual_buf: [nf][m] per-face curves, [m] result, then one gathered face
+    const size_t curves_bytes = (size_t)(nf + 1) * m * sizeof(int64_t);
+    const size_t face_off = (curves_bytes + 255) & ~(size_t)255;
+    rc = ensure_bytes(&ws->dual_buf, &ws->dual_buf_bytes, face_off + (size_t)face_max * eb);
+    if (rc) return rc;
+    int64_t *curves = (int64_t *)ws->dual_buf;
+    int64_t *result = curves + (size_t)nf * m;
+    uint8_t *face = (uint8_t *)ws->dual_buf + face_off;
+    uint64_t neg = 0;
+    for (int f = 0; f < nf; ++f) {
+        int code[3] = {0, 0, 0};
+        for (int k = 0, r = f; k < d; ++k, r /= 3) code[k] = r % 3;
+        int codim = 0, nfree = 0;
+        int64_t base = 0, fs[3] = {1, 1, 1}, fst[3] = {0, 0, 0};
+        for (int k = 0; k < d; ++k) {
+            if (code[k] == 0) {
+                fs[nfree] = n[k];
+                fst[nfree] = st[k];
+                ++nfree;
+            } else {
+                base += (code[k] == 1 ? 0 : n[k] - 1) * st[k];
+                ++codim;
+            }
+        }
+        const void *src = img_dev;
+        if (codim > 0) {
+            // free axes as the trailing axes of an n0 x n1 x n2 gather
+            int64_t g[3] = {1, 1, 1}, gs[3] = {0, 0, 0};
+            for (int i = 0; i < nfree; ++i) {
+                g[3 - nfree + i] = fs[i];
+                gs[3 - nfree + i] = fst[i];
+            }
+            rc = launch_gather(img_dev, (int)eb, base, gs[0], gs[1], gs[2], g[0], g[1], g[2], face, s);
+            if (rc) return rc;
+            src = face;
+        }
+        ecc_dims fd{};
+        fd.ndim = nfree > 0 ? nfree : 1;
+        for (int i = 0; i < 4; ++i) fd.n[i] = 1;
+        for (int i = 0; i < nfree; ++i) fd.n[i] = fs[i];
+        IntView v{};
+        int unsup = 0;
+        if (!normalize_int_view(&fd, &v, &unsup)) {
+            set_error("ecc_compute_dual: face shape not supported");
+            return ECC_E_UNSUPPORTED;
+        }
+        rc = enqueue_int(src, v, dtype, curves + (size_t)f * m, codim == 0 ? ws->status + 2 : nullptr, s, ws, true);
+        if (rc) return rc;
+        if (codim & 1) neg |= 1ull << f;
+    }
+    rc = launch_signed_sum(curves, nf, neg, (d & 1) ? -1 : 1, (int)m, result, s);
+    if (rc) return rc;
+    uint32_t stv = 0;
+    ECC_HIP(hipMemcpyAsync(&stv, ws->status + 2, 4, hipMemcpyDeviceToHost, s));
+    ECC_HIP(hipStreamSynchronize(s));
+    if (stv & kStatusRange) {
+        set_error("a 14-bit image holds a value >= 16384");
+        return ECC_E_RANGE;
+    }
+    if (stv != 0) {
+        set_error("internal error: device status 0x%08x", stv);
+        return ECC_E_HIP;
+    }
+    ECC_HIP(hipMemcpyAsync(curve->chi, result, (size_t)m * sizeof(int64_t), hipMemcpyDefault, s));
+    ECC_HIP(hipStreamSynchronize(s));
+    curve->count = m;
+    return ECC_OK;
+}
+
 }  // extern "C"

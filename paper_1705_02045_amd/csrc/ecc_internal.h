@@ -30,10 +30,7 @@ int hip_fail(hipError_t e, const char *what);
         if (_e != hipSuccess) return hip_fail(_e, #call); \
     } while (0)
 
-// Source of axis-0 planes for one launch: plane p starts at
-// base + p * plane_bytes (one contiguous buffer, so the kernel advances a
-// plane pointer instead of recomputing it).
-// Plane p of a launch (buffer coordinates) is read at base + p * plane_bytes
+// Source of axis-0 planes for one launch.  Plane p of a launch (buffer coordinates) is read at base + p * plane_bytes
 // for p >= 0 and at lo_base + p * plane_bytes for p < 0: a launch can start in
 // a second buffer that holds the planes just before `base` (the carried
 // planes of a stream).  lo_base = base when there is no such buffer.
@@ -91,6 +88,8 @@ struct Workspace {
     size_t img_tmp_bytes = 0;
     void *fbuf = nullptr;        // float path: records, sort scratch, curve staging
     size_t fbuf_bytes = 0;
+    void *dual_buf = nullptr;    // dual complex: gathered faces of the box, per-face curves
+    size_t dual_buf_bytes = 0;
 };
 
 int get_workspace(void *stream, Workspace **out);
@@ -114,6 +113,14 @@ int merge_stage_rows(int rows);
 int launch_merge(const int32_t *partial, int rows, int m, int64_t *stage, int64_t *vcec, bool accumulate,
                  bool do_scan, int64_t *chi, uint32_t *status, uint32_t *status_out, hipStream_t stream,
                  bool reverse = false);
+
+// Copies the n0 x n1 x n2 sub-array of src starting at element `base` with
+// element strides s0, s1, s2 into dst (contiguous, C order).
+int launch_gather(const void *src, int elem, int64_t base, int64_t s0, int64_t s1, int64_t s2, int64_t n0,
+                  int64_t n1, int64_t n2, void *dst, hipStream_t stream);
+// out[t] = sign * sum_f (-1)^((neg_mask >> f) & 1) * curves[f * m + t], t < m.
+int launch_signed_sum(const int64_t *curves, int nf, uint64_t neg_mask, int sign, int m, int64_t *out,
+                      hipStream_t stream);
 
 bool normalize_int_view(const ecc_dims *dims, IntView *v, int *err_ndim_dropped);
 int check_dims(const ecc_dims *dims, int64_t *total);

@@ -244,6 +244,58 @@ int launch_batch_merge(const MergeJob *jobs_dev, int njobs, int max_m, hipStream
     return ECC_OK;
 }
 
+// ----------------------------------------------------------------------------
+// Dual complex helpers: strided gather of a face of the box, signed sum of
+// the faces' curves.
+
+template <typename T>
+__global__ void __launch_bounds__(256) gather_kernel(const T *__restrict__ src, int64_t base, int64_t s0, int64_t s1,
+                                                     int64_t s2, int64_t n1, int64_t n2, int64_t total,
+                                                     T *__restrict__ dst) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const int64_t i2 = i % n2, r = i / n2;
+        const int64_t i1 = r % n1, i0 = r / n1;
+        dst[i] = src[base + i0 * s0 + i1 * s1 + i2 * s2];
+    }
+}
+
+int launch_gather(const void *src, int elem, int64_t base, int64_t s0, int64_t s1, int64_t s2, int64_t n0,
+                  int64_t n1, int64_t n2, void *dst, hipStream_t stream) {
+    const int64_t total = n0 * n1 * n2;
+    if (total <= 0) return ECC_OK;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (elem == 1)
+        hipLaunchKernelGGL(gather_kernel<uint8_t>, dim3((unsigned)blocks), dim3(256), 0, stream, (const uint8_t *)src,
+                           base, s0, s1, s2, n1, n2, total, (uint8_t *)dst);
+    else
+        hipLaunchKernelGGL(gather_kernel<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, stream,
+                           (const uint16_t *)src, base, s0, s1, s2, n1, n2, total, (uint16_t *)dst);
+    ECC_HIP(hipGetLastError());
+    return ECC_OK;
+}
+
+__global__ void __launch_bounds__(256) signed_sum_kernel(const int64_t *__restrict__ curves, int nf, uint64_t neg_mask,
+                                                         int sign, int m, int64_t *__restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    int64_t acc = 0;
+    for (int f = 0; f < nf; ++f) {
+        const int64_t v = curves[(size_t)f * m + t];
+        acc += ((neg_mask >> f) & 1) ? -v : v;
+    }
+    out[t] = sign < 0 ? -acc : acc;
+}
+
+int launch_signed_sum(const int64_t *curves, int nf, uint64_t neg_mask, int sign, int m, int64_t *out,
+                      hipStream_t stream) {
+    hipLaunchKernelGGL(signed_sum_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, curves, nf, neg_mask, sign, m,
+                       out);
+    ECC_HIP(hipGetLastError());
+    return ECC_OK;
+}
+
 int merge_stage_rows(int rows) {
     int by = 1;
     while (by < 32 && by * 8 <= rows) by *= 2;
