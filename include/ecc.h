@@ -51,7 +51,8 @@ typedef enum {
 typedef enum {
     ECC_U8 = 1,   /* uint8,  m = 256 */
     ECC_U14 = 2,  /* uint16 storage, values < 16384, m = 16384 */
-    ECC_U16 = 3,  /* uint16, m = 65536 */
+    ECC_U16 = 3,  /* uint16, m = 65536 (ecc_compute and ecc_compute_async; counted in passes
+                     over windows of 16382 values, see ecc_compute_async) */
     ECC_F32 = 4   /* float32; thresholds are the distinct values (Sec. 3, "Other Ranges of Gray Values") */
 } ecc_dtype;
 
@@ -119,6 +120,10 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
 
 /* Stream-ordered form for integer types with device-resident data: enqueues
  * the whole computation on `stream` and returns without synchronizing.
+ * ECC_U16 images are counted in up to five passes over the image, each
+ * counting one window of 16382 consecutive values (the workgroup histograms
+ * hold 16384 bins); this form runs all five, ecc_compute only those between
+ * the image's minimum and maximum (found first, one extra read).
  *   image_dev: device pointer, prod(n) elements.
  *   chi_dev:   device pointer, m int64 entries; written only if the input is
  *              valid (all U14 values < 16384).

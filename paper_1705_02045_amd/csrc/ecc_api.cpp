@@ -243,6 +243,52 @@ static int enqueue_int(const void *image_dev, const IntView &v, int dtype, int64
                         stream, max_entry);
 }
 
+// 16-bit images (m = 65536): one launch per window of 16382 values, windows
+// w_lo..w_hi (window w holds values 16382 w .. 16382 w + 16381, bins 1..16382
+// of its 16384-bin pass); each pass's column sums go to their place in the
+// 65536-bin changes vector, which is scanned once.
+constexpr int kU16Window = 16382;
+constexpr int kU16Windows = (65536 + kU16Window - 1) / kU16Window;
+
+static int enqueue_u16(const void *image_dev, const IntView &v, int64_t *chi_dev, uint32_t *status_out,
+                       hipStream_t stream, Workspace *ws, int w_lo, int w_hi) {
+    constexpr int mloc = 16384, mtot = 65536;
+    IntTiling tl = choose_int_tiling(v, ECC_U16, v.n0);
+    int rc = ensure_bytes((void **)&ws->partial, &ws->partial_bytes, (size_t)tl.grid * mloc * sizeof(int32_t));
+    if (rc) return rc;
+    rc = ensure_bytes((void **)&ws->vcec, &ws->vcec_bytes, (size_t)mloc * sizeof(int64_t));
+    if (rc) return rc;
+    rc = ensure_bytes((void **)&ws->stage, &ws->stage_bytes,
+                      (size_t)merge_stage_rows(tl.grid) * mloc * sizeof(int64_t));
+    if (rc) return rc;
+    rc = ensure_bytes((void **)&ws->vcec16, &ws->vcec16_bytes, (size_t)mtot * sizeof(int64_t));
+    if (rc) return rc;
+    rc = launch_zero(ws->vcec16, (size_t)mtot * sizeof(int64_t), stream);
+    if (rc) return rc;
+    IntJob job{};
+    job.src.base = (const uint8_t *)image_dev;
+    job.src.lo_base = job.src.base;
+    job.src.plane_bytes = (int64_t)v.n1 * v.n2 * 2;
+    job.view = v;
+    job.e0 = 0;
+    job.e1 = (int32_t)v.n0;
+    job.lo_inf = 1;
+    job.hi_inf = 1;
+    job.dtype = ECC_U16;
+    for (int w = w_lo; w <= w_hi; ++w) {
+        job.win_base = w * kU16Window;
+        rc = launch_int_partial(job, tl, ws->partial, ws->status, nullptr, stream);
+        if (rc) return rc;
+        rc = launch_merge(ws->partial, tl.grid, mloc, ws->stage, ws->vcec, false, false, nullptr, ws->status,
+                          nullptr, stream);
+        if (rc) return rc;
+        const int cnt = mtot - job.win_base < kU16Window ? mtot - job.win_base : kU16Window;
+        ECC_HIP(hipMemcpyAsync(ws->vcec16 + job.win_base, ws->vcec + 1, (size_t)cnt * sizeof(int64_t),
+                               hipMemcpyDeviceToDevice, stream));
+    }
+    return launch_merge(nullptr, 0, mtot, nullptr, ws->vcec16, true, true, chi_dev, ws->status, status_out, stream);
+}
+
 static bool is_device_ptr(const void *p) {
     hipPointerAttribute_t attr;
     memset(&attr, 0, sizeof attr);
@@ -264,8 +310,8 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 // and the merge writes the rows reversed).
 static int compute_int(const void *image, const ecc_dims *dims, int64_t total, ecc_dtype dtype, ecc_curve *curve,
                        hipStream_t s, bool max_entry) {
-    if (dtype == ECC_U16) {
-        set_error("dtype %d not available in this build", (int)dtype);
+    if (dtype == ECC_U16 && max_entry) {
+        set_error("the largest-value convention is available for u8 and u14");
         return ECC_E_UNSUPPORTED;
     }
     const int64_t m = threshold_count(dtype);
@@ -302,7 +348,18 @@ static int compute_int(const void *image, const ecc_dims *dims, int64_t total, e
         if (rc) return rc;
         chi_target = ws->chi_tmp;
     }
-    rc = enqueue_int(img_dev, v, dtype, chi_target, ws->status + 2, s, ws, max_entry);
+    if (dtype == ECC_U16) {  // only the windows between the image's minimum and maximum
+        uint32_t *mm = ws->status + kStatusMinMaxOffset / 4;
+        rc = launch_minmax_u16((const uint16_t *)img_dev, total, mm, s);
+        if (rc) return rc;
+        uint32_t range[2] = {0, 0};
+        ECC_HIP(hipMemcpyAsync(range, mm, sizeof range, hipMemcpyDeviceToHost, s));
+        ECC_HIP(hipStreamSynchronize(s));
+        rc = enqueue_u16(img_dev, v, chi_target, ws->status + 2, s, ws, (int)(range[0] / kU16Window),
+                         (int)(range[1] / kU16Window));
+    } else {
+        rc = enqueue_int(img_dev, v, dtype, chi_target, ws->status + 2, s, ws, max_entry);
+    }
     if (rc) return rc;
     uint32_t st = 0;
     ECC_HIP(hipMemcpyAsync(&st, ws->status + 2, 4, hipMemcpyDeviceToHost, s));
@@ -433,8 +490,8 @@ int ecc_compute_async(const void *image_dev, const ecc_dims *dims, ecc_dtype dty
         set_error("NULL image or chi");
         return ECC_E_ARG;
     }
-    if (dtype != ECC_U8 && dtype != ECC_U14) {
-        if (dtype == ECC_U16 || dtype == ECC_F32) {
+    if (dtype != ECC_U8 && dtype != ECC_U14 && dtype != ECC_U16) {
+        if (dtype == ECC_F32) {
             set_error("ecc_compute_async: dtype %d not available in this build", (int)dtype);
             return ECC_E_UNSUPPORTED;
         }
@@ -450,6 +507,8 @@ int ecc_compute_async(const void *image_dev, const ecc_dims *dims, ecc_dtype dty
     Workspace *ws = nullptr;
     rc = get_workspace(stream, &ws);
     if (rc) return rc;
+    if (dtype == ECC_U16)  // stream-ordered: every window (no host read of the value range)
+        return enqueue_u16(image_dev, v, chi_dev, status_dev, (hipStream_t)stream, ws, 0, kU16Windows - 1);
     return enqueue_int(image_dev, v, dtype, chi_dev, status_dev, (hipStream_t)stream, ws);
 }
 

@@ -42,6 +42,7 @@ struct KParams {
     int32_t lo_inf, hi_inf;
     int32_t zc;
     int32_t tiles_x, tiles_y, tiles_z;
+    int32_t win_shift;    // kXfWindow: window base - 1
     int32_t per_wg;       // tiles per workgroup (at most)
     int32_t tile_stride;  // 0: consecutive runs of per_wg tiles; 1: strided by the grid
     int32_t wx, wy;
@@ -52,6 +53,11 @@ struct KParams {
 
 // Fourth word of a raw buffer resource on gfx9-family parts (32-bit data format).
 constexpr int kBufferWord3 = 0x00020000;
+
+// transforms of the loaded values (template parameter XF)
+constexpr int kXfNone = 0;
+constexpr int kXfInvert = 1;
+constexpr int kXfWindow = 2;
 
 // Field values are LDS byte offsets of their bins (value * 4), computed with
 // packed 16-bit ops.  The 16-bit VOP2 forms (v_lshlrev_b16, v_min_u16) write
@@ -245,7 +251,7 @@ constexpr int lcm(int a, int b) {
 // The plane loop is unrolled by lcm(2, PD+1) so that every register buffer is
 // addressed with a compile-time index (plane p of the tile uses raw buffer
 // (p - zs) mod (PD+1) and field buffer (p - zs) mod 2).
-template <typename T, int NIN, int R, int MODE, bool FULL, int PD, bool INV>
+template <typename T, int NIN, int R, int MODE, bool FULL, int PD, int XF>
 __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uint32_t (&vx)[R + 1],
                                      const uint32_t (&vxl)[R + 1], const uint32_t (&soff)[R + 1], const EdgeMasks &em,
                                      uint32_t &orv) {
@@ -269,9 +275,12 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
         for (int rr = 0; rr < NR; ++rr) {
             a[rr] = load_elem(rs, vx[rr], soff[rr], ESZ);
             b[rr] = load_elem(rs, vxl[rr], soff[rr], ESZ);
-            if constexpr (INV) {  // M-1-v (M a power of two); bits >= log2 M stay for the range check
+            if constexpr (XF == kXfInvert) {  // M-1-v (M a power of two); bits >= log2 M stay for the range check
                 a[rr] ^= kInvMask;
                 b[rr] ^= kInvMask;
+            } else if constexpr (XF == kXfWindow) {  // 16-bit window: v-base+1 clamped to 0..16383
+                a[rr] = (uint32_t)max(0, min(16383, (int32_t)a[rr] - P.win_shift));
+                b[rr] = (uint32_t)max(0, min(16383, (int32_t)b[rr] - P.win_shift));
             }
         }
     };
@@ -379,7 +388,7 @@ constexpr int kWavesPerEU() {
 // The tiles of one workgroup of one image: b = the workgroup's index among
 // the image's G workgroups (G <= tiles).  Writes the counts of its tiles to
 // row b of P.partial.
-template <typename T, int M, int NIN, int R, int MODE, int PD, bool INV = false>
+template <typename T, int M, int NIN, int R, int MODE, int PD, int XF = kXfNone>
 __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const int b, const int G) {
     using W = Walker<NIN, R>;
     constexpr int NR = W::NR;
@@ -468,7 +477,7 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
     }
     if (any && zs < ze) {
         if (full) {
-            walk<T, NIN, R, MODE, true, PD, INV>(P, zs, ze, vx, vxl, soff, em, orv);
+            walk<T, NIN, R, MODE, true, PD, XF>(P, zs, ze, vx, vxl, soff, em, orv);
         } else if constexpr (NIN == 1) {
             // An edge group of segments is walked as pairs of segments, each
             // pair with its own lane masks.
@@ -485,10 +494,10 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
                 e2.lx_any2 = ballot(xb < n2);
                 const uint32_t v2[3] = {vx[r], vx[r + 1], 0u}, vl2[3] = {vxl[r], vxl[r + 1], 0u};
                 const uint32_t s2[3] = {0u, 0u, 0u};
-                walk<T, 1, 2, MODE, false, 1, INV>(P, zs, ze, v2, vl2, s2, e2, orv);
+                walk<T, 1, 2, MODE, false, 1, XF>(P, zs, ze, v2, vl2, s2, e2, orv);
             }
         } else {
-            walk<T, NIN, R, MODE, false, PD, INV>(P, zs, ze, vx, vxl, soff, em, orv);
+            walk<T, NIN, R, MODE, false, PD, XF>(P, zs, ze, vx, vxl, soff, em, orv);
         }
     }
     }  // tiles
@@ -504,14 +513,20 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
         if (i0 + tid < M) dst[i0 + tid] = hist[i0 + tid];
 }
 
-// INV: every loaded value v is replaced by M-1-v, so the histogram counts
-// each cell at M-1 minus the maximum over its voxels (the largest-value
-// convention, read back reversed by the merge).
-template <typename T, int M, int NIN, int R, int MODE, int PD, bool INV = false>
+// XF, a transform of every loaded value v:
+//  kXfInvert: M-1-v, so the histogram counts each cell at M-1 minus the
+//    maximum over its voxels (the largest-value convention, read back
+//    reversed by the merge);
+//  kXfWindow (16-bit images, M = 16384 bins per pass): v - base + 1 clamped
+//    to 0..16383, so values base..base+16381 land in bins 1..16382 and the
+//    values below / above the window in the guard bins 0 / 16383 (dropped by
+//    the merge).  The monotone clamp keeps every comparison that decides a
+//    count in bins 1..16382, since each involves the counted value itself.
+template <typename T, int M, int NIN, int R, int MODE, int PD, int XF = kXfNone>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<NIN, R, PD>())))
 int_vcec_kernel(KParams P) {
     __shared__ int32_t hist[M];
-    tile_body<T, M, NIN, R, MODE, PD, INV>(P, hist, blockIdx.x, gridDim.x);
+    tile_body<T, M, NIN, R, MODE, PD, XF>(P, hist, blockIdx.x, gridDim.x);
 }
 
 // Batched form: the tiles of many images in one launch.  Image j owns
@@ -533,13 +548,13 @@ int_vcec_batch_kernel(const KParams *__restrict__ jobs, const int32_t *__restric
     tile_body<T, M, NIN, 2, 0, 1>(P, hist, b - b0, tile_begin[lo + 1] - b0);
 }
 
-template <typename T, int M, int NIN, int R, int MODE, int PD, bool INV = false>
+template <typename T, int M, int NIN, int R, int MODE, int PD, int XF = kXfNone>
 static int launch_one(const KParams &p, const IntTiling &tl, hipStream_t stream) {
     const int threads = kWave * tl.wx * tl.wy;
     void *tok = nullptr;
     int rc = profile_begin(stream, &tok);
     if (rc) return rc;
-    hipLaunchKernelGGL((int_vcec_kernel<T, M, NIN, R, MODE, PD, INV>), dim3(tl.grid), dim3(threads), 0, stream, p);
+    hipLaunchKernelGGL((int_vcec_kernel<T, M, NIN, R, MODE, PD, XF>), dim3(tl.grid), dim3(threads), 0, stream, p);
     ECC_HIP(hipGetLastError());
     return profile_end(stream, tok);
 }
@@ -574,13 +589,13 @@ static int launch_rows(const KParams &p, const IntTiling &tl, hipStream_t stream
     return ECC_E_UNSUPPORTED;
 }
 
-// Inverted values (largest-value convention): walking mode 0, one plane of
-// look-ahead.
-template <typename T, int M, int NIN>
-static int launch_inverted(const KParams &p, const IntTiling &tl, hipStream_t stream) {
+// Transformed values (largest-value convention, 16-bit windows): walking
+// mode 0, one plane of look-ahead.
+template <typename T, int M, int NIN, int XF>
+static int launch_transformed(const KParams &p, const IntTiling &tl, hipStream_t stream) {
     switch (tl.rows) {
-    case 2: return launch_one<T, M, NIN, 2, 0, 1, true>(p, tl, stream);
-    case 4: return launch_one<T, M, NIN, 4, 0, 1, true>(p, tl, stream);
+    case 2: return launch_one<T, M, NIN, 2, 0, 1, XF>(p, tl, stream);
+    case 4: return launch_one<T, M, NIN, 4, 0, 1, XF>(p, tl, stream);
     default: break;
     }
     set_error("integer kernel: %d rows per wave not built", tl.rows);
@@ -607,6 +622,7 @@ static KParams make_params(const IntJob &job, const IntTiling &tl, int32_t *part
     p.tiles_z = (job.e1 - job.e0 + tl.zc - 1) / tl.zc;
     p.per_wg = tl.per_wg > 0 ? tl.per_wg : 1;
     p.tile_stride = tl.tile_stride;
+    p.win_shift = job.win_base - 1;
     p.partial = partial;
     p.status = status;
     p.zero_vcec = zero_vcec;
@@ -617,13 +633,16 @@ int launch_int_partial(const IntJob &job, const IntTiling &tl, int32_t *partial,
                        int64_t *zero_vcec, hipStream_t stream) {
     const KParams p = make_params(job, tl, partial, status, zero_vcec);
     const int nin = job.view.nin;
+    if (job.dtype == ECC_U16)  // one window of 16382 values per launch
+        return nin == 1 ? launch_transformed<uint16_t, 16384, 1, kXfWindow>(p, tl, stream)
+                        : launch_transformed<uint16_t, 16384, 2, kXfWindow>(p, tl, stream);
     if (job.invert) {
         if (job.dtype == ECC_U8)
-            return nin == 1 ? launch_inverted<uint8_t, 256, 1>(p, tl, stream)
-                            : launch_inverted<uint8_t, 256, 2>(p, tl, stream);
+            return nin == 1 ? launch_transformed<uint8_t, 256, 1, kXfInvert>(p, tl, stream)
+                            : launch_transformed<uint8_t, 256, 2, kXfInvert>(p, tl, stream);
         if (job.dtype == ECC_U14)
-            return nin == 1 ? launch_inverted<uint16_t, 16384, 1>(p, tl, stream)
-                            : launch_inverted<uint16_t, 16384, 2>(p, tl, stream);
+            return nin == 1 ? launch_transformed<uint16_t, 16384, 1, kXfInvert>(p, tl, stream)
+                            : launch_transformed<uint16_t, 16384, 2, kXfInvert>(p, tl, stream);
     }
     if (job.dtype == ECC_U8)
         return nin == 1 ? launch_rows<uint8_t, 256, 1>(p, tl, stream) : launch_rows<uint8_t, 256, 2>(p, tl, stream);

@@ -16,9 +16,11 @@ constexpr uint32_t kStatusRange = ECC_STATUS_RANGE_BIT;
 constexpr uint32_t kStatusNaN = 2u;  // a float image holds a NaN
 // Device status block (1024 bytes per workspace or stream): word 0 status,
 // word 1 its copy taken by the scan, word 2 the copy handed to the host,
-// bytes [kStatusTotalsOffset, +512) the scan's group totals.
+// words 8-9 a value range, bytes [kStatusTotalsOffset, +512) the scan's
+// group totals.
 constexpr size_t kStatusBytes = 1024;
 constexpr size_t kStatusTotalsOffset = 128;
+constexpr size_t kStatusMinMaxOffset = 32;  // two words: minimum and maximum of a 16-bit image
 
 void set_error(const char *fmt, ...);
 void g_err_clear();
@@ -57,6 +59,7 @@ struct IntJob {
     int32_t hi_inf;       // plane e1 lies outside the image
     int dtype;            // ECC_U8 or ECC_U14
     int invert;           // values read as M-1-v (largest-value convention)
+    int32_t win_base;     // ECC_U16: first value of the window counted by this launch
 };
 
 // Tiling of the integer kernel (chosen by choose_int_tiling in ecc_api.cpp).
@@ -90,6 +93,8 @@ struct Workspace {
     size_t fbuf_bytes = 0;
     void *dual_buf = nullptr;    // dual complex: gathered faces of the box, per-face curves
     size_t dual_buf_bytes = 0;
+    int64_t *vcec16 = nullptr;   // [65536] changes vector of a 16-bit image (window passes)
+    size_t vcec16_bytes = 0;
 };
 
 int get_workspace(void *stream, Workspace **out);
@@ -118,6 +123,8 @@ int launch_merge(const int32_t *partial, int rows, int m, int64_t *stage, int64_
 // element strides s0, s1, s2 into dst (contiguous, C order).
 int launch_gather(const void *src, int elem, int64_t base, int64_t s0, int64_t s1, int64_t s2, int64_t n0,
                   int64_t n1, int64_t n2, void *dst, hipStream_t stream);
+// Minimum and maximum of n uint16 values into out[0], out[1].
+int launch_minmax_u16(const uint16_t *img, int64_t n, uint32_t *out, hipStream_t stream);
 // out[t] = sign * sum_f (-1)^((neg_mask >> f) & 1) * curves[f * m + t], t < m.
 int launch_signed_sum(const int64_t *curves, int nf, uint64_t neg_mask, int sign, int m, int64_t *out,
                       hipStream_t stream);

@@ -296,6 +296,54 @@ int launch_signed_sum(const int64_t *curves, int nf, uint64_t neg_mask, int sign
     return ECC_OK;
 }
 
+__global__ void minmax_init_kernel(uint32_t *out) {
+    out[0] = 0xFFFFFFFFu;
+    out[1] = 0u;
+}
+
+__global__ void __launch_bounds__(256) minmax_u16_kernel(const uint16_t *__restrict__ img, int64_t n, int vec,
+                                                         uint32_t *out) {
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t n8 = vec ? n / 8 : 0;  // 16-byte groups when the image is 16-byte aligned
+    const uint4 *v8 = reinterpret_cast<const uint4 *>(img);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8; i += stride) {
+        const uint4 q = v8[i];
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t a = w[j] & 0xFFFFu, b = w[j] >> 16;
+            lo = min(lo, min(a, b));
+            hi = max(hi, max(a, b));
+        }
+    }
+    for (int64_t i = n8 * 8 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        lo = min(lo, (uint32_t)img[i]);
+        hi = max(hi, (uint32_t)img[i]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, (uint32_t)__shfl_xor((int)lo, off, 64));
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&out[0], lo);
+        atomicMax(&out[1], hi);
+    }
+}
+
+int launch_minmax_u16(const uint16_t *img, int64_t n, uint32_t *out, hipStream_t stream) {
+    hipLaunchKernelGGL(minmax_init_kernel, dim3(1), dim3(1), 0, stream, out);
+    ECC_HIP(hipGetLastError());
+    int64_t blocks = (n / 8 + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 4096) blocks = 4096;
+    const int vec = ((uintptr_t)img % 16) == 0;
+    hipLaunchKernelGGL(minmax_u16_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, img, n, vec, out);
+    ECC_HIP(hipGetLastError());
+    return ECC_OK;
+}
+
 int merge_stage_rows(int rows) {
     int by = 1;
     while (by < 32 && by * 8 <= rows) by *= 2;
