@@ -103,6 +103,32 @@ int ecc_compute(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_cu
 int ecc_compute_max_entry(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_curve *curve,
                           void *stream);
 
+/* Float32 curve restricted to its change points (Sec. 3, "Other Ranges of
+ * Gray Values": the curve is a step function over the distinct values): the
+ * distinct values after which chi differs from its value before them (chi
+ * = 0 below the smallest value), ascending, with chi after each.  A subset
+ * of ecc_compute's ECC_F32 output, which lists every distinct value.
+ *   dtype: ECC_F32 (others: ECC_E_UNSUPPORTED).
+ *   curve: keys and chi as for ecc_compute; count = number of change points.
+ * Errors as ecc_compute for ECC_F32. */
+int ecc_compute_change_points(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_curve *curve,
+                              void *stream);
+
+/* Float32 image quantised to integer bins, then the integer curve (Sec. 3,
+ * "Range of Values": values shifted and scaled into {0, ..., m-1}):
+ *   scale = m / (hi - lo), x = (v - lo) * scale, all in float32 with
+ *   round-to-nearest and no fused multiply-add; bin = 0 for x < 0 (and
+ *   v = -inf), m-1 for x >= m (and +inf), else the integer part of x.
+ * chi[t] equals the float curve at the largest value whose bin is <= t (the
+ * sublevel sets of the bins are sublevel sets of the image).
+ *   bins: ECC_U8 (m = 256), ECC_U14 (16384) or ECC_U16 (65536).
+ *   lo < hi, both finite.  image: host or device float32; curve as
+ *   ecc_compute for the integer type.
+ * Errors: ECC_E_ARG, ECC_E_NAN, ECC_E_BUFFER_TOO_SMALL, ECC_E_NOMEM,
+ * ECC_E_HIP, ECC_E_UNSUPPORTED. */
+int ecc_compute_quantized(const float *image, const ecc_dims *dims, float lo, float hi, ecc_dtype bins,
+                          ecc_curve *curve, void *stream);
+
 /* The dual complex of the image (the alternative the footnote to Sec. 2,
  * "Consecutive Thresholded Images as Sublevel Set Filtrations", names:
  * voxels become vertices, with the lower-star filtration).  Vertices are the

@@ -49,6 +49,11 @@ class Curve(ctypes.Structure):
 _vp = ctypes.c_void_p
 _lib.ecc_compute.restype = ctypes.c_int
 _lib.ecc_compute.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_int, ctypes.POINTER(Curve), _vp]
+_lib.ecc_compute_change_points.restype = ctypes.c_int
+_lib.ecc_compute_change_points.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_int, ctypes.POINTER(Curve), _vp]
+_lib.ecc_compute_quantized.restype = ctypes.c_int
+_lib.ecc_compute_quantized.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_float, ctypes.c_float, ctypes.c_int,
+                                       ctypes.POINTER(Curve), _vp]
 _lib.ecc_compute_dual.restype = ctypes.c_int
 _lib.ecc_compute_dual.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_int, ctypes.POINTER(Curve), _vp]
 _lib.ecc_compute_max_entry.restype = ctypes.c_int
@@ -194,6 +199,43 @@ def compute_max_entry(image, dtype: str):
     """ecc_compute_max_entry on a CUDA tensor (integer dtypes): each cell's value
     is the maximum over its voxels.  Returns the int64 curve on the same device."""
     return _compute_int_variant(_lib.ecc_compute_max_entry, "compute_max_entry", image, dtype)
+
+
+def compute_change_points(image):
+    """ecc_compute_change_points on a float32 CUDA tensor: (keys, chi) at the
+    distinct values where chi changes."""
+    import torch
+    if not image.is_cuda:
+        raise ValueError("compute_change_points() takes a device tensor")
+    image = image.contiguous()
+    dims = make_dims(image.shape)
+    dev = image.device
+    n = image.numel()
+    with torch.cuda.device(dev):
+        chi = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+        keys = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+        cv = Curve(capacity=n, count=0, chi=chi.data_ptr(), keys=keys.data_ptr())
+        _check(_lib.ecc_compute_change_points(image.data_ptr(), ctypes.byref(dims), DTYPES["f32"], ctypes.byref(cv),
+                                              _stream_handle(dev)), "ecc_compute_change_points")
+        return keys[: cv.count], chi[: cv.count]
+
+
+def compute_quantized(image, lo: float, hi: float, bins: str):
+    """ecc_compute_quantized on a float32 CUDA tensor: the integer curve of the
+    image quantised to `bins` ("u8", "u14", "u16") over [lo, hi)."""
+    import torch
+    if not image.is_cuda:
+        raise ValueError("compute_quantized() takes a device tensor")
+    image = image.contiguous()
+    dims = make_dims(image.shape)
+    dev = image.device
+    with torch.cuda.device(dev):
+        m = THRESHOLDS[bins]
+        chi = torch.empty(m, dtype=torch.int64, device=dev)
+        cv = Curve(capacity=m, count=0, chi=chi.data_ptr(), keys=None)
+        _check(_lib.ecc_compute_quantized(image.data_ptr(), ctypes.byref(dims), float(lo), float(hi), DTYPES[bins],
+                                          ctypes.byref(cv), _stream_handle(dev)), "ecc_compute_quantized")
+        return chi
 
 
 def compute_dual(image, dtype: str):

@@ -380,7 +380,10 @@ static int compute_int(const void *image, const ecc_dims *dims, int64_t total, e
     return ECC_OK;
 }
 
-static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc_curve *curve, hipStream_t s) {
+// steps_only: the output keeps the keys where chi changes (chi = 0 before
+// the first key), compacted after the full curve is built.
+static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc_curve *curve, hipStream_t s,
+                         bool steps_only = false) {
     if (!curve->keys) {
         set_error("ECC_F32 needs curve->keys");
         return ECC_E_ARG;
@@ -400,16 +403,19 @@ static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc
     // scan sums, the curve's tile sums and the distinct-value count
     const int64_t tiles = radix_tiles(n);
     const int64_t ft = float_tiles(n);
-    size_t off[7], total = 0;
-    const size_t sz[7] = {(size_t)n * 8, (size_t)n * 8, (size_t)(256 * tiles) * 4,
-                          (size_t)radix_scan_tiles(256 * tiles) * 4, (size_t)ft * 8, (size_t)ft * 8, 8};
-    for (int i = 0; i < 7; ++i) {
+    // (and for steps_only: change-point positions, their scan sums and count)
+    size_t off[10], total = 0;
+    const size_t sz[10] = {(size_t)n * 8, (size_t)n * 8, (size_t)(256 * tiles) * 4,
+                           (size_t)radix_scan_tiles(256 * tiles) * 4, (size_t)ft * 8, (size_t)ft * 8, 8,
+                           steps_only ? (size_t)n * 4 : 0, steps_only ? (size_t)radix_scan_tiles(n) * 4 : 0, 8};
+    for (int i = 0; i < 10; ++i) {
         off[i] = total;
         total += align256(sz[i]);
     }
     // curve staging unless the caller's buffers are device memory that holds
     // any possible count (n entries)
-    const bool direct = curve->capacity >= n && is_device_ptr(curve->chi) && is_device_ptr(curve->keys);
+    const bool direct = !steps_only && curve->capacity >= n && is_device_ptr(curve->chi) &&
+                        is_device_ptr(curve->keys);
     const size_t out_k = total, out_c = out_k + align256((size_t)n * 4);
     if (!direct) total = out_c + align256((size_t)n * 8);
     rc = ensure_bytes(&ws->fbuf, &ws->fbuf_bytes, total);
@@ -446,9 +452,21 @@ static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc
         set_error("internal error: device status 0x%08x", st);
         return ECC_E_HIP;
     }
+    if (steps_only) {  // compact into the record buffers, free after the curve
+        float *step_keys = (float *)rec[1];
+        int64_t *step_chi = (int64_t *)rec[0];
+        int64_t *count2_dev = (int64_t *)(b + off[9]);
+        rc = launch_change_points(out_keys, out_chi, kcount, (uint32_t *)(b + off[7]), (uint32_t *)(b + off[8]),
+                                  step_keys, step_chi, count2_dev, s);
+        if (rc) return rc;
+        ECC_HIP(hipMemcpyAsync(&kcount, count2_dev, 8, hipMemcpyDeviceToHost, s));
+        ECC_HIP(hipStreamSynchronize(s));
+        out_keys = step_keys;
+        out_chi = step_chi;
+    }
     if (kcount > curve->capacity) {
         curve->count = kcount;
-        set_error("curve capacity %lld < %lld distinct values", (long long)curve->capacity, (long long)kcount);
+        set_error("curve capacity %lld < %lld output entries", (long long)curve->capacity, (long long)kcount);
         return ECC_E_BUFFER_TOO_SMALL;
     }
     if (!direct) {
@@ -540,6 +558,78 @@ int ecc_compute_max_entry(const void *image, const ecc_dims *dims, ecc_dtype dty
         return ECC_E_UNSUPPORTED;
     }
     return compute_int(image, dims, total, dtype, curve, (hipStream_t)stream, true);
+}
+
+int ecc_compute_change_points(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_curve *curve,
+                              void *stream) {
+    g_err[0] = 0;
+    int64_t total = 0;
+    int rc = check_dims(dims, &total);
+    if (rc) return rc;
+    if (!image || !curve || !curve->chi) {
+        set_error("NULL image, curve or curve->chi");
+        return ECC_E_ARG;
+    }
+    if (dtype != ECC_F32) {
+        set_error("ecc_compute_change_points: ECC_F32 only");
+        return dtype >= ECC_U8 && dtype <= ECC_U16 ? ECC_E_UNSUPPORTED : ECC_E_ARG;
+    }
+    return compute_float(image, dims, total, curve, (hipStream_t)stream, true);
+}
+
+int ecc_compute_quantized(const float *image, const ecc_dims *dims, float lo, float hi, ecc_dtype bins,
+                          ecc_curve *curve, void *stream) {
+    g_err[0] = 0;
+    int64_t total = 0;
+    int rc = check_dims(dims, &total);
+    if (rc) return rc;
+    if (!image || !curve || !curve->chi) {
+        set_error("NULL image, curve or curve->chi");
+        return ECC_E_ARG;
+    }
+    if (bins != ECC_U8 && bins != ECC_U14 && bins != ECC_U16) {
+        set_error("ecc_compute_quantized: bins must be ECC_U8, ECC_U14 or ECC_U16");
+        return ECC_E_ARG;
+    }
+    const float width = hi - lo;
+    if (!(width > 0.0f) || !(width <= 3.0e38f)) {
+        set_error("ecc_compute_quantized: need lo < hi, both finite");
+        return ECC_E_ARG;
+    }
+    const int64_t m = threshold_count(bins);
+    if (curve->capacity < m) {
+        curve->count = m;
+        set_error("curve capacity %lld < %lld", (long long)curve->capacity, (long long)m);
+        return ECC_E_BUFFER_TOO_SMALL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Workspace *ws = nullptr;
+    rc = get_workspace(s, &ws);
+    if (rc) return rc;
+    const float *img_dev = image;
+    const size_t qbytes = (size_t)total * elem_bytes(bins);
+    const size_t qoff = is_device_ptr(image) ? 0 : align256((size_t)total * 4);
+    rc = ensure_bytes(&ws->img_tmp, &ws->img_tmp_bytes, qoff + qbytes);
+    if (rc) return rc;
+    if (qoff) {
+        ECC_HIP(hipMemcpyAsync(ws->img_tmp, image, (size_t)total * 4, hipMemcpyHostToDevice, s));
+        img_dev = (const float *)ws->img_tmp;
+    }
+    void *q = (uint8_t *)ws->img_tmp + qoff;
+    const float scale = (float)m / width;
+    uint32_t *flag = ws->status + kStatusMinMaxOffset / 4 + 2;  // NaN flag word
+    rc = launch_zero(flag, 4, s);
+    if (rc) return rc;
+    rc = launch_quantize(img_dev, total, lo, scale, (int)m, (int)elem_bytes(bins), q, flag, s);
+    if (rc) return rc;
+    uint32_t nan = 0;
+    ECC_HIP(hipMemcpyAsync(&nan, flag, 4, hipMemcpyDeviceToHost, s));
+    ECC_HIP(hipStreamSynchronize(s));
+    if (nan) {
+        set_error("a float image holds a NaN");
+        return ECC_E_NAN;
+    }
+    return compute_int(q, dims, total, bins, curve, s, false);
 }
 
 // Dual complex (voxels as vertices, lower-star filtration).  Its cells are

@@ -377,4 +377,90 @@ int launch_float_curve(const uint64_t *rec, int64_t n, int64_t *tile_chg, int64_
 
 int64_t float_tiles(int64_t n) { return (n + kFTile - 1) / kFTile; }
 
+// ----------------------------------------------------------------------------
+// Change points of a float curve: the keys where chi differs from the
+// previous key's (chi = 0 before the first key).
+
+__device__ __forceinline__ uint32_t is_step(const int64_t *chi, int64_t k) {
+    return chi[k] != (k > 0 ? chi[k - 1] : 0) ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(256) step_flags_kernel(const int64_t *__restrict__ chi, int64_t K,
+                                                         uint32_t *__restrict__ pos) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += stride) pos[k] = is_step(chi, k);
+}
+
+__global__ void __launch_bounds__(256) step_scatter_kernel(const float *__restrict__ keys,
+                                                           const int64_t *__restrict__ chi,
+                                                           const uint32_t *__restrict__ pos, int64_t K,
+                                                           float *__restrict__ out_keys,
+                                                           int64_t *__restrict__ out_chi, int64_t *count) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += stride) {
+        const uint32_t f = is_step(chi, k);
+        if (f) {
+            out_keys[pos[k]] = keys[k];
+            out_chi[pos[k]] = chi[k];
+        }
+        if (k == K - 1) *count = (int64_t)pos[k] + f;
+    }
+}
+
+// pos: K uint32 (positions, scratch); sums: radix_scan_tiles(K) uint32.
+int launch_change_points(const float *keys, const int64_t *chi, int64_t K, uint32_t *pos, uint32_t *sums,
+                         float *out_keys, int64_t *out_chi, int64_t *count, hipStream_t stream) {
+    if (K <= 0) return ECC_OK;
+    int64_t blocks = (K + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(step_flags_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, chi, K, pos);
+    ECC_HIP(hipGetLastError());
+    int rc = exclusive_scan_u32(pos, K, sums, stream);
+    if (rc) return rc;
+    hipLaunchKernelGGL(step_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, keys, chi,
+                       (const uint32_t *)pos, K, out_keys, out_chi, count);
+    ECC_HIP(hipGetLastError());
+    return ECC_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Quantisation of a float image to integer bins: x = (v - lo) * scale in
+// float32 (each operation rounded to nearest); bin 0 below x = 0 (and -inf),
+// m-1 from x = m on (and +inf), else the integer part of x.  NaN sets the
+// status bit and writes bin 0.
+
+template <typename T>
+__global__ void __launch_bounds__(256) quantize_kernel(const float *__restrict__ img, int64_t n, float lo,
+                                                       float scale, int m, T *__restrict__ out,
+                                                       uint32_t *status) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool nan = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const float v = img[i];
+        nan |= v != v;
+        const float x = __fmul_rn(__fsub_rn(v, lo), scale);
+        int q;
+        if (!(x >= 0.0f)) q = 0;
+        else if (x >= (float)m) q = m - 1;
+        else q = (int)x;
+        out[i] = (T)q;
+    }
+    if (__builtin_amdgcn_ballot_w64(nan) != 0 && (threadIdx.x & 63) == 0) atomicOr(status, kStatusNaN);
+}
+
+int launch_quantize(const float *img, int64_t n, float lo, float scale, int m, int elem, void *out,
+                    uint32_t *status, hipStream_t stream) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    if (elem == 1)
+        hipLaunchKernelGGL(quantize_kernel<uint8_t>, dim3((unsigned)blocks), dim3(256), 0, stream, img, n, lo, scale,
+                           m, (uint8_t *)out, status);
+    else
+        hipLaunchKernelGGL(quantize_kernel<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, stream, img, n, lo,
+                           scale, m, (uint16_t *)out, status);
+    ECC_HIP(hipGetLastError());
+    return ECC_OK;
+}
+
 }  // namespace ecc

@@ -162,6 +162,14 @@ int radix_sort_records(uint64_t *rec[2], int64_t n, uint32_t *counts, uint32_t *
 int64_t float_tiles(int64_t n);
 int launch_float_curve(const uint64_t *rec, int64_t n, int64_t *tile_chg, int64_t *tile_last,
                        int64_t *total_last, float *out_keys, int64_t *out_chi, hipStream_t stream);
+// Exclusive scan of n uint32 in place; sums: radix_scan_tiles(n) entries.
+int exclusive_scan_u32(uint32_t *a, int64_t n, uint32_t *sums, hipStream_t stream);
+// Keys where chi changes, compacted (count written on the device).
+int launch_change_points(const float *keys, const int64_t *chi, int64_t K, uint32_t *pos, uint32_t *sums,
+                         float *out_keys, int64_t *out_chi, int64_t *count, hipStream_t stream);
+// Float image to integer bins (elem = 1 or 2 bytes), NaN -> kStatusNaN.
+int launch_quantize(const float *img, int64_t n, float lo, float scale, int m, int elem, void *out,
+                    uint32_t *status, hipStream_t stream);
 
 // Optional event timing of the per-voxel kernels (ecc_profile.cpp).
 int profile_begin(hipStream_t s, void **token);

@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(uint32_t *__re
     }
 }
 
-static int exclusive_scan_u32(uint32_t *a, int64_t n, uint32_t *sums, hipStream_t stream) {
+int exclusive_scan_u32(uint32_t *a, int64_t n, uint32_t *sums, hipStream_t stream) {
     const int64_t nt = (n + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(scan_tile_sums_kernel, dim3((unsigned)nt), dim3(kScanThreads), 0, stream, (const uint32_t *)a, n,
                        sums);
