@@ -13,8 +13,8 @@ the same volume on this host.  Under "legs": the other workloads of the path
 (serving mix at a p99 latency bound, 4-D float32, host-staged streaming of
 8192^2 x 1024 against the measured host-to-device copy rate, the
 2600 x 14450^2 volume made and streamed slab by slab on the device, the
-largest-value and dual constructions on the headline volume, the 2-D 256^2
-uint8 latency), each timed after the headline steps.
+largest-value and dual constructions on the headline volume, 1024^3 16-bit
+images, the 2-D 256^2 uint8 latency), each timed after the headline steps.
 """
 from __future__ import annotations
 
@@ -302,6 +302,31 @@ def leg_conventions(vol, reps: int):
     return out
 
 
+def leg_u16(reps: int):
+    """1024^3 16-bit value noise (lattice 16, jitter +-256, seed 1, full 0..65535
+    range: five windows) and the same volume shifted into 14-bit range as
+    16-bit data (one window): synchronous ecc_compute, device in and out."""
+    import numpy as np
+    import torch
+    import gen
+    import paper_1705_02045_amd as ecc
+    img = gen.value_noise((1024, 1024, 1024), 16, 256, seed=1)
+    out = {}
+    for name, arr in (("full_range", img), ("14bit_range", img >> 2)):
+        t = torch.from_numpy(arr.view(np.int16)).cuda()
+        ecc.compute(t, "u16")
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            ecc.compute(t, "u16")
+            times.append(time.perf_counter() - t0)
+        ms = float(np.median(times)) * 1e3
+        out[name] = {"ms": round(ms, 3), "gvoxel_per_s": round(arr.size / ms / 1e6, 2),
+                     "value_range": [int(arr.min()), int(arr.max())]}
+        del t
+    return out
+
+
 def leg_small_2d(reps: int):
     """2-D 256x256 uint8 i.i.d. (seed 0): latency of one synchronous ecc_compute
     (device image, device curve) and the oracle on the same image."""
@@ -332,7 +357,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, default=1024, help="edge of the cubic volume")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget; 0 skips it")
-    ap.add_argument("--legs", default="serving,float,stream_host,stream_device,conventions,small_2d",
+    ap.add_argument("--legs", default="serving,float,stream_host,stream_device,conventions,u16,small_2d",
                     help="further workloads reported under 'legs' (comma list, or 'none')")
     ap.add_argument("--serve-requests", type=int, default=1024)
     ap.add_argument("--serve-slo-ms", type=float, default=10.0)
@@ -420,6 +445,8 @@ def main():
             legs[leg] = leg_stream_host(1024, 8192, 16, 4)
         elif leg == "stream_device":
             legs[leg] = leg_stream_device((2600, 14450, 14450), 64)
+        elif leg == "u16":
+            legs[leg] = leg_u16(10)
         elif leg == "conventions":
             legs[leg] = leg_conventions(vol, 20)
         elif leg == "small_2d":
