@@ -243,16 +243,41 @@ static int enqueue_int(const void *image_dev, const IntView &v, int dtype, int64
                         stream, max_entry);
 }
 
-// 16-bit images (m = 65536): one launch per window of 16382 values, windows
-// w_lo..w_hi (window w holds values 16382 w .. 16382 w + 16381, bins 1..16382
-// of its 16384-bin pass); each pass's column sums go to their place in the
-// 65536-bin changes vector, which is scanned once.
-constexpr int kU16Window = 16382;
-constexpr int kU16Windows = (65536 + kU16Window - 1) / kU16Window;
+// 16-bit images (m = 65536): the workgroup histograms hold 16384 bins, so
+// one launch counts one window of values.  The kernel reads
+// bin = clamp(v - shift, 0, 16383); bins [klo, khi] are values
+// [shift + klo, shift + khi].  A window needs a guard bin only on a side
+// where the image has values outside it: bin 0 when values below exist
+// (klo = 1), bin 16383 when values above exist (khi = 16382).  The guard
+// bins are dropped; the monotone clamp keeps every comparison that decides a
+// kept bin (each involves the counted value itself).  Each pass's column
+// sums go to their place in the 65536-bin changes vector, scanned once.
+struct U16Window {
+    int32_t shift;
+    int klo, khi;
+};
+
+static int plan_u16_windows(uint32_t vmin, uint32_t vmax, U16Window *w) {
+    int n = 0;
+    int64_t v = vmin;
+    while (v <= (int64_t)vmax) {
+        U16Window x;
+        x.klo = v > (int64_t)vmin ? 1 : 0;
+        x.shift = (int32_t)(v - x.klo);
+        x.khi = (int64_t)x.shift + 16383 >= (int64_t)vmax ? (int)((int64_t)vmax - x.shift) : 16382;
+        w[n++] = x;
+        v = (int64_t)x.shift + x.khi + 1;
+    }
+    return n;
+}
+
+constexpr int kU16MaxWindows = 5;  // 16383 + 3 * 16382 + 16383 >= 65536
 
 static int enqueue_u16(const void *image_dev, const IntView &v, int64_t *chi_dev, uint32_t *status_out,
-                       hipStream_t stream, Workspace *ws, int w_lo, int w_hi) {
+                       hipStream_t stream, Workspace *ws, uint32_t vmin, uint32_t vmax) {
     constexpr int mloc = 16384, mtot = 65536;
+    U16Window win[kU16MaxWindows + 1];
+    const int nwin = plan_u16_windows(vmin, vmax, win);
     IntTiling tl = choose_int_tiling(v, ECC_U16, v.n0);
     int rc = ensure_bytes((void **)&ws->partial, &ws->partial_bytes, (size_t)tl.grid * mloc * sizeof(int32_t));
     if (rc) return rc;
@@ -275,18 +300,46 @@ static int enqueue_u16(const void *image_dev, const IntView &v, int64_t *chi_dev
     job.lo_inf = 1;
     job.hi_inf = 1;
     job.dtype = ECC_U16;
-    for (int w = w_lo; w <= w_hi; ++w) {
-        job.win_base = w * kU16Window;
+    for (int i = 0; i < nwin; ++i) {
+        job.win_shift = win[i].shift;
         rc = launch_int_partial(job, tl, ws->partial, ws->status, nullptr, stream);
         if (rc) return rc;
         rc = launch_merge(ws->partial, tl.grid, mloc, ws->stage, ws->vcec, false, false, nullptr, ws->status,
                           nullptr, stream);
         if (rc) return rc;
-        const int cnt = mtot - job.win_base < kU16Window ? mtot - job.win_base : kU16Window;
-        ECC_HIP(hipMemcpyAsync(ws->vcec16 + job.win_base, ws->vcec + 1, (size_t)cnt * sizeof(int64_t),
-                               hipMemcpyDeviceToDevice, stream));
+        ECC_HIP(hipMemcpyAsync(ws->vcec16 + win[i].shift + win[i].klo, ws->vcec + win[i].klo,
+                               (size_t)(win[i].khi - win[i].klo + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                               stream));
     }
     return launch_merge(nullptr, 0, mtot, nullptr, ws->vcec16, true, true, chi_dev, ws->status, status_out, stream);
+}
+
+// Changes vector only (no scan) of a device image into vcec_out; a range
+// error stays set in ws->status for a later scan to report.
+static int enqueue_int_changes(const void *image_dev, const IntView &v, int dtype, int64_t *vcec_out,
+                               hipStream_t stream, Workspace *ws, bool max_entry) {
+    const int m = (int)threshold_count(dtype);
+    IntTiling tl = choose_int_tiling(v, dtype, v.n0);
+    int rc = ensure_bytes((void **)&ws->partial, &ws->partial_bytes, (size_t)tl.grid * m * sizeof(int32_t));
+    if (rc) return rc;
+    rc = ensure_bytes((void **)&ws->stage, &ws->stage_bytes,
+                      (size_t)merge_stage_rows(tl.grid) * m * sizeof(int64_t));
+    if (rc) return rc;
+    IntJob job{};
+    job.src.base = (const uint8_t *)image_dev;
+    job.src.lo_base = job.src.base;
+    job.src.plane_bytes = (int64_t)v.n1 * v.n2 * (int64_t)elem_bytes(dtype);
+    job.view = v;
+    job.e0 = 0;
+    job.e1 = (int32_t)v.n0;
+    job.lo_inf = 1;
+    job.hi_inf = 1;
+    job.dtype = dtype;
+    job.invert = max_entry ? 1 : 0;
+    rc = launch_int_partial(job, tl, ws->partial, ws->status, nullptr, stream);
+    if (rc) return rc;
+    return launch_merge(ws->partial, tl.grid, m, ws->stage, vcec_out, false, false, nullptr, ws->status, nullptr,
+                        stream, max_entry);
 }
 
 static bool is_device_ptr(const void *p) {
@@ -355,8 +408,7 @@ static int compute_int(const void *image, const ecc_dims *dims, int64_t total, e
         uint32_t range[2] = {0, 0};
         ECC_HIP(hipMemcpyAsync(range, mm, sizeof range, hipMemcpyDeviceToHost, s));
         ECC_HIP(hipStreamSynchronize(s));
-        rc = enqueue_u16(img_dev, v, chi_target, ws->status + 2, s, ws, (int)(range[0] / kU16Window),
-                         (int)(range[1] / kU16Window));
+        rc = enqueue_u16(img_dev, v, chi_target, ws->status + 2, s, ws, range[0], range[1]);
     } else {
         rc = enqueue_int(img_dev, v, dtype, chi_target, ws->status + 2, s, ws, max_entry);
     }
@@ -525,8 +577,8 @@ int ecc_compute_async(const void *image_dev, const ecc_dims *dims, ecc_dtype dty
     Workspace *ws = nullptr;
     rc = get_workspace(stream, &ws);
     if (rc) return rc;
-    if (dtype == ECC_U16)  // stream-ordered: every window (no host read of the value range)
-        return enqueue_u16(image_dev, v, chi_dev, status_dev, (hipStream_t)stream, ws, 0, kU16Windows - 1);
+    if (dtype == ECC_U16)  // stream-ordered: windows over all values (no host read of the value range)
+        return enqueue_u16(image_dev, v, chi_dev, status_dev, (hipStream_t)stream, ws, 0, 65535);
     return enqueue_int(image_dev, v, dtype, chi_dev, status_dev, (hipStream_t)stream, ws);
 }
 
@@ -638,7 +690,9 @@ int ecc_compute_quantized(const float *image, const ecc_dims *dims, float lo, fl
 // inclusion-exclusion over the faces F of the box (every axis free, or fixed
 // at its first or last index):
 //   dual(f)(t) = (-1)^d sum_F (-1)^codim(F) max_entry(f|F)(t).
-// Axes of length 1 are dropped first (a product with a point).
+// The sum is linear, so it is taken over the faces' changes vectors and the
+// result is scanned once.  Axes of length 1 are dropped first (a product
+// with a point).
 int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_curve *curve, void *stream) {
     g_err[0] = 0;
     int64_t total = 0;
@@ -689,7 +743,8 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
     int64_t face_max = 1;  // the largest face of codimension >= 1
     for (int k = 0; k < d; ++k)
         if (total / n[k] > face_max) face_max = total / n[k];
-    // dual_buf: [nf][m] per-face curves, [m] result, then one gathered face
+    // dual_buf: [nf][m] per-face changes vectors, [m] their signed sum, then
+    // one gathered face
     const size_t curves_bytes = (size_t)(nf + 1) * m * sizeof(int64_t);
     const size_t face_off = (curves_bytes + 255) & ~(size_t)255;
     rc = ensure_bytes(&ws->dual_buf, &ws->dual_buf_bytes, face_off + (size_t)face_max * eb);
@@ -735,11 +790,16 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
             set_error("ecc_compute_dual: face shape not supported");
             return ECC_E_UNSUPPORTED;
         }
-        rc = enqueue_int(src, v, dtype, curves + (size_t)f * m, codim == 0 ? ws->status + 2 : nullptr, s, ws, true);
+        rc = enqueue_int_changes(src, v, dtype, curves + (size_t)f * m, s, ws, true);
         if (rc) return rc;
         if (codim & 1) neg |= 1ull << f;
     }
     rc = launch_signed_sum(curves, nf, neg, (d & 1) ? -1 : 1, (int)m, result, s);
+    if (rc) return rc;
+    // scan into slot 0 (its changes are summed already); the status of every
+    // face launch (all read the image's values) is reported and cleared here
+    int64_t *chi_dev = curves;
+    rc = launch_merge(nullptr, 0, (int)m, nullptr, result, true, true, chi_dev, ws->status, ws->status + 2, s);
     if (rc) return rc;
     uint32_t stv = 0;
     ECC_HIP(hipMemcpyAsync(&stv, ws->status + 2, 4, hipMemcpyDeviceToHost, s));
@@ -752,7 +812,7 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
         set_error("internal error: device status 0x%08x", stv);
         return ECC_E_HIP;
     }
-    ECC_HIP(hipMemcpyAsync(curve->chi, result, (size_t)m * sizeof(int64_t), hipMemcpyDefault, s));
+    ECC_HIP(hipMemcpyAsync(curve->chi, chi_dev, (size_t)m * sizeof(int64_t), hipMemcpyDefault, s));
     ECC_HIP(hipStreamSynchronize(s));
     curve->count = m;
     return ECC_OK;

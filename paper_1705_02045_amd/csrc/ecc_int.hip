@@ -42,7 +42,7 @@ struct KParams {
     int32_t lo_inf, hi_inf;
     int32_t zc;
     int32_t tiles_x, tiles_y, tiles_z;
-    int32_t win_shift;    // kXfWindow: window base - 1
+    int32_t win_shift;    // kXfWindow: bin = clamp(v - win_shift, 0, 16383)
     int32_t per_wg;       // tiles per workgroup (at most)
     int32_t tile_stride;  // 0: consecutive runs of per_wg tiles; 1: strided by the grid
     int32_t wx, wy;
@@ -169,21 +169,25 @@ struct Walker {
 
     // Fields of one plane, flattened as item i = r*K + k.  a[rr], b[rr]: raw
     // values at x and at x-1 (clamped) of loaded row rr (NIN == 2: rr = 0 is
-    // the collar row y0-1).
+    // the collar row y0-1); xf(v): the value transform, applied as each value
+    // is consumed.
+    template <typename X>
     static __device__ __forceinline__ void fields(const uint32_t (&a)[NR], const uint32_t (&b)[NR],
-                                                  uint32_t (&g)[NI]) {
+                                                  uint32_t (&g)[NI], X xf) {
         if constexpr (NIN == 1) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                g[2 * r + 0] = bin_off(a[r]);
-                g[2 * r + 1] = bin_off_min(a[r], b[r]);
+                const uint32_t va = xf(a[r]);
+                g[2 * r + 0] = bin_off(va);
+                g[2 * r + 1] = bin_off_min(va, xf(b[r]));
             }
         } else {
             uint32_t f0[NR], fx[NR];
 #pragma unroll
             for (int rr = 0; rr < NR; ++rr) {
-                f0[rr] = bin_off(a[rr]);
-                fx[rr] = bin_off_min(a[rr], b[rr]);
+                const uint32_t va = xf(a[rr]);
+                f0[rr] = bin_off(va);
+                fx[rr] = bin_off_min(va, xf(b[rr]));
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -275,21 +279,29 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
         for (int rr = 0; rr < NR; ++rr) {
             a[rr] = load_elem(rs, vx[rr], soff[rr], ESZ);
             b[rr] = load_elem(rs, vxl[rr], soff[rr], ESZ);
-            if constexpr (XF == kXfInvert) {  // M-1-v (M a power of two); bits >= log2 M stay for the range check
-                a[rr] ^= kInvMask;
-                b[rr] ^= kInvMask;
-            } else if constexpr (XF == kXfWindow) {  // 16-bit window: v-base+1 clamped to 0..16383
-                a[rr] = (uint32_t)max(0, min(16383, (int32_t)a[rr] - P.win_shift));
-                b[rr] = (uint32_t)max(0, min(16383, (int32_t)b[rr] - P.win_shift));
-            }
         }
     };
     auto plane_ptr = [&](int p) { return (p < 0 ? P.src.lo_base : P.src.base) + p * pb; };
     auto load_plane = [&](int p, uint32_t (&a)[NR], uint32_t (&b)[NR]) { load_at(plane_ptr(p), a, b); };
     auto range_acc = [&](const uint32_t (&a)[NR]) {
-        // rows owned by this wave (the collar row is checked by its owner)
+        // rows owned by this wave (the collar row is checked by its owner);
+        // every 16-bit value is valid for the window passes
+        if constexpr (XF != kXfWindow) {
 #pragma unroll
-        for (int rr = NR - R; rr < NR; ++rr) orv |= a[rr];
+            for (int rr = NR - R; rr < NR; ++rr) orv |= a[rr];
+        }
+    };
+    // Fields of a loaded plane.  The value transform is applied here, where
+    // the values are consumed, not at the load: there it would make each load
+    // wait at once and lose the planes of look-ahead.
+    const int32_t wshift = P.win_shift;
+    auto fields = [&](const uint32_t (&a)[NR], const uint32_t (&b)[NR], uint32_t (&g)[NI]) {
+        W::fields(a, b, g, [&](uint32_t v) -> uint32_t {
+            if constexpr (XF == kXfInvert) return v ^ kInvMask;  // M-1-v (M a power of two)
+            else if constexpr (XF == kXfWindow)  // 16-bit window: v - shift clamped to 0..16383
+                return (uint32_t)max(0, min(16383, (int32_t)v - wshift));
+            else return v;
+        });
     };
     auto cmp = [&](uint32_t lo, uint32_t hi, int i) -> uint64_t {
         const uint64_t c = ballot(lo < hi);
@@ -323,12 +335,12 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
     // g[1] <- plane zs-1 (or +inf), g[0] <- plane zs, cp <- [g0 < g1]
     if (lo_real) {
         load_plane(zs - 1, ra[NB - 1], rb[NB - 1]);
-        W::fields(ra[NB - 1], rb[NB - 1], g[1]);
+        fields(ra[NB - 1], rb[NB - 1], g[1]);
     } else {
         W::set_inf(g[1]);
     }
     load_plane(zs, ra[0], rb[0]);
-    W::fields(ra[0], rb[0], g[0]);
+    fields(ra[0], rb[0], g[0]);
     range_acc(ra[0]);
 #pragma unroll
     for (int i = 0; i < NI; ++i) cp[i] = cmp(g[0][i], g[1][i], i);
@@ -347,7 +359,7 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
         for (int u = 0; u < U; ++u) {
             load_at(nxt, ra[u % NB], rb[u % NB]);
             nxt += pb;
-            W::fields(ra[(u + 1) % NB], rb[(u + 1) % NB], g[(u + 1) & 1]);
+            fields(ra[(u + 1) % NB], rb[(u + 1) % NB], g[(u + 1) & 1]);
             range_acc(ra[(u + 1) % NB]);
             step(g[u & 1], g[(u + 1) & 1], cp);
         }
@@ -361,7 +373,7 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
                 if (real(zz + 1 + PD)) load_at(nxt, ra[u % NB], rb[u % NB]);
                 nxt += pb;
                 if (real(zz + 1)) {
-                    W::fields(ra[(u + 1) % NB], rb[(u + 1) % NB], g[(u + 1) & 1]);
+                    fields(ra[(u + 1) % NB], rb[(u + 1) % NB], g[(u + 1) & 1]);
                     if (zz + 1 < ze) range_acc(ra[(u + 1) % NB]);
                 } else {
                     W::set_inf(g[(u + 1) & 1]);
@@ -517,11 +529,11 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
 //  kXfInvert: M-1-v, so the histogram counts each cell at M-1 minus the
 //    maximum over its voxels (the largest-value convention, read back
 //    reversed by the merge);
-//  kXfWindow (16-bit images, M = 16384 bins per pass): v - base + 1 clamped
-//    to 0..16383, so values base..base+16381 land in bins 1..16382 and the
-//    values below / above the window in the guard bins 0 / 16383 (dropped by
-//    the merge).  The monotone clamp keeps every comparison that decides a
-//    count in bins 1..16382, since each involves the counted value itself.
+//  kXfWindow (16-bit images, M = 16384 bins per pass): v - win_shift
+//    clamped to 0..16383; the host keeps the bins of the window's values and
+//    drops guard bins 0 / 16383 where values lie below / above it.  The
+//    monotone clamp keeps every comparison that decides a kept bin, since
+//    each involves the counted value itself.
 template <typename T, int M, int NIN, int R, int MODE, int PD, int XF = kXfNone>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<NIN, R, PD>())))
 int_vcec_kernel(KParams P) {
@@ -622,7 +634,7 @@ static KParams make_params(const IntJob &job, const IntTiling &tl, int32_t *part
     p.tiles_z = (job.e1 - job.e0 + tl.zc - 1) / tl.zc;
     p.per_wg = tl.per_wg > 0 ? tl.per_wg : 1;
     p.tile_stride = tl.tile_stride;
-    p.win_shift = job.win_base - 1;
+    p.win_shift = job.win_shift;
     p.partial = partial;
     p.status = status;
     p.zero_vcec = zero_vcec;

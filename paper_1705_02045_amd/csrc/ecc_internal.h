@@ -59,7 +59,7 @@ struct IntJob {
     int32_t hi_inf;       // plane e1 lies outside the image
     int dtype;            // ECC_U8 or ECC_U14
     int invert;           // values read as M-1-v (largest-value convention)
-    int32_t win_base;     // ECC_U16: first value of the window counted by this launch
+    int32_t win_shift;    // ECC_U16: the launch counts bin = clamp(v - win_shift, 0, 16383)
 };
 
 // Tiling of the integer kernel (chosen by choose_int_tiling in ecc_api.cpp).

@@ -1,9 +1,9 @@
 """GPU parity of 16-bit images (m = 65536 thresholds) against the oracle,
-exact int64.  The GPU counts one window of 16382 values per pass of its
-16384-bin workgroup histograms; these cases put values on and around every
-window edge, span one to all five windows, and run both the synchronous call
-(windows limited to the image's range) and the stream-ordered one (all
-windows)."""
+exact int64.  The GPU counts one window of at most 16384 values per pass of
+its 16384-bin workgroup histograms (guard bins where values lie outside the
+window); these cases put values on and around window edges, span one to all
+five windows, and run both the synchronous call (windows planned from the
+image's range) and the stream-ordered one (windows over 0..65535)."""
 import numpy as np
 import pytest
 
@@ -59,7 +59,8 @@ def test_u16_value_noise(ecc, shape):
 
 
 def test_u16_window_edges(ecc):
-    edges = [0, 1, WIN - 1, WIN, WIN + 1, 2 * WIN - 1, 2 * WIN, 3 * WIN, 4 * WIN - 1, 4 * WIN, 65534, 65535]
+    edges = [0, 1, WIN - 1, WIN, WIN + 1, WIN + 2, 2 * WIN - 1, 2 * WIN, 2 * WIN + 1, 3 * WIN, 3 * WIN + 1,
+             4 * WIN - 1, 4 * WIN, 4 * WIN + 1, 65534, 65535]
     rng = np.random.default_rng(15)
     for shape in [(40, 50), (6, 20, 30), (2000,)]:
         img = rng.choice(np.array(edges, dtype=np.uint16), size=shape)
@@ -68,7 +69,8 @@ def test_u16_window_edges(ecc):
 
 def test_u16_narrow_ranges(ecc):
     rng = np.random.default_rng(16)
-    for lo, hi in [(50000, 50100), (WIN - 3, WIN + 3), (0, 3), (65530, 65535), (20000, 20000)]:
+    for lo, hi in [(50000, 50100), (WIN - 3, WIN + 3), (0, 3), (65530, 65535), (20000, 20000),
+                   (100, 100 + 16383), (100, 100 + 16384), (0, 16383), (0, 16384), (40000, 65535)]:
         img = rng.integers(lo, hi + 1, size=(7, 33, 41)).astype(np.uint16)
         check(ecc, img)
 
