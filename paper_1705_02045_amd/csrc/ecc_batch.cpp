@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <vector>
@@ -32,6 +33,15 @@ struct ecc_batch {
     hipEvent_t done[kSlots] = {};
     bool used[kSlots] = {};
     int next = 0;
+    // per slot, the graph of one run: table copy, persistent tile kernel,
+    // batched merge (captured once for the slot's buffers; each run only
+    // sets the copy's size)
+    bool use_graph = true;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph[kSlots] = {};
+    hipGraphExec_t exec[kSlots] = {};
+    hipGraphNode_t copy_node[kSlots] = {};
+    int tile_grid = 0, colsum_grid = 0, scan_grid = 0;
     // scratch shared by consecutive runs (ordered by the stream)
     int32_t *partial8 = nullptr;
     size_t partial8_bytes = 0;
@@ -90,7 +100,53 @@ struct Prepared {
     IntTiling tl;
     int group;  // (dtype == U14) * 2 + (nin == 2)
     int m;
+    int64_t voxels;
 };
+
+void drop_graph(ecc_batch *b, int s) {
+    if (b->exec[s]) (void)hipGraphExecDestroy(b->exec[s]);
+    if (b->graph[s]) (void)hipGraphDestroy(b->graph[s]);
+    b->exec[s] = nullptr;
+    b->graph[s] = nullptr;
+    b->copy_node[s] = nullptr;
+}
+
+// Captures slot s's run: the copy of the whole table capacity (its size is
+// set per run), the persistent tile kernel, the batched merge.
+int build_graph(ecc_batch *b, int s) {
+    drop_graph(b, s);
+    hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "ecc_batch: begin capture");
+    int rc = ECC_OK;
+    e = hipMemcpyAsync(b->dev[s], b->host[s], b->cap[s], hipMemcpyHostToDevice, b->capture);
+    if (e != hipSuccess) rc = hip_fail(e, "ecc_batch: captured copy");
+    if (!rc) rc = launch_int_persistent(b->dev[s], b->tile_grid, b->capture);
+    if (!rc) rc = launch_batch_merge(b->dev[s], b->colsum_grid, b->scan_grid, b->capture);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->capture, &g);
+    if (!rc && e != hipSuccess) rc = hip_fail(e, "ecc_batch: end capture");
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    b->graph[s] = g;
+    size_t n = 0;
+    e = hipGraphGetNodes(g, nullptr, &n);
+    std::vector<hipGraphNode_t> nodes(n);
+    if (e == hipSuccess) e = hipGraphGetNodes(g, nodes.data(), &n);
+    for (size_t i = 0; e == hipSuccess && i < n; ++i) {
+        hipGraphNodeType t;
+        e = hipGraphNodeGetType(nodes[i], &t);
+        if (e == hipSuccess && t == hipGraphNodeTypeMemcpy) b->copy_node[s] = nodes[i];
+    }
+    if (e == hipSuccess && !b->copy_node[s]) e = hipErrorInvalidValue;
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec[s], g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        drop_graph(b, s);
+        return hip_fail(e, "ecc_batch: graph");
+    }
+    return ECC_OK;
+}
 
 }  // namespace
 
@@ -105,12 +161,20 @@ int ecc_batch_create(void *stream, ecc_batch **out) {
     ecc_batch *b = new ecc_batch();
     b->stream = (hipStream_t)stream;
     hipError_t e = hipGetDevice(&b->device);
+    const int cus = device_cu_count();
+    b->tile_grid = 2 * cus;    // two 1024-thread workgroups per CU (64 KiB histograms)
+    b->colsum_grid = 4 * cus;
+    b->scan_grid = cus;
+    const char *g = getenv("ECC_BATCH_GRAPH");
+    b->use_graph = !(g && g[0] == '0');
     for (int i = 0; e == hipSuccess && i < ecc_batch::kSlots; ++i)
         e = hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming);
+    if (e == hipSuccess && b->use_graph) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
     if (e != hipSuccess) {
         const int rc = hip_fail(e, "ecc_batch_create");
         for (int i = 0; i < ecc_batch::kSlots; ++i)
             if (b->done[i]) (void)hipEventDestroy(b->done[i]);
+        if (b->capture) (void)hipStreamDestroy(b->capture);
         delete b;
         return rc;
     }
@@ -125,10 +189,12 @@ void ecc_batch_destroy(ecc_batch *b) {
     (void)hipSetDevice(b->device);
     (void)hipStreamSynchronize(b->stream);
     for (int i = 0; i < ecc_batch::kSlots; ++i) {
+        drop_graph(b, i);
         if (b->host[i]) (void)hipHostFree(b->host[i]);
         if (b->dev[i]) (void)hipFree(b->dev[i]);
         if (b->done[i]) (void)hipEventDestroy(b->done[i]);
     }
+    if (b->capture) (void)hipStreamDestroy(b->capture);
     if (b->partial8) (void)hipFree(b->partial8);
     if (b->partial14) (void)hipFree(b->partial14);
     if (b->vcec) (void)hipFree(b->vcec);
@@ -145,10 +211,7 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
     }
     if (n_jobs == 0) return ECC_OK;
     std::vector<Prepared> prep(n_jobs);
-    int64_t rows[4] = {0, 0, 0, 0};
-    int64_t cnt[4] = {0, 0, 0, 0};
-    int64_t vcec_words = 0;
-    int max_m = 0;
+    int64_t rows8 = 0, rows14 = 0, ntiles = 0, nitems = 0, vcec_words = 0;
     for (int j = 0; j < n_jobs; ++j) {
         const ecc_job &J = jobs[j];
         int64_t total = 0;
@@ -171,23 +234,27 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
         P.tl = batch_tiling(P.view);
         P.group = (J.dtype == ECC_U14 ? 2 : 0) + (P.view.nin == 2 ? 1 : 0);
         P.m = (int)threshold_count(J.dtype);
-        rows[P.group] += P.tl.grid;
-        cnt[P.group] += 1;
+        P.voxels = total;
+        (P.m == 256 ? rows8 : rows14) += P.tl.grid;
+        ntiles += P.tl.grid;
+        nitems += (P.m + 1023) / 1024;
         vcec_words += P.m;
-        max_m = std::max(max_m, P.m);
     }
-    for (int g = 0; g < 4; ++g)
-        if (rows[g] > INT32_MAX) {
-            set_error("ecc_batch_run: too many tiles in one batch");
-            return ECC_E_UNSUPPORTED;
-        }
+    if (ntiles > INT32_MAX) {
+        set_error("ecc_batch_run: too many tiles in one batch");
+        return ECC_E_UNSUPPORTED;
+    }
+    // tiles of the largest images first, so the persistent workgroups end
+    // on small tiles
+    std::vector<int> order(n_jobs);
+    for (int j = 0; j < n_jobs; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return prep[a].voxels > prep[c].voxels; });
     int prev = -1;
     ECC_HIP(hipGetDevice(&prev));
     if (prev != b->device) ECC_HIP(hipSetDevice(b->device));
     int rc = ECC_OK;
     do {
         // device scratch
-        const int64_t rows8 = rows[0] + rows[1], rows14 = rows[2] + rows[3];
         if ((rc = grow(b, (void **)&b->partial8, &b->partial8_bytes, (size_t)rows8 * 256 * 4))) break;
         if ((rc = grow(b, (void **)&b->partial14, &b->partial14_bytes, (size_t)rows14 * 16384 * 4))) break;
         if ((rc = grow(b, (void **)&b->vcec, &b->vcec_bytes, (size_t)vcec_words * 8))) break;
@@ -195,17 +262,29 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
             if ((rc = grow(b, (void **)&b->status, &b->status_bytes, (size_t)n_jobs * 4))) break;
             if ((rc = launch_zero(b->status, b->status_bytes, b->stream))) break;
         }
-        // table layout: per group KParams[cnt] and tile_begin[cnt + 1], then MergeJob[n]
+        // table: header, KParams[n], tile_begin[n+1], kind[n], MergeJob[n], item_begin[n+1]
         const size_t kp = kparams_bytes();
-        size_t off_kp[4], off_tb[4], total = 0;
-        for (int g = 0; g < 4; ++g) {
-            off_kp[g] = total;
-            total = align_up(total + (size_t)cnt[g] * kp, 16);
-            off_tb[g] = total;
-            total = align_up(total + (size_t)(cnt[g] + 1) * 4, 16);
+        BatchHeader hd{};
+        size_t total = align_up(sizeof(BatchHeader), 16);
+        hd.off_kparams = (uint32_t)total;
+        total = align_up(total + (size_t)n_jobs * kp, 16);
+        hd.off_tile_begin = (uint32_t)total;
+        total = align_up(total + (size_t)(n_jobs + 1) * 4, 16);
+        hd.off_kind = (uint32_t)total;
+        total = align_up(total + (size_t)n_jobs * 4, 16);
+        hd.off_merge = (uint32_t)total;
+        total = align_up(total + (size_t)n_jobs * sizeof(MergeJob), 16);
+        hd.off_item_begin = (uint32_t)total;
+        total = align_up(total + (size_t)(n_jobs + 1) * 4, 256);
+        if (total > UINT32_MAX) {
+            set_error("ecc_batch_run: batch table too large");
+            rc = ECC_E_UNSUPPORTED;
+            break;
         }
-        const size_t off_mj = total;
-        total = align_up(total + (size_t)n_jobs * sizeof(MergeJob), 256);
+        hd.njobs = n_jobs;
+        hd.ntiles = (int32_t)ntiles;
+        hd.nitems = (int32_t)nitems;
+        hd.next_tile = 0;
         // a free slot (its previous run's table copy has been consumed)
         const int s = b->next;
         b->next = (s + 1) % ecc_batch::kSlots;
@@ -217,27 +296,33 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
             }
         }
         if (b->cap[s] < total) {
+            drop_graph(b, s);
             if (b->host[s]) (void)hipHostFree(b->host[s]);
             if (b->dev[s]) (void)hipFree(b->dev[s]);
             b->host[s] = b->dev[s] = nullptr;
             b->cap[s] = 0;
-            hipError_t e = hipHostMalloc(&b->host[s], total, hipHostMallocDefault);
-            if (e == hipSuccess) e = hipMalloc(&b->dev[s], total);
+            const size_t want = std::max(total, (size_t)64 << 10);  // room for later, larger batches
+            hipError_t e = hipHostMalloc(&b->host[s], want, hipHostMallocDefault);
+            if (e == hipSuccess) e = hipMalloc(&b->dev[s], want);
             if (e != hipSuccess) {
                 rc = hip_fail(e, "ecc_batch_run: table allocation");
                 break;
             }
-            b->cap[s] = total;
+            b->cap[s] = want;
         }
         uint8_t *h = (uint8_t *)b->host[s];
         uint8_t *d = (uint8_t *)b->dev[s];
-        int64_t idx[4] = {0, 0, 0, 0}, row_in_group[4] = {0, 0, 0, 0};
+        memcpy(h, &hd, sizeof hd);
+        int32_t *tile_begin = (int32_t *)(h + hd.off_tile_begin);
+        int32_t *kind = (int32_t *)(h + hd.off_kind);
+        MergeJob *mj = (MergeJob *)(h + hd.off_merge);
+        int32_t *item_begin = (int32_t *)(h + hd.off_item_begin);
+        tile_begin[0] = 0;
+        item_begin[0] = 0;
         int64_t row8 = 0, row14 = 0, vw = 0;
-        for (int g = 0; g < 4; ++g) ((int32_t *)(h + off_tb[g]))[0] = 0;
-        MergeJob *mj = (MergeJob *)(h + off_mj);
-        for (int j = 0; j < n_jobs; ++j) {
+        for (int p = 0; p < n_jobs; ++p) {
+            const int j = order[p];
             const Prepared &P = prep[j];
-            const int g = P.group;
             int32_t *part;
             if (P.m == 256) {
                 part = b->partial8 + row8 * 256;
@@ -256,32 +341,38 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
             job.lo_inf = 1;
             job.hi_inf = 1;
             job.dtype = jobs[j].dtype;
-            fill_kparams(h + off_kp[g] + (size_t)idx[g] * kp, job, P.tl, part, b->status + j);
-            row_in_group[g] += P.tl.grid;
-            ((int32_t *)(h + off_tb[g]))[idx[g] + 1] = (int32_t)row_in_group[g];
-            idx[g] += 1;
-            mj[j].partial = part;
-            mj[j].rows = P.tl.grid;
-            mj[j].m = P.m;
-            mj[j].vcec = b->vcec + vw;
-            mj[j].chi = jobs[j].chi;
-            mj[j].status = b->status + j;
-            mj[j].status_out = status_dev ? status_dev + j : nullptr;
+            fill_kparams(h + hd.off_kparams + (size_t)p * kp, job, P.tl, part, b->status + j);
+            tile_begin[p + 1] = tile_begin[p] + P.tl.grid;
+            kind[p] = P.group;
+            mj[p].partial = part;
+            mj[p].rows = P.tl.grid;
+            mj[p].m = P.m;
+            mj[p].vcec = b->vcec + vw;
+            mj[p].chi = jobs[j].chi;
+            mj[p].status = b->status + j;
+            mj[p].status_out = status_dev ? status_dev + j : nullptr;
+            item_begin[p + 1] = item_begin[p] + (P.m + 1023) / 1024;
             vw += P.m;
         }
-        hipError_t e = hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, b->stream);
-        if (e != hipSuccess) {
-            rc = hip_fail(e, "ecc_batch_run: table copy");
-            break;
+        if (b->use_graph) {
+            if (!b->exec[s] && (rc = build_graph(b, s))) break;
+            hipError_t e = hipGraphExecMemcpyNodeSetParams1D(b->exec[s], b->copy_node[s], d, h, total,
+                                                             hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipGraphLaunch(b->exec[s], b->stream);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "ecc_batch_run: graph launch");
+                break;
+            }
+        } else {
+            hipError_t e = hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, b->stream);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "ecc_batch_run: table copy");
+                break;
+            }
+            if ((rc = launch_int_persistent(d, b->tile_grid, b->stream))) break;
+            if ((rc = launch_batch_merge(d, b->colsum_grid, b->scan_grid, b->stream))) break;
         }
-        for (int g = 0; g < 4 && !rc; ++g)
-            if (cnt[g] > 0)
-                rc = launch_int_batch(g >= 2 ? ECC_U14 : ECC_U8, (g & 1) ? 2 : 1, d + off_kp[g],
-                                      (const int32_t *)(d + off_tb[g]), (int)cnt[g], (int)rows[g], b->stream);
-        if (rc) break;
-        rc = launch_batch_merge((const MergeJob *)(d + off_mj), n_jobs, max_m, b->stream);
-        if (rc) break;
-        e = hipEventRecord(b->done[s], b->stream);
+        hipError_t e = hipEventRecord(b->done[s], b->stream);
         if (e != hipSuccess) {
             rc = hip_fail(e, "ecc_batch_run: event");
             break;

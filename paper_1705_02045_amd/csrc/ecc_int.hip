@@ -541,23 +541,43 @@ int_vcec_kernel(KParams P) {
     tile_body<T, M, NIN, R, MODE, PD, XF>(P, hist, blockIdx.x, gridDim.x);
 }
 
-// Batched form: the tiles of many images in one launch.  Image j owns
-// workgroups [tile_begin[j], tile_begin[j+1]); its parameters are jobs[j].
-template <typename T, int M, int NIN>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<NIN, 2, 1>())))
-int_vcec_batch_kernel(const KParams *__restrict__ jobs, const int32_t *__restrict__ tile_begin, int njobs) {
-    __shared__ int32_t hist[M];
-    const int b = blockIdx.x;
-    int lo = 0, hi = njobs - 1;  // last j with tile_begin[j] <= b
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tile_begin[mid] <= b) lo = mid;
-        else hi = mid - 1;
+// Batched form: the tiles of every image of a batch in one persistent
+// launch.  Image j owns tiles [tile_begin[j], tile_begin[j+1]) and its
+// parameters are jobs[j]; its kind selects the value type and rank.  Each
+// workgroup takes the next tile from the table's work counter (a global
+// atomic; the value is passed through hist[0] before tile_body clears the
+// histogram) until the tiles run out.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<2, 2, 1>())))
+int_vcec_persistent_kernel(uint8_t *__restrict__ table) {
+    __shared__ int32_t hist[16384];
+    BatchHeader *H = (BatchHeader *)table;
+    const int ntiles = H->ntiles, njobs = H->njobs;
+    const KParams *jobs = (const KParams *)(table + H->off_kparams);
+    const int32_t *tile_begin = (const int32_t *)(table + H->off_tile_begin);
+    const int32_t *kind = (const int32_t *)(table + H->off_kind);
+    for (;;) {
+        if (threadIdx.x == 0) hist[0] = (int32_t)atomicAdd(&H->next_tile, 1u);
+        __syncthreads();
+        const int v = __builtin_amdgcn_readfirstlane(hist[0]);
+        __syncthreads();
+        if (v >= ntiles) break;
+        int lo = 0, hi = njobs - 1;  // last j with tile_begin[j] <= v
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tile_begin[mid] <= v) lo = mid;
+            else hi = mid - 1;
+        }
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        const KParams P = jobs[lo];
+        const int b = v - tile_begin[lo], G = tile_begin[lo + 1] - tile_begin[lo];
+        switch (__builtin_amdgcn_readfirstlane(kind[lo])) {
+        case 0: tile_body<uint8_t, 256, 1, 2, 0, 1>(P, hist, b, G); break;
+        case 1: tile_body<uint8_t, 256, 2, 2, 0, 1>(P, hist, b, G); break;
+        case 2: tile_body<uint16_t, 16384, 1, 2, 0, 1>(P, hist, b, G); break;
+        default: tile_body<uint16_t, 16384, 2, 2, 0, 1>(P, hist, b, G); break;
+        }
+        __syncthreads();  // the histogram's write-out is done before hist[0] is reused
     }
-    lo = __builtin_amdgcn_readfirstlane(lo);
-    const KParams P = jobs[lo];
-    const int b0 = tile_begin[lo];
-    tile_body<T, M, NIN, 2, 0, 1>(P, hist, b - b0, tile_begin[lo + 1] - b0);
 }
 
 template <typename T, int M, int NIN, int R, int MODE, int PD, int XF = kXfNone>
@@ -672,18 +692,8 @@ void fill_kparams(void *dst, const IntJob &job, const IntTiling &tl, int32_t *pa
     memcpy(dst, &p, sizeof p);
 }
 
-int launch_int_batch(int dtype, int nin, const void *jobs_dev, const int32_t *tile_begin_dev, int njobs, int tiles,
-                     hipStream_t stream) {
-    if (njobs <= 0 || tiles <= 0) return ECC_OK;
-    const KParams *j = (const KParams *)jobs_dev;
-    if (dtype == ECC_U8 && nin == 1)
-        hipLaunchKernelGGL((int_vcec_batch_kernel<uint8_t, 256, 1>), dim3(tiles), dim3(1024), 0, stream, j, tile_begin_dev, njobs);
-    else if (dtype == ECC_U8)
-        hipLaunchKernelGGL((int_vcec_batch_kernel<uint8_t, 256, 2>), dim3(tiles), dim3(1024), 0, stream, j, tile_begin_dev, njobs);
-    else if (nin == 1)
-        hipLaunchKernelGGL((int_vcec_batch_kernel<uint16_t, 16384, 1>), dim3(tiles), dim3(1024), 0, stream, j, tile_begin_dev, njobs);
-    else
-        hipLaunchKernelGGL((int_vcec_batch_kernel<uint16_t, 16384, 2>), dim3(tiles), dim3(1024), 0, stream, j, tile_begin_dev, njobs);
+int launch_int_persistent(const void *table_dev, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL(int_vcec_persistent_kernel, dim3(grid), dim3(1024), 0, stream, (uint8_t *)table_dev);
     ECC_HIP(hipGetLastError());
     return ECC_OK;
 }

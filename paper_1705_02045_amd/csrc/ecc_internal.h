@@ -138,8 +138,24 @@ size_t elem_bytes(int dtype);
 // bytes each, filled by fill_kparams().
 size_t kparams_bytes();
 void fill_kparams(void *dst, const IntJob &job, const IntTiling &tl, int32_t *partial, uint32_t *status);
-int launch_int_batch(int dtype, int nin, const void *jobs_dev, const int32_t *tile_begin_dev, int njobs, int tiles,
-                     hipStream_t stream);
+// Table of one batched run, built on the host and copied to the device as a
+// whole (offsets in bytes from the table start).  The copy also resets the
+// tile kernel's work counter.
+struct BatchHeader {
+    int32_t njobs;
+    int32_t ntiles;           // workgroup-tiles over all images
+    int32_t nitems;           // (image, 1024-column group) items of the merge
+    uint32_t next_tile;       // work counter of the tile kernel (0 in the copied table)
+    uint32_t off_kparams;     // KParams[njobs], kparams_bytes() each
+    uint32_t off_tile_begin;  // int32[njobs + 1]: prefix of the images' tiles
+    uint32_t off_kind;        // int32[njobs]: (dtype == U14) * 2 + (nin == 2)
+    uint32_t off_merge;       // MergeJob[njobs]
+    uint32_t off_item_begin;  // int32[njobs + 1]: prefix of the images' column groups
+    uint32_t pad[7];
+};
+// One persistent launch over the tiles of every image of the table: `grid`
+// workgroups take tiles from the work counter until none are left.
+int launch_int_persistent(const void *table_dev, int grid, hipStream_t stream);
 struct MergeJob {
     const int32_t *partial;  // [rows][m]
     int32_t rows;
@@ -149,7 +165,9 @@ struct MergeJob {
     uint32_t *status;        // device status word of the image (cleared here)
     uint32_t *status_out;    // optional copy for the caller
 };
-int launch_batch_merge(const MergeJob *jobs_dev, int njobs, int max_m, hipStream_t stream);
+// Batched merge of the table's images: column sums into each image's vcec,
+// then each image's scan into its curve (fixed grids, loops over the work).
+int launch_batch_merge(const void *table_dev, int colsum_grid, int scan_grid, hipStream_t stream);
 
 // Float path (ecc_float.hip, ecc_sort.hip).
 // Records: one 64-bit word per voxel, order-preserving key in bits 8..39,

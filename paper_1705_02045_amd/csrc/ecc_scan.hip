@@ -167,79 +167,101 @@ __global__ void __launch_bounds__(256) scan_offsets_kernel(int m, int64_t *__res
 }
 
 // ----------------------------------------------------------------------------
-// Batched merge: one descriptor per image.  batch_colsum_kernel block
-// (group, j) sums the rows of image j over columns group*1024 .. +1023 into
-// its vcec; batch_scan_kernel block j writes image j's curve (if its status
-// word is clear), copies the status out and clears it.
+// Batched merge over the images of a batch table (fixed grids: the graph of
+// a batched run does not change with its contents).
+// batch_colsum_kernel: item i = (image j, 1024-column group g), j found in
+// the table's item prefix: sums image j's rows over those columns into its
+// vcec.  batch_scan_kernel: image j (blocks loop over images) writes its
+// curve if its status word is clear, copies the status out and clears it.
 
-__global__ void __launch_bounds__(256) batch_colsum_kernel(const MergeJob *__restrict__ jobs) {
-    const MergeJob J = jobs[blockIdx.y];
-    const int c0 = blockIdx.x * 1024 + threadIdx.x * 4;
-    if (c0 >= J.m) return;
-    const int4 *p = reinterpret_cast<const int4 *>(J.partial);
-    const size_t stride4 = (size_t)J.m / 4;
-    int64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    for (int r = 0; r < J.rows; ++r) {
-        const int4 a = p[(size_t)r * stride4 + c0 / 4];
-        s0 += a.x;
-        s1 += a.y;
-        s2 += a.z;
-        s3 += a.w;
+__device__ __forceinline__ int find_prefix(const int32_t *begin, int n, int v) {
+    int lo = 0, hi = n - 1;  // last j with begin[j] <= v
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= v) lo = mid;
+        else hi = mid - 1;
     }
-    J.vcec[c0] = s0;
-    J.vcec[c0 + 1] = s1;
-    J.vcec[c0 + 2] = s2;
-    J.vcec[c0 + 3] = s3;
+    return lo;
 }
 
-__global__ void __launch_bounds__(1024) batch_scan_kernel(const MergeJob *__restrict__ jobs) {
+__global__ void __launch_bounds__(256) batch_colsum_kernel(const uint8_t *__restrict__ table) {
+    const BatchHeader *H = (const BatchHeader *)table;
+    const MergeJob *jobs = (const MergeJob *)(table + H->off_merge);
+    const int32_t *item_begin = (const int32_t *)(table + H->off_item_begin);
+    for (int i = blockIdx.x; i < H->nitems; i += gridDim.x) {
+        const int j = __builtin_amdgcn_readfirstlane(find_prefix(item_begin, H->njobs, i));
+        const MergeJob J = jobs[j];
+        const int c0 = (i - item_begin[j]) * 1024 + threadIdx.x * 4;
+        if (c0 >= J.m) continue;
+        const int4 *p = reinterpret_cast<const int4 *>(J.partial);
+        const size_t stride4 = (size_t)J.m / 4;
+        int64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        for (int r = 0; r < J.rows; ++r) {
+            const int4 a = p[(size_t)r * stride4 + c0 / 4];
+            s0 += a.x;
+            s1 += a.y;
+            s2 += a.z;
+            s3 += a.w;
+        }
+        J.vcec[c0] = s0;
+        J.vcec[c0 + 1] = s1;
+        J.vcec[c0 + 2] = s2;
+        J.vcec[c0 + 3] = s3;
+    }
+}
+
+__global__ void __launch_bounds__(1024) batch_scan_kernel(const uint8_t *__restrict__ table) {
     __shared__ int64_t ws[16];
     __shared__ int64_t carry;
-    const MergeJob J = jobs[blockIdx.x];
-    const uint32_t stv = *J.status;
+    const BatchHeader *H = (const BatchHeader *)table;
+    const MergeJob *jobs = (const MergeJob *)(table + H->off_merge);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) carry = 0;
-    __syncthreads();
-    if (stv == 0) {
-        for (int c0 = 0; c0 < J.m; c0 += 1024 * 16) {
-            const int base = c0 + tid * 16;
-            int64_t loc[16];
-            int64_t run = 0;
+    for (int jb = blockIdx.x; jb < H->njobs; jb += gridDim.x) {
+        const MergeJob J = jobs[jb];
+        const uint32_t stv = *J.status;
+        if (tid == 0) carry = 0;
+        __syncthreads();
+        if (stv == 0) {
+            for (int c0 = 0; c0 < J.m; c0 += 1024 * 16) {
+                const int base = c0 + tid * 16;
+                int64_t loc[16];
+                int64_t run = 0;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                run += (base + j < J.m) ? J.vcec[base + j] : 0;
-                loc[j] = run;
+                for (int j = 0; j < 16; ++j) {
+                    run += (base + j < J.m) ? J.vcec[base + j] : 0;
+                    loc[j] = run;
+                }
+                int64_t x = run;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int64_t u = __shfl_up(x, off, 64);
+                    if (lane >= off) x += u;
+                }
+                if (lane == 63) ws[wave] = x;
+                __syncthreads();
+                int64_t pre = carry + x - run;
+                for (int w = 0; w < wave; ++w) pre += ws[w];
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if (base + j < J.m) J.chi[base + j] = pre + loc[j];
+                __syncthreads();
+                if (tid == 0)
+                    for (int w = 0; w < 16; ++w) carry += ws[w];
+                __syncthreads();
             }
-            int64_t x = run;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const int64_t u = __shfl_up(x, off, 64);
-                if (lane >= off) x += u;
-            }
-            if (lane == 63) ws[wave] = x;
-            __syncthreads();
-            int64_t pre = carry + x - run;
-            for (int w = 0; w < wave; ++w) pre += ws[w];
-#pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if (base + j < J.m) J.chi[base + j] = pre + loc[j];
-            __syncthreads();
-            if (tid == 0)
-                for (int w = 0; w < 16; ++w) carry += ws[w];
-            __syncthreads();
         }
-    }
-    if (tid == 0) {
-        if (J.status_out) *J.status_out = stv;
-        *J.status = 0u;
+        if (tid == 0) {
+            if (J.status_out) *J.status_out = stv;
+            *J.status = 0u;
+        }
+        __syncthreads();  // carry and ws are reused by the next image
     }
 }
 
-int launch_batch_merge(const MergeJob *jobs_dev, int njobs, int max_m, hipStream_t stream) {
-    if (njobs <= 0) return ECC_OK;
-    hipLaunchKernelGGL(batch_colsum_kernel, dim3((max_m + 1023) / 1024, njobs), dim3(256), 0, stream, jobs_dev);
+int launch_batch_merge(const void *table_dev, int colsum_grid, int scan_grid, hipStream_t stream) {
+    hipLaunchKernelGGL(batch_colsum_kernel, dim3(colsum_grid), dim3(256), 0, stream, (const uint8_t *)table_dev);
     ECC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(batch_scan_kernel, dim3(njobs), dim3(1024), 0, stream, jobs_dev);
+    hipLaunchKernelGGL(batch_scan_kernel, dim3(scan_grid), dim3(1024), 0, stream, (const uint8_t *)table_dev);
     ECC_HIP(hipGetLastError());
     return ECC_OK;
 }

@@ -99,3 +99,22 @@ def test_serving_stream_sample_full_sides(ecc):
     for r, img, c in zip(reqs, imgs, chis):
         assert (c.cpu().numpy() == oracle.curve(img, m=ecc.THRESHOLDS[r[0]])).all(), f"{r}"
     b.close()
+
+
+@pytest.mark.parametrize("graph", ["1", "0"], ids=["graph", "direct"])
+def test_batch_runs_replay_and_vary(ecc, monkeypatch, graph):
+    """Many runs on one context: the ring's four slots are reused, so each
+    slot's captured graph replays with new tables (more and fewer images,
+    other dtypes and sizes), with eager work on the device between runs;
+    every run is checked against the oracle.  Also through the direct
+    launches (no graph)."""
+    monkeypatch.setenv("ECC_BATCH_GRAPH", graph)
+    b = ecc.Batch()
+    for r in range(10):
+        specs = MIXED[r % 4::2] if r % 3 else MIXED[: 2 + r]
+        print(f"\n[gpu] batch run {r} ({graph}): {len(specs)} images", flush=True)
+        imgs, got = run_batch(ecc, b, specs, seed0=200 + 17 * r)
+        for (d, s), img, g in zip(specs, imgs, got):
+            assert (g == oracle.curve(img, m=ecc.THRESHOLDS[d])).all(), f"run {r}: {d} {s}"
+        ecc.compute(dev(gen.cfg_u14_value_noise((20, 30, 40), seed=r)), "u14")  # eager work between runs
+    b.close()
