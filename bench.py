@@ -76,11 +76,13 @@ def cpu_baseline(img, target_s: float):
             "sample": f"planes 0..{planes - 1} of the {n0}x{n1}x{n2} volume ({vox} voxels, {dt:.1f} s)"}
 
 
-def leg_serving(n_req: int, slo_ms: float):
+def leg_serving(n_req: int, slo_ms: float, budget_bytes: int):
     """Serving mix (50/50 2-D uint8 sides 32..2048 / 3-D 14-bit sides 16..256,
     value noise, seeded): highest Poisson arrival rate whose p99 latency
     (arrival -> curve in host memory) stays within slo_ms, for continuous
-    batching and for one launch per image."""
+    batching (at most 256 requests and budget_bytes of device footprint per
+    batch; one persistent launch per batch, replayed as a graph) and for one
+    launch per image."""
     import numpy as np
     import torch
     import gen
@@ -94,12 +96,16 @@ def leg_serving(n_req: int, slo_ms: float):
     vox = sum(int(np.prod(r[1])) for r in reqs)
     b = ecc.Batch()
     # untimed replays of the whole set: scratch buffers reach their final size
-    b.serve(imgs, dtypes, np.zeros(n_req), max_batch=256)
+    b.serve(imgs, dtypes, np.zeros(n_req), max_batch=256, max_batch_bytes=budget_bytes)
     b.serve(imgs, dtypes, np.zeros(n_req), max_batch=1, one_launch_per_image=True)
     rng = np.random.default_rng(4)
+    sizes = []
 
     def run(arr, single):
-        lat, _ = b.serve(imgs, dtypes, arr, max_batch=256, one_launch_per_image=single)
+        lat, _, bid = b.serve(imgs, dtypes, arr, max_batch=256, one_launch_per_image=single,
+                              max_batch_bytes=budget_bytes, with_batches=True)
+        if not single:
+            sizes.append(n_req / (int(bid.max()) + 1))
         return float(np.percentile(lat, 99)) * 1e3, float(np.percentile(lat, 50)) * 1e3, float(np.max(arr + lat))
 
     out = {}
@@ -119,7 +125,8 @@ def leg_serving(n_req: int, slo_ms: float):
     b.close()
     rb = (out["batched"]["at_slo"] or {}).get("rate_img_per_s")
     rs = (out["one_launch_per_image"]["at_slo"] or {}).get("rate_img_per_s")
-    out.update({"requests": n_req, "voxels": vox, "slo_p99_ms": slo_ms,
+    out.update({"requests": n_req, "voxels": vox, "slo_p99_ms": slo_ms, "batch_budget_bytes": budget_bytes,
+                "mean_batch_size": round(float(np.mean(sizes)), 2) if sizes else None,
                 "speedup_at_slo": round(rb / rs, 2) if rb and rs else None})
     return out
 
@@ -361,6 +368,7 @@ def main():
                     help="further workloads reported under 'legs' (comma list, or 'none')")
     ap.add_argument("--serve-requests", type=int, default=1024)
     ap.add_argument("--serve-slo-ms", type=float, default=10.0)
+    ap.add_argument("--serve-budget-gib", type=int, default=8, help="device footprint admitted per batch")
     ap.add_argument("--calibrate", action="store_true",
                     help="after the steps, run one elementwise kernel that reads and writes the volume's bytes "
                          "(reference for the HBM byte counters)")
@@ -438,7 +446,7 @@ def main():
         log(f"[bench] leg {leg} ...")
         t0 = time.perf_counter()
         if leg == "serving":
-            legs[leg] = leg_serving(args.serve_requests, args.serve_slo_ms)
+            legs[leg] = leg_serving(args.serve_requests, args.serve_slo_ms, args.serve_budget_gib << 30)
         elif leg == "float":
             legs[leg] = leg_float(5)
         elif leg == "stream_host":

@@ -226,20 +226,29 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
 /* Waits for the context's work and frees it.  NULL is ignored. */
 void ecc_batch_destroy(ecc_batch *b);
 
+/* Device memory one request of a batch occupies while in flight: its
+ * image, the per-workgroup count rows of its batch tiling, its changes
+ * vector and its curve (bytes).  Errors: ECC_E_ARG, ECC_E_UNSUPPORTED. */
+int ecc_job_footprint(const ecc_job *job, int64_t *bytes);
+
 /* Serving replay for measurement: request i (jobs[i], device-resident image;
  * its chi field is ignored) becomes available at arrival_s[i] seconds after
  * the call starts (ascending).  Continuous batching (one_launch_per_image =
- * 0): whenever fewer than two batches are in flight, everything that has
- * arrived (at most max_batch requests) goes into the next ecc_batch_run.
- * Otherwise every request is one ecc_compute_async launch as soon as it
- * arrives.  Each request's curve is copied to pinned host memory owned by
- * the call; latency_s[i] receives the time from its arrival until that copy
- * was seen complete.  At the end all curves are copied to chi_host, request
- * i's at chi_host + (sum of the m of the requests before it).  Blocks until all
- * requests are done.  Errors: ECC_E_ARG, ECC_E_UNSUPPORTED, ECC_E_NOMEM,
- * ECC_E_HIP. */
+ * 0): whenever fewer than two batches are in flight, the requests that have
+ * arrived are admitted in order into the next ecc_batch_run while the batch
+ * holds at most max_batch requests and the sum of their footprints
+ * (ecc_job_footprint) stays within max_batch_bytes (0: no byte limit; a
+ * request larger than the limit runs alone).  Otherwise every request is
+ * one ecc_compute_async launch as soon as it arrives.  Each request's curve
+ * is copied to pinned host memory owned by the call; latency_s[i] receives
+ * the time from its arrival until that copy was seen complete; batch_id[i]
+ * (optional) the index of the batch (or launch) that carried it.  At the
+ * end all curves are copied to chi_host, request i's at chi_host + (sum of
+ * the m of the requests before it).  Blocks until all requests are done.
+ * Errors: ECC_E_ARG, ECC_E_UNSUPPORTED, ECC_E_NOMEM, ECC_E_HIP. */
 int ecc_serve_simulate(ecc_batch *b, int32_t n, const ecc_job *jobs, const double *arrival_s, int32_t max_batch,
-                       int32_t one_launch_per_image, int64_t *chi_host, double *latency_s);
+                       int64_t max_batch_bytes, int32_t one_launch_per_image, int64_t *chi_host, double *latency_s,
+                       int32_t *batch_id);
 
 /* Kernel timing (measurement support, not needed for results).  While
  * enabled, every launch of the per-voxel kernels (the integer change-vector

@@ -80,7 +80,10 @@ _lib.ecc_batch_run.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
 _lib.ecc_batch_destroy.restype = None
 _lib.ecc_batch_destroy.argtypes = [_vp]
 _lib.ecc_serve_simulate.restype = ctypes.c_int
-_lib.ecc_serve_simulate.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
+_lib.ecc_serve_simulate.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                    _vp, _vp, _vp]
+_lib.ecc_job_footprint.restype = ctypes.c_int
+_lib.ecc_job_footprint.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
 _lib.ecc_profile_read.restype = ctypes.c_int
 _lib.ecc_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
 _lib.ecc_last_error.restype = ctypes.c_char_p
@@ -330,18 +333,29 @@ class Batch:
         _check(_lib.ecc_batch_run(self._h, len(images), ctypes.cast(arr, _vp),
                                   status.data_ptr() if status is not None else None), "ecc_batch_run")
 
-    def serve(self, images, dtypes, arrival_s, max_batch: int, one_launch_per_image: bool = False):
-        """ecc_serve_simulate: returns (latency seconds per request, host curves concatenated)."""
+    def serve(self, images, dtypes, arrival_s, max_batch: int, one_launch_per_image: bool = False,
+              max_batch_bytes: int = 0, with_batches: bool = False):
+        """ecc_serve_simulate: returns (latency seconds per request, host curves
+        concatenated) and, with with_batches, the batch index of each request."""
         import numpy as np
         arr = _jobs_array(images, dtypes)
         arrival = np.ascontiguousarray(arrival_s, dtype=np.float64)
         total = sum(THRESHOLDS[d] for d in dtypes)
         chi = np.empty(total, dtype=np.int64)
         lat = np.empty(len(images), dtype=np.float64)
+        bid = np.empty(len(images), dtype=np.int32)
         _check(_lib.ecc_serve_simulate(self._h, len(images), ctypes.cast(arr, _vp), arrival.ctypes.data,
-                                       int(max_batch), int(bool(one_launch_per_image)), chi.ctypes.data,
-                                       lat.ctypes.data), "ecc_serve_simulate")
-        return lat, chi
+                                       int(max_batch), int(max_batch_bytes), int(bool(one_launch_per_image)),
+                                       chi.ctypes.data, lat.ctypes.data, bid.ctypes.data), "ecc_serve_simulate")
+        return (lat, chi, bid) if with_batches else (lat, chi)
+
+    @staticmethod
+    def footprint(image, dtype: str) -> int:
+        """ecc_job_footprint of one request (bytes)."""
+        arr = _jobs_array([image], [dtype])
+        out = ctypes.c_int64(0)
+        _check(_lib.ecc_job_footprint(ctypes.cast(arr, _vp), ctypes.byref(out)), "ecc_job_footprint")
+        return out.value
 
     def close(self):
         h, self._h = self._h, ctypes.c_void_p()

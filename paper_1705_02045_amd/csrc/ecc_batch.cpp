@@ -383,12 +383,42 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
     return rc;
 }
 
-int ecc_serve_simulate(ecc_batch *b, int32_t n, const ecc_job *jobs, const double *arrival_s, int32_t max_batch,
-                       int32_t one_launch_per_image, int64_t *chi_host, double *latency_s) {
+int ecc_job_footprint(const ecc_job *job, int64_t *bytes) {
     g_err_clear();
-    if (!b || n < 1 || !jobs || !arrival_s || !chi_host || !latency_s || max_batch < 1) {
+    if (!job || !bytes) {
+        set_error("ecc_job_footprint: NULL argument");
+        return ECC_E_ARG;
+    }
+    int64_t total = 0;
+    int rc = check_dims(&job->dims, &total);
+    if (rc) return rc;
+    if (job->dtype != ECC_U8 && job->dtype != ECC_U14) {
+        set_error("ecc_job_footprint: U8 or U14 images");
+        return (job->dtype == ECC_U16 || job->dtype == ECC_F32) ? ECC_E_UNSUPPORTED : ECC_E_ARG;
+    }
+    IntView v{};
+    int unsup = 0;
+    if (!normalize_int_view(&job->dims, &v, &unsup)) {
+        set_error("ecc_job_footprint: shape not supported");
+        return ECC_E_UNSUPPORTED;
+    }
+    const int64_t m = threshold_count(job->dtype);
+    *bytes = total * (int64_t)elem_bytes(job->dtype) + (int64_t)batch_tiling(v).grid * m * 4 + 2 * m * 8;
+    return ECC_OK;
+}
+
+int ecc_serve_simulate(ecc_batch *b, int32_t n, const ecc_job *jobs, const double *arrival_s, int32_t max_batch,
+                       int64_t max_batch_bytes, int32_t one_launch_per_image, int64_t *chi_host, double *latency_s,
+                       int32_t *batch_id) {
+    g_err_clear();
+    if (!b || n < 1 || !jobs || !arrival_s || !chi_host || !latency_s || max_batch < 1 || max_batch_bytes < 0) {
         set_error("ecc_serve_simulate: bad argument");
         return ECC_E_ARG;
+    }
+    std::vector<int64_t> foot(n, 0);
+    for (int i = 0; i < n && max_batch_bytes > 0; ++i) {
+        const int rc = ecc_job_footprint(&jobs[i], &foot[i]);
+        if (rc) return rc;
     }
     for (int i = 1; i < n; ++i)
         if (arrival_s[i] < arrival_s[i - 1]) {
@@ -432,12 +462,23 @@ int ecc_serve_simulate(ecc_batch *b, int32_t n, const ecc_job *jobs, const doubl
     const int max_inflight = one_launch_per_image ? (1 << 30) : 2;
     const auto t0 = std::chrono::steady_clock::now();
     auto now = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
-    int next = 0, arrived = 0, done = 0;
+    int next = 0, arrived = 0, done = 0, batches = 0;
     while (done < n && !rc) {
         const double t = now();
         while (arrived < n && arrival_s[arrived] <= t) ++arrived;
         while (next < arrived && (int)flight.size() < max_inflight && !rc) {
-            const int k = one_launch_per_image ? 1 : std::min(arrived - next, (int)max_batch);
+            // admission: in arrival order, up to max_batch requests and
+            // max_batch_bytes of footprint (the first request always fits)
+            int k = 1;
+            if (!one_launch_per_image) {
+                int64_t bytes = foot[next];
+                while (next + k < arrived && k < max_batch &&
+                       (max_batch_bytes == 0 || bytes + foot[next + k] <= max_batch_bytes))
+                    bytes += foot[next + k++];
+            }
+            if (batch_id)
+                for (int i = next; i < next + k; ++i) batch_id[i] = batches;
+            ++batches;
             if (one_launch_per_image) {
                 rc = ecc_compute_async(js[next].image, &js[next].dims, (ecc_dtype)js[next].dtype, js[next].chi,
                                        nullptr, b->stream);

@@ -85,8 +85,32 @@ def test_batch_argument_errors():
     lat = (ctypes.c_double * 1)()
     arr = (ctypes.c_double * 1)()
     chi = (ctypes.c_int64 * 256)()
-    assert ecc._lib.ecc_serve_simulate(None, 1, None, arr, 1, 0, chi, lat) == ecc.ECC_E_ARG
+    assert ecc._lib.ecc_serve_simulate(None, 1, None, arr, 1, 0, 0, chi, lat, None) == ecc.ECC_E_ARG
     ecc._lib.ecc_batch_destroy(None)
+
+
+def test_job_footprint():
+    """Host-side sizing of a request: image bytes + count rows + changes
+    vector + curve; larger images need more; no GPU involved."""
+    import paper_1705_02045_amd as ecc
+
+    def fp(shape, dtype):
+        job = ecc.Job()
+        job.dims = ecc.make_dims(shape)
+        job.dtype = ecc.DTYPES[dtype]
+        out = ctypes.c_int64(0)
+        rc = ecc._lib.ecc_job_footprint(ctypes.byref(job), ctypes.byref(out))
+        return rc, out.value
+
+    rc, a = fp((300, 70), "u8")
+    assert rc == 0 and a >= 300 * 70 + 2 * 256 * 8 + 256 * 4
+    rc, b = fp((600, 700), "u8")
+    assert rc == 0 and b > a
+    rc, c = fp((16, 16, 16), "u14")
+    assert rc == 0 and c >= 2 * 16 ** 3 + 2 * 16384 * 8 + 16384 * 4
+    assert fp((4, 4), "u16")[0] == ecc.ECC_E_UNSUPPORTED
+    assert fp((4, 4), "f32")[0] == ecc.ECC_E_UNSUPPORTED
+    assert ecc._lib.ecc_job_footprint(None, None) == ecc.ECC_E_ARG
 
 
 def test_job_struct_layout():

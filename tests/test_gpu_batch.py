@@ -118,3 +118,29 @@ def test_batch_runs_replay_and_vary(ecc, monkeypatch, graph):
             assert (g == oracle.curve(img, m=ecc.THRESHOLDS[d])).all(), f"run {r}: {d} {s}"
         ecc.compute(dev(gen.cfg_u14_value_noise((20, 30, 40), seed=r)), "u14")  # eager work between runs
     b.close()
+
+
+def test_serve_admission_by_footprint(ecc):
+    """All requests arrive at once; a byte budget of three median footprints
+    splits them into consecutive batches whose footprints fit the budget (a
+    larger request runs alone); every curve matches the oracle."""
+    reqs = gen.serving_requests(40, seed=9, side_scale=0.2)
+    imgs = [gen.serving_image(*r) for r in reqs]
+    dimgs = [dev(a) for a in imgs]
+    dtypes = [r[0] for r in reqs]
+    foot = np.array([ecc.Batch.footprint(t, d) for t, d in zip(dimgs, dtypes)])
+    budget = int(3 * np.median(foot))
+    b = ecc.Batch()
+    lat, chi, bid = b.serve(dimgs, dtypes, np.zeros(len(reqs)), max_batch=64, max_batch_bytes=budget,
+                            with_batches=True)
+    b.close()
+    assert (np.diff(bid) >= 0).all() and (np.diff(bid) <= 1).all() and bid[0] == 0
+    assert bid[-1] >= 2  # the budget did split the stream
+    for k in range(bid[-1] + 1):
+        sel = bid == k
+        assert sel.sum() == 1 or foot[sel].sum() <= budget
+    off = 0
+    for (d, s, _), img in zip(reqs, imgs):
+        m = ecc.THRESHOLDS[d]
+        assert (chi[off:off + m] == oracle.curve(img, m=m)).all(), f"{d} {s}"
+        off += m
