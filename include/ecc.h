@@ -163,6 +163,38 @@ int ecc_compute_async(const void *image_dev, const ecc_dims *dims, ecc_dtype dty
                       uint32_t *status_dev, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Tile shapes.  The integer kernel's tiling of a launch has three
+ * parameters: rows per wave (2 or 4), waves along x (up to 16 of a
+ * workgroup's 16) and workgroups per CU (the image is split along axis 0
+ * until about that many tiles per CU exist; planes with more tiles give a
+ * workgroup several).  By default a rule of the launch's size picks them
+ * (measured on MI355X); ecc_autotune times the candidates on an image and
+ * keeps the fastest for its shape in a process-wide table consulted by every
+ * later launch of that shape (dtype, plane shape and number of planes; the
+ * planes of a streamed chunk are its own shape).  Results do not depend on
+ * the tiling. */
+typedef struct {
+    int32_t rows;          /* rows per wave: 2 or 4 */
+    int32_t tiles_per_cu;  /* workgroups per CU: 4, 8 or 16 */
+    int32_t waves_x;       /* waves along x per workgroup: 8 or 16 */
+    float ms;              /* ecc_autotune: the fastest candidate's time (kernel + column sums) */
+} ecc_tiling;
+
+/* Times every candidate tiling (rows {2, 4} x tiles_per_cu {4, 8, 16} x
+ * waves_x {8, 16}) on a device image of an integer dtype (U8, U14) and
+ * stores the fastest for its shape; best receives it.  The image's values
+ * must be valid (ECC_E_RANGE otherwise, nothing stored).
+ * Errors: ECC_E_ARG, ECC_E_RANGE, ECC_E_UNSUPPORTED, ECC_E_NOMEM, ECC_E_HIP. */
+int ecc_autotune(const void *image_dev, const ecc_dims *dims, ecc_dtype dtype, void *stream, ecc_tiling *best);
+
+/* The tiling a resident launch of this shape would use (a stored one, else
+ * the size rule); ms = 0.  Errors: ECC_E_ARG, ECC_E_UNSUPPORTED. */
+int ecc_tiling_for(const ecc_dims *dims, ecc_dtype dtype, ecc_tiling *out);
+
+/* Forgets every tiling ecc_autotune stored. */
+void ecc_autotune_reset(void);
+
+/* ---------------------------------------------------------------------------
  * Streaming (Sec. 3, "Streaming" and "Processing one Chunk"): an image larger
  * than device memory is pushed as consecutive chunks of whole axis-0 planes.
  * Each chunk is processed with a one-plane collar taken from its neighbours
@@ -226,9 +258,19 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
 /* Waits for the context's work and frees it.  NULL is ignored. */
 void ecc_batch_destroy(ecc_batch *b);
 
+/* Tile depth of a batch context: an image of n0 planes is cut into tiles of
+ * max(min_planes, n0 / split) planes (defaults 64 and 4).  Times ecc_batch_run
+ * on the given jobs (their chi buffers are written) for min_planes in
+ * {16, 32, 64, 128} x split in {2, 4, 8} and keeps the fastest for the
+ * context's later runs; the outputs (optional) receive it and its time.
+ * Synchronizes the context's stream.  Errors as ecc_batch_run. */
+int ecc_batch_autotune(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, int32_t *min_planes, int32_t *split,
+                       float *ms);
+
 /* Device memory one request of a batch occupies while in flight: its
- * image, the per-workgroup count rows of its batch tiling, its changes
- * vector and its curve (bytes).  Errors: ECC_E_ARG, ECC_E_UNSUPPORTED. */
+ * image, the per-workgroup count rows of its batch tiling (default tile
+ * depth), its changes vector and its curve (bytes).  Errors: ECC_E_ARG,
+ * ECC_E_UNSUPPORTED. */
 int ecc_job_footprint(const ecc_job *job, int64_t *bytes);
 
 /* Serving replay for measurement: request i (jobs[i], device-resident image;

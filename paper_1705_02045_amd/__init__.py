@@ -41,6 +41,11 @@ class Job(ctypes.Structure):
                 ("chi", ctypes.c_void_p)]
 
 
+class Tiling(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("tiles_per_cu", ctypes.c_int32), ("waves_x", ctypes.c_int32),
+                ("ms", ctypes.c_float)]
+
+
 class Curve(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int64), ("count", ctypes.c_int64),
                 ("chi", ctypes.c_void_p), ("keys", ctypes.c_void_p)]
@@ -54,6 +59,15 @@ _lib.ecc_compute_change_points.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_i
 _lib.ecc_compute_quantized.restype = ctypes.c_int
 _lib.ecc_compute_quantized.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_float, ctypes.c_float, ctypes.c_int,
                                        ctypes.POINTER(Curve), _vp]
+_lib.ecc_autotune.restype = ctypes.c_int
+_lib.ecc_autotune.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_int, _vp, ctypes.POINTER(Tiling)]
+_lib.ecc_tiling_for.restype = ctypes.c_int
+_lib.ecc_tiling_for.argtypes = [ctypes.POINTER(Dims), ctypes.c_int, ctypes.POINTER(Tiling)]
+_lib.ecc_autotune_reset.restype = None
+_lib.ecc_autotune_reset.argtypes = []
+_lib.ecc_batch_autotune.restype = ctypes.c_int
+_lib.ecc_batch_autotune.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
 _lib.ecc_compute_dual.restype = ctypes.c_int
 _lib.ecc_compute_dual.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_int, ctypes.POINTER(Curve), _vp]
 _lib.ecc_compute_max_entry.restype = ctypes.c_int
@@ -241,6 +255,29 @@ def compute_quantized(image, lo: float, hi: float, bins: str):
         return chi
 
 
+def autotune(image, dtype: str) -> dict:
+    """ecc_autotune on a device tensor: times the candidate tilings and stores
+    the fastest for the image's shape; returns it."""
+    import torch
+    t = Tiling()
+    dims = make_dims(image.shape)
+    with torch.cuda.device(image.device):
+        _check(_lib.ecc_autotune(image.contiguous().data_ptr(), ctypes.byref(dims), DTYPES[dtype],
+                                 _stream_handle(image.device), ctypes.byref(t)), "ecc_autotune")
+    return {"rows": t.rows, "tiles_per_cu": t.tiles_per_cu, "waves_x": t.waves_x, "ms": t.ms}
+
+
+def tiling_for(shape, dtype: str) -> dict:
+    """ecc_tiling_for: the tiling a resident launch of this shape would use."""
+    t = Tiling()
+    _check(_lib.ecc_tiling_for(ctypes.byref(make_dims(shape)), DTYPES[dtype], ctypes.byref(t)), "ecc_tiling_for")
+    return {"rows": t.rows, "tiles_per_cu": t.tiles_per_cu, "waves_x": t.waves_x}
+
+
+def autotune_reset():
+    _lib.ecc_autotune_reset()
+
+
 def compute_dual(image, dtype: str):
     """ecc_compute_dual on a CUDA tensor (u8, u14): the dual complex, voxels as
     vertices with the lower-star filtration.  Returns the int64 curve."""
@@ -348,6 +385,15 @@ class Batch:
                                        int(max_batch), int(max_batch_bytes), int(bool(one_launch_per_image)),
                                        chi.ctypes.data, lat.ctypes.data, bid.ctypes.data), "ecc_serve_simulate")
         return (lat, chi, bid) if with_batches else (lat, chi)
+
+    def autotune(self, images, dtypes, chis):
+        """ecc_batch_autotune: picks the context's tile depth on this batch;
+        returns (min_planes, split, ms)."""
+        arr = _jobs_array(images, dtypes, chis)
+        mp, sp, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0)
+        _check(_lib.ecc_batch_autotune(self._h, len(images), ctypes.cast(arr, _vp), ctypes.byref(mp),
+                                       ctypes.byref(sp), ctypes.byref(ms)), "ecc_batch_autotune")
+        return mp.value, sp.value, ms.value
 
     @staticmethod
     def footprint(image, dtype: str) -> int:

@@ -4,6 +4,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <utility>
 
@@ -161,24 +162,15 @@ static int env_int(const char *name, int dflt) {
 
 // Tuning overrides (measurement only): ECC_INT_ROWS, ECC_INT_MODE, ECC_INT_PD, ECC_INT_WX,
 // ECC_INT_WAVES, ECC_INT_TILES_PER_CU, ECC_INT_TILE_STRIDE.
-IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
+// The tiling for given parameters: R rows per wave, up to wx_cap waves
+// along x (16-wave workgroups), about tiles_per_cu workgroups per CU.
+IntTiling make_int_tiling(const IntView &v, int64_t planes, int rows, int tiles_per_cu, int wx_cap) {
     IntTiling t{};
-    // Launch size picks rows per wave and tiles per CU (measured on MI355X):
-    // below 256 MiB four tiles per CU are fastest, above it eight.  From
-    // 4 GiB on (e.g. 62 planes of 8192^2 or of 14450^2) four rows per wave
-    // run at about 2.8 TB/s where two rows reach 2.0-2.4; below 2 GiB two
-    // rows are faster.  Likely cause: four rows keep half as many workgroups
-    // in flight, so fewer distinct 2 MiB pages per plane step need
-    // translating once a plane spans many pages.
-    const int64_t launch_bytes = planes * (int64_t)v.n1 * v.n2 * (dtype == ECC_U8 ? 1 : 2);
-    const bool big = launch_bytes >= ((int64_t)4 << 30);
-    t.rows = env_int("ECC_INT_ROWS", big ? 4 : 2);
+    t.rows = rows;
     t.mode = env_int("ECC_INT_MODE", 0);
     t.pd = env_int("ECC_INT_PD", 1);
     const int cus = device_cu_count();
     const int max_waves = env_int("ECC_INT_WAVES", 16);
-    const int tiles_per_cu =
-        env_int("ECC_INT_TILES_PER_CU", launch_bytes < ((int64_t)256 << 20) ? 4 : (t.rows == 4 ? 16 : 8));
     int64_t tiles_xy;
     if (v.nin == 1) {
         const int64_t segs = (v.n2 + (int64_t)kWave * t.rows - 1) / ((int64_t)kWave * t.rows);
@@ -187,7 +179,6 @@ IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
         tiles_xy = (segs + t.wx - 1) / t.wx;
     } else {
         const int64_t xs = (v.n2 + kWave - 1) / kWave;
-        const int wx_cap = env_int("ECC_INT_WX", 16);
         t.wx = (int)(xs < wx_cap ? xs : wx_cap);
         const int64_t ys = (v.n1 + t.rows - 1) / t.rows;
         const int64_t wy = max_waves / t.wx;
@@ -195,9 +186,8 @@ IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
         tiles_xy = ((xs + t.wx - 1) / t.wx) * ((ys + t.wy - 1) / t.wy);
     }
     // split axis 0 until there are about tiles_per_cu tiles per CU; planes
-    // with more tiles than that get several tiles per workgroup (strided, so
-    // the resident workgroups hold neighbouring tiles), so the per-workgroup
-    // rows stay about tiles_per_cu per CU
+    // with more tiles than that get several tiles per workgroup, so the
+    // per-workgroup rows stay about tiles_per_cu per CU
     const int64_t target = (int64_t)cus * tiles_per_cu;
     int64_t tz = (target + tiles_xy - 1) / tiles_xy;
     if (tz < 1) tz = 1;
@@ -211,6 +201,47 @@ IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
     t.tile_stride = env_int("ECC_INT_TILE_STRIDE", 0);
     t.grid = (int)((tiles + per - 1) / per);
     return t;
+}
+
+// Tilings chosen by ecc_autotune, per (dtype, rank, n1, n2, planes).
+struct TuneKey {
+    int dtype, nin;
+    int32_t n1, n2;
+    int64_t planes;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(dtype, nin, n1, n2, planes) < std::tie(o.dtype, o.nin, o.n1, o.n2, o.planes);
+    }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, ecc_tiling> g_tuned;
+
+static bool tuned_tiling(const IntView &v, int dtype, int64_t planes, ecc_tiling *out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(TuneKey{dtype, v.nin, v.n1, v.n2, planes});
+    if (it == g_tuned.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+// Parameters: ECC_INT_* environment overrides (measurement), else a tiling
+// ecc_autotune stored for this shape, else the launch-size rule below.
+IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
+    // Launch-size rule (measured on MI355X): below 256 MiB four tiles per CU
+    // are fastest, above it eight.  From 4 GiB on (e.g. 62 planes of 8192^2
+    // or of 14450^2) four rows per wave run at about 2.8 TB/s where two rows
+    // reach 2.0-2.4; below 2 GiB two rows are faster.  Likely cause: four
+    // rows keep half as many workgroups in flight, so fewer distinct 2 MiB
+    // pages per plane step need translating once a plane spans many pages.
+    const int64_t launch_bytes = planes * (int64_t)v.n1 * v.n2 * (dtype == ECC_U8 ? 1 : 2);
+    const bool big = launch_bytes >= ((int64_t)4 << 30);
+    ecc_tiling c{};
+    if (!tuned_tiling(v, dtype, planes, &c)) {
+        c.rows = big ? 4 : 2;
+        c.tiles_per_cu = launch_bytes < ((int64_t)256 << 20) ? 4 : (c.rows == 4 ? 16 : 8);
+        c.waves_x = 16;
+    }
+    return make_int_tiling(v, planes, env_int("ECC_INT_ROWS", c.rows), env_int("ECC_INT_TILES_PER_CU", c.tiles_per_cu),
+                           env_int("ECC_INT_WX", c.waves_x));
 }
 
 // Enqueue the whole integer computation for a device-resident image.
@@ -682,6 +713,145 @@ int ecc_compute_quantized(const float *image, const ecc_dims *dims, float lo, fl
         return ECC_E_NAN;
     }
     return compute_int(q, dims, total, bins, curve, s, false);
+}
+
+int ecc_autotune(const void *image_dev, const ecc_dims *dims, ecc_dtype dtype, void *stream, ecc_tiling *best) {
+    g_err[0] = 0;
+    int64_t total = 0;
+    int rc = check_dims(dims, &total);
+    if (rc) return rc;
+    if (!image_dev || !best) {
+        set_error("NULL image or output");
+        return ECC_E_ARG;
+    }
+    if (dtype != ECC_U8 && dtype != ECC_U14) {
+        set_error("ecc_autotune: U8 or U14 images");
+        return (dtype == ECC_U16 || dtype == ECC_F32) ? ECC_E_UNSUPPORTED : ECC_E_ARG;
+    }
+    if (!is_device_ptr(image_dev)) {
+        set_error("ecc_autotune: the image must be device memory");
+        return ECC_E_ARG;
+    }
+    IntView v{};
+    int unsup = 0;
+    if (!normalize_int_view(dims, &v, &unsup)) {
+        set_error("integer path: shape not supported (4 axes longer than 1, or an extent beyond 2^31)");
+        return ECC_E_UNSUPPORTED;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Workspace *ws = nullptr;
+    rc = get_workspace(s, &ws);
+    if (rc) return rc;
+    const int m = (int)threshold_count(dtype);
+    rc = ensure_bytes((void **)&ws->vcec, &ws->vcec_bytes, (size_t)m * sizeof(int64_t));
+    if (rc) return rc;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e != hipSuccess) {
+        if (ev[0]) (void)hipEventDestroy(ev[0]);
+        return hip_fail(e, "ecc_autotune: events");
+    }
+    ecc_tiling win{};
+    win.ms = 1e30f;
+    IntJob job{};
+    job.src.base = (const uint8_t *)image_dev;
+    job.src.lo_base = job.src.base;
+    job.src.plane_bytes = (int64_t)v.n1 * v.n2 * (int64_t)elem_bytes(dtype);
+    job.view = v;
+    job.e0 = 0;
+    job.e1 = (int32_t)v.n0;
+    job.lo_inf = 1;
+    job.hi_inf = 1;
+    job.dtype = dtype;
+    const int rows_c[2] = {2, 4}, tpc_c[3] = {4, 8, 16}, wx_c[2] = {8, 16};
+    for (int a = 0; a < 2 && !rc; ++a)
+        for (int b = 0; b < 3 && !rc; ++b)
+            for (int c = 0; c < (v.nin == 2 ? 2 : 1) && !rc; ++c) {
+                const IntTiling tl = make_int_tiling(v, v.n0, rows_c[a], tpc_c[b], wx_c[c + (v.nin == 2 ? 0 : 1)]);
+                rc = ensure_bytes((void **)&ws->partial, &ws->partial_bytes, (size_t)tl.grid * m * sizeof(int32_t));
+                if (!rc)
+                    rc = ensure_bytes((void **)&ws->stage, &ws->stage_bytes,
+                                      (size_t)merge_stage_rows(tl.grid) * m * sizeof(int64_t));
+                float tmin = 1e30f;
+                for (int rep = 0; rep < 4 && !rc; ++rep) {  // one warm-up, three timed
+                    if ((e = hipEventRecord(ev[0], s)) != hipSuccess) rc = hip_fail(e, "ecc_autotune: event");
+                    if (!rc) rc = launch_int_partial(job, tl, ws->partial, ws->status, nullptr, s);
+                    if (!rc)
+                        rc = launch_merge(ws->partial, tl.grid, m, ws->stage, ws->vcec, false, false, nullptr,
+                                          ws->status, nullptr, s);
+                    if (!rc && (e = hipEventRecord(ev[1], s)) != hipSuccess) rc = hip_fail(e, "ecc_autotune: event");
+                    if (!rc && (e = hipEventSynchronize(ev[1])) != hipSuccess) rc = hip_fail(e, "ecc_autotune: sync");
+                    float ms = 0.0f;
+                    if (!rc && (e = hipEventElapsedTime(&ms, ev[0], ev[1])) != hipSuccess)
+                        rc = hip_fail(e, "ecc_autotune: timing");
+                    if (!rc && rep > 0 && ms < tmin) tmin = ms;
+                }
+                if (!rc && tmin < win.ms) {
+                    win.rows = rows_c[a];
+                    win.tiles_per_cu = tpc_c[b];
+                    win.waves_x = wx_c[c + (v.nin == 2 ? 0 : 1)];
+                    win.ms = tmin;
+                }
+            }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (rc) return rc;
+    // the status word collects range errors of the timed runs; read and clear it
+    uint32_t st = 0;
+    ECC_HIP(hipMemcpyAsync(&st, ws->status, 4, hipMemcpyDeviceToHost, s));
+    ECC_HIP(hipStreamSynchronize(s));
+    rc = launch_zero(ws->status, 8, s);
+    if (rc) return rc;
+    ECC_HIP(hipStreamSynchronize(s));
+    if (st & kStatusRange) {
+        set_error("a 14-bit image holds a value >= 16384");
+        return ECC_E_RANGE;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[TuneKey{dtype, v.nin, v.n1, v.n2, v.n0}] = win;
+    }
+    *best = win;
+    return ECC_OK;
+}
+
+int ecc_tiling_for(const ecc_dims *dims, ecc_dtype dtype, ecc_tiling *out) {
+    g_err[0] = 0;
+    int64_t total = 0;
+    int rc = check_dims(dims, &total);
+    if (rc) return rc;
+    if (!out) {
+        set_error("NULL output");
+        return ECC_E_ARG;
+    }
+    if (dtype != ECC_U8 && dtype != ECC_U14 && dtype != ECC_U16) {
+        set_error("ecc_tiling_for: integer dtypes");
+        return dtype == ECC_F32 ? ECC_E_UNSUPPORTED : ECC_E_ARG;
+    }
+    IntView v{};
+    int unsup = 0;
+    if (!normalize_int_view(dims, &v, &unsup)) {
+        set_error("integer path: shape not supported");
+        return ECC_E_UNSUPPORTED;
+    }
+    const IntTiling t = choose_int_tiling(v, dtype, v.n0);
+    out->rows = t.rows;
+    out->waves_x = t.wx;
+    // tiles per CU is not kept in the tiling: report the parameter used
+    ecc_tiling c{};
+    if (!tuned_tiling(v, dtype, v.n0, &c)) {
+        const int64_t launch_bytes = v.n0 * (int64_t)v.n1 * v.n2 * (dtype == ECC_U8 ? 1 : 2);
+        c.tiles_per_cu = launch_bytes < ((int64_t)256 << 20) ? 4 : (t.rows == 4 ? 16 : 8);
+    }
+    out->tiles_per_cu = env_int("ECC_INT_TILES_PER_CU", c.tiles_per_cu);
+    out->ms = 0.0f;
+    return ECC_OK;
+}
+
+void ecc_autotune_reset(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
 }
 
 // Dual complex (voxels as vertices, lower-star filtration).  Its cells are

@@ -42,6 +42,8 @@ struct ecc_batch {
     hipGraphExec_t exec[kSlots] = {};
     hipGraphNode_t copy_node[kSlots] = {};
     int tile_grid = 0, colsum_grid = 0, scan_grid = 0;
+    // batch tile depth (ecc_batch_autotune)
+    int min_planes = 64, split = 4;
     // scratch shared by consecutive runs (ordered by the stream)
     int32_t *partial8 = nullptr;
     size_t partial8_bytes = 0;
@@ -58,9 +60,12 @@ namespace {
 using namespace ecc;
 
 // Tiling of one image inside a batch: 2 rows per wave, 16-wave workgroups,
-// tiles of at least 64 planes (or the whole image) so that small images take
-// one workgroup and large ones a few hundred.
-IntTiling batch_tiling(const IntView &v) {
+// tiles of max(min_planes, planes / split) planes (or the whole image), so
+// that small images take one workgroup and large ones a few hundred.  The
+// defaults (64, 4) hold until ecc_batch_autotune picks others.
+constexpr int kBatchMinPlanes = 64, kBatchSplit = 4;
+
+IntTiling batch_tiling(const IntView &v, int min_planes = kBatchMinPlanes, int split = kBatchSplit) {
     IntTiling t{};
     t.rows = 2;
     t.mode = 0;
@@ -79,7 +84,7 @@ IntTiling batch_tiling(const IntView &v) {
         t.wy = (int)std::min<int64_t>(ys, max_waves / t.wx);
         tiles_xy = ((xs + t.wx - 1) / t.wx) * ((ys + t.wy - 1) / t.wy);
     }
-    int64_t zc = std::max<int64_t>(64, (v.n0 + 3) / 4);
+    int64_t zc = std::max<int64_t>(min_planes, (v.n0 + split - 1) / split);
     if (zc > v.n0) zc = v.n0;
     t.zc = (int)zc;
     t.per_wg = 1;
@@ -231,7 +236,7 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
             set_error("job %d: shape not supported", j);
             return ECC_E_UNSUPPORTED;
         }
-        P.tl = batch_tiling(P.view);
+        P.tl = batch_tiling(P.view, b->min_planes, b->split);
         P.group = (J.dtype == ECC_U14 ? 2 : 0) + (P.view.nin == 2 ? 1 : 0);
         P.m = (int)threshold_count(J.dtype);
         P.voxels = total;
@@ -379,6 +384,57 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
         }
         b->used[s] = true;
     } while (0);
+    if (prev != b->device) (void)hipSetDevice(prev);
+    return rc;
+}
+
+int ecc_batch_autotune(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, int32_t *min_planes, int32_t *split,
+                       float *ms) {
+    g_err_clear();
+    if (!b || n_jobs < 1 || !jobs) {
+        set_error("ecc_batch_autotune: bad argument");
+        return ECC_E_ARG;
+    }
+    int prev = -1;
+    ECC_HIP(hipGetDevice(&prev));
+    if (prev != b->device) ECC_HIP(hipSetDevice(b->device));
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    int rc = e == hipSuccess ? ECC_OK : hip_fail(e, "ecc_batch_autotune: events");
+    const int mp_c[4] = {16, 32, 64, 128}, sp_c[3] = {2, 4, 8};
+    int best_mp = b->min_planes, best_sp = b->split;
+    float best = 1e30f;
+    for (int i = 0; i < 4 && !rc; ++i)
+        for (int k = 0; k < 3 && !rc; ++k) {
+            b->min_planes = mp_c[i];
+            b->split = sp_c[k];
+            float tmin = 1e30f;
+            for (int rep = 0; rep < 4 && !rc; ++rep) {  // one warm-up, three timed
+                if ((e = hipEventRecord(ev[0], b->stream)) != hipSuccess) rc = hip_fail(e, "ecc_batch_autotune");
+                if (!rc) rc = ecc_batch_run(b, n_jobs, jobs, nullptr);
+                if (!rc && (e = hipEventRecord(ev[1], b->stream)) != hipSuccess) rc = hip_fail(e, "ecc_batch_autotune");
+                if (!rc && (e = hipEventSynchronize(ev[1])) != hipSuccess) rc = hip_fail(e, "ecc_batch_autotune");
+                float t = 0.0f;
+                if (!rc && (e = hipEventElapsedTime(&t, ev[0], ev[1])) != hipSuccess)
+                    rc = hip_fail(e, "ecc_batch_autotune");
+                if (!rc && rep > 0 && t < tmin) tmin = t;
+            }
+            if (!rc && tmin < best) {
+                best = tmin;
+                best_mp = mp_c[i];
+                best_sp = sp_c[k];
+            }
+        }
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    if (ev[1]) (void)hipEventDestroy(ev[1]);
+    b->min_planes = best_mp;
+    b->split = best_sp;
+    if (!rc) {
+        if (min_planes) *min_planes = best_mp;
+        if (split) *split = best_sp;
+        if (ms) *ms = best;
+    }
     if (prev != b->device) (void)hipSetDevice(prev);
     return rc;
 }
