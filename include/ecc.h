@@ -182,7 +182,8 @@ typedef struct {
 
 /* Times every candidate tiling (rows {2, 4} x tiles_per_cu {4, 8, 16} x
  * waves_x {8, 16}) on a device image of an integer dtype (U8, U14) and
- * stores the fastest for its shape; best receives it.  The image's values
+ * stores the fastest for its shape (the launch-size rule's tiling unless
+ * another is at least 2 % faster); best receives it.  The image's values
  * must be valid (ECC_E_RANGE otherwise, nothing stored).
  * Errors: ECC_E_ARG, ECC_E_RANGE, ECC_E_UNSUPPORTED, ECC_E_NOMEM, ECC_E_HIP. */
 int ecc_autotune(const void *image_dev, const ecc_dims *dims, ecc_dtype dtype, void *stream, ecc_tiling *best);

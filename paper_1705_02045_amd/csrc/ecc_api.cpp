@@ -223,25 +223,35 @@ static bool tuned_tiling(const IntView &v, int dtype, int64_t planes, ecc_tiling
     return true;
 }
 
-// Parameters: ECC_INT_* environment overrides (measurement), else a tiling
-// ecc_autotune stored for this shape, else the launch-size rule below.
-IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
-    // Launch-size rule (measured on MI355X): below 256 MiB four tiles per CU
-    // are fastest, above it eight.  From 4 GiB on (e.g. 62 planes of 8192^2
-    // or of 14450^2) four rows per wave run at about 2.8 TB/s where two rows
-    // reach 2.0-2.4; below 2 GiB two rows are faster.  Likely cause: four
-    // rows keep half as many workgroups in flight, so fewer distinct 2 MiB
-    // pages per plane step need translating once a plane spans many pages.
+// Launch-size rule (measured on MI355X): below 256 MiB four tiles per CU are
+// fastest, above it eight.  From 4 GiB on (e.g. 62 planes of 8192^2 or of
+// 14450^2) four rows per wave run at about 2.8 TB/s where two rows reach
+// 2.0-2.4; below 2 GiB two rows are faster.  Likely cause: four rows keep
+// half as many workgroups in flight, so fewer distinct 2 MiB pages per plane
+// step need translating once a plane spans many pages.
+static ecc_tiling rule_tiling(const IntView &v, int dtype, int64_t planes) {
     const int64_t launch_bytes = planes * (int64_t)v.n1 * v.n2 * (dtype == ECC_U8 ? 1 : 2);
-    const bool big = launch_bytes >= ((int64_t)4 << 30);
     ecc_tiling c{};
-    if (!tuned_tiling(v, dtype, planes, &c)) {
-        c.rows = big ? 4 : 2;
-        c.tiles_per_cu = launch_bytes < ((int64_t)256 << 20) ? 4 : (c.rows == 4 ? 16 : 8);
-        c.waves_x = 16;
-    }
-    return make_int_tiling(v, planes, env_int("ECC_INT_ROWS", c.rows), env_int("ECC_INT_TILES_PER_CU", c.tiles_per_cu),
-                           env_int("ECC_INT_WX", c.waves_x));
+    c.rows = launch_bytes >= ((int64_t)4 << 30) ? 4 : 2;
+    c.tiles_per_cu = launch_bytes < ((int64_t)256 << 20) ? 4 : (c.rows == 4 ? 16 : 8);
+    c.waves_x = 16;
+    return c;
+}
+
+// Parameters: ECC_INT_* environment overrides (measurement), else a tiling
+// ecc_autotune stored for this shape, else the launch-size rule.
+static ecc_tiling tiling_params(const IntView &v, int dtype, int64_t planes) {
+    ecc_tiling c{};
+    if (!tuned_tiling(v, dtype, planes, &c)) c = rule_tiling(v, dtype, planes);
+    c.rows = env_int("ECC_INT_ROWS", c.rows);
+    c.tiles_per_cu = env_int("ECC_INT_TILES_PER_CU", c.tiles_per_cu);
+    c.waves_x = env_int("ECC_INT_WX", c.waves_x);
+    return c;
+}
+
+IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
+    const ecc_tiling c = tiling_params(v, dtype, planes);
+    return make_int_tiling(v, planes, c.rows, c.tiles_per_cu, c.waves_x);
 }
 
 // Enqueue the whole integer computation for a device-resident image.
@@ -754,6 +764,8 @@ int ecc_autotune(const void *image_dev, const ecc_dims *dims, ecc_dtype dtype, v
     }
     ecc_tiling win{};
     win.ms = 1e30f;
+    const ecc_tiling rule = rule_tiling(v, dtype, v.n0);
+    float rule_ms = 1e30f;
     IntJob job{};
     job.src.base = (const uint8_t *)image_dev;
     job.src.lo_base = job.src.base;
@@ -787,13 +799,22 @@ int ecc_autotune(const void *image_dev, const ecc_dims *dims, ecc_dtype dtype, v
                         rc = hip_fail(e, "ecc_autotune: timing");
                     if (!rc && rep > 0 && ms < tmin) tmin = ms;
                 }
+                const int wx = wx_c[c + (v.nin == 2 ? 0 : 1)];
+                if (!rc && rows_c[a] == rule.rows && tpc_c[b] == rule.tiles_per_cu && wx == rule.waves_x)
+                    rule_ms = tmin;
                 if (!rc && tmin < win.ms) {
                     win.rows = rows_c[a];
                     win.tiles_per_cu = tpc_c[b];
-                    win.waves_x = wx_c[c + (v.nin == 2 ? 0 : 1)];
+                    win.waves_x = wx;
                     win.ms = tmin;
                 }
             }
+    // the rule stays unless a candidate beats it by 2 % (timing noise would
+    // otherwise flip between near-equal tilings from run to run)
+    if (!rc && win.ms > 0.98f * rule_ms) {
+        win = rule;
+        win.ms = rule_ms;
+    }
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
     if (rc) return rc;
@@ -835,16 +856,7 @@ int ecc_tiling_for(const ecc_dims *dims, ecc_dtype dtype, ecc_tiling *out) {
         set_error("integer path: shape not supported");
         return ECC_E_UNSUPPORTED;
     }
-    const IntTiling t = choose_int_tiling(v, dtype, v.n0);
-    out->rows = t.rows;
-    out->waves_x = t.wx;
-    // tiles per CU is not kept in the tiling: report the parameter used
-    ecc_tiling c{};
-    if (!tuned_tiling(v, dtype, v.n0, &c)) {
-        const int64_t launch_bytes = v.n0 * (int64_t)v.n1 * v.n2 * (dtype == ECC_U8 ? 1 : 2);
-        c.tiles_per_cu = launch_bytes < ((int64_t)256 << 20) ? 4 : (t.rows == 4 ? 16 : 8);
-    }
-    out->tiles_per_cu = env_int("ECC_INT_TILES_PER_CU", c.tiles_per_cu);
+    *out = tiling_params(v, dtype, v.n0);
     out->ms = 0.0f;
     return ECC_OK;
 }
