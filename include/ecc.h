@@ -86,6 +86,8 @@ int ecc_threshold_count(ecc_dtype dtype, int64_t *m_out);
  *          ECC_F32).  chi/keys may be host or device pointers.
  *   stream: work is enqueued on it; the call returns after the curve is
  *          written (it synchronizes that stream).
+ * Integer images with four axes longer than 1 are computed exactly through
+ * the float path (their curve read at every integer threshold).
  * Errors: ECC_E_ARG, ECC_E_RANGE (U14), ECC_E_NAN (F32),
  *         ECC_E_BUFFER_TOO_SMALL, ECC_E_NOMEM, ECC_E_HIP, ECC_E_UNSUPPORTED. */
 int ecc_compute(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_curve *curve, void *stream);

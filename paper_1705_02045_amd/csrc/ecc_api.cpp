@@ -399,6 +399,60 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 // Float images: records -> sort -> per-key running sums (ecc_float.hip,
 // ecc_sort.hip).  Synchronous: the number of distinct values is only known
 // at the end.
+static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc_curve *curve, hipStream_t s,
+                         bool steps_only);
+
+// Integer images the integer kernel does not take (four axes longer than 1):
+// exact through the float path, whose curve is a step function over the
+// image's distinct values; chi(T_t) is its value at the largest distinct
+// value <= t.
+static int compute_int_via_float(const void *image, const ecc_dims *dims, int64_t total, ecc_dtype dtype,
+                                 ecc_curve *curve, hipStream_t s) {
+    const int64_t m = threshold_count(dtype);
+    Workspace *ws = nullptr;
+    int rc = get_workspace(s, &ws);
+    if (rc) return rc;
+    const size_t eb = elem_bytes(dtype);
+    // dual_buf: the float image, the float curve (keys, chi), the expanded curve
+    const size_t o_keys = align256((size_t)total * 4), o_chi = o_keys + align256((size_t)total * 4);
+    const size_t o_out = o_chi + align256((size_t)total * 8);
+    rc = ensure_bytes(&ws->dual_buf, &ws->dual_buf_bytes, o_out + (size_t)m * 8);
+    if (rc) return rc;
+    uint8_t *buf = (uint8_t *)ws->dual_buf;
+    const void *img_dev = image;
+    if (!is_device_ptr(image)) {
+        rc = ensure_bytes(&ws->img_tmp, &ws->img_tmp_bytes, (size_t)total * eb);
+        if (rc) return rc;
+        ECC_HIP(hipMemcpyAsync(ws->img_tmp, image, (size_t)total * eb, hipMemcpyHostToDevice, s));
+        img_dev = ws->img_tmp;
+    }
+    uint32_t *flag = ws->status + kStatusMinMaxOffset / 4 + 3;
+    rc = launch_zero(flag, 4, s);
+    if (rc) return rc;
+    rc = launch_int_to_f32(img_dev, (int)eb, total, (uint32_t)m, (float *)buf, flag, s);
+    if (rc) return rc;
+    uint32_t bad = 0;
+    ECC_HIP(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, s));
+    ECC_HIP(hipStreamSynchronize(s));
+    if (bad) {
+        set_error("a 14-bit image holds a value >= 16384");
+        return ECC_E_RANGE;
+    }
+    ecc_curve fc{};
+    fc.capacity = total;
+    fc.keys = (float *)(buf + o_keys);
+    fc.chi = (int64_t *)(buf + o_chi);
+    rc = compute_float(buf, dims, total, &fc, s, false);
+    if (rc) return rc;
+    int64_t *out = (int64_t *)(buf + o_out);
+    rc = launch_expand_steps(fc.keys, fc.chi, fc.count, (int)m, out, s);
+    if (rc) return rc;
+    ECC_HIP(hipMemcpyAsync(curve->chi, out, (size_t)m * 8, hipMemcpyDefault, s));
+    ECC_HIP(hipStreamSynchronize(s));
+    curve->count = m;
+    return ECC_OK;
+}
+
 // Synchronous integer curve: host or device image and curve.  max_entry:
 // each cell's value is the maximum over its voxels (the kernel reads M-1-v
 // and the merge writes the rows reversed).
@@ -421,6 +475,7 @@ static int compute_int(const void *image, const ecc_dims *dims, int64_t total, e
     IntView v{};
     int unsup = 0;
     if (!normalize_int_view(dims, &v, &unsup)) {
+        if (!max_entry && total <= (int64_t)UINT32_MAX) return compute_int_via_float(image, dims, total, dtype, curve, s);
         set_error("integer path: shape not supported (4 axes longer than 1, or an extent beyond 2^31)");
         return ECC_E_UNSUPPORTED;
     }
@@ -476,7 +531,7 @@ static int compute_int(const void *image, const ecc_dims *dims, int64_t total, e
 // steps_only: the output keeps the keys where chi changes (chi = 0 before
 // the first key), compacted after the full curve is built.
 static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc_curve *curve, hipStream_t s,
-                         bool steps_only = false) {
+                         bool steps_only) {
     if (!curve->keys) {
         set_error("ECC_F32 needs curve->keys");
         return ECC_E_ARG;
@@ -632,7 +687,7 @@ int ecc_compute(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_cu
         set_error("NULL image, curve or curve->chi");
         return ECC_E_ARG;
     }
-    if (dtype == ECC_F32) return compute_float(image, dims, total, curve, (hipStream_t)stream);
+    if (dtype == ECC_F32) return compute_float(image, dims, total, curve, (hipStream_t)stream, false);
     return compute_int(image, dims, total, dtype, curve, (hipStream_t)stream, false);
 }
 

@@ -424,6 +424,62 @@ int launch_change_points(const float *keys, const int64_t *chi, int64_t K, uint3
 }
 
 // ----------------------------------------------------------------------------
+// Integer images through the float path (images the integer kernel does not
+// take: four axes longer than 1).  Values convert exactly to float32; the
+// float curve lists chi after each distinct value, and chi(T_t) for integer
+// t is its value at the largest distinct value <= t (0 below the first).
+
+template <typename T>
+__global__ void __launch_bounds__(256) int_to_f32_kernel(const T *__restrict__ img, int64_t n, uint32_t limit,
+                                                         float *__restrict__ out, uint32_t *status) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t v = img[i];
+        bad |= v >= limit;
+        out[i] = (float)v;
+    }
+    if (__builtin_amdgcn_ballot_w64(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(status, kStatusRange);
+}
+
+int launch_int_to_f32(const void *img, int elem, int64_t n, uint32_t limit, float *out, uint32_t *status,
+                      hipStream_t stream) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    if (elem == 1)
+        hipLaunchKernelGGL(int_to_f32_kernel<uint8_t>, dim3((unsigned)blocks), dim3(256), 0, stream,
+                           (const uint8_t *)img, n, limit, out, status);
+    else
+        hipLaunchKernelGGL(int_to_f32_kernel<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, stream,
+                           (const uint16_t *)img, n, limit, out, status);
+    ECC_HIP(hipGetLastError());
+    return ECC_OK;
+}
+
+__global__ void __launch_bounds__(256) expand_steps_kernel(const float *__restrict__ keys,
+                                                           const int64_t *__restrict__ chi, int64_t K, int m,
+                                                           int64_t *__restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    const float ft = (float)t;
+    int64_t lo = 0, hi = K;  // first index with keys[idx] > t
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] <= ft) lo = mid + 1;
+        else hi = mid;
+    }
+    out[t] = lo > 0 ? chi[lo - 1] : 0;
+}
+
+int launch_expand_steps(const float *keys, const int64_t *chi, int64_t K, int m, int64_t *out,
+                        hipStream_t stream) {
+    hipLaunchKernelGGL(expand_steps_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, keys, chi, K, m, out);
+    ECC_HIP(hipGetLastError());
+    return ECC_OK;
+}
+
+// ----------------------------------------------------------------------------
 // Quantisation of a float image to integer bins: x = (v - lo) * scale in
 // float32 (each operation rounded to nearest); bin 0 below x = 0 (and -inf),
 // m-1 from x = m on (and +inf), else the integer part of x.  NaN sets the

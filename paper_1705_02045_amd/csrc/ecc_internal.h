@@ -185,6 +185,12 @@ int exclusive_scan_u32(uint32_t *a, int64_t n, uint32_t *sums, hipStream_t strea
 // Keys where chi changes, compacted (count written on the device).
 int launch_change_points(const float *keys, const int64_t *chi, int64_t K, uint32_t *pos, uint32_t *sums,
                          float *out_keys, int64_t *out_chi, int64_t *count, hipStream_t stream);
+// Integer image (elem = 1 or 2 bytes) to float32; values >= limit set kStatusRange.
+int launch_int_to_f32(const void *img, int elem, int64_t n, uint32_t limit, float *out, uint32_t *status,
+                      hipStream_t stream);
+// out[t] = chi at the largest key <= t (0 below keys[0]), t < m.
+int launch_expand_steps(const float *keys, const int64_t *chi, int64_t K, int m, int64_t *out,
+                        hipStream_t stream);
 // Float image to integer bins (elem = 1 or 2 bytes), NaN -> kStatusNaN.
 int launch_quantize(const float *img, int64_t n, float lo, float scale, int m, int elem, void *out,
                     uint32_t *status, hipStream_t stream);

@@ -76,11 +76,6 @@ def test_quantized(ecc, bins, k):
     m = ecc.THRESHOLDS[bins]
     lo, hi = -0.05, 1.05
     print(f"\n[gpu] quantised {bins} {img.shape}", flush=True)
-    if img.ndim == 4:  # the integer path takes at most three axes longer than 1
-        with pytest.raises(ecc.EccError) as ei:
-            ecc.compute_quantized(torch.from_numpy(img).cuda(), lo, hi, bins)
-        assert ei.value.code == ecc.ECC_E_UNSUPPORTED
-        return
     got = ecc.compute_quantized(torch.from_numpy(img).cuda(), lo, hi, bins).cpu().numpy()
     q = quantize_np(img, lo, hi, m)
     assert (got == oracle.curve(q, m=m)).all()

@@ -153,3 +153,25 @@ def test_full_size_256_squared_u8(ecc):
     """2-D 256x256 uint8 i.i.d. image (seed 0)."""
     img = gen.cfg_2d_u8_iid((256, 256), seed=0)
     check(ecc, img, "u8")
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 5, 6), (2, 9, 17, 33), (5, 5, 5, 5), (12, 16, 20, 24)], ids=str)
+def test_4d_integer_images(ecc, shape):
+    """Four axes longer than 1: exact through the float path (the curve is
+    the float step function read at every integer threshold)."""
+    print(f"\n[gpu] 4-D integer {shape}", flush=True)
+    check(ecc, gen.iid(shape, 8, seed=41), "u8")
+    check(ecc, gen.value_noise(shape, 14, 64, seed=42), "u14")
+    img16 = gen.iid(shape, 16, seed=43)
+    got = ecc.compute(torch.from_numpy(img16.view(np.int16)).cuda(), dtype="u16").cpu().numpy()
+    assert (got == oracle.curve(img16, m=65536)).all()
+    host = gen.iid(shape, 8, seed=44)
+    assert (ecc.compute_host(host, "u8") == oracle.curve(host, m=256)).all()
+
+
+def test_4d_integer_range_error(ecc):
+    img = gen.value_noise((3, 4, 5, 6), 14, 64, seed=45)
+    img[1, 2, 3, 4] = 16384
+    with pytest.raises(ecc.EccError) as ei:
+        gpu_curve(ecc, img, "u14")
+    assert ei.value.code == ecc.ECC_E_RANGE
