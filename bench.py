@@ -31,7 +31,10 @@ sys.path.insert(0, str(ROOT))
 
 METRIC = "GVoxel/s + % HBM peak, 3D 14-bit ECC; batched images/s at p99 latency"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1705_02045_amd/csrc/ecc_int.hip"]
+# the kernel, and the host code that picks its launch parameters (tiling,
+# look-ahead depth)
+KERNEL_SOURCES = ["paper_1705_02045_amd/csrc/ecc_int.hip", "paper_1705_02045_amd/csrc/ecc_internal.h",
+                  "paper_1705_02045_amd/csrc/ecc_api.cpp"]
 TRAFFIC_FILE = ROOT / "profiles" / "traffic_int_vcec_u14_1024cubed.json"
 
 
