@@ -7,6 +7,10 @@ the wrong plane segment in a later s_cselect and read before the image.  This
 test compiles the kernel and checks that no SCC value produced by compiled code
 is consumed after an SCC-writing asm block, and that no 16-bit VOP2 op (which
 keeps the upper half of its destination) produces an LDS offset.
+
+Image loads are 8- or 16-bit only.  A build that read each row as a dword of
+the values at x-1 and x (2-byte aligned) faulted the GPU with a memory
+violation: misaligned vector-memory accesses trap on the parts this runs on.
 """
 import pathlib
 import re
@@ -77,3 +81,11 @@ def test_no_scc_live_across_update_blocks(asm):
 def test_no_partial_register_16bit_ops(asm):
     bad = [l for l in asm if re.match(r"\s*v_(lshlrev_b16|min_u16)(_e32|_e64)?\s", l)]
     assert bad == []
+
+
+def test_image_loads_are_element_sized(asm):
+    """No multi-byte buffer load in the integer kernels: their image offsets are
+    only element-aligned (see the module docstring)."""
+    loads = [l.strip().split()[0] for l in asm if re.match(r"\s*buffer_load_", l)]
+    assert loads, "no buffer loads found"
+    assert set(loads) <= {"buffer_load_ushort", "buffer_load_ubyte"}, sorted(set(loads))
