@@ -162,7 +162,7 @@ static int env_int(const char *name, int dflt) {
 }
 
 // Tuning overrides (measurement only): ECC_INT_ROWS, ECC_INT_MODE, ECC_INT_PD, ECC_INT_WX,
-// ECC_INT_WAVES, ECC_INT_TILES_PER_CU, ECC_INT_TILE_STRIDE.
+// ECC_INT_WAVES, ECC_INT_TILES_PER_CU, ECC_INT_TILE_STRIDE, ECC_INT_PAIR (0: no row pairs).
 // The tiling for given parameters: R rows per wave, up to wx_cap waves
 // along x (16-wave workgroups), about tiles_per_cu workgroups per CU.
 IntTiling make_int_tiling(const IntView &v, int64_t planes, int rows, int tiles_per_cu, int wx_cap) {
@@ -203,6 +203,7 @@ IntTiling make_int_tiling(const IntView &v, int64_t planes, int rows, int tiles_
     const int64_t per = tiles > target ? (tiles + target - 1) / target : 1;
     t.per_wg = (int)per;
     t.tile_stride = env_int("ECC_INT_TILE_STRIDE", 0);
+    t.pair = env_int("ECC_INT_PAIR", 1);
     t.grid = (int)((tiles + per - 1) / per);
     return t;
 }

@@ -49,6 +49,7 @@ struct KParams {
     int32_t *partial;
     uint32_t *status;
     int64_t *zero_vcec;  // cleared by workgroup 0 when not null
+    int32_t pair;        // 16-bit values, two in-plane axes: row-pair layout (see tile_body)
 };
 
 // Fourth word of a raw buffer resource on gfx9-family parts (32-bit data format).
@@ -70,21 +71,63 @@ constexpr int kXfWindow = 2;
 // every offset (offsets are <= 0xFFFC).
 constexpr uint32_t kInf = 0xFFFFu;
 
+// Shifts by an inline constant use op_sel_hi:[0,1]: the high lane then reads
+// the constant's low half too.  With the default op_sel_hi the high lane
+// reads bits 31:16 of the 32-bit constant 2, i.e. 0, and is not shifted.
+#define ECC_PK_SHL2 "v_pk_lshlrev_b16 %0, 2, %1 op_sel_hi:[0,1]"
+
 // v: zero-extended 16-bit value
 __device__ __forceinline__ uint32_t bin_off(uint32_t v) {
     uint32_t r;
-    asm("v_pk_lshlrev_b16 %0, 2, %1" : "=v"(r) : "v"(v));
+    asm(ECC_PK_SHL2 : "=v"(r) : "v"(v));
     return r;
 }
 // a, b: zero-extended 16-bit values
 __device__ __forceinline__ uint32_t bin_off_min(uint32_t a, uint32_t b) {
     uint32_t m, r;
     asm("v_pk_min_u16 %0, %1, %2" : "=v"(m) : "v"(a), "v"(b));
-    asm("v_pk_lshlrev_b16 %0, 2, %1" : "=v"(r) : "v"(m));
+    asm(ECC_PK_SHL2 : "=v"(r) : "v"(m));
     return r;
 }
 // Both inputs are zero-extended offsets, so a 32-bit minimum is exact.
 __device__ __forceinline__ uint32_t min_off(uint32_t a, uint32_t b) { return a < b ? a : b; }
+
+// Row pairs (interior waves of 16-bit images with even rows, see tile_body):
+// each lane loads the aligned dword that holds the value at its column x,
+// i.e. the values at x & ~1 and (x & ~1) + 1.  The waves start at odd
+// columns, so the left neighbour x-1 is either the low half of the lane's own
+// dword (x odd) or the high half of the dword of the lane before it (x even),
+// which a wave shift moves over; no lane needs another wave's values.  The
+// pair (value at x-1) | (value at x) << 16 is then one byte permute: selector
+// kSelOdd keeps the own dword, kSelEven takes the previous lane's high half
+// and the own low half.  Every image load stays 4-byte aligned.
+constexpr uint32_t kSelOdd = 0x07060504u;
+constexpr uint32_t kSelEven = 0x05040302u;
+constexpr int kDppWaveShr1 = 0x138;  // lane i reads lane i-1 (lane 0 reads 0)
+
+// Lane 0 of a wave has an odd column, so its selector ignores `prev`.
+__device__ __forceinline__ uint32_t row_pair(uint32_t d, uint32_t sel) {
+    const uint32_t prev = (uint32_t)__builtin_amdgcn_mov_dpp((int)d, kDppWaveShr1, 0xF, 0xF, true);
+    return __builtin_amdgcn_perm(d, prev, sel);
+}
+// From a pair q (already transformed): q4 = q * 4 per half, f0 = q4 >> 16
+// (the offset of x), fx = low half of min(q4, f0) (the window {x-1, x}); its
+// high half is min(q4.hi, 0) = 0, so fx is zero-extended.
+__device__ __forceinline__ void pair_offsets(uint32_t q, uint32_t &f0, uint32_t &fx) {
+    uint32_t q4, m;
+    asm(ECC_PK_SHL2 : "=v"(q4) : "v"(q));
+    f0 = q4 >> 16;
+    asm("v_pk_min_u16 %0, %1, %2" : "=v"(m) : "v"(q4), "v"(f0));
+    fx = m;
+}
+// clamp(v - s, 0, 16383) on both halves; s2 = s | s << 16 (0 <= s < 65536)
+__device__ __forceinline__ uint32_t pair_window(uint32_t q, uint32_t s2) {
+    uint32_t m, d, r;
+    asm("v_pk_max_u16 %0, %1, %2" : "=v"(m) : "v"(q), "s"(s2));
+    asm("v_pk_sub_u16 %0, %1, %2" : "=v"(d) : "v"(m), "s"(s2));
+    asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(d), "s"(0x3FFF3FFFu));
+    return r;
+}
 
 __device__ __forceinline__ uint32_t load_elem(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, int esz) {
     if (esz == 1) return __builtin_amdgcn_raw_buffer_load_b8(rs, voff, soff, 0);
@@ -199,6 +242,25 @@ struct Walker {
         }
     }
 
+    // The same fields (NIN == 2) from the loaded dwords d[rr] of the row-pair
+    // layout; sel: the lane's byte selector; xfp: the value transform applied
+    // to both halves of a pair.
+    template <typename X>
+    static __device__ __forceinline__ void fields_pair(const uint32_t (&d)[NR], uint32_t sel, uint32_t (&g)[NI],
+                                                       X xfp) {
+        static_assert(NIN == 2, "row pairs: two in-plane axes");
+        uint32_t f0[NR], fx[NR];
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) pair_offsets(xfp(row_pair(d[rr], sel)), f0[rr], fx[rr]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            g[4 * r + 0] = f0[r + 1];
+            g[4 * r + 1] = fx[r + 1];
+            g[4 * r + 2] = min_off(f0[r], f0[r + 1]);
+            g[4 * r + 3] = min_off(fx[r], fx[r + 1]);
+        }
+    }
+
     static __device__ __forceinline__ void set_inf(uint32_t (&g)[NI]) {
 #pragma unroll
         for (int i = 0; i < NI; ++i) g[i] = kInf;
@@ -251,14 +313,17 @@ constexpr int lcm(int a, int b) {
 
 // One wave walks the planes [zs, ze) of its rows.  FULL: no position of this
 // wave lies on a far edge, so the comparison masks need no validity mask.
+// PAIR (FULL waves of the row-pair layout): one dword load per row at byte
+// offset vx[rr], and psel, the lane's pair selector; vxl is unused.
 // PD: planes of raw loads kept in flight ahead of the plane being compared.
 // The plane loop is unrolled by lcm(2, PD+1) so that every register buffer is
 // addressed with a compile-time index (plane p of the tile uses raw buffer
 // (p - zs) mod (PD+1) and field buffer (p - zs) mod 2).
-template <typename T, int NIN, int R, int MODE, bool FULL, int PD, int XF>
+template <typename T, int NIN, int R, int MODE, bool FULL, int PD, int XF, bool PAIR = false>
 __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uint32_t (&vx)[R + 1],
                                      const uint32_t (&vxl)[R + 1], const uint32_t (&soff)[R + 1], const EdgeMasks &em,
-                                     uint32_t &orv) {
+                                     uint32_t &orv, uint32_t psel = 0) {
+    static_assert(!PAIR || (FULL && NIN == 2 && sizeof(T) == 2), "row pairs: interior 16-bit waves, 2 axes");
     using W = Walker<NIN, R>;
     constexpr int NR = W::NR;
     constexpr int NI = W::NI;
@@ -277,8 +342,12 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
         __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)pp, (short)0, pbytes, kBufferWord3);
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) {
-            a[rr] = load_elem(rs, vx[rr], soff[rr], ESZ);
-            b[rr] = load_elem(rs, vxl[rr], soff[rr], ESZ);
+            if constexpr (PAIR) {
+                a[rr] = __builtin_amdgcn_raw_buffer_load_b32(rs, vx[rr], soff[rr], 0);
+            } else {
+                a[rr] = load_elem(rs, vx[rr], soff[rr], ESZ);
+                b[rr] = load_elem(rs, vxl[rr], soff[rr], ESZ);
+            }
         }
     };
     auto plane_ptr = [&](int p) { return (p < 0 ? P.src.lo_base : P.src.base) + p * pb; };
@@ -296,6 +365,14 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
     // wait at once and lose the planes of look-ahead.
     const int32_t wshift = P.win_shift;
     auto fields = [&](const uint32_t (&a)[NR], const uint32_t (&b)[NR], uint32_t (&g)[NI]) {
+        if constexpr (PAIR) {
+            W::fields_pair(a, psel, g, [&](uint32_t q) -> uint32_t {
+                if constexpr (XF == kXfInvert) return q ^ (kInvMask * 0x10001u);
+                else if constexpr (XF == kXfWindow) return pair_window(q, (uint32_t)wshift * 0x10001u);
+                else return q;
+            });
+            return;
+        }
         W::fields(a, b, g, [&](uint32_t v) -> uint32_t {
             if constexpr (XF == kXfInvert) return v ^ kInvMask;  // M-1-v (M a power of two)
             else if constexpr (XF == kXfWindow)  // 16-bit window: v - shift clamped to 0..16383
@@ -429,6 +506,7 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
     // (batched launches use a fixed workgroup size: waves past wx * wy idle)
     const bool wave_in = wave < P.wx * P.wy;
     const int32_t n1 = P.n1, n2 = P.n2;
+    const bool pair = NIN == 2 && ESZ == 2 && P.pair;
 
     // workgroup b (permuted: the workgroups of one XCD take neighbouring
     // indices) walks its tiles into one histogram: a run of per_wg
@@ -452,6 +530,7 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
     uint32_t vx[R + 1] = {}, vxl[R + 1] = {}, soff[R + 1] = {};
     EdgeMasks em{};
     bool full = false, any = false;
+    uint32_t psel = 0;
     if constexpr (NIN == 1) {
         const int32_t seg0 = (tx * P.wx + wxi) * R;
         any = wave_in && seg0 * kWave < n2;
@@ -463,16 +542,22 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
             vxl[r] = (uint32_t)(xcl > 0 ? xcl - 1 : 0) * ESZ;
         }
     } else {
-        const int32_t x0 = (tx * P.wx + wxi) * kWave;
-        const int32_t x = x0 + lane;
+        // Row-pair layout: waves start at odd columns (x0 = 64 k + 1) and
+        // column 0 is taken by the lane of column n2 (n2 is even there, so
+        // that lane exists, in the last wave of the row, an edge wave).
+        const int32_t x0 = (tx * P.wx + wxi) * kWave + (pair ? 1 : 0);
+        int32_t x = x0 + lane;
+        if (pair && x == n2) x = 0;
         const int32_t y0 = (ty * P.wy + wyi) * R;
         any = wave_in && x0 < n2 && y0 < n1;
         full = (x0 + kWave - 1 <= n2 - 2) && (y0 + R - 1 <= n1 - 2);
+        psel = (x & 1) ? kSelOdd : kSelEven;
         const int32_t xcl = min(x, n2 - 1);
         const uint32_t ox = (uint32_t)xcl * ESZ, oxl = (uint32_t)(xcl > 0 ? xcl - 1 : 0) * ESZ;
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) {
-            vx[rr] = ox;
+            // row pairs: the aligned dword holding column x
+            vx[rr] = (pair && full) ? (uint32_t)(x & ~1) * 2u : ox;
             vxl[rr] = oxl;
             const int32_t y = min(max(y0 + rr - 1, 0), n1 - 1);
             soff[rr] = (uint32_t)y * (uint32_t)n2 * ESZ;
@@ -489,7 +574,14 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
     }
     if (any && zs < ze) {
         if (full) {
-            walk<T, NIN, R, MODE, true, PD, XF>(P, zs, ze, vx, vxl, soff, em, orv);
+            if constexpr (NIN == 2 && ESZ == 2) {
+                if (pair)
+                    walk<T, NIN, R, MODE, true, PD, XF, true>(P, zs, ze, vx, vxl, soff, em, orv, psel);
+                else
+                    walk<T, NIN, R, MODE, true, PD, XF>(P, zs, ze, vx, vxl, soff, em, orv);
+            } else {
+                walk<T, NIN, R, MODE, true, PD, XF>(P, zs, ze, vx, vxl, soff, em, orv);
+            }
         } else if constexpr (NIN == 1) {
             // An edge group of segments is walked as pairs of segments, each
             // pair with its own lane masks.
@@ -515,7 +607,8 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
     }  // tiles
 
     if constexpr (M != 256) {
-        if (orv >= (uint32_t)M) atomicOr(P.status, kStatusRange);
+        // (row pairs hold a second value in the high half)
+        if (((orv | (orv >> 16)) & 0xFFFFu) >= (uint32_t)M) atomicOr(P.status, kStatusRange);
     }
     // the update blocks' LDS adds are not tracked by the compiler's counters
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -655,6 +748,9 @@ static KParams make_params(const IntJob &job, const IntTiling &tl, int32_t *part
     p.per_wg = tl.per_wg > 0 ? tl.per_wg : 1;
     p.tile_stride = tl.tile_stride;
     p.win_shift = job.win_shift;
+    // row pairs need every row to start 4-byte aligned
+    p.pair = nin == 2 && elem_bytes(job.dtype) == 2 && job.view.n2 % 2 == 0 &&
+             ((uintptr_t)job.src.base & 3) == 0 && ((uintptr_t)job.src.lo_base & 3) == 0 && tl.pair != 0;
     p.partial = partial;
     p.status = status;
     p.zero_vcec = zero_vcec;

@@ -72,6 +72,7 @@ struct IntTiling {
     int per_wg;    // tiles walked by one workgroup into one histogram (at most)
     int tile_stride;  // 0: a workgroup walks per_wg consecutive tiles; 1: tiles strided by the grid
     int grid;      // workgroups = ceil(tiles / per_wg)
+    int pair = 1;  // row-pair layout allowed (used where the shape and alignment permit)
 };
 
 // Device scratch of one (device, stream) pair.

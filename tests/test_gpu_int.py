@@ -37,12 +37,18 @@ SHAPES_3D = [(1, 1, 1), (2, 2, 2), (3, 5, 7), (5, 64, 64), (4, 63, 65), (7, 66, 
              (33, 40, 200), (20, 129, 63), (64, 64, 64), (3, 1, 300), (100, 2, 2), (2, 300, 1)]
 
 
-FAULTED_THIS_ROUND = pytest.mark.skip(
-    reason="faulted the GPU twice with an inline-asm build that clobbered SCC (cause found in the ISA and "
-           "fixed; tests/test_isa_checks.py); kept off the GPU for the rest of this round")
+FAULTED_THIS_ROUND = {
+    (33, 40, 200): pytest.mark.skip(
+        reason="faulted the GPU twice with an inline-asm build that clobbered SCC (cause found in the ISA and "
+               "fixed; tests/test_isa_checks.py); kept off the GPU for the rest of this round"),
+    (7, 66, 130): pytest.mark.skip(
+        reason="faulted the GPU twice with row-pair builds whose packed shift left the high lane unshifted "
+               "(misaligned LDS adds; cause shown in the compiler's encoding and fixed, tests/test_isa_checks.py); "
+               "kept off the GPU for the rest of this round"),
+}
 
 
-@pytest.mark.parametrize("shape", [pytest.param(s, marks=FAULTED_THIS_ROUND) if s == (33, 40, 200) else s
+@pytest.mark.parametrize("shape", [pytest.param(s, marks=FAULTED_THIS_ROUND[s]) if s in FAULTED_THIS_ROUND else s
                                    for s in SHAPES_3D], ids=str)
 def test_u14_value_noise_3d(ecc, shape):
     print(f"\n[gpu] u14 value noise {shape}", flush=True)
@@ -175,3 +181,28 @@ def test_4d_integer_range_error(ecc):
     with pytest.raises(ecc.EccError) as ei:
         gpu_curve(ecc, img, "u14")
     assert ei.value.code == ecc.ECC_E_RANGE
+
+
+ROW_PAIR_SHAPES = [(6, 34, 258), (5, 70, 194), (11, 9, 1026), (3, 130, 132), (2, 3, 4098), (4, 65, 450)]
+
+
+@pytest.mark.parametrize("tiling", [{}, {"ECC_INT_ROWS": "4"}, {"ECC_INT_PD": "2"},
+                                    {"ECC_INT_ROWS": "4", "ECC_INT_PD": "2"}, {"ECC_INT_PAIR": "0"}], ids=str)
+@pytest.mark.parametrize("shape", ROW_PAIR_SHAPES, ids=str)
+def test_row_pair_layout(ecc, shape, tiling, monkeypatch):
+    """16-bit images with even rows: interior waves read aligned dwords and
+    form (x-1, x) pairs with a wave shift; waves start at odd columns and
+    column 0 goes to the spare lane of each row's last wave.  Several interior
+    waves per row, ragged last waves, two and four rows per wave, one and two
+    planes of look-ahead, and the same shapes without row pairs; the
+    largest-value convention and 16-bit windows use the same loads."""
+    for k, v in tiling.items():
+        monkeypatch.setenv(k, v)
+    print(f"\n[gpu] row pairs {shape} {tiling}", flush=True)
+    img = gen.cfg_u14_value_noise(shape, seed=21)
+    check(ecc, img, "u14")
+    t = torch.from_numpy(img.view(np.int16)).cuda()
+    assert (ecc.compute_max_entry(t, "u14").cpu().numpy() == oracle.curve_max_entry(img, m=16384)).all()
+    img16 = gen.iid(shape, 16, seed=22)
+    got16 = ecc.compute(torch.from_numpy(img16.view(np.int16)).cuda(), dtype="u16").cpu().numpy()
+    assert (got16 == oracle.curve(img16, m=65536)).all()

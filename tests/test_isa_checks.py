@@ -8,9 +8,16 @@ test compiles the kernel and checks that no SCC value produced by compiled code
 is consumed after an SCC-writing asm block, and that no 16-bit VOP2 op (which
 keeps the upper half of its destination) produces an LDS offset.
 
-Image loads are 8- or 16-bit only.  A build that read each row as a dword of
-the values at x-1 and x (2-byte aligned) faulted the GPU with a memory
-violation: misaligned vector-memory accesses trap on the parts this runs on.
+Two builds of the row-pair path (16-bit values at x-1 and x packed in one
+register) faulted the GPU with a memory violation.  Their packed shift by an
+inline constant, `v_pk_lshlrev_b16 d, 2, s`, kept the default op_sel_hi, so
+the high lane read bits 31:16 of the constant (0) and was not shifted: the
+LDS byte offsets of the high values were not multiples of 4, and the
+histogram adds trapped on them.  The compiler's own splat shift carries
+op_sel_hi:[0,1].  Checked here: every packed op with an inline constant
+reads that constant's low half in both lanes.  Dword image loads exist only
+in the row-pair path, whose offsets are 4-byte aligned by construction
+(test_row_pair_map.py); it is recognisable by its wave shift and byte permute.
 """
 import pathlib
 import re
@@ -83,9 +90,59 @@ def test_no_partial_register_16bit_ops(asm):
     assert bad == []
 
 
-def test_image_loads_are_element_sized(asm):
-    """No multi-byte buffer load in the integer kernels: their image offsets are
-    only element-aligned (see the module docstring)."""
-    loads = [l.strip().split()[0] for l in asm if re.match(r"\s*buffer_load_", l)]
-    assert loads, "no buffer loads found"
-    assert set(loads) <= {"buffer_load_ushort", "buffer_load_ubyte"}, sorted(set(loads))
+
+def functions(asm):
+    """(name, lines) of each function of the assembly."""
+    out, name, body = [], None, []
+    for line in asm:
+        m = re.match(r"^(_Z\w+):", line)
+        if m:
+            if name:
+                out.append((name, body))
+            name, body = m.group(1), []
+        elif name:
+            body.append(line)
+    if name:
+        out.append((name, body))
+    return out
+
+
+def test_dword_image_loads_only_in_row_pair_path(asm):
+    """Image loads are 8- or 16-bit, except in functions that carry the
+    row-pair form (a wave shift by one lane and a byte permute)."""
+    seen = 0
+    for name, body in functions(asm):
+        loads = {l.strip().split()[0] for l in body if re.match(r"\s*buffer_load_", l)}
+        wide = loads - {"buffer_load_ushort", "buffer_load_ubyte"}
+        if not wide:
+            continue
+        assert wide == {"buffer_load_dword"}, (name, sorted(wide))
+        text = "\n".join(body)
+        assert "wave_shr:1" in text and "v_perm_b32" in text, name
+        assert "int_vcec" in name, name
+        seen += 1
+    assert seen > 0, "row-pair path not found"
+
+
+PK_OP = re.compile(r"\s*(v_pk_\w+)\s+([^;]*)")
+
+
+def test_packed_inline_constants_reach_both_lanes(asm):
+    """A packed op whose source k is an inline integer constant has bit k of
+    op_sel_hi clear (the high lane reads the constant's low half)."""
+    bad, seen = [], 0
+    for line in asm:
+        m = PK_OP.match(line)
+        if not m:
+            continue
+        text = m.group(2)
+        mods = dict(re.findall(r"(\w+):\[([\d,]+)\]", text))
+        ops = [o.strip() for o in re.sub(r"\s\w+:\[[\d,]+\]", "", text).split(",")][1:]
+        hi = [int(b) for b in mods.get("op_sel_hi", "1,1,1").split(",")]
+        for k, o in enumerate(ops):
+            if re.fullmatch(r"-?\d+", o):
+                seen += 1
+                if k < len(hi) and hi[k] != 0:
+                    bad.append(line.strip())
+    assert seen > 0, "no packed op with an inline constant found"
+    assert bad == [], bad[:5]
