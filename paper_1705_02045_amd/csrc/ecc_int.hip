@@ -697,6 +697,7 @@ static int launch_mode(const KParams &p, const IntTiling &tl, hipStream_t stream
     switch (tl.mode) {
     case 0: return launch_pd<T, M, NIN, R, 0>(p, tl, stream);
     case 1: return launch_pd<T, M, NIN, R, 1>(p, tl, stream);
+    case 3: return launch_pd<T, M, NIN, R, 3>(p, tl, stream);
     default: break;
     }
     set_error("integer kernel: update mode %d not built", tl.mode);
