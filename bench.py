@@ -378,7 +378,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget; 0 skips it")
     ap.add_argument("--legs", default="serving,float,stream_host,stream_device,conventions,u16,small_2d",
                     help="further workloads reported under 'legs' (comma list, or 'none')")
-    ap.add_argument("--serve-requests", type=int, default=1024)
+    ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-slo-ms", type=float, default=10.0)
     ap.add_argument("--serve-budget-gib", type=int, default=8, help="device footprint admitted per batch")
     ap.add_argument("--no-autotune", action="store_true", help="keep the launch-size tiling rule")
