@@ -14,7 +14,8 @@
 //     change(v) = sum_s (-1)^dim(s) [U_s = 0] = 1 - sum_{s != 0} (-1)^dim(s) U_s
 // (the first sum over all s is prod_i (2 - 1) = 1).
 //
-// On the GPU a wave holds 64 consecutive voxels of one line of the last axis;
+// On the GPU a wave holds 64 consecutive voxels of one line of the last axis
+// (their neighbourhoods staged in LDS by the workgroup);
 // "precedes" for each of the 3^D - 1 neighbour directions is one ballot, the
 // recursion for U_s runs on those wave-wide masks in scalar registers, and
 // each U_s is accumulated per lane with one add-with-carry.
@@ -74,93 +75,140 @@ struct FloatView {
     int32_t n[4];       // extents, axis 0 slowest, padded in front with 1
     uint32_t stride[4]; // element strides
     int32_t bpr;        // blocks per line of the last axis
+    int32_t run;        // lines along axis 2 walked by one workgroup
+    int32_t nruns;      // runs per axis-2 extent
 };
 
 // One thread per voxel.  D = number of axes after dropping axes of extent 1
 // (the complex of the others times unit intervals has the same curve).
-template <int D>
-__global__ void __launch_bounds__(256) float_change_kernel(const float *__restrict__ img, uint32_t img_bytes,
-                                                           FloatView v, uint64_t *__restrict__ rec,
-                                                           uint32_t *status) {
+//
+// A workgroup of T threads takes T consecutive voxels (x in [xs, xs+T)) of a
+// run of consecutive lines along axis 2 of the padded view and walks the run
+// line by line.  The values of the 3^D neighbourhood come from LDS: a ring of
+// four slots, one per line position along axis 2, each holding the
+// S = 3^(D-2) lines at offsets -1, 0, +1 along the axes before it, over
+// x in [xs-1, xs+T].  While line y is compared, the loads for line y+2 are in
+// flight; each line is loaded once per workgroup (one coalesced load per
+// thread and line, plus one load for the two ends of all S lines), instead of
+// 3^D - 1 scattered loads per voxel.  Absent neighbours (outside the image)
+// are stored as NaN, which compares false and so never precedes.
+template <int D, int T>
+__global__ void __launch_bounds__(T) float_change_kernel(const float *__restrict__ img, uint32_t img_bytes,
+                                                         FloatView v, uint64_t *__restrict__ rec,
+                                                         uint32_t *status) {
     constexpr int P = pow3(D);
-    constexpr int C = (P - 1) / 2;  // code of the zero direction
-    const int32_t nx = v.n[3];
-    const int64_t line = blockIdx.x / v.bpr;
-    const int32_t x = (int32_t)(blockIdx.x % v.bpr) * (int32_t)blockDim.x + (int32_t)threadIdx.x;
-    // lanes past the end of the line stay in step (no early exit keeps the
-    // ballots and the scalar mask arithmetic in uniform control flow)
+    constexpr int C = (P - 1) / 2;             // code of the zero direction
+    constexpr int S = D >= 2 ? pow3(D - 2) : 1;  // lines per slot
+    constexpr int PITCH = T + 2;
+    __shared__ float ring[4 * S * PITCH];
+    const int32_t nx = v.n[3], n2 = v.n[2];
+    const int tid = (int)threadIdx.x;
+    // block -> (outer line over axes 0..1, run along axis 2, x block); uniform
+    int32_t r = __builtin_amdgcn_readfirstlane((int32_t)blockIdx.x);
+    const int32_t xs = (r % v.bpr) * T;
+    r /= v.bpr;
+    const int32_t y0 = (r % v.nruns) * v.run;
+    const int32_t y1 = min(y0 + v.run, n2);
+    r /= v.nruns;
+    const int32_t c1 = r % v.n[1];
+    const int32_t c0 = r / v.n[1];
+    const int32_t x = xs + tid;
     const bool act = x < nx;
-    // coordinates of the line (uniform): axes 4-D .. 2 of the padded view
-    int32_t c[4];
-    {
-        // (readfirstlane: the compiler must see these as wave-uniform, so that
-        // the per-direction tests below stay scalar branches)
-        int32_t r = __builtin_amdgcn_readfirstlane((int32_t)line);
-#pragma unroll
-        for (int k = 2; k >= 4 - D; --k) {
-            c[k] = __builtin_amdgcn_readfirstlane(r % v.n[k]);
-            r = __builtin_amdgcn_readfirstlane(r / v.n[k]);
-        }
-    }
-    uint32_t base = (uint32_t)x;  // element index of v
-#pragma unroll
-    for (int k = 4 - D; k <= 2; ++k) base += (uint32_t)c[k] * v.stride[k];
     __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)img, (short)0, (int)img_bytes, 0x00020000);
-    // Every load below is unconditional, at a clamped address when its
-    // result is not used (offsets past the buffer read 0), so that no branch
-    // surrounds the ballots.
-    const uint32_t own_bits = __builtin_amdgcn_raw_buffer_load_b32(rs, base * 4u, 0, 0);
-    const uint32_t k0 = f32_key(own_bits);
-    const float f0 = __uint_as_float(own_bits);
+    const float nan = __uint_as_float(0x7FC00000u);
 
-    // prec[t]: the neighbour in direction t exists and precedes v
-    uint64_t prec[P];
+    // slot line j: offsets (digit 0 of j -> axis 1, digit 1 -> axis 0); the
+    // element index of (line j at axis-2 position y, x = 0), or -1 if absent
+    auto line_base = [&](int j, int32_t y) -> int64_t {
+        const int32_t a1 = c1 + (D >= 3 ? (j % 3) - 1 : 0);
+        const int32_t a0 = c0 + (D >= 4 ? (j / 3) % 3 - 1 : 0);
+        if (y < 0 || y >= n2 || a1 < 0 || a1 >= v.n[1] || a0 < 0 || a0 >= v.n[0]) return -1;
+        return (int64_t)a0 * v.stride[0] + (int64_t)a1 * v.stride[1] + (int64_t)y * v.stride[2];
+    };
+    // the end values x = xs-1 (even lanes) and xs+T (odd lanes) of line
+    // (tid >> 1), lanes 0 .. 2S-1
+    const int ej = tid >> 1;
+    const int32_t xe = (tid & 1) ? xs + T : xs - 1;
+    auto fetch = [&](int32_t y, float (&val)[S], float &end) {
 #pragma unroll
-    for (int t = 0; t < P; ++t) {
-        prec[t] = 0;
-        if (t == C) continue;  // compile-time
-        // axes other than the last: uniform validity
-        bool ok = true;
-        int32_t off = 0;
-#pragma unroll
-        for (int j = 1; j < D; ++j) {  // digit j <-> padded axis 3 - j
-            const int k = 3 - j;
-            const int dg = digit3(t, j);
-            if (dg == 0) ok = ok && c[k] > 0;
-            if (dg == 2) ok = ok && c[k] < v.n[k] - 1;
-            off += (dg - 1) * (int32_t)v.stride[k];
+        for (int j = 0; j < S; ++j) {
+            const int64_t lb = line_base(j, y);  // uniform
+            val[j] = nan;
+            if (lb >= 0 && act) val[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)(lb + x) * 4u, 0, 0));
         }
-        const int dx = digit3(t, 0) - 1;
-        const bool lane_ok = ok && act && ((dx == 0) || (dx < 0 ? x > 0 : x < nx - 1));
-        const uint32_t idx = lane_ok ? base + (uint32_t)(off + dx) : base;
-        // IEEE comparisons: -0 == +0, infinities are ordinary values (a NaN
-        // anywhere fails the whole call)
-        const float fn = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, idx * 4u, 0, 0));
-        const bool p = earlier<D>(t) ? (fn <= f0) : (fn < f0);
-        prec[t] = ballot64(lane_ok && p);
-    }
-    // U_s over increasing numbers of non-zero components, then the signed sum
-    uint64_t U[P];
-    U[C] = 0;  // the zero direction: empty box
-    int32_t acc = 0;
+        end = nan;
+        if (tid < 2 * S) {
+            int64_t lb = -1;
 #pragma unroll
-    for (int lvl = 1; lvl <= D; ++lvl) {
+            for (int j = 0; j < S; ++j)
+                if (j == ej) lb = line_base(j, y);
+            if (lb >= 0 && xe >= 0 && xe < nx)
+                end = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)(lb + xe) * 4u, 0, 0));
+        }
+    };
+    auto store = [&](int32_t y, const float (&val)[S], float end) {
+        float *slot = ring + (y & 3) * (S * PITCH);
+#pragma unroll
+        for (int j = 0; j < S; ++j) slot[j * PITCH + 1 + tid] = val[j];
+        if (tid < 2 * S) slot[ej * PITCH + ((tid & 1) ? T + 1 : 0)] = end;
+    };
+
+    float val[S], end;
+    for (int32_t y = y0 - 1; y <= y0 + 1; ++y) {
+        fetch(y, val, end);
+        store(y, val, end);
+    }
+    for (int32_t y = y0; y < y1; ++y) {
+        __syncthreads();  // slots y-1 .. y+1 written; slot y+2 (= y-2) no longer read
+        const bool next = y + 1 < y1;
+        if (next) fetch(y + 2, val, end);
+        // this voxel's column in the three slots around y
+        const float *col[3];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) col[dy] = ring + ((y - 1 + dy) & 3) * (S * PITCH) + 1 + tid;
+        const float f0 = col[1][(S / 2) * PITCH];
+        const uint32_t own_bits = __float_as_uint(f0);
+        const uint32_t k0 = f32_key(own_bits);
+
+        // prec[t]: the neighbour in direction t exists and precedes v
+        uint64_t prec[P];
 #pragma unroll
         for (int t = 0; t < P; ++t) {
-            if (nonzeros<D>(t) != lvl) continue;
-            uint64_t u = prec[t];
-#pragma unroll
-            for (int j = 0; j < D; ++j)
-                if (digit3(t, j) != 1) u |= U[t + (1 - digit3(t, j)) * pow3(j)];
-            U[t] = u;
-            // (-1)^dim, dim = D - lvl: subtract for even dim, add for odd
-            if (((D - lvl) & 1) == 0) add_bit(acc, u);
-            else sub_bit(acc, u);
+            prec[t] = 0;
+            if (t == C) continue;  // compile-time
+            const int dx = digit3(t, 0) - 1;
+            const int dyi = D >= 2 ? digit3(t, 1) : 1;
+            const int j = D >= 3 ? t / 9 : 0;
+            // IEEE comparisons: -0 == +0, infinities are ordinary values, NaN
+            // (an absent neighbour) never precedes; a NaN in the image fails the call
+            const float fn = col[dyi][j * PITCH + dx];
+            const bool p = earlier<D>(t) ? (fn <= f0) : (fn < f0);
+            prec[t] = ballot64(p);
         }
+        // U_s over increasing numbers of non-zero components, then the signed sum
+        uint64_t U[P];
+        U[C] = 0;  // the zero direction: empty box
+        int32_t acc = 0;
+#pragma unroll
+        for (int lvl = 1; lvl <= D; ++lvl) {
+#pragma unroll
+            for (int t = 0; t < P; ++t) {
+                if (nonzeros<D>(t) != lvl) continue;
+                uint64_t u = prec[t];
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    if (digit3(t, j) != 1) u |= U[t + (1 - digit3(t, j)) * pow3(j)];
+                U[t] = u;
+                // (-1)^dim, dim = D - lvl: subtract for even dim, add for odd
+                if (((D - lvl) & 1) == 0) add_bit(acc, u);
+                else sub_bit(acc, u);
+            }
+        }
+        if (ballot64(act && (own_bits & 0x7FFFFFFFu) > 0x7F800000u) != 0 && (threadIdx.x & (kWave - 1)) == 0)
+            atomicOr(status, kStatusNaN);
+        if (act) rec[line_base(S / 2, y) + x] = ((uint64_t)k0 << 8) | (uint8_t)(int8_t)(1 - acc);
+        if (next) store(y + 2, val, end);
     }
-    if (ballot64(act && (own_bits & 0x7FFFFFFFu) > 0x7F800000u) != 0 && (threadIdx.x & (kWave - 1)) == 0)
-        atomicOr(status, kStatusNaN);
-    if (act) rec[base] = ((uint64_t)k0 << 8) | (uint8_t)(int8_t)(1 - acc);
 }
 
 int launch_float_change(const float *img_dev, const ecc_dims *dims, uint64_t *rec, uint32_t *status,
@@ -190,8 +238,9 @@ int launch_float_change(const float *img_dev, const ecc_dims *dims, uint64_t *re
     const int nx = v.n[3];
     const int threads = nx >= 256 ? 256 : ((nx + 63) / 64) * 64;
     v.bpr = (nx + threads - 1) / threads;
-    const int64_t lines = total / nx;
-    const int64_t grid = lines * v.bpr;
+    v.run = v.n[2] < 32 ? v.n[2] : 32;
+    v.nruns = (v.n[2] + v.run - 1) / v.run;
+    const int64_t grid = (int64_t)v.n[0] * v.n[1] * v.nruns * v.bpr;
     if (grid > INT32_MAX) {
         set_error("float image: too many lines");
         return ECC_E_UNSUPPORTED;
@@ -200,12 +249,21 @@ int launch_float_change(const float *img_dev, const ecc_dims *dims, uint64_t *re
     void *tok = nullptr;
     int rc = profile_begin(stream, &tok);
     if (rc) return rc;
-    switch (D) {
-    case 1: hipLaunchKernelGGL(float_change_kernel<1>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, rec, status); break;
-    case 2: hipLaunchKernelGGL(float_change_kernel<2>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, rec, status); break;
-    case 3: hipLaunchKernelGGL(float_change_kernel<3>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, rec, status); break;
-    default: hipLaunchKernelGGL(float_change_kernel<4>, dim3((unsigned)grid), dim3(threads), 0, stream, img_dev, bytes, v, rec, status); break;
+    const dim3 g((unsigned)grid), b(threads);
+#define ECC_FCK(DD)                                                                                              \
+    switch (threads) {                                                                                           \
+    case 64: hipLaunchKernelGGL((float_change_kernel<DD, 64>), g, b, 0, stream, img_dev, bytes, v, rec, status); break;   \
+    case 128: hipLaunchKernelGGL((float_change_kernel<DD, 128>), g, b, 0, stream, img_dev, bytes, v, rec, status); break; \
+    case 192: hipLaunchKernelGGL((float_change_kernel<DD, 192>), g, b, 0, stream, img_dev, bytes, v, rec, status); break; \
+    default: hipLaunchKernelGGL((float_change_kernel<DD, 256>), g, b, 0, stream, img_dev, bytes, v, rec, status); break;  \
     }
+    switch (D) {
+    case 1: ECC_FCK(1); break;
+    case 2: ECC_FCK(2); break;
+    case 3: ECC_FCK(3); break;
+    default: ECC_FCK(4); break;
+    }
+#undef ECC_FCK
     ECC_HIP(hipGetLastError());
     return profile_end(stream, tok);
 }
