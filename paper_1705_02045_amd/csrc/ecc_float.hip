@@ -371,9 +371,30 @@ __global__ void __launch_bounds__(kFThreads) fwrite_kernel(const uint64_t *__res
                                                           const int64_t *__restrict__ tile_last,
                                                           float *__restrict__ out_keys, int64_t *__restrict__ out_chi) {
     __shared__ int64_t wc[4], wl[4];
+    // the tile and the record after it, loaded coalesced; slot i at i + i / 16
+    // (threads then read 16 consecutive records without bank conflicts)
+    __shared__ uint64_t tile[kFTile + kFTile / 16 + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t t0 = (int64_t)blockIdx.x * kFTile;
+#pragma unroll
+    for (int j = 0; j < kFItems; ++j) {
+        const int q = j * kFThreads + tid;
+        const int64_t i = t0 + q;
+        tile[q + q / 16] = i < n ? rec[i] : 0ull;
+    }
+    if (tid == 0) {
+        const int64_t i = t0 + kFTile;
+        tile[kFTile + kFTile / 16] = i < n ? rec[i] : 0ull;
+    }
+    __syncthreads();
     // each thread takes kFItems consecutive records of the tile
-    const int64_t i0 = (int64_t)blockIdx.x * kFTile + (int64_t)tid * kFItems;
+    const int64_t i0 = t0 + (int64_t)tid * kFItems;
+    uint64_t r[kFItems + 1];
+#pragma unroll
+    for (int j = 0; j <= kFItems; ++j) {
+        const int q = tid * kFItems + j;
+        r[j] = tile[q + q / 16];
+    }
     int64_t c[kFItems];
     bool last[kFItems];
     int64_t sc = 0, sl = 0;
@@ -381,9 +402,9 @@ __global__ void __launch_bounds__(kFThreads) fwrite_kernel(const uint64_t *__res
     for (int j = 0; j < kFItems; ++j) {
         const int64_t i = i0 + j;
         const bool in = i < n;
-        sc += in ? rec_chg(rec[i]) : 0;
+        sc += in ? rec_chg(r[j]) : 0;
         c[j] = sc;
-        last[j] = in && last_of_key(rec, i, n);
+        last[j] = in && (i == n - 1 || rec_key(r[j]) != rec_key(r[j + 1]));
         sl += last[j];
     }
     int64_t xc = sc, xl = sl;
@@ -408,7 +429,7 @@ __global__ void __launch_bounds__(kFThreads) fwrite_kernel(const uint64_t *__res
 #pragma unroll
     for (int j = 0; j < kFItems; ++j) {
         if (last[j]) {
-            out_keys[bl] = key_to_f32(rec_key(rec[i0 + j]));
+            out_keys[bl] = key_to_f32(rec_key(r[j]));
             out_chi[bl] = bc + c[j];
             ++bl;
         }
