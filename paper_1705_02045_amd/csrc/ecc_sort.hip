@@ -7,10 +7,11 @@
 //  1. radix_count_kernel: digit counts per (digit, tile), digit-major;
 //  2. exclusive scan of that table: the output position of the first record
 //     of each digit of each tile;
-//  3. radix_scatter_kernel: the tile is ranked stably in LDS (per round of
-//     1024 records, lanes with equal digits find each other with eight
-//     ballots; the waves' counts are prefixed per digit), reordered by digit
-//     in LDS, and written out: records of one digit leave a tile as one
+//  3. radix_scatter_kernel: the tile is ranked stably in LDS (each wave
+//     ranks its 512 consecutive records: lanes with equal digits find each
+//     other with eight ballots and the wave keeps its digit counts in its
+//     own LDS row; then one prefix over the waves per digit), reordered by
+//     digit in LDS, and written out: records of one digit leave a tile as one
 //     contiguous run, so the stores coalesce.
 
 #include "ecc_internal.h"
@@ -41,37 +42,32 @@ __global__ void __launch_bounds__(kSortThreads) radix_count_kernel(const uint64_
     if (tid < 256) counts[(int64_t)tid * tiles + blockIdx.x] = cnt[tid];
 }
 
-__global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const uint64_t *__restrict__ in, int64_t n,
+__global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(8))) radix_scatter_kernel(const uint64_t *__restrict__ in, int64_t n,
                                                                      int shift, int64_t tiles,
                                                                      const uint32_t *__restrict__ offsets,
                                                                      uint64_t *__restrict__ out) {
-    __shared__ uint64_t buf[kTile];
-    __shared__ uint32_t wcnt[2][kSortWaves][256];  // per round (alternating): waves' digit counts
-    __shared__ uint32_t run[256];                  // records of each digit ranked so far
-    __shared__ uint32_t start[256];                // first LDS slot of each digit
+    constexpr int kChunk = kItems * kWave;       // records of one wave, consecutive
+    __shared__ uint64_t buf[kTile];              // the tile reordered by digit
+    __shared__ uint16_t wcnt[kSortWaves][256];   // per wave: digit counts, then the wave's offset per digit
+    __shared__ uint32_t start[256];              // digit totals, then the first slot of each digit
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
     const int64_t t0 = (int64_t)blockIdx.x * kTile;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    if (tid < 256) {
-        run[tid] = 0;
-        for (int w = 0; w < kSortWaves; ++w) wcnt[0][w][tid] = 0;
-    }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wcnt[wave][lane * 4 + q] = 0;  // the wave's own row
 
+    // wave w ranks records t0 + w*kChunk + j*64 + lane (j = 0..kItems-1), in
+    // that order: tile order, so the ranking is stable
     uint64_t r[kItems];
     uint32_t rank[kItems];
+    const int64_t wb = t0 + (int64_t)wave * kChunk;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
-        const int64_t i = t0 + (int64_t)j * kSortThreads + tid;
-        r[j] = i < n ? in[i] : ~0ull;  // past the end: digit 255, never written
+        const int64_t i = wb + (int64_t)j * kWave + lane;
+        r[j] = i < n ? in[i] : ~0ull;  // past the end: digit 255, last in the tile, never written
     }
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
-        // round j: records t0 + j*1024 .. +1023, in thread order.  Table
-        // j & 1 was cleared before this round; the prefix step clears the
-        // other one for the next round (its last readers passed the barrier
-        // at the start of this round's prefix step).
-        const int B = j & 1;
         const uint32_t d = digit_of(r[j], shift);
         uint64_t peers = ~0ull;
 #pragma unroll
@@ -80,28 +76,29 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const uint6
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
         const uint32_t rw = (uint32_t)__builtin_popcountll(peers & lt);
-        if (rw == 0) wcnt[B][wave][d] = (uint32_t)__builtin_popcountll(peers);
-        __syncthreads();
-        if (tid < 256) {  // prefix over the waves, per digit
-            uint32_t acc = run[tid];
-            for (int w = 0; w < kSortWaves; ++w) {
-                const uint32_t c = wcnt[B][w][tid];
-                wcnt[B][w][tid] = acc;
-                acc += c;
-                wcnt[B ^ 1][w][tid] = 0;
-            }
-            run[tid] = acc;
-        }
-        __syncthreads();
-        rank[j] = wcnt[B][wave][d] + rw;
+        // the wave's own count row: LDS operations of one wave take effect in order
+        const uint32_t base = wcnt[wave][d];
+        rank[j] = base + rw;
+        if (rw == 0) wcnt[wave][d] = (uint16_t)(base + (uint32_t)__builtin_popcountll(peers));
     }
-    // first slot of each digit: exclusive scan of run[] (256 values, one wave
-    // of 64 lanes, four digits per lane)
+    __syncthreads();
+    if (tid < 256) {  // per digit: the waves' offsets and the digit's total
+        uint32_t acc = 0;
+        for (int w = 0; w < kSortWaves; ++w) {
+            const uint32_t c = wcnt[w][tid];
+            wcnt[w][tid] = (uint16_t)acc;
+            acc += c;
+        }
+        start[tid] = acc;
+    }
+    __syncthreads();
+    // first slot of each digit: exclusive scan of the totals (one wave, four
+    // digits per lane)
     if (tid < kWave) {
         uint32_t v[4], s = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            v[q] = run[tid * 4 + q];
+            v[q] = start[tid * 4 + q];
             s += v[q];
         }
         uint32_t x = s;
@@ -119,7 +116,10 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(const uint6
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) buf[start[digit_of(r[j], shift)] + rank[j]] = r[j];
+    for (int j = 0; j < kItems; ++j) {
+        const uint32_t d = digit_of(r[j], shift);
+        buf[start[d] + wcnt[wave][d] + rank[j]] = r[j];
+    }
     __syncthreads();
     const int64_t valid = (n - t0) < kTile ? (n - t0) : kTile;
 #pragma unroll
