@@ -197,8 +197,10 @@ IntTiling make_int_tiling(const IntView &v, int64_t planes, int rows, int tiles_
     t.zc = (int)zc;
     // planes of loads in flight: two on walks of 128 planes and more (1024^3:
     // 2 % faster, 512 x 4096^2: 7 %), one on shorter walks, where the longer
-    // prologue costs more than it hides (14 x 8192^2: 20 % slower with two)
-    t.pd = env_int("ECC_INT_PD", zc >= 128 ? 2 : 1);
+    // prologue costs more than it hides (14 x 8192^2: 20 % slower with two);
+    // two with four rows per wave, whose register budget (one workgroup per
+    // CU) holds them without spills (64-plane slabs of 14450^2: 2 % faster)
+    t.pd = env_int("ECC_INT_PD", (zc >= 128 || rows >= 4) ? 2 : 1);
     const int64_t tiles = tiles_xy * ((planes + zc - 1) / zc);
     const int64_t per = tiles > target ? (tiles + target - 1) / target : 1;
     t.per_wg = (int)per;
