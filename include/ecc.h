@@ -279,13 +279,15 @@ int ecc_job_footprint(const ecc_job *job, int64_t *bytes);
 /* Serving replay for measurement: request i (jobs[i], device-resident image;
  * its chi field is ignored) becomes available at arrival_s[i] seconds after
  * the call starts (ascending).  Continuous batching (one_launch_per_image =
- * 0): whenever fewer than two batches are in flight, the requests that have
+ * 0): whenever fewer than three batches are in flight, the requests that have
  * arrived are admitted in order into the next ecc_batch_run while the batch
  * holds at most max_batch requests and the sum of their footprints
  * (ecc_job_footprint) stays within max_batch_bytes (0: no byte limit; a
  * request larger than the limit runs alone).  Otherwise every request is
  * one ecc_compute_async launch as soon as it arrives.  Each request's curve
- * is copied to pinned host memory owned by the call; latency_s[i] receives
+ * is copied to pinned host memory owned by the call, on a second stream of
+ * the call's own that waits for the launch (so one launch's copy overlaps
+ * the next launch's kernels); latency_s[i] receives
  * the time from its arrival until that copy was seen complete; batch_id[i]
  * (optional) the index of the batch (or launch) that carried it.  At the
  * end all curves are copied to chi_host, request i's at chi_host + (sum of

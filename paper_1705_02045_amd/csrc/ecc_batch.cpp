@@ -508,14 +508,33 @@ int ecc_serve_simulate(ecc_batch *b, int32_t n, const ecc_job *jobs, const doubl
     }
     std::vector<ecc_job> js(jobs, jobs + n);
     for (int i = 0; i < n; ++i) js[i].chi = chi_dev + off[i];
+    // The curves go to the host on a second stream (default priority), each
+    // copy ordered after its launch by an event, so the copy of one batch
+    // overlaps the kernels of the next.
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        (void)hipHostFree(chi_pin);
+        (void)hipFree(chi_dev);
+        if (prev != b->device) (void)hipSetDevice(prev);
+        return hip_fail(e, "ecc_serve_simulate: copy stream");
+    }
     struct Flight {
-        hipEvent_t ev;
+        hipEvent_t ev, kev;  // copy done, kernels done
         int first, last;
     };
     std::deque<Flight> flight;
     std::vector<hipEvent_t> pool;
     int rc = ECC_OK;
-    const int max_inflight = one_launch_per_image ? (1 << 30) : 2;
+    const int max_inflight = one_launch_per_image ? (1 << 30) : 3;
+    auto take_event = [&](hipEvent_t *ev) -> hipError_t {
+        if (!pool.empty()) {
+            *ev = pool.back();
+            pool.pop_back();
+            return hipSuccess;
+        }
+        return hipEventCreateWithFlags(ev, hipEventDisableTiming);
+    };
     const auto t0 = std::chrono::steady_clock::now();
     auto now = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
     int next = 0, arrived = 0, done = 0, batches = 0;
@@ -542,23 +561,22 @@ int ecc_serve_simulate(ecc_batch *b, int32_t n, const ecc_job *jobs, const doubl
                 rc = ecc_batch_run(b, k, js.data() + next, nullptr);
             }
             if (rc) break;
-            e = hipMemcpyAsync(chi_pin + off[next], chi_dev + off[next], (size_t)(off[next + k] - off[next]) * 8,
-                               hipMemcpyDeviceToHost, b->stream);
-            hipEvent_t ev = nullptr;
-            if (e == hipSuccess) {
-                if (!pool.empty()) {
-                    ev = pool.back();
-                    pool.pop_back();
-                } else {
-                    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-                }
-            }
-            if (e == hipSuccess) e = hipEventRecord(ev, b->stream);
+            hipEvent_t ev = nullptr, kev = nullptr;
+            e = take_event(&kev);
+            if (e == hipSuccess) e = take_event(&ev);
+            if (e == hipSuccess) e = hipEventRecord(kev, b->stream);
+            if (e == hipSuccess) e = hipStreamWaitEvent(cs, kev, 0);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(chi_pin + off[next], chi_dev + off[next],
+                                   (size_t)(off[next + k] - off[next]) * 8, hipMemcpyDeviceToHost, cs);
+            if (e == hipSuccess) e = hipEventRecord(ev, cs);
             if (e != hipSuccess) {
+                if (kev) pool.push_back(kev);
+                if (ev) pool.push_back(ev);
                 rc = hip_fail(e, "ecc_serve_simulate: launch");
                 break;
             }
-            flight.push_back({ev, next, next + k});
+            flight.push_back({ev, kev, next, next + k});
             next += k;
         }
         while (!flight.empty() && !rc) {
@@ -572,12 +590,18 @@ int ecc_serve_simulate(ecc_batch *b, int32_t n, const ecc_job *jobs, const doubl
             for (int i = flight.front().first; i < flight.front().last; ++i) latency_s[i] = tc - arrival_s[i];
             done += flight.front().last - flight.front().first;
             pool.push_back(flight.front().ev);
+            pool.push_back(flight.front().kev);
             flight.pop_front();
         }
     }
     (void)hipStreamSynchronize(b->stream);
-    for (auto &f : flight) (void)hipEventDestroy(f.ev);
+    (void)hipStreamSynchronize(cs);
+    for (auto &f : flight) {
+        (void)hipEventDestroy(f.ev);
+        (void)hipEventDestroy(f.kev);
+    }
     for (auto ev : pool) (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(cs);
     if (!rc) memcpy(chi_host, chi_pin, (size_t)off[n] * 8);
     (void)hipHostFree(chi_pin);
     (void)hipFree(chi_dev);
