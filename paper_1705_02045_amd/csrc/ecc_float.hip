@@ -60,6 +60,22 @@ constexpr bool earlier(int t) {
 
 __device__ __forceinline__ uint64_t ballot64(bool b) { return __builtin_amdgcn_ballot_w64(b); }
 
+// Visiting order of the 81 directions in 4-D (digit value 1 = zero offset):
+// blocks (digit 3, digit 2) in the order (1,1) (2,1) (1,2) (2,2) (1,0) (2,0)
+// (0,1) (0,2) (0,0), each block's nine (digit 0, digit 1) pairs by
+// increasing non-zeros.  A block depends on itself and on the blocks with one
+// or both outer digits set to 1, all visited before it.
+struct Order4 {
+    int t[81];
+    constexpr Order4() : t{} {
+        const int ba[9] = {1, 2, 1, 2, 1, 2, 0, 0, 0}, bb[9] = {1, 1, 2, 2, 0, 0, 1, 2, 0};
+        const int w0[9] = {1, 0, 2, 1, 1, 0, 2, 0, 2}, w1[9] = {1, 1, 1, 0, 2, 0, 0, 2, 2};
+        for (int k = 0; k < 81; ++k) t[k] = w0[k % 9] + 3 * w1[k % 9] + 9 * bb[k / 9] + 27 * ba[k / 9];
+    }
+};
+constexpr Order4 kOrder4Tab{};
+#define kOrder4 kOrder4Tab.t
+
 // acc += lane bit of m  /  acc -= lane bit of m  (one VALU op each: the mask is
 // the carry-in; the carry-out goes to a scratch scalar pair)
 __device__ __forceinline__ void add_bit(int32_t &acc, uint64_t m) {
@@ -117,35 +133,45 @@ __global__ void __launch_bounds__(T) float_change_kernel(const float *__restrict
     __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)img, (short)0, (int)img_bytes, 0x00020000);
     const float nan = __uint_as_float(0x7FC00000u);
 
-    // slot line j: offsets (digit 0 of j -> axis 1, digit 1 -> axis 0); the
-    // element index of (line j at axis-2 position y, x = 0), or -1 if absent
-    auto line_base = [&](int j, int32_t y) -> int64_t {
+    // slot line j: offsets (digit 0 of j -> axis 1, digit 1 -> axis 0).  Per
+    // workgroup: its element offset at axis-2 position 0 (32-bit: images
+    // hold fewer than 2^30 elements) and whether it exists (bit j of lmask).
+    uint32_t lb0[S];
+    uint32_t lmask = 0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
         const int32_t a1 = c1 + (D >= 3 ? (j % 3) - 1 : 0);
         const int32_t a0 = c0 + (D >= 4 ? (j / 3) % 3 - 1 : 0);
-        if (y < 0 || y >= n2 || a1 < 0 || a1 >= v.n[1] || a0 < 0 || a0 >= v.n[0]) return -1;
-        return (int64_t)a0 * v.stride[0] + (int64_t)a1 * v.stride[1] + (int64_t)y * v.stride[2];
-    };
+        lb0[j] = (uint32_t)a0 * v.stride[0] + (uint32_t)a1 * v.stride[1];
+        if (a1 >= 0 && a1 < v.n[1] && a0 >= 0 && a0 < v.n[0]) lmask |= 1u << j;
+    }
     // the end values x = xs-1 (even lanes) and xs+T (odd lanes) of line
     // (tid >> 1), lanes 0 .. 2S-1
     const int ej = tid >> 1;
     const int32_t xe = (tid & 1) ? xs + T : xs - 1;
+    uint32_t elb0 = 0;
+#pragma unroll
+    for (int j = 0; j < S; ++j)
+        if (j == ej) elb0 = lb0[j];
+    const bool eok = tid < 2 * S && ((lmask >> (ej < S ? ej : 0)) & 1u) && xe >= 0 && xe < nx;
+    // Every load is issued, branch-free: offsets of absent lines or of lanes
+    // past the line's end may point anywhere (wrapped 32-bit arithmetic), but a
+    // raw buffer load is bounds-checked against the image (past the end it
+    // returns 0 and touches nothing), and such values are replaced by NaN.
     auto fetch = [&](int32_t y, float (&val)[S], float &end) {
+        const bool yok = y >= 0 && y < n2;
+        const uint32_t ys = (uint32_t)y * v.stride[2];
 #pragma unroll
         for (int j = 0; j < S; ++j) {
-            const int64_t lb = line_base(j, y);  // uniform
-            val[j] = nan;
-            if (lb >= 0 && act) val[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)(lb + x) * 4u, 0, 0));
+            const float w = __uint_as_float(
+                __builtin_amdgcn_raw_buffer_load_b32(rs, (lb0[j] + ys + (uint32_t)x) * 4u, 0, 0));
+            val[j] = (yok && ((lmask >> j) & 1u) && act) ? w : nan;
         }
-        end = nan;
-        if (tid < 2 * S) {
-            int64_t lb = -1;
-#pragma unroll
-            for (int j = 0; j < S; ++j)
-                if (j == ej) lb = line_base(j, y);
-            if (lb >= 0 && xe >= 0 && xe < nx)
-                end = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)(lb + xe) * 4u, 0, 0));
-        }
+        const float we = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (elb0 + ys + (uint32_t)xe) * 4u, 0, 0));
+        end = (yok && eok) ? we : nan;
     };
+    // element index of this thread's voxel in line (S / 2) at position y
+    auto own_index = [&](int32_t y) -> uint32_t { return lb0[S / 2] + (uint32_t)y * v.stride[2] + (uint32_t)x; };
     auto store = [&](int32_t y, const float (&val)[S], float end) {
         float *slot = ring + (y & 3) * (S * PITCH);
 #pragma unroll
@@ -170,12 +196,10 @@ __global__ void __launch_bounds__(T) float_change_kernel(const float *__restrict
         const uint32_t own_bits = __float_as_uint(f0);
         const uint32_t k0 = f32_key(own_bits);
 
-        // prec[t]: the neighbour in direction t exists and precedes v
-        uint64_t prec[P];
-#pragma unroll
-        for (int t = 0; t < P; ++t) {
-            prec[t] = 0;
-            if (t == C) continue;  // compile-time
+        // "Neighbour t precedes v" is computed where the recursion first needs
+        // it (level by level), so that only the U masks of two adjacent levels
+        // are live in scalar registers, not all 3^D - 1 comparison masks too.
+        auto prec = [&](int t) -> uint64_t {
             const int dx = digit3(t, 0) - 1;
             const int dyi = D >= 2 ? digit3(t, 1) : 1;
             const int j = D >= 3 ? t / 9 : 0;
@@ -183,30 +207,44 @@ __global__ void __launch_bounds__(T) float_change_kernel(const float *__restrict
             // (an absent neighbour) never precedes; a NaN in the image fails the call
             const float fn = col[dyi][j * PITCH + dx];
             const bool p = earlier<D>(t) ? (fn <= f0) : (fn < f0);
-            prec[t] = ballot64(p);
-        }
-        // U_s over increasing numbers of non-zero components, then the signed sum
+            return ballot64(p);
+        };
+        // U_s, each after the U it depends on, then the signed sum
         uint64_t U[P];
         U[C] = 0;  // the zero direction: empty box
         int32_t acc = 0;
+        auto visit = [&](int t) {
+            uint64_t u = prec(t);
 #pragma unroll
-        for (int lvl = 1; lvl <= D; ++lvl) {
+            for (int j = 0; j < D; ++j)
+                if (digit3(t, j) != 1) u |= U[t + (1 - digit3(t, j)) * pow3(j)];
+            U[t] = u;
+            // (-1)^dim, dim = D - (non-zero components): subtract for even dim
+            if (((D - nonzeros<D>(t)) & 1) == 0) add_bit(acc, u);
+            else sub_bit(acc, u);
+        };
+        if constexpr (D == 4) {
+            // blocks of nine by the two outer digits, in an order that lets
+            // each block's masks die early (at most five blocks live)
 #pragma unroll
-            for (int t = 0; t < P; ++t) {
-                if (nonzeros<D>(t) != lvl) continue;
-                uint64_t u = prec[t];
-#pragma unroll
-                for (int j = 0; j < D; ++j)
-                    if (digit3(t, j) != 1) u |= U[t + (1 - digit3(t, j)) * pow3(j)];
-                U[t] = u;
-                // (-1)^dim, dim = D - lvl: subtract for even dim, add for odd
-                if (((D - lvl) & 1) == 0) add_bit(acc, u);
-                else sub_bit(acc, u);
+            for (int k = 0; k < P; ++k) {
+                const int t = kOrder4[k];
+                if (t != C) visit(t);
+                // keep the scheduler from hoisting later blocks' compares
+                // (their masks would all be live at once and spill)
+                if (k % 9 == 8) __builtin_amdgcn_sched_barrier(0);
             }
+        } else {
+            // increasing numbers of non-zero components
+#pragma unroll
+            for (int lvl = 1; lvl <= D; ++lvl)
+#pragma unroll
+                for (int t = 0; t < P; ++t)
+                    if (nonzeros<D>(t) == lvl) visit(t);
         }
         if (ballot64(act && (own_bits & 0x7FFFFFFFu) > 0x7F800000u) != 0 && (threadIdx.x & (kWave - 1)) == 0)
             atomicOr(status, kStatusNaN);
-        if (act) rec[line_base(S / 2, y) + x] = ((uint64_t)k0 << 8) | (uint8_t)(int8_t)(1 - acc);
+        if (act) rec[own_index(y)] = ((uint64_t)k0 << 8) | (uint8_t)(int8_t)(1 - acc);
         if (next) store(y + 2, val, end);
     }
 }
