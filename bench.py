@@ -76,13 +76,14 @@ def cpu_baseline(img, target_s: float):
     rate = probe * n1 * n2 / max(dt, 1e-6)
     planes = int(min(n0, max(probe, target_s * rate / (n1 * n2))))
     # when the whole volume takes well under the budget, time it more than once
-    reps = 1
-    if planes == n0:
-        reps = int(max(1, min(4, round(target_s * rate / (n0 * n1 * n2)))))
+    reps = 0
     t = time.perf_counter()
-    for _ in range(reps):
+    while True:
         oracle.curve(img[:planes], m=16384, nthreads=threads)
-    dt = time.perf_counter() - t
+        reps += 1
+        dt = time.perf_counter() - t
+        if planes < n0 or reps >= 4 or dt * (reps + 1) / reps > 1.3 * target_s:
+            break
     vox = planes * n1 * n2 * reps
     what = f"planes 0..{planes - 1} of the {n0}x{n1}x{n2} volume" + (f", {reps} times" if reps > 1 else "")
     return {"value": round(vox / dt / 1e9, 6), "unit": "GVoxel/s", "cores": threads, "kind": "oracle",
