@@ -73,8 +73,7 @@ struct Order4 {
         for (int k = 0; k < 81; ++k) t[k] = w0[k % 9] + 3 * w1[k % 9] + 9 * bb[k / 9] + 27 * ba[k / 9];
     }
 };
-constexpr Order4 kOrder4Tab{};
-#define kOrder4 kOrder4Tab.t
+constexpr Order4 kOrder4{};
 
 // acc += lane bit of m  /  acc -= lane bit of m  (one VALU op each: the mask is
 // the carry-in; the carry-out goes to a scratch scalar pair)
@@ -228,7 +227,7 @@ __global__ void __launch_bounds__(T) float_change_kernel(const float *__restrict
             // each block's masks die early (at most five blocks live)
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                const int t = kOrder4[k];
+                const int t = kOrder4.t[k];
                 if (t != C) visit(t);
                 // keep the scheduler from hoisting later blocks' compares
                 // (their masks would all be live at once and spill)
