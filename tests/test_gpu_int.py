@@ -206,3 +206,19 @@ def test_row_pair_layout(ecc, shape, tiling, monkeypatch):
     img16 = gen.iid(shape, 16, seed=22)
     got16 = ecc.compute(torch.from_numpy(img16.view(np.int16)).cuda(), dtype="u16").cpu().numpy()
     assert (got16 == oracle.curve(img16, m=65536)).all()
+
+
+@pytest.mark.parametrize("shape", [(5, 34, 258), (4, 20, 130)], ids=str)
+def test_row_pairs_need_aligned_buffers(ecc, shape):
+    """Row pairs need 4-byte aligned rows: an image that starts 2 bytes into
+    its allocation (even rows, so every row start is 2 mod 4) takes the
+    element loads instead, with the same curve; so does the aligned copy."""
+    img = gen.cfg_u14_value_noise(shape, seed=31)
+    flat = torch.zeros(img.size + 2, dtype=torch.int16, device="cuda")
+    flat[1:1 + img.size] = torch.from_numpy(img.view(np.int16).ravel()).cuda()
+    view = flat[1:1 + img.size].view(shape)
+    assert view.data_ptr() % 4 == 2
+    print(f"\n[gpu] row pairs, base 2 mod 4 {shape}", flush=True)
+    ref = oracle.curve(img, m=16384)
+    assert (ecc.compute(view, "u14").cpu().numpy() == ref).all()
+    assert (ecc.compute(view.clone(), "u14").cpu().numpy() == ref).all()
