@@ -244,7 +244,9 @@ static ecc_tiling rule_tiling(const IntView &v, int dtype, int64_t planes) {
     const int64_t launch_bytes = planes * (int64_t)v.n1 * v.n2 * (dtype == ECC_U8 ? 1 : 2);
     ecc_tiling c{};
     c.rows = launch_bytes >= ((int64_t)4 << 30) ? 4 : 2;
-    c.waves_x = 16;
+    // four rows: workgroups two waves tall (64-plane slabs of 14450^2: 2 %
+    // faster than one row of 16 waves)
+    c.waves_x = c.rows == 4 ? 8 : 16;
     if (launch_bytes < ((int64_t)256 << 20)) c.tiles_per_cu = 4;
     else if (c.rows == 4) c.tiles_per_cu = 16;
     else c.tiles_per_cu = make_int_tiling(v, planes, c.rows, 4, c.waves_x).zc >= 256 ? 4 : 8;
