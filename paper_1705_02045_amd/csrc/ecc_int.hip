@@ -716,12 +716,13 @@ static int launch_rows(const KParams &p, const IntTiling &tl, hipStream_t stream
 }
 
 // Transformed values (largest-value convention, 16-bit windows): walking
-// mode 0, one plane of look-ahead.
+// mode 0, the tiling's planes of look-ahead.
 template <typename T, int M, int NIN, int XF>
 static int launch_transformed(const KParams &p, const IntTiling &tl, hipStream_t stream) {
+    const bool pd2 = tl.pd == 2;
     switch (tl.rows) {
-    case 2: return launch_one<T, M, NIN, 2, 0, 1, XF>(p, tl, stream);
-    case 4: return launch_one<T, M, NIN, 4, 0, 1, XF>(p, tl, stream);
+    case 2: return pd2 ? launch_one<T, M, NIN, 2, 0, 2, XF>(p, tl, stream) : launch_one<T, M, NIN, 2, 0, 1, XF>(p, tl, stream);
+    case 4: return pd2 ? launch_one<T, M, NIN, 4, 0, 2, XF>(p, tl, stream) : launch_one<T, M, NIN, 4, 0, 1, XF>(p, tl, stream);
     default: break;
     }
     set_error("integer kernel: %d rows per wave not built", tl.rows);
