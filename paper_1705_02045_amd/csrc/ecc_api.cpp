@@ -1010,16 +1010,23 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
     int64_t face_max = 1;  // the largest face of codimension >= 1
     for (int k = 0; k < d; ++k)
         if (total / n[k] > face_max) face_max = total / n[k];
-    // dual_buf: [nf][m] per-face changes vectors, [m] their signed sum, then
-    // one gathered face
+    // dual_buf: [nf][m] per-face changes vectors, [m] their signed sum, the
+    // table of faces of at most one dimension, then one gathered face
     const size_t curves_bytes = (size_t)(nf + 1) * m * sizeof(int64_t);
-    const size_t face_off = (curves_bytes + 255) & ~(size_t)255;
+    const size_t low_off = (curves_bytes + 255) & ~(size_t)255;
+    const size_t face_off = low_off + ((nf * sizeof(LowFace) + 255) & ~(size_t)255);
     rc = ensure_bytes(&ws->dual_buf, &ws->dual_buf_bytes, face_off + (size_t)face_max * eb);
     if (rc) return rc;
     int64_t *curves = (int64_t *)ws->dual_buf;
     int64_t *result = curves + (size_t)nf * m;
+    LowFace *low_dev = (LowFace *)((uint8_t *)ws->dual_buf + low_off);
     uint8_t *face = (uint8_t *)ws->dual_buf + face_off;
-    uint64_t neg = 0;
+    const int gsign = (d & 1) ? -1 : 1;
+    uint64_t neg = 0, skip = 0;
+    // Box edges and corners (faces of at most one dimension, below the full
+    // box) have a closed-form changes vector; they are added by one launch
+    // after the signed sum instead of a gather, a kernel and a merge each.
+    std::vector<LowFace> low;
     for (int f = 0; f < nf; ++f) {
         int code[3] = {0, 0, 0};
         for (int k = 0, r = f; k < d; ++k, r /= 3) code[k] = r % 3;
@@ -1034,6 +1041,16 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
                 base += (code[k] == 1 ? 0 : n[k] - 1) * st[k];
                 ++codim;
             }
+        }
+        if (codim > 0 && nfree <= 1) {
+            LowFace L{};
+            L.base = base;
+            L.stride = nfree ? fst[0] : 0;
+            L.len = nfree ? fs[0] : 0;
+            L.sign = (codim & 1) ? -gsign : gsign;
+            low.push_back(L);
+            skip |= 1ull << f;
+            continue;
         }
         const void *src = img_dev;
         if (codim > 0) {
@@ -1061,16 +1078,31 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
         if (rc) return rc;
         if (codim & 1) neg |= 1ull << f;
     }
-    rc = launch_signed_sum(curves, nf, neg, (d & 1) ? -1 : 1, (int)m, result, s);
+    rc = launch_signed_sum(curves, nf, neg, skip, gsign, (int)m, result, s);
     if (rc) return rc;
+    if (!low.empty()) {
+        // the host table must outlive the copy: every return below this point
+        // synchronizes the stream first
+        ECC_HIP(hipMemcpyAsync(low_dev, low.data(), low.size() * sizeof(LowFace), hipMemcpyHostToDevice, s));
+        rc = launch_low_faces(img_dev, (int)eb, low_dev, (int)low.size(), (int)m, result, s);
+        if (rc) {
+            (void)hipStreamSynchronize(s);
+            return rc;
+        }
+    }
     // scan into slot 0 (its changes are summed already); the status of every
     // face launch (all read the image's values) is reported and cleared here
     int64_t *chi_dev = curves;
     rc = launch_merge(nullptr, 0, (int)m, nullptr, result, true, true, chi_dev, ws->status, ws->status + 2, s);
-    if (rc) return rc;
+    if (rc) {
+        (void)hipStreamSynchronize(s);
+        return rc;
+    }
     uint32_t stv = 0;
-    ECC_HIP(hipMemcpyAsync(&stv, ws->status + 2, 4, hipMemcpyDeviceToHost, s));
-    ECC_HIP(hipStreamSynchronize(s));
+    hipError_t ce = hipMemcpyAsync(&stv, ws->status + 2, 4, hipMemcpyDeviceToHost, s);
+    const hipError_t se = hipStreamSynchronize(s);
+    if (ce != hipSuccess) return hip_fail(ce, "hipMemcpyAsync(status)");
+    if (se != hipSuccess) return hip_fail(se, "hipStreamSynchronize");
     if (stv & kStatusRange) {
         set_error("a 14-bit image holds a value >= 16384");
         return ECC_E_RANGE;

@@ -127,8 +127,17 @@ int launch_gather(const void *src, int elem, int64_t base, int64_t s0, int64_t s
 // Minimum and maximum of n uint16 values into out[0], out[1].
 int launch_minmax_u16(const uint16_t *img, int64_t n, uint32_t *out, hipStream_t stream);
 // out[t] = sign * sum_f (-1)^((neg_mask >> f) & 1) * curves[f * m + t], t < m.
-int launch_signed_sum(const int64_t *curves, int nf, uint64_t neg_mask, int sign, int m, int64_t *out,
-                      hipStream_t stream);
+int launch_signed_sum(const int64_t *curves, int nf, uint64_t neg_mask, uint64_t skip_mask, int sign, int m,
+                      int64_t *out, hipStream_t stream);
+// A face of the box of at most one dimension: elements base + i * stride,
+// i < len (len = 0: a corner, the single element at base), added with sign.
+struct LowFace {
+    int64_t base, stride, len;
+    int64_t sign;
+};
+// Largest-value changes vectors of such faces, added into out (ecc_scan.hip).
+int launch_low_faces(const void *img, int elem, const LowFace *faces_dev, int nfaces, int m, int64_t *out,
+                     hipStream_t stream);
 
 bool normalize_int_view(const ecc_dims *dims, IntView *v, int *err_ndim_dropped);
 int check_dims(const ecc_dims *dims, int64_t *total);

@@ -299,21 +299,64 @@ int launch_gather(const void *src, int elem, int64_t base, int64_t s0, int64_t s
 }
 
 __global__ void __launch_bounds__(256) signed_sum_kernel(const int64_t *__restrict__ curves, int nf, uint64_t neg_mask,
-                                                         int sign, int m, int64_t *__restrict__ out) {
+                                                         uint64_t skip_mask, int sign, int m,
+                                                         int64_t *__restrict__ out) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m) return;
     int64_t acc = 0;
     for (int f = 0; f < nf; ++f) {
+        if ((skip_mask >> f) & 1) continue;
         const int64_t v = curves[(size_t)f * m + t];
         acc += ((neg_mask >> f) & 1) ? -v : v;
     }
     out[t] = sign < 0 ? -acc : acc;
 }
 
-int launch_signed_sum(const int64_t *curves, int nf, uint64_t neg_mask, int sign, int m, int64_t *out,
-                      hipStream_t stream) {
-    hipLaunchKernelGGL(signed_sum_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, curves, nf, neg_mask, sign, m,
-                       out);
+int launch_signed_sum(const int64_t *curves, int nf, uint64_t neg_mask, uint64_t skip_mask, int sign, int m,
+                      int64_t *out, hipStream_t stream) {
+    hipLaunchKernelGGL(signed_sum_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, curves, nf, neg_mask, skip_mask,
+                       sign, m, out);
+    ECC_HIP(hipGetLastError());
+    return ECC_OK;
+}
+
+// Faces of at most one dimension (box edges and corners), largest-value
+// convention, added with their signs straight into a changes vector.  A
+// line of n voxels is the 1-D complex of n intervals (value: the voxel's)
+// and n + 1 vertices (value: the larger of the voxels they touch); its
+// changes vector adds +1 at each vertex's value and -1 at each interval's.
+// A corner is one vertex.  Values >= m are skipped (the volume's own launch
+// reports them as range errors).  One workgroup per face.
+template <typename T>
+__global__ void __launch_bounds__(256) low_faces_kernel(const T *__restrict__ img, const LowFace *__restrict__ faces,
+                                                        int m, int64_t *__restrict__ out) {
+    const LowFace F = faces[blockIdx.x];
+    auto val = [&](int64_t i) -> uint32_t { return (uint32_t)img[F.base + i * F.stride]; };
+    auto add = [&](uint32_t v, int64_t c) {
+        if (v < (uint32_t)m) atomicAdd((unsigned long long *)&out[v], (unsigned long long)c);
+    };
+    const int64_t s = F.sign;
+    for (int64_t i = threadIdx.x; i <= F.len; i += blockDim.x) {
+        if (F.len == 0) {  // a corner: one vertex
+            if (i == 0) add(val(0), s);
+            continue;
+        }
+        // vertex i: between voxels i-1 and i (one voxel at either end)
+        const uint32_t a = i > 0 ? val(i - 1) : 0u, b = i < F.len ? val(i) : 0u;
+        add(i == 0 ? b : i == F.len ? a : (a > b ? a : b), s);
+        if (i < F.len) add(b, -s);  // interval i
+    }
+}
+
+int launch_low_faces(const void *img, int elem, const LowFace *faces_dev, int nfaces, int m, int64_t *out,
+                     hipStream_t stream) {
+    if (nfaces <= 0) return ECC_OK;
+    if (elem == 1)
+        hipLaunchKernelGGL(low_faces_kernel<uint8_t>, dim3(nfaces), dim3(256), 0, stream, (const uint8_t *)img,
+                           faces_dev, m, out);
+    else
+        hipLaunchKernelGGL(low_faces_kernel<uint16_t>, dim3(nfaces), dim3(256), 0, stream, (const uint16_t *)img,
+                           faces_dev, m, out);
     ECC_HIP(hipGetLastError());
     return ECC_OK;
 }
