@@ -372,9 +372,16 @@ static int enqueue_u16(const void *image_dev, const IntView &v, int64_t *chi_dev
 
 // Changes vector only (no scan) of a device image into vcec_out; a range
 // error stays set in ws->status for a later scan to report.
+// plane_stride: elements between consecutive planes of a view with one
+// in-plane axis (0: the planes are contiguous rows); the kernel reads only
+// the first n2 elements of each plane.
 static int enqueue_int_changes(const void *image_dev, const IntView &v, int dtype, int64_t *vcec_out,
-                               hipStream_t stream, Workspace *ws, bool max_entry) {
+                               hipStream_t stream, Workspace *ws, bool max_entry, int64_t plane_stride = 0) {
     const int m = (int)threshold_count(dtype);
+    if (plane_stride != 0 && (v.nin != 1 || plane_stride < v.n2 || plane_stride * (int64_t)elem_bytes(dtype) > INT32_MAX)) {
+        set_error("internal error: plane stride %lld for a view of %d in-plane axes", (long long)plane_stride, v.nin);
+        return ECC_E_ARG;
+    }
     IntTiling tl = choose_int_tiling(v, dtype, v.n0);
     int rc = ensure_bytes((void **)&ws->partial, &ws->partial_bytes, (size_t)tl.grid * m * sizeof(int32_t));
     if (rc) return rc;
@@ -384,7 +391,7 @@ static int enqueue_int_changes(const void *image_dev, const IntView &v, int dtyp
     IntJob job{};
     job.src.base = (const uint8_t *)image_dev;
     job.src.lo_base = job.src.base;
-    job.src.plane_bytes = (int64_t)v.n1 * v.n2 * (int64_t)elem_bytes(dtype);
+    job.src.plane_bytes = (plane_stride ? plane_stride : (int64_t)v.n1 * v.n2) * (int64_t)elem_bytes(dtype);
     job.view = v;
     job.e0 = 0;
     job.e1 = (int32_t)v.n0;
@@ -1053,7 +1060,13 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
             continue;
         }
         const void *src = img_dev;
-        if (codim > 0) {
+        int64_t pstride = 0;
+        if (codim > 0 && nfree == 2 && fst[1] == 1 && fst[0] * (int64_t)eb <= INT32_MAX) {
+            // a 2-D face whose rows are contiguous in the image: walked in
+            // place, one row per plane, fst[0] elements apart
+            src = (const uint8_t *)img_dev + base * (int64_t)eb;
+            pstride = fst[0];
+        } else if (codim > 0) {
             // free axes as the trailing axes of an n0 x n1 x n2 gather
             int64_t g[3] = {1, 1, 1}, gs[3] = {0, 0, 0};
             for (int i = 0; i < nfree; ++i) {
@@ -1074,7 +1087,7 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
             set_error("ecc_compute_dual: face shape not supported");
             return ECC_E_UNSUPPORTED;
         }
-        rc = enqueue_int_changes(src, v, dtype, curves + (size_t)f * m, s, ws, true);
+        rc = enqueue_int_changes(src, v, dtype, curves + (size_t)f * m, s, ws, true, pstride);
         if (rc) return rc;
         if (codim & 1) neg |= 1ull << f;
     }
