@@ -89,8 +89,20 @@ int get_workspace(void *stream, Workspace **out) {
             return hip_fail(e, "hipMalloc(status)");
         }
         w->status = (uint32_t *)p;
+        void *hp = nullptr, *hd = nullptr;
+        e = hipHostMalloc(&hp, 64, hipHostMallocMapped | hipHostMallocCoherent);
+        if (e == hipSuccess) e = hipHostGetDevicePointer(&hd, hp, 0);
+        if (e != hipSuccess) {
+            if (hp) (void)hipHostFree(hp);
+            (void)hipFree(p);
+            delete w;
+            return hip_fail(e, "hipHostMalloc(status word)");
+        }
+        w->host_status = (volatile uint32_t *)hp;
+        w->host_status_dev = (uint32_t *)hd;
         int rc = launch_zero(p, kStatusBytes, (hipStream_t)stream);
         if (rc) {
+            (void)hipHostFree(hp);
             (void)hipFree(p);
             delete w;
             return rc;
@@ -526,14 +538,22 @@ static int compute_int(const void *image, const ecc_dims *dims, int64_t total, e
         uint32_t range[2] = {0, 0};
         ECC_HIP(hipMemcpyAsync(range, mm, sizeof range, hipMemcpyDeviceToHost, s));
         ECC_HIP(hipStreamSynchronize(s));
-        rc = enqueue_u16(img_dev, v, chi_target, ws->status + 2, s, ws, range[0], range[1]);
+        *ws->host_status = 0xFFFFFFFFu;  // overwritten by the scan
+        rc = enqueue_u16(img_dev, v, chi_target, ws->host_status_dev, s, ws, range[0], range[1]);
     } else {
-        rc = enqueue_int(img_dev, v, dtype, chi_target, ws->status + 2, s, ws, max_entry);
+        *ws->host_status = 0xFFFFFFFFu;
+        rc = enqueue_int(img_dev, v, dtype, chi_target, ws->host_status_dev, s, ws, max_entry);
     }
-    if (rc) return rc;
-    uint32_t st = 0;
-    ECC_HIP(hipMemcpyAsync(&st, ws->status + 2, 4, hipMemcpyDeviceToHost, s));
+    if (rc) {
+        (void)hipStreamSynchronize(s);  // the scan may still write the host word
+        return rc;
+    }
     ECC_HIP(hipStreamSynchronize(s));
+    const uint32_t st = *ws->host_status;
+    if (st == 0xFFFFFFFFu) {
+        set_error("internal error: the scan did not report a status");
+        return ECC_E_HIP;
+    }
     if (st & kStatusRange) {
         set_error("a 14-bit image holds a value >= 16384");
         return ECC_E_RANGE;
@@ -1106,16 +1126,18 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
     // scan into slot 0 (its changes are summed already); the status of every
     // face launch (all read the image's values) is reported and cleared here
     int64_t *chi_dev = curves;
-    rc = launch_merge(nullptr, 0, (int)m, nullptr, result, true, true, chi_dev, ws->status, ws->status + 2, s);
+    *ws->host_status = 0xFFFFFFFFu;  // overwritten by the scan
+    rc = launch_merge(nullptr, 0, (int)m, nullptr, result, true, true, chi_dev, ws->status, ws->host_status_dev, s);
     if (rc) {
         (void)hipStreamSynchronize(s);
         return rc;
     }
-    uint32_t stv = 0;
-    hipError_t ce = hipMemcpyAsync(&stv, ws->status + 2, 4, hipMemcpyDeviceToHost, s);
-    const hipError_t se = hipStreamSynchronize(s);
-    if (ce != hipSuccess) return hip_fail(ce, "hipMemcpyAsync(status)");
-    if (se != hipSuccess) return hip_fail(se, "hipStreamSynchronize");
+    ECC_HIP(hipStreamSynchronize(s));
+    const uint32_t stv = *ws->host_status;
+    if (stv == 0xFFFFFFFFu) {
+        set_error("internal error: the scan did not report a status");
+        return ECC_E_HIP;
+    }
     if (stv & kStatusRange) {
         set_error("a 14-bit image holds a value >= 16384");
         return ECC_E_RANGE;

@@ -84,6 +84,11 @@ struct Workspace {
     int64_t *vcec = nullptr;     // [m] changes vector
     size_t vcec_bytes = 0;
     uint32_t *status = nullptr;  // device status block (kStatusBytes)
+    // One pinned, coherent host word that the scan writes the status into
+    // (read after the stream is synchronized, without a device-to-host copy),
+    // and its device-side address.
+    volatile uint32_t *host_status = nullptr;
+    uint32_t *host_status_dev = nullptr;
     int64_t *stage = nullptr;    // merge stage rows
     size_t stage_bytes = 0;
     int64_t *chi_tmp = nullptr;  // [m] curve staging for host outputs
