@@ -409,6 +409,100 @@ int launch_minmax_u16(const uint16_t *img, int64_t n, uint32_t *out, hipStream_t
     return ECC_OK;
 }
 
+// Curves of at most 1024 thresholds from at most kSmallMergeRows rows: the
+// three merge kernels above in one workgroup (256 threads x 4 columns), for
+// the latency of small images.  The column sums are placed through LDS
+// (with `reverse`, column c lands at m-1-c, in another thread's columns);
+// then vcec, the scan into chi (only with a clear status word), and the
+// status copy and clear, as in the three-kernel form.
+constexpr int kSmallMergeRows = 64;
+__global__ void __launch_bounds__(256) merge_scan_small_kernel(const int32_t *__restrict__ partial, int rows, int m,
+                                                               int64_t *__restrict__ vcec, int accumulate, int reverse,
+                                                               int64_t *__restrict__ chi, uint32_t *status,
+                                                               uint32_t *status_out) {
+    __shared__ int64_t col[1024];
+    __shared__ int64_t wsum[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c0 = tid * 4;
+    const bool own = c0 < m;
+    const uint32_t stv = *status;  // cleared below, after a barrier
+    if (rows > 0) {
+        if (own) {
+            int64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+            const int4 *p = reinterpret_cast<const int4 *>(partial) + c0 / 4;
+            const size_t stride4 = (size_t)m / 4;
+            int r = 0;
+            for (; r + 8 <= rows; r += 8) {
+                int4 a[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) a[j] = p[(size_t)(r + j) * stride4];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    s0 += a[j].x;
+                    s1 += a[j].y;
+                    s2 += a[j].z;
+                    s3 += a[j].w;
+                }
+            }
+            for (; r < rows; ++r) {
+                const int4 a = p[(size_t)r * stride4];
+                s0 += a.x;
+                s1 += a.y;
+                s2 += a.z;
+                s3 += a.w;
+            }
+            if (reverse) {
+                col[m - 1 - c0] = s0;
+                col[m - 2 - c0] = s1;
+                col[m - 3 - c0] = s2;
+                col[m - 4 - c0] = s3;
+            } else {
+                col[c0] = s0;
+                col[c0 + 1] = s1;
+                col[c0 + 2] = s2;
+                col[c0 + 3] = s3;
+            }
+        }
+        __syncthreads();
+    }
+    int64_t v[4] = {0, 0, 0, 0};
+    if (own) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int64_t x = (rows == 0 || accumulate) ? vcec[c0 + j] : 0;
+            if (rows > 0) x += col[c0 + j];
+            v[j] = x;
+        }
+        if (rows > 0) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) vcec[c0 + j] = v[j];
+        }
+    }
+    // inclusive scan: within the thread, across the wave, across the 4 waves
+    v[1] += v[0];
+    v[2] += v[1];
+    v[3] += v[2];
+    int64_t x = v[3];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t u = __shfl_up(x, off, 64);
+        if (lane >= off) x += u;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    int64_t base = x - v[3];
+    for (int w = 0; w < wave; ++w) base += wsum[w];
+    if (own && stv == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) chi[c0 + j] = base + v[j];
+    }
+    if (tid == 0) {
+        status[1] = stv;
+        if (status_out) *status_out = stv;
+        status[0] = 0u;
+    }
+}
+
 int merge_stage_rows(int rows) {
     int by = 1;
     while (by < 32 && by * 8 <= rows) by *= 2;
@@ -423,6 +517,12 @@ int launch_merge(const int32_t *partial, int rows, int m, int64_t *stage, int64_
         return ECC_E_ARG;
     }
     const int groups = (m + 1023) / 1024;
+    if (do_scan && groups == 1 && rows <= kSmallMergeRows) {
+        hipLaunchKernelGGL(merge_scan_small_kernel, dim3(1), dim3(256), 0, stream, partial, rows, m, vcec,
+                           accumulate ? 1 : 0, reverse ? 1 : 0, chi, status, status_out);
+        ECC_HIP(hipGetLastError());
+        return ECC_OK;
+    }
     int by = 0;
     if (rows > 0) {
         by = merge_stage_rows(rows);
