@@ -112,7 +112,20 @@ __global__ void __launch_bounds__(256) fold_scan_kernel(const int64_t *__restric
 #pragma unroll
         for (int j = 0; j < 4; ++j) v[j] = (stage == nullptr || accumulate) ? vcec[c0 + j] : 0;
         if (stage != nullptr) {
-            for (int y = 0; y < by; ++y) {
+            // eight rows of loads in flight (by is a power of two, 2..32)
+            int y = 0;
+            for (; y + 8 <= by; y += 8) {
+                int64_t a[8][4];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) a[u][j] = stage[(size_t)(y + u) * m + c0 + j];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) v[j] += a[u][j];
+            }
+            for (; y < by; ++y) {
                 const int64_t *st = stage + (size_t)y * m + c0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) v[j] += st[j];
