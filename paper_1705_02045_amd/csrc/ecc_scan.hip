@@ -385,8 +385,7 @@ __global__ void __launch_bounds__(256) minmax_u16_kernel(const uint16_t *__restr
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t n8 = vec ? n / 8 : 0;  // 16-byte groups when the image is 16-byte aligned
     const uint4 *v8 = reinterpret_cast<const uint4 *>(img);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8; i += stride) {
-        const uint4 q = v8[i];
+    auto fold = [&](const uint4 q) {
         const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -394,7 +393,22 @@ __global__ void __launch_bounds__(256) minmax_u16_kernel(const uint16_t *__restr
             lo = min(lo, min(a, b));
             hi = max(hi, max(a, b));
         }
+    };
+    // each workgroup streams one contiguous chunk, four independent 16-byte
+    // loads in flight per thread
+    const int64_t chunk = (n8 + gridDim.x - 1) / gridDim.x;
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = beg + chunk < n8 ? beg + chunk : n8;
+    const int64_t bd = blockDim.x;
+    int64_t i = beg + threadIdx.x;
+    for (; i + 3 * bd < end; i += 4 * bd) {
+        uint4 q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = v8[i + u * bd];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) fold(q[u]);
     }
+    for (; i < end; i += bd) fold(v8[i]);
     for (int64_t i = n8 * 8 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         lo = min(lo, (uint32_t)img[i]);
         hi = max(hi, (uint32_t)img[i]);
@@ -414,8 +428,9 @@ int launch_minmax_u16(const uint16_t *img, int64_t n, uint32_t *out, hipStream_t
     hipLaunchKernelGGL(minmax_init_kernel, dim3(1), dim3(1), 0, stream, out);
     ECC_HIP(hipGetLastError());
     int64_t blocks = (n / 8 + 255) / 256;
+    const int64_t cap = 8 * (int64_t)device_cu_count();  // eight workgroups of 4 waves per CU
     if (blocks < 1) blocks = 1;
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > cap) blocks = cap;
     const int vec = ((uintptr_t)img % 16) == 0;
     hipLaunchKernelGGL(minmax_u16_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, img, n, vec, out);
     ECC_HIP(hipGetLastError());
