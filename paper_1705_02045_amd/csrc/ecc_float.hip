@@ -403,19 +403,26 @@ __global__ void __launch_bounds__(1024) fscan_tiles_kernel(int64_t *a, int64_t *
     if (tid == 0) *total_last = carry_b;
 }
 
-__global__ void __launch_bounds__(kFThreads) fwrite_kernel(const uint64_t *__restrict__ rec, int64_t n,
+// The curve write walks the same tiles with twice the threads (8 records
+// each): its LDS tile allows four workgroups per CU, so 512 threads keep 32
+// waves per CU in flight instead of 16.
+constexpr int kWThreads = 512;
+constexpr int kWItems = kFTile / kWThreads;
+constexpr int kWWaves = kWThreads / 64;
+static_assert(kWItems * kWThreads == kFTile && kWThreads % 64 == 0, "curve write: whole tiles of whole waves");
+__global__ void __launch_bounds__(kWThreads) fwrite_kernel(const uint64_t *__restrict__ rec, int64_t n,
                                                           const int64_t *__restrict__ tile_chg,
                                                           const int64_t *__restrict__ tile_last,
                                                           float *__restrict__ out_keys, int64_t *__restrict__ out_chi) {
-    __shared__ int64_t wc[4], wl[4];
+    __shared__ int64_t wc[kWWaves], wl[kWWaves];
     // the tile and the record after it, loaded coalesced; slot i at i + i / 16
-    // (threads then read 16 consecutive records without bank conflicts)
+    // (fewer bank conflicts when threads read runs of consecutive records)
     __shared__ uint64_t tile[kFTile + kFTile / 16 + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t t0 = (int64_t)blockIdx.x * kFTile;
 #pragma unroll
-    for (int j = 0; j < kFItems; ++j) {
-        const int q = j * kFThreads + tid;
+    for (int j = 0; j < kWItems; ++j) {
+        const int q = j * kWThreads + tid;
         const int64_t i = t0 + q;
         tile[q + q / 16] = i < n ? rec[i] : 0ull;
     }
@@ -424,19 +431,19 @@ __global__ void __launch_bounds__(kFThreads) fwrite_kernel(const uint64_t *__res
         tile[kFTile + kFTile / 16] = i < n ? rec[i] : 0ull;
     }
     __syncthreads();
-    // each thread takes kFItems consecutive records of the tile
-    const int64_t i0 = t0 + (int64_t)tid * kFItems;
-    uint64_t r[kFItems + 1];
+    // each thread takes kWItems consecutive records of the tile
+    const int64_t i0 = t0 + (int64_t)tid * kWItems;
+    uint64_t r[kWItems + 1];
 #pragma unroll
-    for (int j = 0; j <= kFItems; ++j) {
-        const int q = tid * kFItems + j;
+    for (int j = 0; j <= kWItems; ++j) {
+        const int q = tid * kWItems + j;
         r[j] = tile[q + q / 16];
     }
-    int64_t c[kFItems];
-    bool last[kFItems];
+    int64_t c[kWItems];
+    bool last[kWItems];
     int64_t sc = 0, sl = 0;
 #pragma unroll
-    for (int j = 0; j < kFItems; ++j) {
+    for (int j = 0; j < kWItems; ++j) {
         const int64_t i = i0 + j;
         const bool in = i < n;
         sc += in ? rec_chg(r[j]) : 0;
@@ -464,7 +471,7 @@ __global__ void __launch_bounds__(kFThreads) fwrite_kernel(const uint64_t *__res
         bl += wl[w];
     }
 #pragma unroll
-    for (int j = 0; j < kFItems; ++j) {
+    for (int j = 0; j < kWItems; ++j) {
         if (last[j]) {
             out_keys[bl] = key_to_f32(rec_key(r[j]));
             out_chi[bl] = bc + c[j];
@@ -485,7 +492,7 @@ int launch_float_curve(const uint64_t *rec, int64_t n, int64_t *tile_chg, int64_
     ECC_HIP(hipGetLastError());
     hipLaunchKernelGGL(fscan_tiles_kernel, dim3(1), dim3(1024), 0, stream, tile_chg, tile_last, nt, total_last);
     ECC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(fwrite_kernel, dim3((unsigned)nt), dim3(kFThreads), 0, stream, rec, n, tile_chg,
+    hipLaunchKernelGGL(fwrite_kernel, dim3((unsigned)nt), dim3(kWThreads), 0, stream, rec, n, tile_chg,
                        tile_last, out_keys, out_chi);
     ECC_HIP(hipGetLastError());
     return ECC_OK;
