@@ -209,7 +209,20 @@ __global__ void __launch_bounds__(256) batch_colsum_kernel(const uint8_t *__rest
         const int4 *p = reinterpret_cast<const int4 *>(J.partial);
         const size_t stride4 = (size_t)J.m / 4;
         int64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        for (int r = 0; r < J.rows; ++r) {
+        int r = 0;
+        for (; r + 8 <= J.rows; r += 8) {  // eight rows of loads in flight
+            int4 a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = p[(size_t)(r + u) * stride4 + c0 / 4];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                s0 += a[u].x;
+                s1 += a[u].y;
+                s2 += a[u].z;
+                s3 += a[u].w;
+            }
+        }
+        for (; r < J.rows; ++r) {
             const int4 a = p[(size_t)r * stride4 + c0 / 4];
             s0 += a.x;
             s1 += a.y;
