@@ -219,13 +219,28 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(uint32_t *__re
     __shared__ uint32_t ws[kScanThreads / kWave];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t i0 = (int64_t)blockIdx.x * kScanTile + (int64_t)tid * kScanItems;
+    // a thread's run of kScanItems counts is 64 contiguous bytes: 16-byte
+    // loads and stores where the whole run is in range and aligned
+    static_assert(kScanItems % 4 == 0, "runs of whole 16-byte groups");
+    const bool vec = ((reinterpret_cast<uintptr_t>(a) & 15u) == 0) && i0 + kScanItems <= n;
     uint32_t v[kScanItems];
     uint32_t s = 0;
+    if (vec) {
+        const uint4 *a4 = reinterpret_cast<const uint4 *>(a + i0);
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        v[j] = (i0 + j < n) ? a[i0 + j] : 0u;
-        s += v[j];
+        for (int q = 0; q < kScanItems / 4; ++q) {
+            const uint4 w = a4[q];
+            v[4 * q] = w.x;
+            v[4 * q + 1] = w.y;
+            v[4 * q + 2] = w.z;
+            v[4 * q + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) v[j] = (i0 + j < n) ? a[i0 + j] : 0u;
     }
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) s += v[j];
     uint32_t x = s;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -236,10 +251,20 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(uint32_t *__re
     __syncthreads();
     uint32_t p = sums[blockIdx.x] + x - s;
     for (int w = 0; w < wave; ++w) p += ws[w];
+    uint32_t e[kScanItems];  // exclusive prefix of the run
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        if (i0 + j < n) a[i0 + j] = p;
+        e[j] = p;
         p += v[j];
+    }
+    if (vec) {
+        uint4 *a4 = reinterpret_cast<uint4 *>(a + i0);
+#pragma unroll
+        for (int q = 0; q < kScanItems / 4; ++q) a4[q] = make_uint4(e[4 * q], e[4 * q + 1], e[4 * q + 2], e[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j)
+            if (i0 + j < n) a[i0 + j] = e[j];
     }
 }
 
