@@ -236,51 +236,68 @@ __global__ void __launch_bounds__(256) batch_colsum_kernel(const uint8_t *__rest
     }
 }
 
+// One image per workgroup of 1024 threads, chunks of 16384 entries: thread t
+// holds entries c0 + k * 1024 + t (k < 16: sixteen rows, every load and
+// store coalesced).  Each row is scanned across the wave with shuffles; the
+// wave totals per row go to LDS, where 16 threads turn them into per-wave
+// prefixes and row totals; every thread then adds the rows before its row and
+// the waves before its wave.  The running carry is the same in all threads.
 __global__ void __launch_bounds__(1024) batch_scan_kernel(const uint8_t *__restrict__ table) {
-    __shared__ int64_t ws[16];
-    __shared__ int64_t carry;
+    __shared__ int64_t ws[16][17];   // [row][wave]: wave totals, then exclusive prefixes over the waves
+    __shared__ int64_t rowtot[16];
     const BatchHeader *H = (const BatchHeader *)table;
     const MergeJob *jobs = (const MergeJob *)(table + H->off_merge);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int jb = blockIdx.x; jb < H->njobs; jb += gridDim.x) {
         const MergeJob J = jobs[jb];
         const uint32_t stv = *J.status;
-        if (tid == 0) carry = 0;
-        __syncthreads();
+        __syncthreads();  // every wave holds the status before thread 0 clears it below
         if (stv == 0) {
+            int64_t carry = 0;
             for (int c0 = 0; c0 < J.m; c0 += 1024 * 16) {
-                const int base = c0 + tid * 16;
-                int64_t loc[16];
-                int64_t run = 0;
+                int64_t v[16];
 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    run += (base + j < J.m) ? J.vcec[base + j] : 0;
-                    loc[j] = run;
+                for (int k = 0; k < 16; ++k) {
+                    const int i = c0 + k * 1024 + tid;
+                    v[k] = i < J.m ? J.vcec[i] : 0;
                 }
-                int64_t x = run;
 #pragma unroll
                 for (int off = 1; off < 64; off <<= 1) {
-                    const int64_t u = __shfl_up(x, off, 64);
-                    if (lane >= off) x += u;
-                }
-                if (lane == 63) ws[wave] = x;
-                __syncthreads();
-                int64_t pre = carry + x - run;
-                for (int w = 0; w < wave; ++w) pre += ws[w];
 #pragma unroll
-                for (int j = 0; j < 16; ++j)
-                    if (base + j < J.m) J.chi[base + j] = pre + loc[j];
+                    for (int k = 0; k < 16; ++k) {
+                        const int64_t u = __shfl_up(v[k], off, 64);
+                        if (lane >= off) v[k] += u;
+                    }
+                }
+                if (lane == 63) {
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) ws[k][wave] = v[k];
+                }
                 __syncthreads();
-                if (tid == 0)
-                    for (int w = 0; w < 16; ++w) carry += ws[w];
+                if (tid < 16) {  // row tid: exclusive prefix over the waves, and the row total
+                    int64_t run = 0;
+                    for (int w = 0; w < 16; ++w) {
+                        const int64_t x = ws[tid][w];
+                        ws[tid][w] = run;
+                        run += x;
+                    }
+                    rowtot[tid] = run;
+                }
                 __syncthreads();
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const int i = c0 + k * 1024 + tid;
+                    if (i < J.m) J.chi[i] = carry + ws[k][wave] + v[k];
+                    carry += rowtot[k];
+                }
+                __syncthreads();  // ws and rowtot are rewritten by the next chunk
             }
         }
         if (tid == 0) {
             if (J.status_out) *J.status_out = stv;
             *J.status = 0u;
         }
-        __syncthreads();  // carry and ws are reused by the next image
+        __syncthreads();  // the status of the next image of this workgroup
     }
 }
 
