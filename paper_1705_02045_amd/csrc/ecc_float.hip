@@ -359,72 +359,73 @@ __global__ void __launch_bounds__(kFThreads) fsum_tiles_kernel(const uint64_t *_
 
 // Exclusive scan in place of two int64 arrays of length nt by one workgroup;
 // total_last receives the sum of the second (the number of distinct keys).
-// Exclusive scans of both tile arrays in one workgroup: each thread takes a
-// run of kFsItems consecutive tiles (all its loads in flight at once), so
-// 2^16 tiles take four rounds of the block-wide scan instead of 64 (0.14 ms
-// instead of 0.16 ms: one CU's address unit, fed 64 lines per load, is the
-// limit; a scan over several workgroups would lift it).
-constexpr int kFsItems = 16;
+// Exclusive scans of both tile arrays in one workgroup of 1024 threads, in
+// chunks of 16384 tiles: thread t holds tiles c0 + k * 1024 + t (k < 16:
+// sixteen rows, every load and store coalesced).  Each row is scanned
+// across the wave with shuffles; the wave totals per row go to LDS, where
+// 32 threads turn them into per-wave prefixes and row totals.  The running
+// carries are the same in all threads.  (With runs of consecutive tiles per
+// thread one CU's address unit, fed 64 cache lines per load, was the limit:
+// 0.14 ms for 2^16 tiles, 0.16 ms with one tile per thread.)
 __global__ void __launch_bounds__(1024) fscan_tiles_kernel(int64_t *a, int64_t *b, int64_t nt, int64_t *total_last) {
-    __shared__ int64_t wa[16], wb[16];
-    __shared__ int64_t carry_a, carry_b;
+    __shared__ int64_t wsa[16][17], wsb[16][17];  // [row][wave]
+    __shared__ int64_t tota[16], totb[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) carry_a = carry_b = 0;
-    __syncthreads();
-    for (int64_t c0 = 0; c0 < nt; c0 += 1024 * kFsItems) {
-        const int64_t i0 = c0 + (int64_t)tid * kFsItems;
-        int64_t va[kFsItems], vb[kFsItems];
+    int64_t ca = 0, cb = 0;
+    for (int64_t c0 = 0; c0 < nt; c0 += 1024 * 16) {
+        int64_t xa[16], xb[16];
 #pragma unroll
-        for (int j = 0; j < kFsItems; ++j) {
-            const int64_t i = i0 + j;
-            va[j] = i < nt ? a[i] : 0;
-            vb[j] = i < nt ? b[i] : 0;
+        for (int k = 0; k < 16; ++k) {
+            const int64_t i = c0 + k * 1024 + tid;
+            xa[k] = i < nt ? a[i] : 0;
+            xb[k] = i < nt ? b[i] : 0;
         }
-        int64_t sa = 0, sb = 0;
-#pragma unroll
-        for (int j = 0; j < kFsItems; ++j) {
-            sa += va[j];
-            sb += vb[j];
-        }
-        int64_t xa = sa, xb = sb;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            const int64_t ua = __shfl_up(xa, off, 64), ub = __shfl_up(xb, off, 64);
-            if (lane >= off) {
-                xa += ua;
-                xb += ub;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int64_t ua = __shfl_up(xa[k], off, 64), ub = __shfl_up(xb[k], off, 64);
+                if (lane >= off) {
+                    xa[k] += ua;
+                    xb[k] += ub;
+                }
             }
         }
         if (lane == 63) {
-            wa[wave] = xa;
-            wb[wave] = xb;
-        }
-        __syncthreads();
-        int64_t pa = carry_a + xa - sa, pb = carry_b + xb - sb;
-        for (int w = 0; w < wave; ++w) {
-            pa += wa[w];
-            pb += wb[w];
-        }
 #pragma unroll
-        for (int j = 0; j < kFsItems; ++j) {
-            const int64_t i = i0 + j;
-            if (i < nt) {
-                a[i] = pa;
-                b[i] = pb;
+            for (int k = 0; k < 16; ++k) {
+                wsa[k][wave] = xa[k];
+                wsb[k][wave] = xb[k];
             }
-            pa += va[j];
-            pb += vb[j];
         }
         __syncthreads();
-        if (tid == 0) {
+        if (tid < 32) {  // row tid & 15 of array tid >> 4: exclusive prefix over the waves, row total
+            int64_t(*ws)[17] = tid < 16 ? wsa : wsb;
+            const int k = tid & 15;
+            int64_t run = 0;
             for (int w = 0; w < 16; ++w) {
-                carry_a += wa[w];
-                carry_b += wb[w];
+                const int64_t x = ws[k][w];
+                ws[k][w] = run;
+                run += x;
             }
+            (tid < 16 ? tota : totb)[k] = run;
         }
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            // exclusive within the wave: the inclusive value of the lane below
+            const int64_t pa = __shfl_up(xa[k], 1, 64), pb = __shfl_up(xb[k], 1, 64);
+            const int64_t i = c0 + k * 1024 + tid;
+            if (i < nt) {
+                a[i] = ca + wsa[k][wave] + (lane > 0 ? pa : 0);
+                b[i] = cb + wsb[k][wave] + (lane > 0 ? pb : 0);
+            }
+            ca += tota[k];
+            cb += totb[k];
+        }
+        __syncthreads();  // the LDS rows are rewritten by the next chunk
     }
-    if (tid == 0) *total_last = carry_b;
+    if (tid == 0) *total_last = cb;
 }
 
 // The curve write walks the same tiles with twice the threads (8 records
