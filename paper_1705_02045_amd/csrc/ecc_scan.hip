@@ -369,9 +369,10 @@ int launch_signed_sum(const int64_t *curves, int nf, uint64_t neg_mask, uint64_t
 // and n + 1 vertices (value: the larger of the voxels they touch); its
 // changes vector adds +1 at each vertex's value and -1 at each interval's.
 // A corner is one vertex.  Values >= m are skipped (the volume's own launch
-// reports them as range errors).  One workgroup per face.
+// reports them as range errors).  One workgroup of 1024 threads per face
+// (an edge of up to 1023 voxels in one round of loads).
 template <typename T>
-__global__ void __launch_bounds__(256) low_faces_kernel(const T *__restrict__ img, const LowFace *__restrict__ faces,
+__global__ void __launch_bounds__(1024) low_faces_kernel(const T *__restrict__ img, const LowFace *__restrict__ faces,
                                                         int m, int64_t *__restrict__ out) {
     const LowFace F = faces[blockIdx.x];
     auto val = [&](int64_t i) -> uint32_t { return (uint32_t)img[F.base + i * F.stride]; };
@@ -395,10 +396,10 @@ int launch_low_faces(const void *img, int elem, const LowFace *faces_dev, int nf
                      hipStream_t stream) {
     if (nfaces <= 0) return ECC_OK;
     if (elem == 1)
-        hipLaunchKernelGGL(low_faces_kernel<uint8_t>, dim3(nfaces), dim3(256), 0, stream, (const uint8_t *)img,
+        hipLaunchKernelGGL(low_faces_kernel<uint8_t>, dim3(nfaces), dim3(1024), 0, stream, (const uint8_t *)img,
                            faces_dev, m, out);
     else
-        hipLaunchKernelGGL(low_faces_kernel<uint16_t>, dim3(nfaces), dim3(256), 0, stream, (const uint16_t *)img,
+        hipLaunchKernelGGL(low_faces_kernel<uint16_t>, dim3(nfaces), dim3(1024), 0, stream, (const uint16_t *)img,
                            faces_dev, m, out);
     ECC_HIP(hipGetLastError());
     return ECC_OK;
