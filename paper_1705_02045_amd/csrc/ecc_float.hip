@@ -1,4 +1,4 @@
-// Float32 images (Sec. 3, "Floating Point Values"): the values are not known
+// Float32 images (Sec. 3, "Other Ranges of Gray Values"): the values are not known
 // in advance, so every voxel emits a record (key, change) and the records
 // are sorted by key, summed per distinct key and prefix-summed.
 //

@@ -1,4 +1,4 @@
-// Stable LSD radix sort of float records (Sec. 3, "Floating Point Values":
+// Stable LSD radix sort of float records (Sec. 3, "Other Ranges of Gray Values":
 // the values are sorted before the running sum).  A record is one 64-bit word:
 // the 32-bit order-preserving key in bits 8..39 and the voxel's change (int8)
 // in bits 0..7.  Four passes of 8-bit digits.

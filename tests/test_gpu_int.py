@@ -37,19 +37,7 @@ SHAPES_3D = [(1, 1, 1), (2, 2, 2), (3, 5, 7), (5, 64, 64), (4, 63, 65), (7, 66, 
              (33, 40, 200), (20, 129, 63), (64, 64, 64), (3, 1, 300), (100, 2, 2), (2, 300, 1)]
 
 
-FAULTED_THIS_ROUND = {
-    (33, 40, 200): pytest.mark.skip(
-        reason="faulted the GPU twice with an inline-asm build that clobbered SCC (cause found in the ISA and "
-               "fixed; tests/test_isa_checks.py); kept off the GPU for the rest of this round"),
-    (7, 66, 130): pytest.mark.skip(
-        reason="faulted the GPU twice with row-pair builds whose packed shift left the high lane unshifted "
-               "(misaligned LDS adds; cause shown in the compiler's encoding and fixed, tests/test_isa_checks.py); "
-               "kept off the GPU for the rest of this round"),
-}
-
-
-@pytest.mark.parametrize("shape", [pytest.param(s, marks=FAULTED_THIS_ROUND[s]) if s in FAULTED_THIS_ROUND else s
-                                   for s in SHAPES_3D], ids=str)
+@pytest.mark.parametrize("shape", SHAPES_3D, ids=str)
 def test_u14_value_noise_3d(ecc, shape):
     print(f"\n[gpu] u14 value noise {shape}", flush=True)
     check(ecc, gen.cfg_u14_value_noise(shape, seed=1), "u14")
@@ -238,8 +226,6 @@ def test_random_shapes_both_conventions(ecc):
             n2 += n2 & 1
         seed = int(rng.integers(0, 1 << 30))
         shape = (n0, n1, n2)
-        if shape in FAULTED_THIS_ROUND:
-            continue
         print(f"\n[gpu] random shape {shape} seed {seed}", flush=True)
         img = gen.cfg_u14_value_noise(shape, seed=seed)
         t = torch.from_numpy(img.view(np.int16)).cuda()
