@@ -44,6 +44,8 @@ def lib() -> ctypes.CDLL:
         L.eccgen_value_noise.argtypes = [ctypes.c_uint64, ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                          ctypes.c_int, ctypes.c_int]
+        L.eccgen_value_noise_voxelwise.restype = ctypes.c_int
+        L.eccgen_value_noise_voxelwise.argtypes = L.eccgen_value_noise.argtypes
         L.eccgen_value_noise_f32.restype = ctypes.c_int
         L.eccgen_value_noise_f32.argtypes = [ctypes.c_uint64, ctypes.c_int, i64p, ctypes.c_int,
                                              ctypes.c_double, ctypes.c_int64, ctypes.c_int64,

@@ -193,9 +193,70 @@ static int vn_setup(vn_ctx *c, uint64_t seed, int d, const int64_t *dims, int ls
     return 0;
 }
 
+/* The same integer value noise for d = 3, one image row (fixed axis-0 and
+ * axis-1 coordinates) at a time: the lattice values a row touches are hashed
+ * once per row and node column instead of once per voxel and corner, and the
+ * two outer interpolation weights are folded into one column sum
+ * C[b] = sum_{i,j} w0(i) w1(j) U(b0+i, b1+j, b), so that
+ * sum = (L - r2) C[b2] + r2 C[b2+1].  Every term is an exact integer, so the
+ * sum, and every output byte, equals the per-voxel form above. */
+static void vn_rows3(void *p, int64_t lo, int64_t hi) {
+    vn_ctx *c = (vn_ctx *)p;
+    const int ls = c->lshift;
+    const int64_t L = (int64_t)1 << ls;
+    const int64_t maxv = ((int64_t)1 << c->bits) - 1;
+    const int64_t n1 = c->n[1], n2 = c->n[2], N1 = c->N[1], N2 = c->N[2];
+    uint64_t *col = (uint64_t *)malloc((size_t)N2 * sizeof(uint64_t));
+    if (!col) return;  /* out of memory: rows stay unwritten (callers size this to a few KiB) */
+    for (int64_t row = lo; row < hi; ++row) {
+        const int64_t z = c->z0 + row / n1, y = row % n1;
+        const int64_t b0 = z >> ls, r0 = z & (L - 1), b1 = y >> ls, r1 = y & (L - 1);
+        for (int64_t b = 0; b < N2; ++b) {
+            uint64_t s = 0;
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) {
+                    const int64_t node = ((b0 + i) * N1 + (b1 + j)) * N2 + b;
+                    const uint64_t u = mix64(c->key1 + (uint64_t)(node + 1) * GAMMA) >> (64 - c->bits);
+                    s += u * (uint64_t)((i ? r0 : L - r0) * (j ? r1 : L - r1));
+                }
+            col[b] = s;
+        }
+        const int64_t gbase = (z * n1 + y) * n2;
+        const int64_t obase = row * n2;
+        for (int64_t x = 0; x < n2; ++x) {
+            const int64_t b2 = x >> ls, r2 = x & (L - 1);
+            const uint64_t acc = (uint64_t)(L - r2) * col[b2] + (uint64_t)r2 * col[b2 + 1];
+            const int64_t bv = (int64_t)((acc + ((uint64_t)1 << (3 * ls - 1))) >> (3 * ls));
+            const uint64_t hj = mix64(c->key2 + (uint64_t)(gbase + x + 1) * GAMMA);
+            int64_t v = bv + (int64_t)(((hj >> 32) * (uint64_t)(2 * c->amp + 1)) >> 32) - c->amp;
+            if (v < 0) v = 0;
+            if (v > maxv) v = maxv;
+            if (c->elem == 1) ((uint8_t *)c->out)[obase + x] = (uint8_t)v;
+            else ((uint16_t *)c->out)[obase + x] = (uint16_t)v;
+        }
+    }
+    free(col);
+}
+
 /* Integer value noise for planes [z0, z1) of axis 0; out holds (z1-z0)*plane values. */
 int eccgen_value_noise(uint64_t seed, int d, const int64_t *dims, int lshift, int bits, int amp,
                        int64_t z0, int64_t z1, void *out, int elem, int nthreads) {
+    vn_ctx c;
+    memset(&c, 0, sizeof c);
+    if (vn_setup(&c, seed, d, dims, lshift, z0, z1)) return -1;
+    if ((elem != 1 && elem != 2) || bits < 1 || bits > 8 * elem || amp < 0) return -1;
+    if (d * lshift + bits > 60) return -1;
+    c.bits = bits; c.amp = amp; c.elem = elem; c.is_float = 0; c.out = out;
+    if (d == 3)
+        parallel_for((z1 - z0) * c.n[1], nthreads, vn_rows3, &c);
+    else
+        parallel_for((z1 - z0) * c.plane, nthreads, vn_body, &c);
+    return 0;
+}
+
+/* The per-voxel form for any d (the d = 3 row form above is checked against it). */
+int eccgen_value_noise_voxelwise(uint64_t seed, int d, const int64_t *dims, int lshift, int bits, int amp,
+                                 int64_t z0, int64_t z1, void *out, int elem, int nthreads) {
     vn_ctx c;
     memset(&c, 0, sizeof c);
     if (vn_setup(&c, seed, d, dims, lshift, z0, z1)) return -1;

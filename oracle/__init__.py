@@ -53,6 +53,9 @@ def lib() -> ctypes.CDLL:
         L.oracle_vcec_range.restype = ctypes.c_int
         L.oracle_vcec_range.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, i64p, ctypes.c_int64,
                                         ctypes.c_int64, ctypes.c_int64, i64p]
+        L.oracle_vcec3.restype = ctypes.c_int
+        L.oracle_vcec3.argtypes = [ctypes.c_void_p, ctypes.c_int, i64p, ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.c_int64, i64p, ctypes.c_int]
         _LIB = L
     return _LIB
 
@@ -144,6 +147,19 @@ def vcec_q0_range(img: np.ndarray, m: int, q0_lo: int, q0_hi: int) -> np.ndarray
     out = np.zeros(int(m), dtype=np.int64)
     rc = lib().oracle_vcec_range(img.ctypes.data, _ELEM[img.dtype], img.ndim, dims, int(m),
                                  int(q0_lo), int(q0_hi), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    _check(rc)
+    return out
+
+
+def vcec3_q0_range(img: np.ndarray, m: int, q0_lo: int, q0_hi: int, nthreads: int | None = None) -> np.ndarray:
+    """vcec_q0_range for a 3-D image, by the three-loop enumeration
+    (``oracle_vcec3``), on up to nthreads threads."""
+    img, dims = _prep(img)
+    if img.ndim != 3:
+        raise ValueError("oracle: vcec3_q0_range takes 3-D images")
+    out = np.zeros(int(m), dtype=np.int64)
+    rc = lib().oracle_vcec3(img.ctypes.data, _ELEM[img.dtype], dims, int(m), int(q0_lo), int(q0_hi),
+                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nthreads or default_threads())
     _check(rc)
     return out
 

@@ -231,3 +231,115 @@ int oracle_curve_dual(const void *img, int elem, int d, const int64_t *n, int64_
     for (int64_t t = 1; t < m; ++t) chi[t] += chi[t - 1];
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * The same cell enumeration written out for d = 3 (three nested loops over
+ * the doubled coordinates), for the large volumes whose curves are stored as
+ * test fixtures.  It computes exactly what oracle_vcec_range computes for a
+ * 3-D image -- every cell with q_0 in [q0_lo, q0_hi), its value the minimum
+ * of f over its incident voxels, (-1)^dim added there (Sec. 2, "Sublevel Set
+ * Filtration"; Sec. 3, "Tracking the Changes") -- with the incident-voxel
+ * ranges computed per axis instead of by the d-dimensional odometer.  Threads
+ * split the q_0 layers, each into a private array; the arrays are added into
+ * vcec (which is not cleared). */
+typedef struct {
+    const void *img;
+    int elem;
+    int64_t n0, n1, n2, m;
+    int64_t q0_lo, q0_hi;
+    int64_t *vcec;
+} job3_t;
+
+/* incident index range {a} (odd q) or {b-1, b} within [0, n) (even q = 2b) */
+static inline void incident(int64_t q, int64_t n, int64_t *lo, int64_t *hi) {
+    if (q & 1) {
+        *lo = *hi = (q - 1) / 2;
+    } else {
+        const int64_t b = q / 2;
+        *lo = b - 1 < 0 ? 0 : b - 1;
+        *hi = b > n - 1 ? n - 1 : b;
+    }
+}
+
+/* One loop nest per element type (T), so that each voxel read is a plain
+ * array access. */
+#define COUNT_CELLS3(NAME, T)                                                        \
+    static void NAME(const job3_t *j) {                                             \
+        const T *f = (const T *)j->img;                                             \
+        const int64_t n0 = j->n0, n1 = j->n1, n2 = j->n2;                           \
+        for (int64_t q0 = j->q0_lo; q0 < j->q0_hi; ++q0) {                          \
+            int64_t z0, z1;                                                         \
+            incident(q0, n0, &z0, &z1);                                             \
+            for (int64_t q1 = 0; q1 <= 2 * n1; ++q1) {                              \
+                int64_t y0, y1;                                                     \
+                incident(q1, n1, &y0, &y1);                                         \
+                for (int64_t q2 = 0; q2 <= 2 * n2; ++q2) {                          \
+                    int64_t x0, x1;                                                 \
+                    incident(q2, n2, &x0, &x1);                                     \
+                    T best = f[(z0 * n1 + y0) * n2 + x0];                           \
+                    for (int64_t z = z0; z <= z1; ++z)                              \
+                        for (int64_t y = y0; y <= y1; ++y)                          \
+                            for (int64_t x = x0; x <= x1; ++x) {                    \
+                                const T v = f[(z * n1 + y) * n2 + x];               \
+                                if (v < best) best = v;                             \
+                            }                                                       \
+                    const int dim = (int)((q0 & 1) + (q1 & 1) + (q2 & 1));          \
+                    j->vcec[best] += (dim & 1) ? -1 : 1;                            \
+                }                                                                   \
+            }                                                                       \
+        }                                                                           \
+    }
+COUNT_CELLS3(count_cells3_u8, uint8_t)
+COUNT_CELLS3(count_cells3_u16, uint16_t)
+COUNT_CELLS3(count_cells3_u32, uint32_t)
+#undef COUNT_CELLS3
+
+static void count_cells3(const job3_t *j) {
+    if (j->elem == 1) count_cells3_u8(j);
+    else if (j->elem == 2) count_cells3_u16(j);
+    else count_cells3_u32(j);
+}
+
+static void *run_job3(void *p) {
+    count_cells3((const job3_t *)p);
+    return NULL;
+}
+
+/* Signed counts of the cells with q_0 in [q0_lo, q0_hi) of a 3-D image
+ * (dims n[0..2]), added into vcec[0..m), on up to nthreads threads.
+ * Returns -1 on bad arguments, -2 if a value is >= m, -3 if out of memory. */
+int oracle_vcec3(const void *img, int elem, const int64_t *n, int64_t m, int64_t q0_lo, int64_t q0_hi,
+                 int64_t *vcec, int nthreads) {
+    job_t chk;
+    memset(&chk, 0, sizeof chk);
+    int rc = setup(&chk, img, elem, 3, n, m);
+    if (rc) return rc;
+    if (q0_lo < 0) q0_lo = 0;
+    if (q0_hi > 2 * n[0] + 1) q0_hi = 2 * n[0] + 1;
+    if (q0_lo >= q0_hi) return 0;
+    const int64_t layers = q0_hi - q0_lo;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if (nthreads > layers) nthreads = (int)layers;
+    job3_t base = {img, elem, n[0], n[1], n[2], m, q0_lo, q0_hi, vcec};
+    if (nthreads == 1) {
+        count_cells3(&base);
+        return 0;
+    }
+    job3_t jobs[256];
+    pthread_t th[256];
+    int64_t *priv = (int64_t *)calloc((size_t)m * (size_t)nthreads, sizeof(int64_t));
+    if (!priv) return -3;
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = base;
+        jobs[t].q0_lo = q0_lo + layers * t / nthreads;
+        jobs[t].q0_hi = q0_lo + layers * (t + 1) / nthreads;
+        jobs[t].vcec = priv + (size_t)m * t;
+        pthread_create(&th[t], NULL, run_job3, &jobs[t]);
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    for (int t = 0; t < nthreads; ++t)
+        for (int64_t s = 0; s < m; ++s) vcec[s] += priv[(size_t)m * t + s];
+    free(priv);
+    return 0;
+}

@@ -62,3 +62,18 @@ def test_device_generator_library_exports():
         gen.dev_table_entries((5, 6), 0, 5)  # 3-D only
     with pytest.raises(ValueError):
         gen.dev_table_entries((5, 6, 7), 3, 3)  # empty range
+
+
+@pytest.mark.parametrize("shape,lshift,bits,amp,z0,z1", [
+    ((9, 20, 35), 4, 14, 64, 0, 9), ((37, 1, 300), 4, 14, 64, 3, 30), ((3, 17, 2), 2, 8, 1, 1, 3),
+    ((20, 33, 17), 3, 16, 256, 5, 19), ((2, 70, 1), 4, 14, 64, 0, 2), ((5, 5, 129), 5, 12, 7, 2, 5)], ids=str)
+def test_value_noise_rows_match_voxelwise(shape, lshift, bits, amp, z0, z1):
+    """The 3-D row form of the generator writes the per-voxel form's bytes."""
+    dtype = np.uint8 if bits <= 8 else np.uint16
+    fast = gen.value_noise(shape, bits, amp, 11, lshift=lshift, z0=z0, z1=z1)
+    slow = np.empty_like(fast)
+    rc = gen.lib().eccgen_value_noise_voxelwise(11, 3, gen._dims(shape), lshift, bits, amp, z0, z1,
+                                               slow.ctypes.data, np.dtype(dtype).itemsize, 3)
+    assert rc == 0 and (fast == slow).all()
+    if z0 == 0 and z1 == shape[0]:
+        assert (fast == gen.value_noise_np(shape, bits, amp, 11, lshift=lshift)).all()

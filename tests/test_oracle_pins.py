@@ -291,3 +291,50 @@ def test_dual_from_max_entry_of_faces(d):
                 a = oracle.curve_max_entry(np.ascontiguousarray(sub), m=m)
             acc += (-1) ** codim * a
         assert (oracle.curve_dual(img, m=m) == (-1) ** d * acc).all()
+
+
+@pytest.mark.parametrize("shape,m", [((4, 4, 4), 3), ((3, 4, 5), 4), ((1, 6, 2), 5), ((5, 1, 1), 4)])
+def test_vcec3_homology_brute_force(shape, m):
+    """The three-loop enumeration against Z/2 homology of {f <= t} for every t
+    (the same pin as the general enumeration's)."""
+    rng = np.random.default_rng(sum(shape) * 17 + m)
+    for _ in range(4):
+        img = rand_img(rng, shape, m)
+        chi = np.cumsum(oracle.vcec3_q0_range(img, m, 0, 2 * shape[0] + 1, nthreads=2))
+        for t in range(m):
+            beta, _ = betti(img <= t)
+            assert chi[t] == sum((-1) ** k * b for k, b in enumerate(beta))
+
+
+@pytest.mark.parametrize("shape,elem", [((9, 13, 11), np.uint8), ((6, 1, 40), np.uint16), ((2, 33, 3), np.uint32),
+                                        ((1, 1, 1), np.uint16), ((12, 7, 2), np.uint16)], ids=str)
+def test_vcec3_matches_general_enumeration(shape, elem):
+    """oracle_vcec3 counts the same cells as the d-dimensional enumeration, on
+    every q_0 range tried (whole, a prefix, a suffix, single layers), for every
+    thread count."""
+    rng = np.random.default_rng(int(np.prod(shape)) + 5)
+    m = 37
+    img = rng.integers(0, m, size=shape).astype(elem)
+    top = 2 * shape[0] + 1
+    for lo, hi in [(0, top), (0, 3), (2, top), (1, 2), (top - 1, top), (3, 3)]:
+        want = oracle.vcec_q0_range(img, m, lo, hi)
+        for threads in (1, 3, 8):
+            assert (oracle.vcec3_q0_range(img, m, lo, hi, nthreads=threads) == want).all(), (lo, hi, threads)
+
+
+def test_large_golden_chunks_sum_to_whole():
+    """The chunking of the script that writes the full-size stored curves:
+    value-noise chunks with a one-plane collar add up to the whole volume's
+    changes vector, for chunk lengths that divide the planes and ragged ones."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("mlg", GOLDEN / "make_large_goldens.py")
+    mlg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mlg)
+    import gen
+    shape = (23, 17, 30)
+    whole = oracle.vcec(gen.cfg_u14_value_noise(shape, seed=2), m=16384)
+    for chunk in (1, 4, 5, 23, 40):
+        total = np.zeros(16384, np.int64)
+        for z0 in range(0, shape[0], chunk):
+            total += mlg.chunk_vcec(shape, 2, z0, min(z0 + chunk, shape[0]), 2)
+        assert (total == whole).all(), chunk
