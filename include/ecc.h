@@ -164,6 +164,21 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
 int ecc_compute_async(const void *image_dev, const ecc_dims *dims, ecc_dtype dtype, int64_t *chi_dev,
                       uint32_t *status_dev, void *stream);
 
+/* For callers that cannot allocate (work under HIP graph capture, serving
+ * loops or harnesses that forbid hipMalloc): ecc_compute_async with every
+ * scratch buffer in one statically sized device array of the library
+ * (68.6 MiB per GPU, held by each GPU the library runs on until the process
+ * ends) instead of a workspace.  Arguments, results and errors as
+ * ecc_compute_async; it allocates no memory, host or device.  A launch uses
+ * at most 1024 workgroups (larger images give each workgroup more tiles), so
+ * every image ecc_compute_async takes fits; ECC_E_NOMEM reports a need
+ * beyond the array, which this build does not produce.
+ * Every call on one GPU shares that GPU's array and it keeps the last call's
+ * contents: calls that overlap in time on one GPU (different streams, or
+ * host threads) race and give wrong curves; order them, e.g. on one stream. */
+int ecc_compute_async_noalloc(const void *image_dev, const ecc_dims *dims, ecc_dtype dtype, int64_t *chi_dev,
+                              uint32_t *status_dev, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Tile shapes.  The integer kernel's tiling of a launch has three
  * parameters: rows per wave (2 or 4), waves along x (up to 16 of a

@@ -74,6 +74,8 @@ _lib.ecc_compute_max_entry.restype = ctypes.c_int
 _lib.ecc_compute_max_entry.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_int, ctypes.POINTER(Curve), _vp]
 _lib.ecc_compute_async.restype = ctypes.c_int
 _lib.ecc_compute_async.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_int, _vp, _vp, _vp]
+_lib.ecc_compute_async_noalloc.restype = ctypes.c_int
+_lib.ecc_compute_async_noalloc.argtypes = [_vp, ctypes.POINTER(Dims), ctypes.c_int, _vp, _vp, _vp]
 _lib.ecc_threshold_count.restype = ctypes.c_int
 _lib.ecc_threshold_count.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
 _lib.ecc_stream_begin.restype = ctypes.c_int
@@ -291,6 +293,17 @@ def compute_async(image, out_chi, dtype: str, status=None, stream=None):
     s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream_handle(image.device)
     _check(_lib.ecc_compute_async(image.data_ptr(), ctypes.byref(dims), DTYPES[dtype], out_chi.data_ptr(),
                                   status.data_ptr() if status is not None else None, s), "ecc_compute_async")
+
+
+def compute_async_noalloc(image, out_chi, dtype: str, status=None, stream=None):
+    """ecc_compute_async_noalloc on device tensors: as compute_async, with the
+    library's static scratch array (no allocation); calls on one GPU must not
+    overlap in time."""
+    dims = make_dims(image.shape)
+    s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream_handle(image.device)
+    _check(_lib.ecc_compute_async_noalloc(image.data_ptr(), ctypes.byref(dims), DTYPES[dtype], out_chi.data_ptr(),
+                                          status.data_ptr() if status is not None else None, s),
+           "ecc_compute_async_noalloc")
 
 
 def compute_host(array, dtype: str):

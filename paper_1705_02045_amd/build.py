@@ -10,8 +10,8 @@ ROOT = HERE.parent
 CSRC = HERE / "csrc"
 LIB = HERE / "libecc.so"
 
-SOURCES = ["ecc_api.cpp", "ecc_stream.cpp", "ecc_batch.cpp", "ecc_profile.cpp", "ecc_int.hip", "ecc_scan.hip",
-           "ecc_float.hip", "ecc_sort.hip"]
+SOURCES = ["ecc_api.cpp", "ecc_stream.cpp", "ecc_batch.cpp", "ecc_profile.cpp", "ecc_noalloc.cpp", "ecc_int.hip",
+           "ecc_scan.hip", "ecc_float.hip", "ecc_sort.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

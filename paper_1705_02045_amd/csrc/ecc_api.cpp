@@ -69,6 +69,13 @@ int ensure_bytes(void **ptr, size_t *cap, size_t need) {
     return ECC_OK;
 }
 
+int ws_ensure(Workspace *ws, void **ptr, size_t *cap, size_t need) {
+    if (!ws->fixed) return ensure_bytes(ptr, cap, need);
+    if (*ptr && *cap >= need) return ECC_OK;
+    set_error("fixed scratch too small: %zu bytes needed, %zu held", need, *cap);
+    return ECC_E_NOMEM;
+}
+
 static std::mutex g_ws_mu;
 static std::map<std::pair<int, void *>, Workspace *> g_ws;
 
@@ -177,7 +184,8 @@ static int env_int(const char *name, int dflt) {
 // ECC_INT_WAVES, ECC_INT_TILES_PER_CU, ECC_INT_TILE_STRIDE, ECC_INT_PAIR (0: no row pairs).
 // The tiling for given parameters: R rows per wave, up to wx_cap waves
 // along x (16-wave workgroups), about tiles_per_cu workgroups per CU.
-IntTiling make_int_tiling(const IntView &v, int64_t planes, int rows, int tiles_per_cu, int wx_cap) {
+IntTiling make_int_tiling(const IntView &v, int64_t planes, int rows, int tiles_per_cu, int wx_cap,
+                          int max_grid = 0) {
     IntTiling t{};
     t.rows = rows;
     t.mode = env_int("ECC_INT_MODE", 0);
@@ -214,7 +222,9 @@ IntTiling make_int_tiling(const IntView &v, int64_t planes, int rows, int tiles_
     // CU) holds them without spills (64-plane slabs of 14450^2: 2 % faster)
     t.pd = env_int("ECC_INT_PD", (zc >= 128 || rows >= 4) ? 2 : 1);
     const int64_t tiles = tiles_xy * ((planes + zc - 1) / zc);
-    const int64_t per = tiles > target ? (tiles + target - 1) / target : 1;
+    int64_t per = tiles > target ? (tiles + target - 1) / target : 1;
+    // a cap on the workgroups (fixed scratch): more tiles per workgroup
+    if (max_grid > 0 && (tiles + per - 1) / per > max_grid) per = (tiles + max_grid - 1) / max_grid;
     t.per_wg = (int)per;
     t.tile_stride = env_int("ECC_INT_TILE_STRIDE", 0);
     t.pair = env_int("ECC_INT_PAIR", 1);
@@ -276,9 +286,9 @@ static ecc_tiling tiling_params(const IntView &v, int dtype, int64_t planes) {
     return c;
 }
 
-IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes) {
+IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes, int max_grid) {
     const ecc_tiling c = tiling_params(v, dtype, planes);
-    return make_int_tiling(v, planes, c.rows, c.tiles_per_cu, c.waves_x);
+    return make_int_tiling(v, planes, c.rows, c.tiles_per_cu, c.waves_x, max_grid);
 }
 
 // Enqueue the whole integer computation for a device-resident image.
@@ -286,10 +296,10 @@ static int enqueue_int(const void *image_dev, const IntView &v, int dtype, int64
                        uint32_t *status_out, hipStream_t stream, Workspace *ws, bool max_entry = false) {
     const int m = (int)threshold_count(dtype);
     const size_t eb = elem_bytes(dtype);
-    IntTiling tl = choose_int_tiling(v, dtype, v.n0);
-    int rc = ensure_bytes((void **)&ws->partial, &ws->partial_bytes, (size_t)tl.grid * m * sizeof(int32_t));
+    IntTiling tl = choose_int_tiling(v, dtype, v.n0, ws->max_grid);
+    int rc = ws_ensure(ws, (void **)&ws->partial, &ws->partial_bytes, (size_t)tl.grid * m * sizeof(int32_t));
     if (rc) return rc;
-    rc = ensure_bytes((void **)&ws->vcec, &ws->vcec_bytes, (size_t)m * sizeof(int64_t));
+    rc = ws_ensure(ws, (void **)&ws->vcec, &ws->vcec_bytes, (size_t)m * sizeof(int64_t));
     if (rc) return rc;
     IntJob job{};
     job.src.base = (const uint8_t *)image_dev;
@@ -302,8 +312,7 @@ static int enqueue_int(const void *image_dev, const IntView &v, int dtype, int64
     job.hi_inf = 1;
     job.dtype = dtype;
     job.invert = max_entry ? 1 : 0;
-    rc = ensure_bytes((void **)&ws->stage, &ws->stage_bytes,
-                      (size_t)merge_stage_rows(tl.grid) * m * sizeof(int64_t));
+    rc = ws_ensure(ws, (void **)&ws->stage, &ws->stage_bytes, (size_t)merge_stage_rows(tl.grid) * m * sizeof(int64_t));
     if (rc) return rc;
     rc = launch_int_partial(job, tl, ws->partial, ws->status, nullptr, stream);
     if (rc) return rc;
@@ -346,15 +355,15 @@ static int enqueue_u16(const void *image_dev, const IntView &v, int64_t *chi_dev
     constexpr int mloc = 16384, mtot = 65536;
     U16Window win[kU16MaxWindows + 1];
     const int nwin = plan_u16_windows(vmin, vmax, win);
-    IntTiling tl = choose_int_tiling(v, ECC_U16, v.n0);
-    int rc = ensure_bytes((void **)&ws->partial, &ws->partial_bytes, (size_t)tl.grid * mloc * sizeof(int32_t));
+    IntTiling tl = choose_int_tiling(v, ECC_U16, v.n0, ws->max_grid);
+    int rc = ws_ensure(ws, (void **)&ws->partial, &ws->partial_bytes, (size_t)tl.grid * mloc * sizeof(int32_t));
     if (rc) return rc;
-    rc = ensure_bytes((void **)&ws->vcec, &ws->vcec_bytes, (size_t)mloc * sizeof(int64_t));
+    rc = ws_ensure(ws, (void **)&ws->vcec, &ws->vcec_bytes, (size_t)mloc * sizeof(int64_t));
     if (rc) return rc;
-    rc = ensure_bytes((void **)&ws->stage, &ws->stage_bytes,
-                      (size_t)merge_stage_rows(tl.grid) * mloc * sizeof(int64_t));
+    rc = ws_ensure(ws, (void **)&ws->stage, &ws->stage_bytes,
+                   (size_t)merge_stage_rows(tl.grid) * mloc * sizeof(int64_t));
     if (rc) return rc;
-    rc = ensure_bytes((void **)&ws->vcec16, &ws->vcec16_bytes, (size_t)mtot * sizeof(int64_t));
+    rc = ws_ensure(ws, (void **)&ws->vcec16, &ws->vcec16_bytes, (size_t)mtot * sizeof(int64_t));
     if (rc) return rc;
     rc = launch_zero(ws->vcec16, (size_t)mtot * sizeof(int64_t), stream);
     if (rc) return rc;
@@ -668,6 +677,39 @@ static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc
     return ECC_OK;
 }
 
+// ws == nullptr: the per-(device, stream) workspace.
+int compute_async_ws(const void *image_dev, const ecc_dims *dims, ecc_dtype dtype, int64_t *chi_dev,
+                     uint32_t *status_dev, hipStream_t stream, Workspace *ws) {
+    int64_t total = 0;
+    int rc = check_dims(dims, &total);
+    if (rc) return rc;
+    if (!image_dev || !chi_dev) {
+        set_error("NULL image or chi");
+        return ECC_E_ARG;
+    }
+    if (dtype != ECC_U8 && dtype != ECC_U14 && dtype != ECC_U16) {
+        if (dtype == ECC_F32) {
+            set_error("ecc_compute_async: dtype %d not available in this build", (int)dtype);
+            return ECC_E_UNSUPPORTED;
+        }
+        set_error("unknown dtype %d", (int)dtype);
+        return ECC_E_ARG;
+    }
+    IntView v{};
+    int unsup = 0;
+    if (!normalize_int_view(dims, &v, &unsup)) {
+        set_error("integer path: shape not supported (4 axes longer than 1, or an extent beyond 2^31)");
+        return ECC_E_UNSUPPORTED;
+    }
+    if (!ws) {
+        rc = get_workspace(stream, &ws);
+        if (rc) return rc;
+    }
+    if (dtype == ECC_U16)  // stream-ordered: windows over all values (no host read of the value range)
+        return enqueue_u16(image_dev, v, chi_dev, status_dev, stream, ws, 0, 65535);
+    return enqueue_int(image_dev, v, dtype, chi_dev, status_dev, stream, ws);
+}
+
 }  // namespace ecc
 
 using namespace ecc;
@@ -691,33 +733,7 @@ int ecc_threshold_count(ecc_dtype dtype, int64_t *m_out) {
 int ecc_compute_async(const void *image_dev, const ecc_dims *dims, ecc_dtype dtype, int64_t *chi_dev,
                       uint32_t *status_dev, void *stream) {
     g_err[0] = 0;
-    int64_t total = 0;
-    int rc = check_dims(dims, &total);
-    if (rc) return rc;
-    if (!image_dev || !chi_dev) {
-        set_error("NULL image or chi");
-        return ECC_E_ARG;
-    }
-    if (dtype != ECC_U8 && dtype != ECC_U14 && dtype != ECC_U16) {
-        if (dtype == ECC_F32) {
-            set_error("ecc_compute_async: dtype %d not available in this build", (int)dtype);
-            return ECC_E_UNSUPPORTED;
-        }
-        set_error("unknown dtype %d", (int)dtype);
-        return ECC_E_ARG;
-    }
-    IntView v{};
-    int unsup = 0;
-    if (!normalize_int_view(dims, &v, &unsup)) {
-        set_error("integer path: shape not supported (4 axes longer than 1, or an extent beyond 2^31)");
-        return ECC_E_UNSUPPORTED;
-    }
-    Workspace *ws = nullptr;
-    rc = get_workspace(stream, &ws);
-    if (rc) return rc;
-    if (dtype == ECC_U16)  // stream-ordered: windows over all values (no host read of the value range)
-        return enqueue_u16(image_dev, v, chi_dev, status_dev, (hipStream_t)stream, ws, 0, 65535);
-    return enqueue_int(image_dev, v, dtype, chi_dev, status_dev, (hipStream_t)stream, ws);
+    return compute_async_ws(image_dev, dims, dtype, chi_dev, status_dev, (hipStream_t)stream, nullptr);
 }
 
 int ecc_compute(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_curve *curve, void *stream) {

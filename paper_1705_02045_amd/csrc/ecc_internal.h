@@ -101,15 +101,28 @@ struct Workspace {
     size_t dual_buf_bytes = 0;
     int64_t *vcec16 = nullptr;   // [65536] changes vector of a 16-bit image (window passes)
     size_t vcec16_bytes = 0;
+    // Fixed scratch (the entry point that allocates nothing): the buffers
+    // above point into memory the library does not own and never grow;
+    // ws_ensure fails instead of allocating.  max_grid caps the workgroup
+    // count of a launch (0: no cap) so the count rows fit.
+    bool fixed = false;
+    int max_grid = 0;
 };
 
 int get_workspace(void *stream, Workspace **out);
 int ensure_bytes(void **ptr, size_t *cap, size_t need);
+// ensure_bytes for a buffer of ws: grows it, or on a fixed workspace fails
+// with ECC_E_NOMEM when the buffer is smaller than need.
+int ws_ensure(Workspace *ws, void **ptr, size_t *cap, size_t need);
+// The stream-ordered integer curve of a device image (ecc_compute_async's
+// work) with the scratch of ws.
+int compute_async_ws(const void *image_dev, const ecc_dims *dims, ecc_dtype dtype, int64_t *chi_dev,
+                     uint32_t *status_dev, hipStream_t stream, Workspace *ws);
 
 int64_t threshold_count(int dtype);
 int device_cu_count();
 
-IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes);
+IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes, int max_grid = 0);
 
 // Kernels (ecc_int.hip / ecc_scan.hip).  All enqueue on `stream`.
 // zero_vcec: when not null, workgroup 0 clears m int64 entries there first.
