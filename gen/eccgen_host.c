@@ -238,6 +238,44 @@ static void vn_rows3(void *p, int64_t lo, int64_t hi) {
     free(col);
 }
 
+/* The d = 2 row form: one row (fixed axis-0 coordinate) at a time, the
+ * lattice values of its two node rows hashed once per node column and folded
+ * into C[b] = sum_i w0(i) U(b0+i, b); sum = (L - r1) C[b1] + r1 C[b1+1]. */
+static void vn_rows2(void *p, int64_t lo, int64_t hi) {
+    vn_ctx *c = (vn_ctx *)p;
+    const int ls = c->lshift;
+    const int64_t L = (int64_t)1 << ls;
+    const int64_t maxv = ((int64_t)1 << c->bits) - 1;
+    const int64_t n1 = c->n[1], N1 = c->N[1];
+    uint64_t *col = (uint64_t *)malloc((size_t)N1 * sizeof(uint64_t));
+    if (!col) return;
+    for (int64_t row = lo; row < hi; ++row) {
+        const int64_t z = c->z0 + row;
+        const int64_t b0 = z >> ls, r0 = z & (L - 1);
+        for (int64_t b = 0; b < N1; ++b) {
+            uint64_t s = 0;
+            for (int i = 0; i < 2; ++i) {
+                const int64_t node = (b0 + i) * N1 + b;
+                const uint64_t u = mix64(c->key1 + (uint64_t)(node + 1) * GAMMA) >> (64 - c->bits);
+                s += u * (uint64_t)(i ? r0 : L - r0);
+            }
+            col[b] = s;
+        }
+        for (int64_t x = 0; x < n1; ++x) {
+            const int64_t b1 = x >> ls, r1 = x & (L - 1);
+            const uint64_t acc = (uint64_t)(L - r1) * col[b1] + (uint64_t)r1 * col[b1 + 1];
+            const int64_t bv = (int64_t)((acc + ((uint64_t)1 << (2 * ls - 1))) >> (2 * ls));
+            const uint64_t hj = mix64(c->key2 + (uint64_t)(z * n1 + x + 1) * GAMMA);
+            int64_t v = bv + (int64_t)(((hj >> 32) * (uint64_t)(2 * c->amp + 1)) >> 32) - c->amp;
+            if (v < 0) v = 0;
+            if (v > maxv) v = maxv;
+            if (c->elem == 1) ((uint8_t *)c->out)[row * n1 + x] = (uint8_t)v;
+            else ((uint16_t *)c->out)[row * n1 + x] = (uint16_t)v;
+        }
+    }
+    free(col);
+}
+
 /* Integer value noise for planes [z0, z1) of axis 0; out holds (z1-z0)*plane values. */
 int eccgen_value_noise(uint64_t seed, int d, const int64_t *dims, int lshift, int bits, int amp,
                        int64_t z0, int64_t z1, void *out, int elem, int nthreads) {
@@ -249,6 +287,8 @@ int eccgen_value_noise(uint64_t seed, int d, const int64_t *dims, int lshift, in
     c.bits = bits; c.amp = amp; c.elem = elem; c.is_float = 0; c.out = out;
     if (d == 3)
         parallel_for((z1 - z0) * c.n[1], nthreads, vn_rows3, &c);
+    else if (d == 2)
+        parallel_for(z1 - z0, nthreads, vn_rows2, &c);
     else
         parallel_for((z1 - z0) * c.plane, nthreads, vn_body, &c);
     return 0;

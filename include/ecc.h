@@ -291,23 +291,57 @@ int ecc_batch_autotune(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, int32_
  * ECC_E_UNSUPPORTED. */
 int ecc_job_footprint(const ecc_job *job, int64_t *bytes);
 
-/* Serving replay for measurement: request i (jobs[i], device-resident image;
- * its chi field is ignored) becomes available at arrival_s[i] seconds after
- * the call starts (ascending).  Continuous batching (one_launch_per_image =
- * 0): whenever fewer than three batches are in flight, the requests that have
- * arrived are admitted in order into the next ecc_batch_run while the batch
+/* Serving replay for measurement (Sec. 3, "Parallel Computations": every
+ * request's changes vector is its own; "Streaming": an image is consumed
+ * chunk by chunk of axis-0 planes).  Request i (jobs[i]; its chi field is
+ * ignored) becomes available at arrival_s[i] seconds after the call starts
+ * (ascending).  Its image is device memory, or, when cfg->arena_bytes > 0,
+ * host memory (pinned, e.g. hipHostMalloc, for the copies to overlap).
+ *
+ * Continuous batching (one_launch_per_image = 0): whenever fewer than
+ * max_inflight batches are in flight, the requests that have arrived are
+ * admitted in arrival order into the next ecc_batch_run while the batch
  * holds at most max_batch requests and the sum of their footprints
- * (ecc_job_footprint) stays within max_batch_bytes (0: no byte limit; a
- * request larger than the limit runs alone).  Otherwise every request is
- * one ecc_compute_async launch as soon as it arrives.  Each request's curve
- * is copied to pinned host memory owned by the call, on a second stream of
- * the call's own that waits for the launch (so one launch's copy overlaps
- * the next launch's kernels); latency_s[i] receives
- * the time from its arrival until that copy was seen complete; batch_id[i]
- * (optional) the index of the batch (or launch) that carried it.  At the
- * end all curves are copied to chi_host, request i's at chi_host + (sum of
- * the m of the requests before it).  Blocks until all requests are done.
- * Errors: ECC_E_ARG, ECC_E_UNSUPPORTED, ECC_E_NOMEM, ECC_E_HIP. */
+ * (ecc_job_footprint) stays within max_batch_bytes (0: no limit; the first
+ * request of a batch always counts).  Otherwise every request is one
+ * ecc_compute_async launch as soon as it is admitted.
+ * Host-origin requests: admission also reserves a block of the arena (one
+ * device buffer of arena_bytes) for the image, copies it in on a copy stream
+ * of the call and frees the block when the request's kernels are done; a
+ * request waits while its image does not fit.
+ * Requests whose image exceeds stream_above_bytes (0: arena_bytes / 4 for
+ * host-origin requests, else never) are not batched: one at a time, each is
+ * pushed through the streaming interface on a stream of its own in chunks
+ * of whole axis-0 planes of about chunk_bytes (0: 64 MiB; host-origin: at
+ * most arena_bytes / 4, each chunk in an arena block), two chunks in
+ * flight, its partial changes vector kept on the device, while batches of
+ * the other requests keep running.
+ * Curves are copied to pinned host memory owned by the call on a copy
+ * stream that waits for the kernels; latency_s[i] receives the time from
+ * arrival until that copy was seen complete; batch_id[i] (optional) the
+ * index of the batch, launch or stream that carried it; status[i]
+ * (optional) ECC_OK or ECC_E_RANGE.  At the end the curves are copied to
+ * chi_host, request i's at chi_host + (sum of the m of the requests before
+ * it); a request that failed gets zeros.  Blocks until all requests are done.
+ * U8 and U14 requests.  Errors: ECC_E_ARG, ECC_E_UNSUPPORTED (a plane of a
+ * streamed request above arena_bytes / 4), ECC_E_NOMEM, ECC_E_HIP, and
+ * ECC_E_RANGE when a request held a 14-bit value >= 16384 (every other
+ * request's curve is still delivered). */
+typedef struct {
+    int32_t max_batch;            /* requests per batch, >= 1 */
+    int32_t one_launch_per_image; /* 1: one ecc_compute_async per request */
+    int64_t max_batch_bytes;      /* footprint per batch; 0: no limit */
+    int64_t arena_bytes;          /* > 0: host-origin requests, device arena of this size */
+    int64_t stream_above_bytes;   /* images above this are streamed; 0: default (above) */
+    int64_t chunk_bytes;          /* streamed chunk size; 0: default (above) */
+    int32_t max_inflight;         /* batches in flight; 0: 3 (batched) or unbounded (per image) */
+} ecc_serve_config;
+
+int ecc_serve(ecc_batch *b, int32_t n, const ecc_job *jobs, const double *arrival_s, const ecc_serve_config *cfg,
+              int64_t *chi_host, double *latency_s, int32_t *batch_id, int32_t *status);
+
+/* ecc_serve with device-resident requests, no streaming and the default
+ * number of batches in flight. */
 int ecc_serve_simulate(ecc_batch *b, int32_t n, const ecc_job *jobs, const double *arrival_s, int32_t max_batch,
                        int64_t max_batch_bytes, int32_t one_launch_per_image, int64_t *chi_host, double *latency_s,
                        int32_t *batch_id);

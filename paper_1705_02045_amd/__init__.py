@@ -46,6 +46,13 @@ class Tiling(ctypes.Structure):
                 ("ms", ctypes.c_float)]
 
 
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("one_launch_per_image", ctypes.c_int32),
+                ("max_batch_bytes", ctypes.c_int64), ("arena_bytes", ctypes.c_int64),
+                ("stream_above_bytes", ctypes.c_int64), ("chunk_bytes", ctypes.c_int64),
+                ("max_inflight", ctypes.c_int32)]
+
+
 class Curve(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int64), ("count", ctypes.c_int64),
                 ("chi", ctypes.c_void_p), ("keys", ctypes.c_void_p)]
@@ -99,6 +106,8 @@ _lib.ecc_serve_simulate.restype = ctypes.c_int
 _lib.ecc_serve_simulate.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                     _vp, _vp, _vp]
 _lib.ecc_job_footprint.restype = ctypes.c_int
+_lib.ecc_serve.restype = ctypes.c_int
+_lib.ecc_serve.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.POINTER(ServeConfig), _vp, _vp, _vp, _vp]
 _lib.ecc_job_footprint.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
 _lib.ecc_profile_read.restype = ctypes.c_int
 _lib.ecc_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -398,6 +407,32 @@ class Batch:
                                        int(max_batch), int(max_batch_bytes), int(bool(one_launch_per_image)),
                                        chi.ctypes.data, lat.ctypes.data, bid.ctypes.data), "ecc_serve_simulate")
         return (lat, chi, bid) if with_batches else (lat, chi)
+
+    def serve_config(self, images, dtypes, arrival_s, max_batch: int = 256, one_launch_per_image: bool = False,
+                     max_batch_bytes: int = 0, arena_bytes: int = 0, stream_above_bytes: int = 0,
+                     chunk_bytes: int = 0, max_inflight: int = 0, check: bool = True):
+        """ecc_serve.  images: device tensors, or (arena_bytes > 0) pinned host
+        tensors.  Returns (latency seconds, host curves concatenated in request
+        order, batch index, per-request status code, return code); with check,
+        a non-zero return code raises instead."""
+        import numpy as np
+        arr = _jobs_array(images, dtypes)
+        arrival = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        total = sum(THRESHOLDS[d] for d in dtypes)
+        chi = np.empty(total, dtype=np.int64)
+        n = len(images)
+        lat = np.empty(n, dtype=np.float64)
+        bid = np.empty(n, dtype=np.int32)
+        st = np.empty(n, dtype=np.int32)
+        cfg = ServeConfig(max_batch=int(max_batch), one_launch_per_image=int(bool(one_launch_per_image)),
+                          max_batch_bytes=int(max_batch_bytes), arena_bytes=int(arena_bytes),
+                          stream_above_bytes=int(stream_above_bytes), chunk_bytes=int(chunk_bytes),
+                          max_inflight=int(max_inflight))
+        rc = _lib.ecc_serve(self._h, n, ctypes.cast(arr, _vp), arrival.ctypes.data, ctypes.byref(cfg),
+                            chi.ctypes.data, lat.ctypes.data, bid.ctypes.data, st.ctypes.data)
+        if check:
+            _check(rc, "ecc_serve")
+        return lat, chi, bid, st, rc
 
     def autotune(self, images, dtypes, chis):
         """ecc_batch_autotune: picks the context's tile depth on this batch;

@@ -7,17 +7,22 @@
 // parameters and its range of workgroups, and a batched merge sums and scans
 // each image's rows into its own curve.
 //
-// ecc_serve_simulate replays a stream of requests with given arrival times
-// against the device, either with continuous batching (everything that has
-// arrived when the device can take more work goes into the next batch) or
-// one launch per image, and reports each request's latency from arrival to
-// its curve being in host memory.
+// ecc_serve replays a stream of requests with given arrival times against
+// the device, either with continuous batching (everything that has arrived
+// when the device can take more work goes into the next batch) or one launch
+// per image, and reports each request's latency from arrival to its curve
+// being in host memory.  Requests may start in device memory or in pinned
+// host memory; host-origin images are copied into an arena of device memory
+// as they are admitted, and requests above a size are pushed chunk by chunk
+// through the streaming path (Sec. 3, "Streaming") while batches of the
+// others keep running.
 
 #include <algorithm>
 #include <chrono>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <vector>
 
 #include "ecc_internal.h"
@@ -152,6 +157,405 @@ int build_graph(ecc_batch *b, int s) {
     }
     return ECC_OK;
 }
+
+// ------------------------------------------------------------------ serving
+// One request of a serving run, as the loop sees it.
+struct Req {
+    int m = 0;
+    int64_t bytes = 0;         // image bytes
+    int64_t foot = 0;          // ecc_job_footprint (batched requests)
+    bool streamed = false;     // pushed chunk by chunk through the streaming path
+    int64_t plane_bytes = 0;   // streamed: bytes of one axis-0 plane
+    int64_t chunk_planes = 0;  // streamed: planes per pushed chunk
+};
+
+// First-fit allocator over one device buffer in 256-byte granules: the
+// images (and streamed chunks) of host-origin requests while they are in
+// flight.  Admission takes blocks from it and completion returns them, so
+// the device memory held by requests never exceeds the arena.
+class Arena {
+  public:
+    void reset(uint8_t *base, int64_t cap) {
+        base_ = base;
+        free_.clear();
+        if (cap > 0) free_[0] = cap;
+    }
+    int64_t alloc(int64_t bytes) {
+        bytes = round(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const int64_t off = it->first, size = it->second;
+            free_.erase(it);
+            if (size > bytes) free_[off + bytes] = size - bytes;
+            return off;
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t bytes) {
+        bytes = round(bytes);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    uint8_t *at(int64_t off) const { return base_ + off; }
+
+  private:
+    static int64_t round(int64_t b) { return (b + 255) & ~(int64_t)255; }
+    uint8_t *base_ = nullptr;
+    std::map<int64_t, int64_t> free_;  // offset -> bytes
+};
+
+class Serve {
+  public:
+    Serve(ecc_batch *b, int n) : b_(b), n_(n) {}
+
+    int setup(const std::vector<Req> &req, int64_t arena_bytes) {
+        int64_t words = 0;
+        for (const Req &R : req) words += R.m;
+        slot_req_.assign(n_, -1);
+        slot_off_.assign(n_ + 1, 0);
+        js_.assign(n_, ecc_job{});
+        hipError_t e = hipMalloc(&chi_dev_, (size_t)words * 8);
+        if (e == hipSuccess) e = hipHostMalloc(&chi_pin_, (size_t)words * 8, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc(&status_dev_, (size_t)n_ * 4);
+        if (e == hipSuccess && arena_bytes > 0) e = hipMalloc(&arena_buf_, (size_t)arena_bytes);
+        for (hipStream_t *s : {&h2d_, &d2h_, &os_})
+            if (e == hipSuccess) e = hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "ecc_serve: set-up");
+        arena_.reset((uint8_t *)arena_buf_, arena_bytes);
+        return launch_zero(status_dev_, (size_t)n_ * 4, b_->stream);
+    }
+
+    int run(const ecc_job *jobs, const std::vector<Req> &req, const double *arrival, const ecc_serve_config &c,
+            bool single, bool host_origin, double *latency, int32_t *batch_id) {
+        jobs_ = jobs;
+        req_ = &req;
+        host_origin_ = host_origin;
+        latency_ = latency;
+        batch_id_ = batch_id;
+        arrival_ = arrival;
+        const int max_inflight = c.max_inflight > 0 ? c.max_inflight : (single ? (1 << 30) : 3);
+        ECC_HIP(hipStreamSynchronize(b_->stream));  // the status clear
+        t0_ = std::chrono::steady_clock::now();
+        int arrived = 0, rc = ECC_OK;
+        while (done_ < n_ && !rc) {
+            const double t = now();
+            for (; arrived < n_ && arrival[arrived] <= t; ++arrived)
+                (req[arrived].streamed ? sq_ : bq_).push_back(arrived);
+            rc = pump_stream();
+            while (!rc && !bq_.empty() && (int)flights_.size() < max_inflight) {
+                bool formed = false;
+                rc = dispatch(c, single, &formed);
+                if (!formed) break;
+            }
+            if (!rc) rc = poll_flights();
+        }
+        return rc;
+    }
+
+    // Status and curves to the caller, in request order.
+    int collect(const std::vector<Req> &req, int64_t *chi_host, int32_t *status) {
+        std::vector<uint32_t> st(n_, 0);
+        ECC_HIP(hipMemcpy(st.data(), status_dev_, (size_t)n_ * 4, hipMemcpyDeviceToHost));
+        std::vector<int64_t> roff(n_ + 1, 0);
+        for (int i = 0; i < n_; ++i) roff[i + 1] = roff[i] + req[i].m;
+        int rc = ECC_OK;
+        for (int s = 0; s < nslots_; ++s) {
+            const int r = slot_req_[s];
+            const int m = req[r].m;
+            int code = ECC_OK;
+            if (st[s] & kStatusRange) code = ECC_E_RANGE;
+            else if (st[s] != 0) code = ECC_E_HIP;
+            if (status) status[r] = code;
+            if (code == ECC_OK) {
+                memcpy(chi_host + roff[r], chi_pin_ + slot_off_[s], (size_t)m * 8);
+            } else {
+                memset(chi_host + roff[r], 0, (size_t)m * 8);
+                if (!rc) {
+                    rc = code;
+                    if (code == ECC_E_RANGE) set_error("ecc_serve: request %d holds a 14-bit value >= 16384", r);
+                    else set_error("ecc_serve: request %d: device status 0x%08x", r, st[s]);
+                }
+            }
+        }
+        return rc;
+    }
+
+    void teardown() {
+        (void)hipStreamSynchronize(b_->stream);
+        for (hipStream_t s : {os_, h2d_, d2h_})
+            if (s) (void)hipStreamSynchronize(s);
+        if (cur_.st) ecc_stream_abort(cur_.st);
+        for (auto &f : flights_) {
+            pool_.push_back(f.kev);
+            pool_.push_back(f.cev);
+        }
+        for (auto &ch : cur_.chunks) pool_.push_back(ch.ev);
+        if (cur_.cev) pool_.push_back(cur_.cev);
+        for (hipEvent_t ev : pool_)
+            if (ev) (void)hipEventDestroy(ev);
+        for (hipStream_t s : {h2d_, d2h_, os_})
+            if (s) (void)hipStreamDestroy(s);
+        if (arena_buf_) (void)hipFree(arena_buf_);
+        if (status_dev_) (void)hipFree(status_dev_);
+        if (chi_pin_) (void)hipHostFree(chi_pin_);
+        if (chi_dev_) (void)hipFree(chi_dev_);
+    }
+
+  private:
+    struct Flight {  // one batch, or one launch of a single image
+        hipEvent_t kev = nullptr;  // its kernels are done: its arena blocks return
+        hipEvent_t cev = nullptr;  // its curves are in host memory
+        int s0 = 0, s1 = 0;        // its dispatch slots
+        std::vector<std::pair<int64_t, int64_t>> held;
+        bool released = false;
+    };
+    struct Chunk {
+        hipEvent_t ev;  // the kernels reading it are done
+        int64_t off, bytes;
+    };
+    struct Streamed {  // the request being pushed chunk by chunk
+        int r = -1, slot = -1;
+        ecc_stream *st = nullptr;
+        int64_t pushed = 0;
+        std::deque<Chunk> chunks;
+        bool finishing = false;
+        hipEvent_t cev = nullptr;
+    };
+
+    double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count(); }
+
+    int event(hipEvent_t *ev) {
+        if (!pool_.empty()) {
+            *ev = pool_.back();
+            pool_.pop_back();
+            return ECC_OK;
+        }
+        ECC_HIP(hipEventCreateWithFlags(ev, hipEventDisableTiming));
+        return ECC_OK;
+    }
+
+    // Curve slot s for request r (dispatch order, so a batch's curves are contiguous).
+    int new_slot(int r) {
+        const int s = nslots_++;
+        slot_req_[s] = r;
+        slot_off_[s + 1] = slot_off_[s] + (*req_)[r].m;
+        return s;
+    }
+
+    // Copy of the curves of slots [s0, s1) to pinned host memory after the
+    // work recorded by kev, on the copy-out stream; records cev.
+    int copy_out(hipEvent_t kev, int s0, int s1, hipEvent_t *cev) {
+        int rc = event(cev);
+        if (rc) return rc;
+        ECC_HIP(hipStreamWaitEvent(d2h_, kev, 0));
+        ECC_HIP(hipMemcpyAsync(chi_pin_ + slot_off_[s0], chi_dev_ + slot_off_[s0],
+                               (size_t)(slot_off_[s1] - slot_off_[s0]) * 8, hipMemcpyDeviceToHost, d2h_));
+        ECC_HIP(hipEventRecord(*cev, d2h_));
+        return ECC_OK;
+    }
+
+    // The next batch from the queue, in arrival order: at most max_batch
+    // requests (one in the per-image mode) and max_batch_bytes of footprint
+    // (the first request always counts), each host-origin image in an arena
+    // block, copied in on the copy-in stream.
+    int dispatch(const ecc_serve_config &c, bool single, bool *formed) {
+        const std::vector<Req> &req = *req_;
+        const int cap = single ? 1 : c.max_batch;
+        int k = 0;
+        int64_t foot = 0;
+        Flight f;
+        while (k < cap && k < (int)bq_.size()) {
+            const int r = bq_[k];
+            if (k > 0 && c.max_batch_bytes > 0 && foot + req[r].foot > c.max_batch_bytes) break;
+            if (host_origin_) {
+                const int64_t off = arena_.alloc(req[r].bytes);
+                if (off < 0) break;
+                f.held.emplace_back(off, req[r].bytes);
+            }
+            foot += req[r].foot;
+            ++k;
+        }
+        *formed = k > 0;
+        if (!k) return ECC_OK;
+        f.s0 = nslots_;
+        for (int i = 0; i < k; ++i) {
+            const int r = bq_.front();
+            bq_.pop_front();
+            const int s = new_slot(r);
+            js_[s] = jobs_[r];
+            js_[s].chi = chi_dev_ + slot_off_[s];
+            if (batch_id_) batch_id_[r] = groups_;
+            if (host_origin_) {
+                js_[s].image = arena_.at(f.held[i].first);
+                ECC_HIP(hipMemcpyAsync((void *)js_[s].image, jobs_[r].image, (size_t)req[r].bytes,
+                                       hipMemcpyHostToDevice, h2d_));
+            }
+        }
+        f.s1 = nslots_;
+        ++groups_;
+        int rc = ECC_OK;
+        if (host_origin_) {
+            hipEvent_t in = nullptr;
+            if ((rc = event(&in))) return rc;
+            ECC_HIP(hipEventRecord(in, h2d_));
+            ECC_HIP(hipStreamWaitEvent(b_->stream, in, 0));
+            pool_.push_back(in);  // reusable: the wait has taken its record
+        }
+        if (single) {
+            const ecc_job &J = js_[f.s0];
+            rc = ecc_compute_async(J.image, &J.dims, (ecc_dtype)J.dtype, J.chi, status_dev_ + f.s0, b_->stream);
+        } else {
+            rc = ecc_batch_run(b_, k, js_.data() + f.s0, status_dev_ + f.s0);
+        }
+        if (rc) return rc;
+        if ((rc = event(&f.kev))) return rc;
+        ECC_HIP(hipEventRecord(f.kev, b_->stream));
+        if ((rc = copy_out(f.kev, f.s0, f.s1, &f.cev))) return rc;
+        flights_.push_back(std::move(f));
+        return ECC_OK;
+    }
+
+    // Oversized requests, one at a time: chunks of whole planes pushed through
+    // the streaming path on a stream of their own (two chunks in flight, each
+    // in an arena block for host-origin requests); the partial changes vector
+    // stays on the device between chunks; the curve is scanned and copied out
+    // after the last chunk.
+    int pump_stream() {
+        int rc = ECC_OK;
+        if (!cur_.st && !sq_.empty()) {
+            cur_ = Streamed{};
+            cur_.r = sq_.front();
+            sq_.pop_front();
+            cur_.slot = new_slot(cur_.r);
+            if (batch_id_) batch_id_[cur_.r] = groups_;
+            ++groups_;
+            const ecc_job &J = jobs_[cur_.r];
+            if ((rc = ecc_stream_begin(&J.dims, (ecc_dtype)J.dtype, os_, &cur_.st))) return rc;
+        }
+        if (!cur_.st) return ECC_OK;
+        const Req &R = (*req_)[cur_.r];
+        const ecc_job &J = jobs_[cur_.r];
+        const int64_t planes = J.dims.n[0];
+        while (!cur_.chunks.empty()) {
+            const hipError_t e = hipEventQuery(cur_.chunks.front().ev);
+            if (e == hipErrorNotReady) break;
+            if (e != hipSuccess) return hip_fail(e, "ecc_serve: chunk");
+            if (cur_.chunks.front().off >= 0) arena_.release(cur_.chunks.front().off, cur_.chunks.front().bytes);
+            pool_.push_back(cur_.chunks.front().ev);
+            cur_.chunks.pop_front();
+        }
+        while (cur_.pushed < planes && cur_.chunks.size() < 2) {
+            const int64_t np = std::min(R.chunk_planes, planes - cur_.pushed);
+            const int64_t bytes = np * R.plane_bytes;
+            const uint8_t *src = (const uint8_t *)J.image + cur_.pushed * R.plane_bytes;
+            const uint8_t *dst = src;
+            int64_t off = -1;
+            if (host_origin_) {
+                off = arena_.alloc(bytes);
+                if (off < 0) break;
+                dst = arena_.at(off);
+                hipEvent_t in = nullptr;
+                if ((rc = event(&in))) return rc;
+                ECC_HIP(hipMemcpyAsync((void *)dst, src, (size_t)bytes, hipMemcpyHostToDevice, h2d_));
+                ECC_HIP(hipEventRecord(in, h2d_));
+                ECC_HIP(hipStreamWaitEvent(os_, in, 0));
+                pool_.push_back(in);
+            }
+            if ((rc = ecc_stream_push_chunk(cur_.st, dst, np))) return rc;
+            Chunk ch{nullptr, off, bytes};
+            if ((rc = event(&ch.ev))) return rc;
+            ECC_HIP(hipEventRecord(ch.ev, os_));
+            cur_.chunks.push_back(ch);
+            cur_.pushed += np;
+        }
+        if (cur_.pushed == planes && !cur_.finishing) {
+            if ((rc = stream_finish_async(cur_.st, chi_dev_ + slot_off_[cur_.slot], status_dev_ + cur_.slot)))
+                return rc;
+            hipEvent_t k = nullptr;
+            if ((rc = event(&k))) return rc;
+            ECC_HIP(hipEventRecord(k, os_));
+            if ((rc = copy_out(k, cur_.slot, cur_.slot + 1, &cur_.cev))) return rc;
+            pool_.push_back(k);
+            cur_.finishing = true;
+        }
+        if (cur_.finishing) {
+            const hipError_t e = hipEventQuery(cur_.cev);
+            if (e == hipErrorNotReady) return ECC_OK;
+            if (e != hipSuccess) return hip_fail(e, "ecc_serve: streamed request");
+            latency_[cur_.r] = now() - arrival_[cur_.r];
+            ++done_;
+            for (auto &ch : cur_.chunks) {  // done: recorded before the scan
+                if (ch.off >= 0) arena_.release(ch.off, ch.bytes);
+                pool_.push_back(ch.ev);
+            }
+            pool_.push_back(cur_.cev);
+            ecc_stream_abort(cur_.st);
+            cur_ = Streamed{};
+        }
+        return ECC_OK;
+    }
+
+    int poll_flights() {
+        for (auto &f : flights_) {  // arena blocks return as soon as a batch's kernels are done
+            if (f.released) continue;
+            const hipError_t e = hipEventQuery(f.kev);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) return hip_fail(e, "ecc_serve: kernels");
+            for (auto &h : f.held) arena_.release(h.first, h.second);
+            f.released = true;
+        }
+        while (!flights_.empty()) {
+            Flight &f = flights_.front();
+            const hipError_t e = hipEventQuery(f.cev);
+            if (e == hipErrorNotReady) break;
+            if (e != hipSuccess) return hip_fail(e, "ecc_serve: completion");
+            if (!f.released) {  // (the copy waited for the kernels)
+                for (auto &h : f.held) arena_.release(h.first, h.second);
+            }
+            const double tc = now();
+            for (int s = f.s0; s < f.s1; ++s) latency_[slot_req_[s]] = tc - arrival_[slot_req_[s]];
+            done_ += f.s1 - f.s0;
+            pool_.push_back(f.kev);
+            pool_.push_back(f.cev);
+            flights_.pop_front();
+        }
+        return ECC_OK;
+    }
+
+    ecc_batch *b_;
+    int n_;
+    const ecc_job *jobs_ = nullptr;
+    const std::vector<Req> *req_ = nullptr;
+    const double *arrival_ = nullptr;
+    double *latency_ = nullptr;
+    int32_t *batch_id_ = nullptr;
+    bool host_origin_ = false;
+    std::chrono::steady_clock::time_point t0_;
+    int64_t *chi_dev_ = nullptr, *chi_pin_ = nullptr;
+    uint32_t *status_dev_ = nullptr;
+    void *arena_buf_ = nullptr;
+    Arena arena_;
+    hipStream_t h2d_ = nullptr, d2h_ = nullptr, os_ = nullptr;
+    std::vector<int> slot_req_;
+    std::vector<int64_t> slot_off_;
+    std::vector<ecc_job> js_;
+    int nslots_ = 0, groups_ = 0, done_ = 0;
+    std::deque<int> bq_, sq_;
+    std::deque<Flight> flights_;
+    Streamed cur_;
+    std::vector<hipEvent_t> pool_;
+};
 
 }  // namespace
 
@@ -466,145 +870,71 @@ int ecc_job_footprint(const ecc_job *job, int64_t *bytes) {
 int ecc_serve_simulate(ecc_batch *b, int32_t n, const ecc_job *jobs, const double *arrival_s, int32_t max_batch,
                        int64_t max_batch_bytes, int32_t one_launch_per_image, int64_t *chi_host, double *latency_s,
                        int32_t *batch_id) {
+    ecc_serve_config c{};
+    c.max_batch = max_batch;
+    c.one_launch_per_image = one_launch_per_image;
+    c.max_batch_bytes = max_batch_bytes;
+    return ecc_serve(b, n, jobs, arrival_s, &c, chi_host, latency_s, batch_id, nullptr);
+}
+
+int ecc_serve(ecc_batch *b, int32_t n, const ecc_job *jobs, const double *arrival_s, const ecc_serve_config *cfg,
+              int64_t *chi_host, double *latency_s, int32_t *batch_id, int32_t *status) {
     g_err_clear();
-    if (!b || n < 1 || !jobs || !arrival_s || !chi_host || !latency_s || max_batch < 1 || max_batch_bytes < 0) {
-        set_error("ecc_serve_simulate: bad argument");
+    if (!b || n < 1 || !jobs || !arrival_s || !cfg || !chi_host || !latency_s || cfg->max_batch < 1 ||
+        cfg->max_batch_bytes < 0 || cfg->arena_bytes < 0 || cfg->stream_above_bytes < 0 || cfg->chunk_bytes < 0 ||
+        cfg->max_inflight < 0) {
+        set_error("ecc_serve: bad argument");
         return ECC_E_ARG;
-    }
-    std::vector<int64_t> foot(n, 0);
-    for (int i = 0; i < n && max_batch_bytes > 0; ++i) {
-        const int rc = ecc_job_footprint(&jobs[i], &foot[i]);
-        if (rc) return rc;
     }
     for (int i = 1; i < n; ++i)
         if (arrival_s[i] < arrival_s[i - 1]) {
-            set_error("ecc_serve_simulate: arrivals must be sorted");
+            set_error("ecc_serve: arrivals must be sorted");
             return ECC_E_ARG;
         }
-    // every request writes its curve to a device staging area laid out in
-    // request order, so a batch's curves go to the host in one copy
-    std::vector<int64_t> off(n + 1, 0);
+    const bool host_origin = cfg->arena_bytes > 0;
+    const bool single = cfg->one_launch_per_image != 0;
+    const int64_t stream_above =
+        cfg->stream_above_bytes > 0 ? cfg->stream_above_bytes : (host_origin ? cfg->arena_bytes / 4 : 0);
+    if (host_origin && stream_above > cfg->arena_bytes / 2) {
+        set_error("ecc_serve: stream_above_bytes must be at most half of arena_bytes");
+        return ECC_E_ARG;
+    }
+    const int64_t chunk_target = cfg->chunk_bytes > 0 ? cfg->chunk_bytes : ((int64_t)64 << 20);
+    std::vector<Req> req(n);
     for (int i = 0; i < n; ++i) {
+        int64_t total = 0;
+        int rc = check_dims(&jobs[i].dims, &total);
+        if (rc) return rc;
         const int64_t m = threshold_count(jobs[i].dtype);
-        if (m < 0) {
-            set_error("request %d: bad dtype", i);
-            return ECC_E_ARG;
+        if (!jobs[i].image || (jobs[i].dtype != ECC_U8 && jobs[i].dtype != ECC_U14)) {
+            set_error("request %d: NULL image, or a dtype other than U8/U14", i);
+            return jobs[i].image ? ECC_E_UNSUPPORTED : ECC_E_ARG;
         }
-        off[i + 1] = off[i] + m;
+        Req &R = req[i];
+        R.m = (int)m;
+        R.bytes = total * (int64_t)elem_bytes(jobs[i].dtype);
+        R.streamed = stream_above > 0 && R.bytes > stream_above;
+        if (!R.streamed && (rc = ecc_job_footprint(&jobs[i], &R.foot))) return rc;
+        if (R.streamed) {
+            const int64_t planes = jobs[i].dims.n[0];
+            R.plane_bytes = R.bytes / planes;
+            if (host_origin && R.plane_bytes > cfg->arena_bytes / 4) {
+                set_error("request %d: one axis-0 plane (%lld bytes) exceeds a quarter of the arena", i,
+                          (long long)R.plane_bytes);
+                return ECC_E_UNSUPPORTED;
+            }
+            const int64_t cap = host_origin ? cfg->arena_bytes / 4 : chunk_target;
+            R.chunk_planes = std::max<int64_t>(1, std::min(chunk_target, cap) / R.plane_bytes);
+        }
     }
     int prev = -1;
     ECC_HIP(hipGetDevice(&prev));
     if (prev != b->device) ECC_HIP(hipSetDevice(b->device));
-    // curves land in pinned host memory (a copy into pageable memory would
-    // block the host thread until the stream drains) and are copied to
-    // chi_host at the end
-    int64_t *chi_dev = nullptr, *chi_pin = nullptr;
-    hipError_t e = hipMalloc(&chi_dev, (size_t)off[n] * 8);
-    if (e == hipSuccess) e = hipHostMalloc(&chi_pin, (size_t)off[n] * 8, hipHostMallocDefault);
-    if (e != hipSuccess) {
-        if (chi_dev) (void)hipFree(chi_dev);
-        if (prev != b->device) (void)hipSetDevice(prev);
-        return hip_fail(e, "ecc_serve_simulate: curve staging");
-    }
-    std::vector<ecc_job> js(jobs, jobs + n);
-    for (int i = 0; i < n; ++i) js[i].chi = chi_dev + off[i];
-    // The curves go to the host on a second stream (default priority), each
-    // copy ordered after its launch by an event, so the copy of one batch
-    // overlaps the kernels of the next.
-    hipStream_t cs = nullptr;
-    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        (void)hipHostFree(chi_pin);
-        (void)hipFree(chi_dev);
-        if (prev != b->device) (void)hipSetDevice(prev);
-        return hip_fail(e, "ecc_serve_simulate: copy stream");
-    }
-    struct Flight {
-        hipEvent_t ev, kev;  // copy done, kernels done
-        int first, last;
-    };
-    std::deque<Flight> flight;
-    std::vector<hipEvent_t> pool;
-    int rc = ECC_OK;
-    const int max_inflight = one_launch_per_image ? (1 << 30) : 3;
-    auto take_event = [&](hipEvent_t *ev) -> hipError_t {
-        if (!pool.empty()) {
-            *ev = pool.back();
-            pool.pop_back();
-            return hipSuccess;
-        }
-        return hipEventCreateWithFlags(ev, hipEventDisableTiming);
-    };
-    const auto t0 = std::chrono::steady_clock::now();
-    auto now = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
-    int next = 0, arrived = 0, done = 0, batches = 0;
-    while (done < n && !rc) {
-        const double t = now();
-        while (arrived < n && arrival_s[arrived] <= t) ++arrived;
-        while (next < arrived && (int)flight.size() < max_inflight && !rc) {
-            // admission: in arrival order, up to max_batch requests and
-            // max_batch_bytes of footprint (the first request always fits)
-            int k = 1;
-            if (!one_launch_per_image) {
-                int64_t bytes = foot[next];
-                while (next + k < arrived && k < max_batch &&
-                       (max_batch_bytes == 0 || bytes + foot[next + k] <= max_batch_bytes))
-                    bytes += foot[next + k++];
-            }
-            if (batch_id)
-                for (int i = next; i < next + k; ++i) batch_id[i] = batches;
-            ++batches;
-            if (one_launch_per_image) {
-                rc = ecc_compute_async(js[next].image, &js[next].dims, (ecc_dtype)js[next].dtype, js[next].chi,
-                                       nullptr, b->stream);
-            } else {
-                rc = ecc_batch_run(b, k, js.data() + next, nullptr);
-            }
-            if (rc) break;
-            hipEvent_t ev = nullptr, kev = nullptr;
-            e = take_event(&kev);
-            if (e == hipSuccess) e = take_event(&ev);
-            if (e == hipSuccess) e = hipEventRecord(kev, b->stream);
-            if (e == hipSuccess) e = hipStreamWaitEvent(cs, kev, 0);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(chi_pin + off[next], chi_dev + off[next],
-                                   (size_t)(off[next + k] - off[next]) * 8, hipMemcpyDeviceToHost, cs);
-            if (e == hipSuccess) e = hipEventRecord(ev, cs);
-            if (e != hipSuccess) {
-                if (kev) pool.push_back(kev);
-                if (ev) pool.push_back(ev);
-                rc = hip_fail(e, "ecc_serve_simulate: launch");
-                break;
-            }
-            flight.push_back({ev, kev, next, next + k});
-            next += k;
-        }
-        while (!flight.empty() && !rc) {
-            e = hipEventQuery(flight.front().ev);
-            if (e == hipErrorNotReady) break;
-            if (e != hipSuccess) {
-                rc = hip_fail(e, "ecc_serve_simulate: completion");
-                break;
-            }
-            const double tc = now();
-            for (int i = flight.front().first; i < flight.front().last; ++i) latency_s[i] = tc - arrival_s[i];
-            done += flight.front().last - flight.front().first;
-            pool.push_back(flight.front().ev);
-            pool.push_back(flight.front().kev);
-            flight.pop_front();
-        }
-    }
-    (void)hipStreamSynchronize(b->stream);
-    (void)hipStreamSynchronize(cs);
-    for (auto &f : flight) {
-        (void)hipEventDestroy(f.ev);
-        (void)hipEventDestroy(f.kev);
-    }
-    for (auto ev : pool) (void)hipEventDestroy(ev);
-    (void)hipStreamDestroy(cs);
-    if (!rc) memcpy(chi_host, chi_pin, (size_t)off[n] * 8);
-    (void)hipHostFree(chi_pin);
-    (void)hipFree(chi_dev);
+    Serve S(b, n);
+    int rc = S.setup(req, host_origin ? cfg->arena_bytes : 0);
+    if (!rc) rc = S.run(jobs, req, arrival_s, *cfg, single, host_origin, latency_s, batch_id);
+    if (!rc) rc = S.collect(req, chi_host, status);
+    S.teardown();
     if (prev != b->device) (void)hipSetDevice(prev);
     return rc;
 }

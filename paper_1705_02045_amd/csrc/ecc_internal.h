@@ -223,6 +223,10 @@ int launch_expand_steps(const float *keys, const int64_t *chi, int64_t K, int m,
 int launch_quantize(const float *img, int64_t n, float lo, float scale, int m, int elem, void *out,
                     uint32_t *status, hipStream_t stream);
 
+// Streaming internals for the serving loop (ecc_stream.cpp).
+int stream_finish_async(ecc_stream *st, int64_t *chi_dev, uint32_t *status_dev);
+int64_t stream_plane_bytes(const ecc_stream *st);
+
 // Optional event timing of the per-voxel kernels (ecc_profile.cpp).
 int profile_begin(hipStream_t s, void **token);
 int profile_end(hipStream_t s, void *token);

@@ -347,3 +347,27 @@ int ecc_stream_finish(ecc_stream *st, ecc_curve *curve) {
 void ecc_stream_abort(ecc_stream *st) { destroy(st); }
 
 }  // extern "C"
+
+namespace ecc {
+
+// The end of ecc_stream_finish without waiting (the serving loop): after
+// the last plane was pushed, the prefix sum of the changes vector is
+// enqueued on the handle's stream into chi_dev (device memory, m entries,
+// written only if no range error was seen) and the status word is copied to
+// status_dev.  The handle stays valid until ecc_stream_abort.
+int stream_finish_async(ecc_stream *st, int64_t *chi_dev, uint32_t *status_dev) {
+    if (!st || !chi_dev) {
+        set_error("stream_finish_async: NULL argument");
+        return ECC_E_ARG;
+    }
+    if (st->pushed != st->view.n0) {
+        set_error("stream_finish_async: %lld of %lld planes pushed", (long long)st->pushed, (long long)st->view.n0);
+        return ECC_E_STATE;
+    }
+    return launch_merge(nullptr, 0, st->m, nullptr, st->vcec, true, true, chi_dev, st->status, status_dev,
+                        st->compute);
+}
+
+int64_t stream_plane_bytes(const ecc_stream *st) { return st->plane_bytes; }
+
+}  // namespace ecc

@@ -66,10 +66,18 @@ def test_device_generator_library_exports():
 
 @pytest.mark.parametrize("shape,lshift,bits,amp,z0,z1", [
     ((9, 20, 35), 4, 14, 64, 0, 9), ((37, 1, 300), 4, 14, 64, 3, 30), ((3, 17, 2), 2, 8, 1, 1, 3),
+    ((700, 1, 2049), 4, 8, 1, 0, 700), ((65, 1, 33), 3, 16, 256, 10, 60),
     ((20, 33, 17), 3, 16, 256, 5, 19), ((2, 70, 1), 4, 14, 64, 0, 2), ((5, 5, 129), 5, 12, 7, 2, 5)], ids=str)
 def test_value_noise_rows_match_voxelwise(shape, lshift, bits, amp, z0, z1):
-    """The 3-D row form of the generator writes the per-voxel form's bytes."""
+    """The 3-D and 2-D row forms of the generator write the per-voxel form's bytes."""
     dtype = np.uint8 if bits <= 8 else np.uint16
+    if shape[1] == 1:  # also as a 2-D image
+        s2 = (shape[0], shape[2])
+        f2 = gen.value_noise(s2, bits, amp, 12, lshift=lshift, z0=z0, z1=z1)
+        g2 = np.empty_like(f2)
+        assert gen.lib().eccgen_value_noise_voxelwise(12, 2, gen._dims(s2), lshift, bits, amp, z0, z1, g2.ctypes.data,
+                                                      np.dtype(dtype).itemsize, 2) == 0
+        assert (f2 == g2).all()
     fast = gen.value_noise(shape, bits, amp, 11, lshift=lshift, z0=z0, z1=z1)
     slow = np.empty_like(fast)
     rc = gen.lib().eccgen_value_noise_voxelwise(11, 3, gen._dims(shape), lshift, bits, amp, z0, z1,
