@@ -96,28 +96,26 @@ __device__ __forceinline__ uint32_t min_off(uint32_t a, uint32_t b) { return a <
 // each lane loads the aligned dword that holds the value at its column x,
 // i.e. the values at x & ~1 and (x & ~1) + 1.  The waves start at odd
 // columns, so the left neighbour x-1 is either the low half of the lane's own
-// dword (x odd) or the high half of the dword of the lane before it (x even),
-// which a wave shift moves over; no lane needs another wave's values.  The
-// pair (value at x-1) | (value at x) << 16 is then one byte permute: selector
-// kSelOdd keeps the own dword, kSelEven takes the previous lane's high half
-// and the own low half.  Every image load stays 4-byte aligned.
-constexpr uint32_t kSelOdd = 0x07060504u;
-constexpr uint32_t kSelEven = 0x05040302u;
-constexpr int kDppWaveShr1 = 0x138;  // lane i reads lane i-1 (lane 0 reads 0)
+// dword (x odd) or the value of the lane before it (x even).  Both values of
+// the dword are scaled to byte offsets with one packed shift; the lane's own
+// offset is one bit-field extract (shift 16 for odd x, 0 for even x); one
+// wave shift moves every lane's own offset to the next lane, and lane 0,
+// which has no lane before it (and an odd column), keeps its own scaled
+// dword instead, whose low half is the offset of x-1.  The window field is
+// then one packed minimum of that and the own offset, whose high half is
+// min(.., 0) = 0.  No lane needs another wave's values, and every image load
+// stays 4-byte aligned.
+constexpr int kDppWaveShr1 = 0x138;  // lane i reads lane i-1 (lane 0 has no source)
 
-// Lane 0 of a wave has an odd column, so its selector ignores `prev`.
-__device__ __forceinline__ uint32_t row_pair(uint32_t d, uint32_t sel) {
-    const uint32_t prev = (uint32_t)__builtin_amdgcn_mov_dpp((int)d, kDppWaveShr1, 0xF, 0xF, true);
-    return __builtin_amdgcn_perm(d, prev, sel);
-}
-// From a pair q (already transformed): q4 = q * 4 per half, f0 = q4 >> 16
-// (the offset of x), fx = low half of min(q4, f0) (the window {x-1, x}); its
-// high half is min(q4.hi, 0) = 0, so fx is zero-extended.
-__device__ __forceinline__ void pair_offsets(uint32_t q, uint32_t &f0, uint32_t &fx) {
-    uint32_t q4, m;
-    asm(ECC_PK_SHL2 : "=v"(q4) : "v"(q));
-    f0 = q4 >> 16;
-    asm("v_pk_min_u16 %0, %1, %2" : "=v"(m) : "v"(q4), "v"(f0));
+// d: the loaded dword (already transformed); sh: 16 for odd x, 0 for even x.
+// f0 = 4 * value at x, fx = 4 * min(value at x-1, value at x).
+__device__ __forceinline__ void pair_offsets(uint32_t d, uint32_t sh, uint32_t &f0, uint32_t &fx) {
+    uint32_t d4, m;
+    asm(ECC_PK_SHL2 : "=v"(d4) : "v"(d));
+    f0 = __builtin_amdgcn_ubfe(d4, sh, 16);
+    // lanes 1..63: the previous lane's f0; lane 0 (bound_ctrl off): d4 itself
+    const uint32_t pv = (uint32_t)__builtin_amdgcn_update_dpp((int)d4, (int)f0, kDppWaveShr1, 0xF, 0xF, false);
+    asm("v_pk_min_u16 %0, %1, %2" : "=v"(m) : "v"(pv), "v"(f0));
     fx = m;
 }
 // clamp(v - s, 0, 16383) on both halves; s2 = s | s << 16 (0 <= s < 65536)
@@ -243,15 +241,15 @@ struct Walker {
     }
 
     // The same fields (NIN == 2) from the loaded dwords d[rr] of the row-pair
-    // layout; sel: the lane's byte selector; xfp: the value transform applied
-    // to both halves of a pair.
+    // layout; sh: the lane's half (16 for odd x, 0 for even x); xfp: the
+    // value transform applied to both halves of a dword.
     template <typename X>
-    static __device__ __forceinline__ void fields_pair(const uint32_t (&d)[NR], uint32_t sel, uint32_t (&g)[NI],
+    static __device__ __forceinline__ void fields_pair(const uint32_t (&d)[NR], uint32_t sh, uint32_t (&g)[NI],
                                                        X xfp) {
         static_assert(NIN == 2, "row pairs: two in-plane axes");
         uint32_t f0[NR], fx[NR];
 #pragma unroll
-        for (int rr = 0; rr < NR; ++rr) pair_offsets(xfp(row_pair(d[rr], sel)), f0[rr], fx[rr]);
+        for (int rr = 0; rr < NR; ++rr) pair_offsets(xfp(d[rr]), sh, f0[rr], fx[rr]);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             g[4 * r + 0] = f0[r + 1];
@@ -313,8 +311,9 @@ constexpr int lcm(int a, int b) {
 
 // One wave walks the planes [zs, ze) of its rows.  FULL: no position of this
 // wave lies on a far edge, so the comparison masks need no validity mask.
-// PAIR (FULL waves of the row-pair layout): one dword load per row at byte
-// offset vx[rr], and psel, the lane's pair selector; vxl is unused.
+// PAIR (FULL waves of the row-pair layout): one aligned dword load per row at
+// byte offset vx[rr], and psel, the lane's half of it (16 for odd x, 0 for
+// even x); vxl is unused.
 // PD: planes of raw loads kept in flight ahead of the plane being compared.
 // The plane loop is unrolled by lcm(2, PD+1) so that every register buffer is
 // addressed with a compile-time index (plane p of the tile uses raw buffer
@@ -551,7 +550,7 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
         const int32_t y0 = (ty * P.wy + wyi) * R;
         any = wave_in && x0 < n2 && y0 < n1;
         full = (x0 + kWave - 1 <= n2 - 2) && (y0 + R - 1 <= n1 - 2);
-        psel = (x & 1) ? kSelOdd : kSelEven;
+        psel = (x & 1) ? 16u : 0u;
         const int32_t xcl = min(x, n2 - 1);
         const uint32_t ox = (uint32_t)xcl * ESZ, oxl = (uint32_t)(xcl > 0 ? xcl - 1 : 0) * ESZ;
 #pragma unroll

@@ -17,7 +17,8 @@ histogram adds trapped on them.  The compiler's own splat shift carries
 op_sel_hi:[0,1].  Checked here: every packed op with an inline constant
 reads that constant's low half in both lanes.  Dword image loads exist only
 in the row-pair path, whose offsets are 4-byte aligned by construction
-(test_row_pair_map.py); it is recognisable by its wave shift and byte permute.
+(test_row_pair_map.py); it is recognisable by its wave shift and bit-field
+extract.
 """
 import pathlib
 import re
@@ -109,7 +110,7 @@ def functions(asm):
 
 def test_dword_image_loads_only_in_row_pair_path(asm):
     """Image loads are 8- or 16-bit, except in functions that carry the
-    row-pair form (a wave shift by one lane and a byte permute)."""
+    row-pair form (a wave shift by one lane and a bit-field extract)."""
     seen = 0
     for name, body in functions(asm):
         loads = {l.strip().split()[0] for l in body if re.match(r"\s*buffer_load_", l)}
@@ -118,7 +119,7 @@ def test_dword_image_loads_only_in_row_pair_path(asm):
             continue
         assert wide == {"buffer_load_dword"}, (name, sorted(wide))
         text = "\n".join(body)
-        assert "wave_shr:1" in text and "v_perm_b32" in text, name
+        assert "wave_shr:1" in text and "v_bfe_u32" in text, name
         assert "int_vcec" in name, name
         seen += 1
     assert seen > 0, "row-pair path not found"

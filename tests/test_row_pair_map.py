@@ -1,17 +1,17 @@
 """The row-pair layout of the integer kernel, checked on the host.
 
 Interior waves of 16-bit images with an even row length read each row as
-aligned dwords (tile_body / row_pair in ecc_int.hip): wave k of a row starts at
+aligned dwords (tile_body / pair_offsets in ecc_int.hip): wave k of a row starts at
 column 64 k + 1, lane l has column x0 + l, and the lane of column n2 (in the
 last wave, an edge wave) takes column 0.  An interior ("full") wave, with
 x0 + 63 <= n2 - 2, loads the dword at column x & ~1; for odd x that dword is
-the pair (x-1, x), for even x the pair is the previous lane's high half and
-the own low half.  This restates those formulas and checks, for many row
+the pair (x-1, x), for even x the value at x-1 is the previous lane's own
+value (its column is x-1).  This restates those formulas and checks, for many row
 lengths and waves per workgroup:
   - every column [0, n2) is owned by exactly one lane;
   - every dword load of a full wave is 4-byte aligned and inside its row;
   - lane 0 of a full wave has an odd column (it never needs the lane before);
-  - an even column's left neighbour lies in the previous lane's dword.
+  - an even column's left neighbour is the previous lane's column.
 """
 import pytest
 
@@ -45,7 +45,7 @@ def test_row_pair_map(wx_cap):
                 if lane == 0:
                     assert x % 2 == 1
                 if x % 2 == 0:
-                    assert lane >= 1 and ((x - 1) & ~1) + 1 == x - 1
+                    assert lane >= 1 and x0 + lane - 1 == x - 1
                 else:
                     assert col == x - 1
             if x < n2:
