@@ -8,9 +8,11 @@ i.e. every kernel of the path: change-vector kernel, merge, prefix sum.
 
 Prints ONE JSON line: GVoxel/s over the timed steps, the roofline of the
 dominant kernel (HBM bytes it must read / its measured average duration, HIP
-events on its launch stream) and the CPU oracle timed on a bounded sample of
-the same volume on this host.  Under "legs": the other workloads of the path
-(serving mix at a p99 latency bound, 4-D float32, host-staged streaming of
+events on its launch stream) and the CPU oracle on this host: the whole
+volume on the process's CPU share (its curve must equal the GPU's) and a
+sample of planes on one thread.  Under "legs": the other workloads of the path
+(serving mix at a p99 latency bound, device-resident and from pinned host
+memory, 4-D float32, host-staged streaming of
 8192^2 x 1024 against the measured host-to-device copy rate, the
 2600 x 14450^2 volume made and streamed slab by slab on the device, the
 largest-value and dual constructions on the headline volume, 1024^3 16-bit
@@ -63,51 +65,79 @@ def measured_traffic(voxels: int, tiling):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(img, target_s: float):
-    """The oracle on the first planes of the volume, sized to about target_s seconds."""
+def cpu_model() -> str:
+    try:
+        for line in pathlib.Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_share() -> int:
+    """Threads the oracle may use here: the process's CPU share (OMP_NUM_THREADS
+    when the environment sets it, e.g. 16 per GPU on a shared box), else every
+    core the host reports."""
+    n = os.cpu_count() or 1
+    share = os.environ.get("OMP_NUM_THREADS")
+    if share and share.isdigit() and int(share) > 0:
+        n = min(n, int(share))
+    return n
+
+
+def cpu_baseline(img, gpu_chi, target_s: float):
+    """The oracle, as it stands, on this host: the whole volume on the
+    process's CPU share (its curve must equal the GPU's), then a sample of
+    planes on one thread sized to about target_s seconds."""
+    import numpy as np
     import oracle
-    threads = oracle.default_threads()
+    threads = cpu_share()
     n0, n1, n2 = img.shape
-    probe = max(1, min(n0, 8))
-    oracle.curve(img[:probe], m=16384, nthreads=threads)  # untimed: threads and pages warm up
     t = time.perf_counter()
-    oracle.curve(img[:probe], m=16384, nthreads=threads)
-    dt = time.perf_counter() - t
-    rate = probe * n1 * n2 / max(dt, 1e-6)
-    planes = int(min(n0, max(probe, target_s * rate / (n1 * n2))))
-    # when the whole volume takes well under the budget, time it more than once
-    reps = 0
+    ref = oracle.curve(img, m=16384, nthreads=threads)
+    dt_all = time.perf_counter() - t
+    parity = bool(np.array_equal(ref, gpu_chi))
+    probe = max(1, min(n0, 2))
     t = time.perf_counter()
-    while True:
-        oracle.curve(img[:planes], m=16384, nthreads=threads)
-        reps += 1
-        dt = time.perf_counter() - t
-        if planes < n0 or reps >= 4 or dt * (reps + 1) / reps > 1.3 * target_s:
-            break
-    vox = planes * n1 * n2 * reps
-    what = f"planes 0..{planes - 1} of the {n0}x{n1}x{n2} volume" + (f", {reps} times" if reps > 1 else "")
-    return {"value": round(vox / dt / 1e9, 6), "unit": "GVoxel/s", "cores": threads, "kind": "oracle",
-            "sample": f"{what} ({vox} voxels, {dt:.1f} s)"}
+    oracle.curve(img[:probe], m=16384, nthreads=1)
+    rate1 = probe * n1 * n2 / max(time.perf_counter() - t, 1e-6)
+    planes = int(min(n0, max(probe, target_s * rate1 / (n1 * n2))))
+    t = time.perf_counter()
+    oracle.curve(img[:planes], m=16384, nthreads=1)
+    dt1 = time.perf_counter() - t
+    vox = n0 * n1 * n2
+    return {"value": round(vox / dt_all / 1e9, 6), "unit": "GVoxel/s", "cores": threads, "kind": "oracle",
+            "sample": f"the whole {n0}x{n1}x{n2} volume ({vox} voxels, {dt_all:.1f} s) on {threads} threads",
+            "host_cores": os.cpu_count(), "threads": threads, "model": cpu_model(),
+            "one_core": {"value": round(planes * n1 * n2 / dt1 / 1e9, 6), "unit": "GVoxel/s",
+                         "sample": f"planes 0..{planes - 1} ({planes * n1 * n2} voxels, {dt1:.1f} s) on 1 thread"},
+            "parity": parity}
 
 
-def leg_serving(n_req: int, slo_ms: float, budget_bytes: int):
+def leg_serving(n_req: int, slo_ms: float, budget_bytes: int, arena_bytes: int):
     """Serving mix (50/50 2-D uint8 sides 32..2048 / 3-D 14-bit sides 16..256,
     value noise, seeded): highest Poisson arrival rate whose p99 latency
     (arrival -> curve in host memory) stays within slo_ms, for continuous
     batching (at most 256 requests and budget_bytes of device footprint per
     batch; one persistent launch per batch, replayed as a graph) and for one
-    launch per image."""
+    launch per image.  Once with the request images already in HBM
+    ("device_resident"), once with every image starting in pinned host memory
+    ("host_origin": admission reserves an arena block of arena_bytes for the
+    image and copies it in; the latency includes that copy)."""
     import numpy as np
     import torch
     import gen
     import paper_1705_02045_amd as ecc
     reqs = gen.serving_requests(n_req, seed=4)
-    imgs = []
+    host = []
     for r in reqs:
         a = gen.serving_image(*r)
-        imgs.append(torch.from_numpy(a.view(np.int16) if a.dtype == np.uint16 else a).cuda())
+        host.append(torch.from_numpy(a.view(np.int16) if a.dtype == np.uint16 else a))
+    imgs = [t.cuda() for t in host]
     dtypes = [r[0] for r in reqs]
     vox = sum(int(np.prod(r[1])) for r in reqs)
+    img_bytes = sum(int(t.numel() * t.element_size()) for t in host)
     b = ecc.Batch()
     # untimed: the batch tile depth tuned on the first 256 requests, then
     # replays of the whole set so that scratch buffers reach their final size
@@ -115,39 +145,52 @@ def leg_serving(n_req: int, slo_ms: float, budget_bytes: int):
     chis = [torch.empty(ecc.THRESHOLDS[d], dtype=torch.int64, device="cuda") for d in dtypes[:k]]
     depth = b.autotune(imgs[:k], dtypes[:k], chis)
     del chis
-    b.serve(imgs, dtypes, np.zeros(n_req), max_batch=256, max_batch_bytes=budget_bytes)
-    b.serve(imgs, dtypes, np.zeros(n_req), max_batch=1, one_launch_per_image=True)
+    b.serve_config(imgs, dtypes, np.zeros(n_req), max_batch=256, max_batch_bytes=budget_bytes)
+    b.serve_config(imgs, dtypes, np.zeros(n_req), max_batch=1, one_launch_per_image=True)
     rng = np.random.default_rng(4)
-    sizes = []
 
-    def run(arr, single):
-        lat, _, bid = b.serve(imgs, dtypes, arr, max_batch=256, one_launch_per_image=single,
-                              max_batch_bytes=budget_bytes, with_batches=True)
-        if not single:
+    def sweep(images, single, extra):
+        sizes = []
+
+        def run(arr):
+            lat, _, bid, st, _ = b.serve_config(images, dtypes, arr, max_batch=256, one_launch_per_image=single,
+                                                max_batch_bytes=budget_bytes, **extra)
+            assert (st == 0).all()
             sizes.append(n_req / (int(bid.max()) + 1))
-        return float(np.percentile(lat, 99)) * 1e3, float(np.percentile(lat, 50)) * 1e3, float(np.max(arr + lat))
+            return float(np.percentile(lat, 99)) * 1e3, float(np.percentile(lat, 50)) * 1e3, float(np.max(arr + lat))
 
-    out = {}
-    for name, single in (("batched", False), ("one_launch_per_image", True)):
-        _, _, span = run(np.zeros(n_req), single)
+        _, _, span = run(np.zeros(n_req))
         sat = n_req / span
         best = None
         for f in (0.3, 0.5, 0.7, 0.8, 0.9, 0.95):
             lam = f * sat
             arr = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
             arr -= arr[0]
-            p99, p50, _ = run(arr, single)
+            p99, p50, _ = run(arr)
             if p99 <= slo_ms:
                 best = {"rate_img_per_s": round(lam, 1), "p50_ms": round(p50, 3), "p99_ms": round(p99, 3)}
-        out[name] = {"saturation_img_per_s": round(sat, 1), "saturation_gvoxel_per_s": round(vox / span / 1e9, 2),
-                     "at_slo": best}
+        return {"saturation_img_per_s": round(sat, 1), "saturation_gvoxel_per_s": round(vox / span / 1e9, 2),
+                "at_slo": best, "mean_batch_size": round(float(np.mean(sizes)), 2)}
+
+    def ratio(d):
+        rb = (d["batched"]["at_slo"] or {}).get("rate_img_per_s")
+        rs = (d["one_launch_per_image"]["at_slo"] or {}).get("rate_img_per_s")
+        return round(rb / rs, 2) if rb and rs else None
+
+    out = {"requests": n_req, "voxels": vox, "image_bytes": img_bytes, "slo_p99_ms": slo_ms,
+           "batch_budget_bytes": budget_bytes, "batch_tile_depth": {"min_planes": depth[0], "split": depth[1]}}
+    dev = {name: sweep(imgs, single, {}) for name, single in (("batched", False), ("one_launch_per_image", True))}
+    dev["speedup_at_slo"] = ratio(dev)
+    out["device_resident"] = dev
+    del imgs
+    pinned = [t.pin_memory() for t in host]
+    del host
+    ho = {name: sweep(pinned, single, {"arena_bytes": arena_bytes})
+          for name, single in (("batched", False), ("one_launch_per_image", True))}
+    ho["speedup_at_slo"] = ratio(ho)
+    ho["arena_bytes"] = arena_bytes
+    out["host_origin"] = ho
     b.close()
-    rb = (out["batched"]["at_slo"] or {}).get("rate_img_per_s")
-    rs = (out["one_launch_per_image"]["at_slo"] or {}).get("rate_img_per_s")
-    out.update({"requests": n_req, "voxels": vox, "slo_p99_ms": slo_ms, "batch_budget_bytes": budget_bytes,
-                "batch_tile_depth": {"min_planes": depth[0], "split": depth[1]},
-                "mean_batch_size": round(float(np.mean(sizes)), 2) if sizes else None,
-                "speedup_at_slo": round(rb / rs, 2) if rb and rs else None})
     return out
 
 
@@ -383,12 +426,14 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, default=1024, help="edge of the cubic volume")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget; 0 skips it")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="one-thread oracle sample budget (the whole volume also runs on the CPU share); 0 skips both")
     ap.add_argument("--legs", default="serving,float,stream_host,stream_device,conventions,u16,small_2d",
                     help="further workloads reported under 'legs' (comma list, or 'none')")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-slo-ms", type=float, default=10.0)
     ap.add_argument("--serve-budget-gib", type=int, default=8, help="device footprint admitted per batch")
+    ap.add_argument("--serve-arena-gib", type=int, default=4, help="device arena for host-origin request images")
     ap.add_argument("--no-autotune", action="store_true", help="keep the launch-size tiling rule")
     ap.add_argument("--calibrate", action="store_true",
                     help="after the steps, run one elementwise kernel that reads and writes the volume's bytes "
@@ -464,14 +509,16 @@ def main():
     cpu = None
     if args.cpu_seconds > 0:
         log("[bench] CPU oracle baseline ...")
-        cpu = cpu_baseline(img, args.cpu_seconds)
+        cpu = cpu_baseline(img, chi.cpu().numpy(), args.cpu_seconds)
+        assert cpu["parity"], "the GPU curve of the volume differs from the oracle's"
 
     legs = {}
     for leg in [x for x in args.legs.split(",") if x and x != "none"]:
         log(f"[bench] leg {leg} ...")
         t0 = time.perf_counter()
         if leg == "serving":
-            legs[leg] = leg_serving(args.serve_requests, args.serve_slo_ms, args.serve_budget_gib << 30)
+            legs[leg] = leg_serving(args.serve_requests, args.serve_slo_ms, args.serve_budget_gib << 30,
+                                    args.serve_arena_gib << 30)
         elif leg == "float":
             legs[leg] = leg_float(5)
         elif leg == "stream_host":
