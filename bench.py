@@ -434,6 +434,8 @@ def main():
     ap.add_argument("--serve-slo-ms", type=float, default=10.0)
     ap.add_argument("--serve-budget-gib", type=int, default=8, help="device footprint admitted per batch")
     ap.add_argument("--serve-arena-gib", type=int, default=4, help="device arena for host-origin request images")
+    ap.add_argument("--stream-host-planes", type=int, default=1024,
+                    help="planes of 8192^2 in the host-staged streaming leg (1024: 128 GiB)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the launch-size tiling rule")
     ap.add_argument("--calibrate", action="store_true",
                     help="after the steps, run one elementwise kernel that reads and writes the volume's bytes "
@@ -522,7 +524,7 @@ def main():
         elif leg == "float":
             legs[leg] = leg_float(5)
         elif leg == "stream_host":
-            legs[leg] = leg_stream_host(1024, 8192, 16, 4)
+            legs[leg] = leg_stream_host(args.stream_host_planes, 8192, 16, 4)
         elif leg == "stream_device":
             legs[leg] = leg_stream_device((2600, 14450, 14450), 64)
         elif leg == "u16":

@@ -4,6 +4,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <string>
 #include <tuple>
 #include <mutex>
 #include <utility>
@@ -56,6 +57,37 @@ int device_cu_count() {
     return cus;
 }
 
+// Allocation-failure injection (testing the error paths): with
+// ECC_FAIL_ALLOC=k set, the k-th and every later device or pinned-host
+// allocation the library attempts fails as out of memory; the count restarts
+// whenever the variable's value changes.
+static std::mutex g_fail_mu;
+static std::string g_fail_val;
+static int64_t g_fail_count = 0;
+
+static bool injected_failure() {
+    const char *v = getenv("ECC_FAIL_ALLOC");
+    std::lock_guard<std::mutex> lk(g_fail_mu);
+    const std::string cur = v ? v : "";
+    if (cur != g_fail_val) {
+        g_fail_val = cur;
+        g_fail_count = 0;
+    }
+    if (cur.empty()) return false;
+    const int64_t k = atoll(cur.c_str());
+    return k > 0 && ++g_fail_count >= k;
+}
+
+hipError_t dev_malloc(void **p, size_t bytes) {
+    if (injected_failure()) return hipErrorOutOfMemory;
+    return hipMalloc(p, bytes);
+}
+
+hipError_t host_malloc(void **p, size_t bytes, unsigned flags) {
+    if (injected_failure()) return hipErrorOutOfMemory;
+    return hipHostMalloc(p, bytes, flags);
+}
+
 int ensure_bytes(void **ptr, size_t *cap, size_t need) {
     if (*cap >= need && *ptr) return ECC_OK;
     if (*ptr) {
@@ -64,7 +96,7 @@ int ensure_bytes(void **ptr, size_t *cap, size_t need) {
         *cap = 0;
     }
     size_t sz = need < 256 ? 256 : need;
-    ECC_HIP(hipMalloc(ptr, sz));
+    ECC_HIP(dev_malloc((void **)ptr, sz));
     *cap = sz;
     return ECC_OK;
 }
@@ -90,14 +122,14 @@ int get_workspace(void *stream, Workspace **out) {
         w->device = dev;
         w->stream = stream;
         void *p = nullptr;
-        hipError_t e = hipMalloc(&p, kStatusBytes);
+        hipError_t e = dev_malloc((void **)&p, kStatusBytes);
         if (e != hipSuccess) {
             delete w;
             return hip_fail(e, "hipMalloc(status)");
         }
         w->status = (uint32_t *)p;
         void *hp = nullptr, *hd = nullptr;
-        e = hipHostMalloc(&hp, 64, hipHostMallocMapped | hipHostMallocCoherent);
+        e = host_malloc((void **)&hp, 64, hipHostMallocMapped | hipHostMallocCoherent);
         if (e == hipSuccess) e = hipHostGetDevicePointer(&hd, hp, 0);
         if (e != hipSuccess) {
             if (hp) (void)hipHostFree(hp);

@@ -225,10 +225,10 @@ class Serve {
         slot_req_.assign(n_, -1);
         slot_off_.assign(n_ + 1, 0);
         js_.assign(n_, ecc_job{});
-        hipError_t e = hipMalloc(&chi_dev_, (size_t)words * 8);
-        if (e == hipSuccess) e = hipHostMalloc(&chi_pin_, (size_t)words * 8, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipMalloc(&status_dev_, (size_t)n_ * 4);
-        if (e == hipSuccess && arena_bytes > 0) e = hipMalloc(&arena_buf_, (size_t)arena_bytes);
+        hipError_t e = dev_malloc((void **)&chi_dev_, (size_t)words * 8);
+        if (e == hipSuccess) e = host_malloc((void **)&chi_pin_, (size_t)words * 8, hipHostMallocDefault);
+        if (e == hipSuccess) e = dev_malloc((void **)&status_dev_, (size_t)n_ * 4);
+        if (e == hipSuccess && arena_bytes > 0) e = dev_malloc((void **)&arena_buf_, (size_t)arena_bytes);
         for (hipStream_t *s : {&h2d_, &d2h_, &os_})
             if (e == hipSuccess) e = hipStreamCreateWithFlags(s, hipStreamNonBlocking);
         if (e != hipSuccess) return hip_fail(e, "ecc_serve: set-up");
@@ -711,8 +711,8 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
             b->host[s] = b->dev[s] = nullptr;
             b->cap[s] = 0;
             const size_t want = std::max(total, (size_t)64 << 10);  // room for later, larger batches
-            hipError_t e = hipHostMalloc(&b->host[s], want, hipHostMallocDefault);
-            if (e == hipSuccess) e = hipMalloc(&b->dev[s], want);
+            hipError_t e = host_malloc((void **)&b->host[s], want, hipHostMallocDefault);
+            if (e == hipSuccess) e = dev_malloc((void **)&b->dev[s], want);
             if (e != hipSuccess) {
                 rc = hip_fail(e, "ecc_batch_run: table allocation");
                 break;

@@ -109,6 +109,11 @@ struct Workspace {
     int max_grid = 0;
 };
 
+// hipMalloc / hipHostMalloc through the allocation-failure injection hook
+// (ECC_FAIL_ALLOC, ecc_api.cpp); every allocation of the library uses them.
+hipError_t dev_malloc(void **p, size_t bytes);
+hipError_t host_malloc(void **p, size_t bytes, unsigned flags);
+
 int get_workspace(void *stream, Workspace **out);
 int ensure_bytes(void **ptr, size_t *cap, size_t need);
 // ensure_bytes for a buffer of ws: grows it, or on a fixed workspace fails

@@ -201,16 +201,16 @@ int ecc_stream_begin(const ecc_dims *full_dims, ecc_dtype dtype, void *stream, e
     hipError_t e = hipStreamCreateWithFlags(&st->copy, hipStreamNonBlocking);
     if (e != hipSuccess) return fail(hip_fail(e, "hipStreamCreate"));
     for (int i = 0; i < 2; ++i) {
-        if ((e = hipMalloc(&st->carry_buf[i], (size_t)st->plane_bytes * 2)) != hipSuccess)
+        if ((e = dev_malloc((void **)&st->carry_buf[i], (size_t)st->plane_bytes * 2)) != hipSuccess)
             return fail(hip_fail(e, "hipMalloc(carry)"));
         if ((e = hipEventCreateWithFlags(&st->ready[i], hipEventDisableTiming)) != hipSuccess)
             return fail(hip_fail(e, "hipEventCreate"));
         if ((e = hipEventCreateWithFlags(&st->released[i], hipEventDisableTiming)) != hipSuccess)
             return fail(hip_fail(e, "hipEventCreate"));
     }
-    if ((e = hipMalloc(&st->vcec, (size_t)st->m * sizeof(int64_t))) != hipSuccess)
+    if ((e = dev_malloc((void **)&st->vcec, (size_t)st->m * sizeof(int64_t))) != hipSuccess)
         return fail(hip_fail(e, "hipMalloc(vcec)"));
-    if ((e = hipMalloc(&st->status, kStatusBytes)) != hipSuccess) return fail(hip_fail(e, "hipMalloc(status)"));
+    if ((e = dev_malloc((void **)&st->status, kStatusBytes)) != hipSuccess) return fail(hip_fail(e, "hipMalloc(status)"));
     if ((rc = launch_zero(st->vcec, (size_t)st->m * sizeof(int64_t), st->compute))) return fail(rc);
     if ((rc = launch_zero(st->status, kStatusBytes, st->compute))) return fail(rc);
     *out = st;
@@ -250,7 +250,7 @@ int ecc_stream_push_chunk(ecc_stream *st, const void *planes, int64_t n_planes) 
                 st->released_recorded[i] = false;
             }
             st->stage_cap = 0;
-            for (int i = 0; i < 2; ++i) ECC_HIP(hipMalloc(&st->stage[i], bytes));
+            for (int i = 0; i < 2; ++i) ECC_HIP(dev_malloc((void **)&st->stage[i], bytes));
             st->stage_cap = bytes;
         }
         if (st->released_recorded[k]) ECC_HIP(hipStreamWaitEvent(st->copy, st->released[k], 0));
@@ -311,7 +311,7 @@ int ecc_stream_finish(ecc_stream *st, ecc_curve *curve) {
             break;
         }
         int64_t *tmp = nullptr;
-        hipError_t e = hipMalloc(&tmp, (size_t)st->m * sizeof(int64_t));
+        hipError_t e = dev_malloc((void **)&tmp, (size_t)st->m * sizeof(int64_t));
         if (e != hipSuccess) {
             rc = hip_fail(e, "hipMalloc(curve)");
             break;
