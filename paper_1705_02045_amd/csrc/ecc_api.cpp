@@ -12,6 +12,8 @@
 
 #include "ecc_internal.h"
 
+#include <algorithm>
+
 namespace ecc {
 
 static thread_local char g_err[512] = "";
@@ -630,16 +632,24 @@ static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc
         ECC_HIP(hipMemcpyAsync(ws->img_tmp, image, bytes, hipMemcpyHostToDevice, s));
         img_dev = (const float *)ws->img_tmp;
     }
-    // carve the float scratch: two record buffers, the digit table and its
-    // scan sums, the curve's tile sums and the distinct-value count
-    const int64_t tiles = radix_tiles(n);
+    // carve the float scratch: two key buffers (sort), the record regions
+    // (keys then changes; after the records are compacted, the change-point
+    // output's chi), the region counts and offsets, the digit table and its
+    // scan sums, the curve's tile sums, the counts
+    int64_t slots = 0;
+    const int64_t regions = float_regions(dims, &slots);
+    if (regions < 0) return ECC_E_UNSUPPORTED;
+    const int64_t tiles = std::max(radix_tiles(n, 4), radix_tiles(n, 8));
     const int64_t ft = float_tiles(n);
-    // (and for steps_only: change-point positions, their scan sums and count)
-    size_t off[10], total = 0;
-    const size_t sz[10] = {(size_t)n * 8, (size_t)n * 8, (size_t)(256 * tiles) * 4,
-                           (size_t)radix_scan_tiles(256 * tiles) * 4, (size_t)ft * 8, (size_t)ft * 8, 8,
-                           steps_only ? (size_t)n * 4 : 0, steps_only ? (size_t)radix_scan_tiles(n) * 4 : 0, 8};
-    for (int i = 0; i < 10; ++i) {
+    enum { kKey0, kKey1, kNz, kNzCnt, kNzOff, kCounts, kSums, kTileA, kTileB, kBound, kCnt, kSteps, kNbuf };
+    size_t off[kNbuf], total = 0;
+    const int64_t scan_entries = std::max(std::max(256 * tiles, regions), steps_only ? n : 0);
+    const size_t sz[kNbuf] = {(size_t)n * 4, (size_t)n * 4, (size_t)slots * 8, (size_t)regions * 4,
+                              (size_t)regions * 4, (size_t)(256 * tiles) * 4,
+                              (size_t)radix_scan_tiles(scan_entries) * 4, (size_t)ft * 8, (size_t)ft * 8,
+                              (size_t)(ft + 1) * 8, 64,
+                              steps_only ? (size_t)n * 4 : 0};
+    for (int i = 0; i < kNbuf; ++i) {
         off[i] = total;
         total += align256(sz[i]);
     }
@@ -652,20 +662,60 @@ static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc
     rc = ensure_bytes(&ws->fbuf, &ws->fbuf_bytes, total);
     if (rc) return rc;
     uint8_t *b = (uint8_t *)ws->fbuf;
-    uint64_t *rec[2] = {(uint64_t *)(b + off[0]), (uint64_t *)(b + off[1])};
-    uint32_t *counts = (uint32_t *)(b + off[2]);
-    uint32_t *sums = (uint32_t *)(b + off[3]);
-    int64_t *tile_chg = (int64_t *)(b + off[4]);
-    int64_t *tile_last = (int64_t *)(b + off[5]);
-    int64_t *count_dev = (int64_t *)(b + off[6]);
+    uint32_t *key[2] = {(uint32_t *)(b + off[kKey0]), (uint32_t *)(b + off[kKey1])};
+    uint32_t *nz_key = (uint32_t *)(b + off[kNz]);
+    int32_t *nz_chg = (int32_t *)(nz_key + slots);
+    uint32_t *nz_cnt = (uint32_t *)(b + off[kNzCnt]);
+    uint32_t *nz_off = (uint32_t *)(b + off[kNzOff]);
+    uint32_t *counts = (uint32_t *)(b + off[kCounts]);
+    uint32_t *sums = (uint32_t *)(b + off[kSums]);
+    int64_t *tile_a = (int64_t *)(b + off[kTileA]);
+    int64_t *tile_b = (int64_t *)(b + off[kTileB]);
+    int64_t *bound = (int64_t *)(b + off[kBound]);
+    int64_t *nnz_dev = (int64_t *)(b + off[kCnt]);
+    int64_t *count_dev = (int64_t *)(b + off[kCnt] + 8);
+    int64_t *count2_dev = (int64_t *)(b + off[kCnt] + 16);
     float *out_keys = direct ? curve->keys : (float *)(b + out_k);
     int64_t *out_chi = direct ? curve->chi : (int64_t *)(b + out_c);
+    // the record count, read on the host while the keys are sorted: a word of
+    // the host-mapped status block
+    volatile int64_t *nnz_host = (volatile int64_t *)(ws->host_status + 2);
+    int64_t *nnz_host_dev = (int64_t *)(ws->host_status_dev + 2);
+    *nnz_host = -1;
 
-    rc = launch_float_change(img_dev, dims, rec[0], ws->status, s);
+    rc = launch_float_change(img_dev, dims, key[0], nz_key, nz_chg, nz_cnt, nz_off, ws->status, s);
     if (rc) return rc;
-    rc = radix_sort_records(rec, n, counts, sums, s);
+    rc = launch_nz_total(nz_cnt, nz_off, regions, sums, nnz_dev, nnz_host_dev, s);
     if (rc) return rc;
-    rc = launch_float_curve(rec[0], n, tile_chg, tile_last, count_dev, out_keys, out_chi, s);
+    hipEvent_t counted = nullptr;
+    ECC_HIP(hipEventCreateWithFlags(&counted, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(counted, s);
+    if (e == hipSuccess) {
+        rc = radix_sort_keys(key, n, counts, sums, s);
+        e = hipEventSynchronize(counted);
+    }
+    (void)hipEventDestroy(counted);
+    ECC_HIP(e);
+    if (rc) return rc;
+    const int64_t nnz = *nnz_host;
+    if (nnz < 0 || nnz > n) {
+        set_error("internal error: %lld change records for %lld voxels", (long long)nnz, (long long)n);
+        return ECC_E_HIP;
+    }
+    // the dense records (two sort buffers) and their prefix
+    const size_t rb = align256((size_t)nnz * 8);
+    rc = ensure_bytes(&ws->frec, &ws->frec_bytes, 3 * rb + 256);
+    if (rc) return rc;
+    uint64_t *rec[2] = {(uint64_t *)ws->frec, (uint64_t *)((uint8_t *)ws->frec + rb)};
+    int64_t *prefix = (int64_t *)((uint8_t *)ws->frec + 2 * rb);
+    if (nnz > 0) {
+        rc = launch_nz_compact(nz_key, nz_chg, nz_cnt, nz_off, regions, slots / regions, rec[0], s);
+        if (rc) return rc;
+        rc = radix_sort_records(rec, nnz, counts, sums, s);
+        if (rc) return rc;
+    }
+    rc = launch_float_curve(key[0], n, rec[0], nnz, prefix, (uint32_t *)tile_b, sums, tile_a, bound, count_dev, out_keys,
+                            out_chi, s);
     if (rc) return rc;
     uint32_t st = 0;
     int64_t kcount = 0;
@@ -683,12 +733,11 @@ static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc
         set_error("internal error: device status 0x%08x", st);
         return ECC_E_HIP;
     }
-    if (steps_only) {  // compact into the record buffers, free after the curve
-        float *step_keys = (float *)rec[1];
-        int64_t *step_chi = (int64_t *)rec[0];
-        int64_t *count2_dev = (int64_t *)(b + off[9]);
-        rc = launch_change_points(out_keys, out_chi, kcount, (uint32_t *)(b + off[7]), (uint32_t *)(b + off[8]),
-                                  step_keys, step_chi, count2_dev, s);
+    if (steps_only) {  // compact into buffers free after the curve: the second key buffer, the regions
+        float *step_keys = (float *)key[1];
+        int64_t *step_chi = (int64_t *)nz_key;
+        rc = launch_change_points(out_keys, out_chi, kcount, (uint32_t *)(b + off[kSteps]), sums, step_keys,
+                                  step_chi, count2_dev, s);
         if (rc) return rc;
         ECC_HIP(hipMemcpyAsync(&kcount, count2_dev, 8, hipMemcpyDeviceToHost, s));
         ECC_HIP(hipStreamSynchronize(s));

@@ -1,6 +1,9 @@
 // Float32 images (Sec. 3, "Other Ranges of Gray Values"): the values are not known
-// in advance, so every voxel emits a record (key, change) and the records
-// are sorted by key, summed per distinct key and prefix-summed.
+// in advance, so every voxel's key is written and the keys are sorted to
+// find the distinct values; the voxels whose change is not zero (a few in a
+// hundred) are also written, as (key, change) records, and each change is
+// added at its key's rank among the distinct values; a prefix sum over the
+// distinct values gives the curve.
 //
 // The change of a voxel v is the signed count of the cells of the cubical
 // complex that v introduces (Sec. 3, Algorithm 1: a cell enters with the
@@ -22,7 +25,6 @@
 //
 // Keys: the canonical float (-0 folded into +0) mapped to an unsigned integer
 // with the same order (sign bit set: all bits flipped; else the sign bit set).
-// A record is one 64-bit word: key in bits 8..39, change (int8) in bits 0..7.
 
 #include "ecc_internal.h"
 
@@ -107,17 +109,28 @@ struct FloatView {
 // thread and line, plus one load for the two ends of all S lines), instead of
 // 3^D - 1 scattered loads per voxel.  Absent neighbours (outside the image)
 // are stored as NaN, which compares false and so never precedes.
+// Outputs: keys[i] for every voxel i; for every voxel whose change is not
+// zero, one (key, change) record in the workgroup's own region of the record
+// arrays (region b = records [b * T * run, (b+1) * T * run), as many slots as
+// the workgroup has voxels), at a slot taken from an LDS counter (one LDS
+// add per wave and line); nz_cnt[b] and nz_off[b] receive the region's
+// record count.
 template <int D, int T>
 __global__ void __launch_bounds__(T) float_change_kernel(const float *__restrict__ img, uint32_t img_bytes,
-                                                         FloatView v, uint64_t *__restrict__ rec,
+                                                         FloatView v, uint32_t *__restrict__ keys,
+                                                         uint32_t *__restrict__ nz_key, int32_t *__restrict__ nz_chg,
+                                                         uint32_t *__restrict__ nz_cnt, uint32_t *__restrict__ nz_off,
                                                          uint32_t *status) {
     constexpr int P = pow3(D);
     constexpr int C = (P - 1) / 2;             // code of the zero direction
     constexpr int S = D >= 2 ? pow3(D - 2) : 1;  // lines per slot
     constexpr int PITCH = T + 2;
     __shared__ float ring[4 * S * PITCH];
+    __shared__ uint32_t region_count;
     const int32_t nx = v.n[3], n2 = v.n[2];
     const int tid = (int)threadIdx.x;
+    if (tid == 0) region_count = 0;  // (the first barrier below orders it)
+    const uint32_t region = (uint32_t)blockIdx.x * (uint32_t)(T * v.run);
     // block -> (outer line over axes 0..1, run along axis 2, x block); uniform
     int32_t r = __builtin_amdgcn_readfirstlane((int32_t)blockIdx.x);
     const int32_t xs = (r % v.bpr) * T;
@@ -243,13 +256,40 @@ __global__ void __launch_bounds__(T) float_change_kernel(const float *__restrict
         }
         if (ballot64(act && (own_bits & 0x7FFFFFFFu) > 0x7F800000u) != 0 && (threadIdx.x & (kWave - 1)) == 0)
             atomicOr(status, kStatusNaN);
-        if (act) rec[own_index(y)] = ((uint64_t)k0 << 8) | (uint8_t)(int8_t)(1 - acc);
+        const int32_t chg = 1 - acc;
+        if (act) keys[own_index(y)] = k0;
+        const uint64_t nzm = ballot64(act && chg != 0);
+        if (nzm != 0) {
+            const int lane = (int)(threadIdx.x & (kWave - 1));
+            const int leader = __builtin_ctzll(nzm);
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(&region_count, (uint32_t)__builtin_popcountll(nzm));
+            base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+            if (act && chg != 0) {
+                const uint64_t below = lane == 0 ? 0ull : (nzm & (~0ull >> (64 - lane)));
+                const uint32_t slot = region + base + (uint32_t)__builtin_popcountll(below);
+                nz_key[slot] = k0;
+                nz_chg[slot] = chg;
+            }
+        }
         if (next) store(y + 2, val, end);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        nz_cnt[blockIdx.x] = region_count;
+        nz_off[blockIdx.x] = region_count;
     }
 }
 
-int launch_float_change(const float *img_dev, const ecc_dims *dims, uint64_t *rec, uint32_t *status,
-                        hipStream_t stream) {
+// Geometry of the change kernel's launch for an image (workgroups, threads,
+// lines per run), shared by the launch and by the record layout.
+struct FloatGrid {
+    FloatView v;
+    int D, threads;
+    int64_t grid;
+};
+
+static int float_grid(const ecc_dims *dims, FloatGrid *g) {
     // drop axes of extent 1, pad in front to four axes
     int32_t ext[4];
     int d = 0;
@@ -262,7 +302,8 @@ int launch_float_change(const float *img_dev, const ecc_dims *dims, uint64_t *re
         set_error("float images are limited to 2^30 elements in this build");
         return ECC_E_UNSUPPORTED;
     }
-    FloatView v{};
+    FloatView &v = g->v;
+    v = FloatView{};
     const int D = d == 0 ? 1 : d;
     if (d == 0) ext[d++] = 1;
     for (int k = 0; k < 4; ++k) v.n[k] = 1;
@@ -278,21 +319,44 @@ int launch_float_change(const float *img_dev, const ecc_dims *dims, uint64_t *re
     v.run = v.n[2] < 32 ? v.n[2] : 32;
     v.nruns = (v.n[2] + v.run - 1) / v.run;
     const int64_t grid = (int64_t)v.n[0] * v.n[1] * v.nruns * v.bpr;
-    if (grid > INT32_MAX) {
+    if (grid > INT32_MAX || grid * threads * v.run > (int64_t)UINT32_MAX) {
         set_error("float image: too many lines");
         return ECC_E_UNSUPPORTED;
     }
+    g->D = D;
+    g->threads = threads;
+    g->grid = grid;
+    return ECC_OK;
+}
+
+int64_t float_regions(const ecc_dims *dims, int64_t *slots) {
+    FloatGrid g;
+    if (float_grid(dims, &g)) return -1;
+    *slots = g.grid * g.threads * g.v.run;
+    return g.grid;
+}
+
+int launch_float_change(const float *img_dev, const ecc_dims *dims, uint32_t *keys, uint32_t *nz_key,
+                        int32_t *nz_chg, uint32_t *nz_cnt, uint32_t *nz_off, uint32_t *status, hipStream_t stream) {
+    FloatGrid fg;
+    int rc = float_grid(dims, &fg);
+    if (rc) return rc;
+    const FloatView v = fg.v;
+    const int D = fg.D, threads = fg.threads;
+    const int64_t grid = fg.grid;
+    int64_t total = 1;
+    for (int i = 0; i < dims->ndim; ++i) total *= dims->n[i];
     const uint32_t bytes = (uint32_t)(total * 4);
     void *tok = nullptr;
-    int rc = profile_begin(stream, &tok);
+    rc = profile_begin(stream, &tok);
     if (rc) return rc;
     const dim3 g((unsigned)grid), b(threads);
 #define ECC_FCK(DD)                                                                                              \
     switch (threads) {                                                                                           \
-    case 64: hipLaunchKernelGGL((float_change_kernel<DD, 64>), g, b, 0, stream, img_dev, bytes, v, rec, status); break;   \
-    case 128: hipLaunchKernelGGL((float_change_kernel<DD, 128>), g, b, 0, stream, img_dev, bytes, v, rec, status); break; \
-    case 192: hipLaunchKernelGGL((float_change_kernel<DD, 192>), g, b, 0, stream, img_dev, bytes, v, rec, status); break; \
-    default: hipLaunchKernelGGL((float_change_kernel<DD, 256>), g, b, 0, stream, img_dev, bytes, v, rec, status); break;  \
+    case 64: hipLaunchKernelGGL((float_change_kernel<DD, 64>), g, b, 0, stream, img_dev, bytes, v, keys, nz_key, nz_chg, nz_cnt, nz_off, status); break;   \
+    case 128: hipLaunchKernelGGL((float_change_kernel<DD, 128>), g, b, 0, stream, img_dev, bytes, v, keys, nz_key, nz_chg, nz_cnt, nz_off, status); break; \
+    case 192: hipLaunchKernelGGL((float_change_kernel<DD, 192>), g, b, 0, stream, img_dev, bytes, v, keys, nz_key, nz_chg, nz_cnt, nz_off, status); break; \
+    default: hipLaunchKernelGGL((float_change_kernel<DD, 256>), g, b, 0, stream, img_dev, bytes, v, keys, nz_key, nz_chg, nz_cnt, nz_off, status); break;  \
     }
     switch (D) {
     case 1: ECC_FCK(1); break;
@@ -306,21 +370,75 @@ int launch_float_change(const float *img_dev, const ecc_dims *dims, uint64_t *re
 }
 
 // ----------------------------------------------------------------------------
-// After sorting: chi after each distinct key = running sum of the changes up
-// to and including the last record with that key.  Records are taken in tiles
-// of kFTile; pass 1 sums each tile (changes, and the number of last-of-key
-// positions), pass 2 scans the tile sums in one workgroup, pass 3 writes
-// (key, chi) at the rank of each last-of-key position.
+// The non-zero change records, from the workgroups' regions to one dense
+// array of 64-bit words (key << 32 | change as uint32), sorted by key.
+
+// After the exclusive scan of nz_off (region offsets): the record count.
+// Written to device memory and to host-mapped memory (read by the host
+// after an event, to size the record sort).
+__global__ void nz_total_kernel(const uint32_t *nz_cnt, const uint32_t *nz_off, int64_t regions, int64_t *total_dev,
+                                int64_t *total_host) {
+    const int64_t t = (int64_t)nz_off[regions - 1] + nz_cnt[regions - 1];
+    *total_dev = t;
+    *total_host = t;
+}
+
+int launch_nz_total(const uint32_t *nz_cnt, uint32_t *nz_off, int64_t regions, uint32_t *sums, int64_t *total_dev,
+                    int64_t *total_host, hipStream_t stream) {
+    int rc = exclusive_scan_u32(nz_off, regions, sums, stream);
+    if (rc) return rc;
+    hipLaunchKernelGGL(nz_total_kernel, dim3(1), dim3(1), 0, stream, nz_cnt, (const uint32_t *)nz_off, regions,
+                       total_dev, total_host);
+    ECC_HIP(hipGetLastError());
+    return ECC_OK;
+}
+
+__global__ void __launch_bounds__(256) nz_compact_kernel(const uint32_t *__restrict__ nz_key,
+                                                         const int32_t *__restrict__ nz_chg,
+                                                         const uint32_t *__restrict__ nz_cnt,
+                                                         const uint32_t *__restrict__ nz_off, int64_t region_slots,
+                                                         uint64_t *__restrict__ rec) {
+    const uint32_t c = nz_cnt[blockIdx.x];
+    const int64_t src = (int64_t)blockIdx.x * region_slots, dst = nz_off[blockIdx.x];
+    for (uint32_t i = threadIdx.x; i < c; i += blockDim.x)
+        rec[dst + i] = ((uint64_t)nz_key[src + i] << 32) | (uint32_t)nz_chg[src + i];
+}
+
+int launch_nz_compact(const uint32_t *nz_key, const int32_t *nz_chg, const uint32_t *nz_cnt, const uint32_t *nz_off,
+                      int64_t regions, int64_t region_slots, uint64_t *rec, hipStream_t stream) {
+    if (regions > INT32_MAX) {
+        set_error("float image: too many regions");
+        return ECC_E_UNSUPPORTED;
+    }
+    hipLaunchKernelGGL(nz_compact_kernel, dim3((unsigned)regions), dim3(256), 0, stream, nz_key, nz_chg, nz_cnt, nz_off,
+                       region_slots, rec);
+    ECC_HIP(hipGetLastError());
+    return ECC_OK;
+}
+
+// ----------------------------------------------------------------------------
+// After both sorts: the distinct keys and the curve.  chi after a distinct
+// value v is the sum of the changes of the voxels with key <= v, i.e. the
+// inclusive prefix P of the sorted records' changes at the last record with
+// key <= v (0 if there is none).
+//  1. ukey_count_kernel: per tile of kFTile sorted keys, the number of
+//     last-of-key positions (a key differing from the next one), and its
+//     exclusive scan: the tile's first rank;
+//  2. rec_tile_sums_kernel, fscan_tiles_kernel, rec_prefix_kernel: P over
+//     the records;
+//  4. slice_bounds_kernel, curve_write_kernel: each last-of-key position
+//     writes its key (as float) and chi at its rank.  Tile t of the keys,
+//     [i0, i1), owns the key values in [key[i0], key[i1]) (from minus
+//     infinity for the first tile, to plus infinity for the last): those
+//     whose last position lies in the tile.  Its records are the ones in
+//     [lower_bound(key[i0]), lower_bound(key[i1])) (one binary search per
+//     tile, all tiles at once); each distinct key then searches only that
+//     slice, from LDS when it is short.  The last tile writes K (known on
+//     the device only).
 
 constexpr int kFThreads = 256;
 constexpr int kFItems = 16;
 constexpr int kFTile = kFThreads * kFItems;
-
-__device__ __forceinline__ uint32_t rec_key(uint64_t r) { return (uint32_t)(r >> 8); }
-__device__ __forceinline__ int32_t rec_chg(uint64_t r) { return (int32_t)(int8_t)(uint8_t)(r & 0xFFu); }
-__device__ __forceinline__ bool last_of_key(const uint64_t *rec, int64_t i, int64_t n) {
-    return i == n - 1 || rec_key(rec[i]) != rec_key(rec[i + 1]);
-}
 
 template <typename T>
 __device__ T block_sum(T v, T *sh) {
@@ -335,39 +453,62 @@ __device__ T block_sum(T v, T *sh) {
     return t;
 }
 
-__global__ void __launch_bounds__(kFThreads) fsum_tiles_kernel(const uint64_t *__restrict__ rec, int64_t n,
-                                                              int64_t *__restrict__ tile_chg,
-                                                              int64_t *__restrict__ tile_last) {
+__device__ __forceinline__ bool last_of_key(const uint32_t *key, int64_t i, int64_t n) {
+    return i == n - 1 || key[i] != key[i + 1];
+}
+
+// Last-of-key positions per tile: four 16-byte loads per thread (groups of
+// four keys, coalesced across the wave), the key after each group from the
+// next group (a cache hit).
+__global__ void __launch_bounds__(kFThreads) ukey_count_kernel(const uint32_t *__restrict__ key, int64_t n,
+                                                              uint32_t *__restrict__ tile_last) {
+    __shared__ uint32_t sh[4];
+    const int64_t t0 = (int64_t)blockIdx.x * kFTile;
+    uint32_t l = 0;
+    const bool vec = (reinterpret_cast<uintptr_t>(key) & 15u) == 0;
+#pragma unroll
+    for (int j = 0; j < kFItems / 4; ++j) {
+        const int64_t g = t0 + ((int64_t)j * kFThreads + threadIdx.x) * 4;
+        if (vec && g + 4 < n) {
+            const uint4 w = *reinterpret_cast<const uint4 *>(key + g);
+            const uint32_t nx = key[g + 4];
+            l += (w.x != w.y) + (w.y != w.z) + (w.z != w.w) + (w.w != nx);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (g + q < n) l += last_of_key(key, g + q, n);
+        }
+    }
+    l = block_sum(l, sh);
+    if (threadIdx.x == 0) tile_last[blockIdx.x] = l;
+}
+
+__device__ __forceinline__ int32_t rec_change(uint64_t r) { return (int32_t)(uint32_t)r; }
+__device__ __forceinline__ uint32_t rec_key(uint64_t r) { return (uint32_t)(r >> 32); }
+
+// Change sums of record tiles [t * kFTile, (t+1) * kFTile).
+__global__ void __launch_bounds__(kFThreads) rec_tile_sums_kernel(const uint64_t *__restrict__ rec, int64_t nnz,
+                                                                 int64_t *__restrict__ tsum) {
     __shared__ int64_t sh[4];
     const int64_t t0 = (int64_t)blockIdx.x * kFTile;
-    int64_t s = 0, l = 0;
+    int64_t s = 0;
 #pragma unroll
     for (int j = 0; j < kFItems; ++j) {
         const int64_t i = t0 + (int64_t)j * kFThreads + threadIdx.x;
-        if (i < n) {
-            s += rec_chg(rec[i]);
-            l += last_of_key(rec, i, n);
-        }
+        if (i < nnz) s += rec_change(rec[i]);
     }
     s = block_sum(s, sh);
-    l = block_sum(l, sh);
-    if (threadIdx.x == 0) {
-        tile_chg[blockIdx.x] = s;
-        tile_last[blockIdx.x] = l;
-    }
+    if (threadIdx.x == 0) tsum[blockIdx.x] = s;
 }
 
-// Exclusive scan in place of two int64 arrays of length nt by one workgroup;
-// total_last receives the sum of the second (the number of distinct keys).
 // Exclusive scans of both tile arrays in one workgroup of 1024 threads, in
 // chunks of 16384 tiles: thread t holds tiles c0 + k * 1024 + t (k < 16:
 // sixteen rows, every load and store coalesced).  Each row is scanned
 // across the wave with shuffles; the wave totals per row go to LDS, where
 // 32 threads turn them into per-wave prefixes and row totals.  The running
-// carries are the same in all threads.  (With runs of consecutive tiles per
-// thread one CU's address unit, fed 64 cache lines per load, was the limit:
-// 0.14 ms for 2^16 tiles, 0.16 ms with one tile per thread.)
-__global__ void __launch_bounds__(1024) fscan_tiles_kernel(int64_t *a, int64_t *b, int64_t nt, int64_t *total_last) {
+// carries are the same in all threads.  total_b receives the sum of b.  b may
+// be null (then only a is scanned).
+__global__ void __launch_bounds__(1024) fscan_tiles_kernel(int64_t *a, int64_t *b, int64_t nt, int64_t *total_b) {
     __shared__ int64_t wsa[16][17], wsb[16][17];  // [row][wave]
     __shared__ int64_t tota[16], totb[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -378,7 +519,7 @@ __global__ void __launch_bounds__(1024) fscan_tiles_kernel(int64_t *a, int64_t *
         for (int k = 0; k < 16; ++k) {
             const int64_t i = c0 + k * 1024 + tid;
             xa[k] = i < nt ? a[i] : 0;
-            xb[k] = i < nt ? b[i] : 0;
+            xb[k] = b && i < nt ? b[i] : 0;
         }
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -418,107 +559,199 @@ __global__ void __launch_bounds__(1024) fscan_tiles_kernel(int64_t *a, int64_t *
             const int64_t i = c0 + k * 1024 + tid;
             if (i < nt) {
                 a[i] = ca + wsa[k][wave] + (lane > 0 ? pa : 0);
-                b[i] = cb + wsb[k][wave] + (lane > 0 ? pb : 0);
+                if (b) b[i] = cb + wsb[k][wave] + (lane > 0 ? pb : 0);
             }
             ca += tota[k];
             cb += totb[k];
         }
         __syncthreads();  // the LDS rows are rewritten by the next chunk
     }
-    if (tid == 0) *total_last = cb;
+    if (tid == 0 && b && total_b) *total_b = cb;
 }
 
-// The curve write walks the same tiles with twice the threads (8 records
-// each): its LDS tile allows four workgroups per CU, so 512 threads keep 32
-// waves per CU in flight instead of 16.
-constexpr int kWThreads = 512;
-constexpr int kWItems = kFTile / kWThreads;
-constexpr int kWWaves = kWThreads / 64;
-static_assert(kWItems * kWThreads == kFTile && kWThreads % 64 == 0, "curve write: whole tiles of whole waves");
-__global__ void __launch_bounds__(kWThreads) fwrite_kernel(const uint64_t *__restrict__ rec, int64_t n,
-                                                          const int64_t *__restrict__ tile_chg,
-                                                          const int64_t *__restrict__ tile_last,
-                                                          float *__restrict__ out_keys, int64_t *__restrict__ out_chi) {
-    __shared__ int64_t wc[kWWaves], wl[kWWaves];
-    // the tile and the record after it, loaded coalesced; slot i at i + i / 16
-    // (fewer bank conflicts when threads read runs of consecutive records)
-    __shared__ uint64_t tile[kFTile + kFTile / 16 + 1];
+// LDS slot of tile position i: one pad word per 16 entries, so that a
+// thread's run of 16 (thread t reads 17 t + j) spreads over the banks.
+__device__ __forceinline__ int fpad(int i) { return i + (i >> 4); }
+
+// Inclusive prefix of the records' changes: the tile's changes staged in LDS
+// (coalesced loads), a thread's run of kFItems scanned, the runs scanned over
+// the workgroup with the tile's offset added, the prefixes staged back for
+// coalesced stores.
+__global__ void __launch_bounds__(kFThreads) rec_prefix_kernel(const uint64_t *__restrict__ rec, int64_t nnz,
+                                                              const int64_t *__restrict__ tbase,
+                                                              int64_t *__restrict__ prefix) {
+    __shared__ int64_t st[kFTile + kFTile / 16];
+    __shared__ int64_t ws[kFThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t t0 = (int64_t)blockIdx.x * kFTile;
 #pragma unroll
-    for (int j = 0; j < kWItems; ++j) {
-        const int q = j * kWThreads + tid;
-        const int64_t i = t0 + q;
-        tile[q + q / 16] = i < n ? rec[i] : 0ull;
-    }
-    if (tid == 0) {
-        const int64_t i = t0 + kFTile;
-        tile[kFTile + kFTile / 16] = i < n ? rec[i] : 0ull;
+    for (int j = 0; j < kFItems; ++j) {
+        const int i = j * kFThreads + tid;
+        st[fpad(i)] = t0 + i < nnz ? rec_change(rec[t0 + i]) : 0;
     }
     __syncthreads();
-    // each thread takes kWItems consecutive records of the tile
-    const int64_t i0 = t0 + (int64_t)tid * kWItems;
-    uint64_t r[kWItems + 1];
+    const int r0 = tid * kFItems;
+    int64_t v[kFItems], s = 0;
 #pragma unroll
-    for (int j = 0; j <= kWItems; ++j) {
-        const int q = tid * kWItems + j;
-        r[j] = tile[q + q / 16];
+    for (int j = 0; j < kFItems; ++j) {
+        v[j] = st[fpad(r0 + j)];
+        s += v[j];
     }
-    int64_t c[kWItems];
-    bool last[kWItems];
-    int64_t sc = 0, sl = 0;
-#pragma unroll
-    for (int j = 0; j < kWItems; ++j) {
-        const int64_t i = i0 + j;
-        const bool in = i < n;
-        sc += in ? rec_chg(r[j]) : 0;
-        c[j] = sc;
-        last[j] = in && (i == n - 1 || rec_key(r[j]) != rec_key(r[j + 1]));
-        sl += last[j];
-    }
-    int64_t xc = sc, xl = sl;
+    int64_t x = s;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        const int64_t uc = __shfl_up(xc, off, 64), ul = __shfl_up(xl, off, 64);
-        if (lane >= off) {
-            xc += uc;
-            xl += ul;
-        }
+        const int64_t u = __shfl_up(x, off, 64);
+        if (lane >= off) x += u;
     }
-    if (lane == 63) {
-        wc[wave] = xc;
-        wl[wave] = xl;
+    if (lane == 63) ws[wave] = x;
+    __syncthreads();
+    int64_t p = tbase[blockIdx.x] + x - s;
+    for (int w = 0; w < wave; ++w) p += ws[w];
+#pragma unroll
+    for (int j = 0; j < kFItems; ++j) {
+        p += v[j];
+        st[fpad(r0 + j)] = p;
     }
     __syncthreads();
-    int64_t bc = tile_chg[blockIdx.x] + xc - sc, bl = tile_last[blockIdx.x] + xl - sl;
-    for (int w = 0; w < wave; ++w) {
-        bc += wc[w];
-        bl += wl[w];
-    }
 #pragma unroll
-    for (int j = 0; j < kWItems; ++j) {
-        if (last[j]) {
-            out_keys[bl] = key_to_f32(rec_key(r[j]));
-            out_chi[bl] = bc + c[j];
-            ++bl;
-        }
+    for (int j = 0; j < kFItems; ++j) {
+        const int i = j * kFThreads + tid;
+        if (t0 + i < nnz) prefix[t0 + i] = st[fpad(i)];
     }
 }
 
-int launch_float_curve(const uint64_t *rec, int64_t n, int64_t *tile_chg, int64_t *tile_last,
-                       int64_t *total_last, float *out_keys, int64_t *out_chi, hipStream_t stream) {
+// First record index in [lo, hi) whose key is >= k (strict: > k), or hi.
+template <bool STRICT>
+__device__ __forceinline__ int64_t rec_bound(const uint64_t *rec, int64_t lo, int64_t hi, uint32_t k) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const uint32_t x = rec_key(rec[mid]);
+        if (STRICT ? x <= k : x < k) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// bound[t] = the first record whose key is >= the first key of key tile t
+// (0 for t = 0; the record count for t = nt): one thread per tile, all
+// searches in flight together.
+__global__ void __launch_bounds__(256) slice_bounds_kernel(const uint32_t *__restrict__ key, int64_t n, int64_t nt,
+                                                           const uint64_t *__restrict__ rec, int64_t nnz,
+                                                           int64_t *__restrict__ bound) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > nt) return;
+    bound[t] = t == 0 ? 0 : t == nt ? nnz : rec_bound<false>(rec, 0, nnz, key[t * kFTile]);
+}
+
+constexpr int kSliceCap = 2048;  // records of a tile's slice kept in LDS
+
+// The tile's distinct keys are gathered in LDS in rank order, then written
+// by all threads together: coalesced stores, and one slice search each.
+__global__ void __launch_bounds__(kFThreads) curve_write_kernel(const uint32_t *__restrict__ key, int64_t n,
+                                                               int64_t nt, const uint32_t *__restrict__ tile_base,
+                                                               const int64_t *__restrict__ bound,
+                                                               const uint64_t *__restrict__ rec,
+                                                               const int64_t *__restrict__ prefix,
+                                                               float *__restrict__ out_keys,
+                                                               int64_t *__restrict__ out_chi, int64_t *kcount) {
+    __shared__ uint32_t sk[kFTile + kFTile / 16 + 1];  // the tile's keys, then its distinct keys
+    __shared__ uint32_t sl[kSliceCap];
+    __shared__ uint32_t ws[kFThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t t0 = (int64_t)blockIdx.x * kFTile, t1 = t0 + kFTile;
+    const int64_t j0 = bound[blockIdx.x], j1 = bound[blockIdx.x + 1];
+    const int64_t len = j1 - j0;
+    const bool in_lds = len <= kSliceCap;  // (uniform)
+#pragma unroll
+    for (int j = 0; j < kFItems; ++j) {  // coalesced: the tile and the key after it
+        const int i = j * kFThreads + tid;
+        sk[fpad(i)] = t0 + i < n ? key[t0 + i] : 0u;
+    }
+    if (tid == 0) sk[fpad(kFTile)] = t1 < n ? key[t1] : 0u;
+    if (in_lds)
+        for (int i = tid; i < (int)len; i += kFThreads) sl[i] = rec_key(rec[j0 + i]);
+    __syncthreads();
+    const int r0 = tid * kFItems;
+    uint32_t k[kFItems + 1];
+#pragma unroll
+    for (int j = 0; j <= kFItems; ++j) k[j] = sk[fpad(r0 + j)];
+    uint32_t s = 0;
+    bool last[kFItems];
+#pragma unroll
+    for (int j = 0; j < kFItems; ++j) {
+        const int64_t i = t0 + r0 + j;
+        last[j] = i < n && (i == n - 1 || k[j] != k[j + 1]);
+        s += last[j];
+    }
+    uint32_t x = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t u = __shfl_up(x, off, 64);
+        if (lane >= off) x += u;
+    }
+    if (lane == 63) ws[wave] = x;
+    __syncthreads();  // (also: every thread has read its keys from sk)
+    uint32_t r = x - s, cnt = 0;
+    for (int w = 0; w < kFThreads / 64; ++w) {
+        if (w < wave) r += ws[w];
+        cnt += ws[w];
+    }
+#pragma unroll
+    for (int j = 0; j < kFItems; ++j)
+        if (last[j]) sk[r++] = k[j];
+    __syncthreads();
+    const int64_t base = tile_base[blockIdx.x];
+    if (tid == 0 && (int64_t)blockIdx.x == nt - 1) *kcount = base + cnt;
+    for (uint32_t q = tid; q < cnt; q += kFThreads) {
+        const uint32_t v = sk[q];
+        int64_t u;
+        if (in_lds) {
+            int lo = 0, hi = (int)len;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (sl[mid] <= v) lo = mid + 1;
+                else hi = mid;
+            }
+            u = j0 + lo;
+        } else {
+            u = rec_bound<true>(rec, j0, j1, v);
+        }
+        out_keys[base + q] = key_to_f32(v);
+        out_chi[base + q] = u > 0 ? prefix[u - 1] : 0;
+    }
+}
+
+int launch_float_curve(const uint32_t *key, int64_t n, const uint64_t *rec, int64_t nnz, int64_t *prefix,
+                       uint32_t *tile_cnt, uint32_t *sums, int64_t *tile_sum, int64_t *bound, int64_t *kcount,
+                       float *out_keys, int64_t *out_chi, hipStream_t stream) {
     const int64_t nt = (n + kFTile - 1) / kFTile;
-    if (nt > INT32_MAX) {
-        set_error("float curve: too many records");
+    if (nt > INT32_MAX || nnz > n) {
+        set_error("float curve: too many keys");
         return ECC_E_UNSUPPORTED;
     }
-    hipLaunchKernelGGL(fsum_tiles_kernel, dim3((unsigned)nt), dim3(kFThreads), 0, stream, rec, n, tile_chg,
-                       tile_last);
+    // the distinct keys' first rank per key tile
+    hipLaunchKernelGGL(ukey_count_kernel, dim3((unsigned)nt), dim3(kFThreads), 0, stream, key, n, tile_cnt);
     ECC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(fscan_tiles_kernel, dim3(1), dim3(1024), 0, stream, tile_chg, tile_last, nt, total_last);
+    int rc = exclusive_scan_u32(tile_cnt, nt, sums, stream);
+    if (rc) return rc;
+    // the records' prefix
+    const int64_t rt = (nnz + kFTile - 1) / kFTile;
+    if (rt > 0) {
+        hipLaunchKernelGGL(rec_tile_sums_kernel, dim3((unsigned)rt), dim3(kFThreads), 0, stream, rec, nnz, tile_sum);
+        ECC_HIP(hipGetLastError());
+        hipLaunchKernelGGL(fscan_tiles_kernel, dim3(1), dim3(1024), 0, stream, tile_sum, (int64_t *)nullptr, rt,
+                           (int64_t *)nullptr);
+        ECC_HIP(hipGetLastError());
+        hipLaunchKernelGGL(rec_prefix_kernel, dim3((unsigned)rt), dim3(kFThreads), 0, stream, rec, nnz,
+                           (const int64_t *)tile_sum, prefix);
+        ECC_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(slice_bounds_kernel, dim3((unsigned)((nt + 256) / 256)), dim3(256), 0, stream, key, n, nt, rec,
+                       nnz, bound);
     ECC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(fwrite_kernel, dim3((unsigned)nt), dim3(kWThreads), 0, stream, rec, n, tile_chg,
-                       tile_last, out_keys, out_chi);
+    hipLaunchKernelGGL(curve_write_kernel, dim3((unsigned)nt), dim3(kFThreads), 0, stream, key, n, nt,
+                       (const uint32_t *)tile_cnt, (const int64_t *)bound, rec, (const int64_t *)prefix, out_keys,
+                       out_chi, kcount);
     ECC_HIP(hipGetLastError());
     return ECC_OK;
 }

@@ -95,8 +95,10 @@ struct Workspace {
     size_t chi_tmp_bytes = 0;
     void *img_tmp = nullptr;     // device copy of a host image
     size_t img_tmp_bytes = 0;
-    void *fbuf = nullptr;        // float path: records, sort scratch, curve staging
+    void *fbuf = nullptr;        // float path: keys, record regions, sort scratch, curve staging
     size_t fbuf_bytes = 0;
+    void *frec = nullptr;        // float path: the dense records (two buffers) and their prefix
+    size_t frec_bytes = 0;
     void *dual_buf = nullptr;    // dual complex: gathered faces of the box, per-face curves
     size_t dual_buf_bytes = 0;
     int64_t *vcec16 = nullptr;   // [65536] changes vector of a 16-bit image (window passes)
@@ -203,16 +205,36 @@ struct MergeJob {
 int launch_batch_merge(const void *table_dev, int colsum_grid, int scan_grid, hipStream_t stream);
 
 // Float path (ecc_float.hip, ecc_sort.hip).
-// Records: one 64-bit word per voxel, order-preserving key in bits 8..39,
-// change (int8) in bits 0..7.
-int launch_float_change(const float *img_dev, const ecc_dims *dims, uint64_t *rec, uint32_t *status,
-                        hipStream_t stream);
-int64_t radix_tiles(int64_t n);
+// The change kernel writes every voxel's order-preserving 32-bit key and,
+// for the voxels whose change is not zero, (key, change) records into its
+// workgroup's region: region b holds slots [b * R, (b+1) * R) of nz_key and
+// nz_chg, R = slots / regions (float_regions); nz_cnt[b] and nz_off[b]
+// receive the region's record count.
+int64_t float_regions(const ecc_dims *dims, int64_t *slots);  // regions, or -1 with the error set
+int launch_float_change(const float *img_dev, const ecc_dims *dims, uint32_t *keys, uint32_t *nz_key,
+                        int32_t *nz_chg, uint32_t *nz_cnt, uint32_t *nz_off, uint32_t *status, hipStream_t stream);
+// Exclusive scan of nz_off (regions entries; sums: radix_scan_tiles(regions)),
+// then the record count into *total_dev and *total_host (host-mapped).
+int launch_nz_total(const uint32_t *nz_cnt, uint32_t *nz_off, int64_t regions, uint32_t *sums, int64_t *total_dev,
+                    int64_t *total_host, hipStream_t stream);
+// The regions' records, densely, as key << 32 | (uint32) change.
+int launch_nz_compact(const uint32_t *nz_key, const int32_t *nz_chg, const uint32_t *nz_cnt, const uint32_t *nz_off,
+                      int64_t regions, int64_t region_slots, uint64_t *rec, hipStream_t stream);
+// Tiles of the radix sort for n words of elem (4 or 8) bytes.
+int64_t radix_tiles(int64_t n, int elem);
 int64_t radix_scan_tiles(int64_t entries);
+// counts: 256 * radix_tiles(n, elem) entries; sums: radix_scan_tiles of that.
+int radix_sort_keys(uint32_t *key[2], int64_t n, uint32_t *counts, uint32_t *sums, hipStream_t stream);
 int radix_sort_records(uint64_t *rec[2], int64_t n, uint32_t *counts, uint32_t *sums, hipStream_t stream);
 int64_t float_tiles(int64_t n);
-int launch_float_curve(const uint64_t *rec, int64_t n, int64_t *tile_chg, int64_t *tile_last,
-                       int64_t *total_last, float *out_keys, int64_t *out_chi, hipStream_t stream);
+// From the sorted keys and the sorted records: the K distinct keys as
+// float32 (out_keys) and the curve (out_chi), K written to *kcount.
+// tile_cnt: float_tiles(n) uint32; sums: radix_scan_tiles(float_tiles(n));
+// tile_sum: float_tiles(n) int64; bound: float_tiles(n) + 1 int64; prefix:
+// nnz int64.
+int launch_float_curve(const uint32_t *key, int64_t n, const uint64_t *rec, int64_t nnz, int64_t *prefix,
+                       uint32_t *tile_cnt, uint32_t *sums, int64_t *tile_sum, int64_t *bound, int64_t *kcount,
+                       float *out_keys, int64_t *out_chi, hipStream_t stream);
 // Exclusive scan of n uint32 in place; sums: radix_scan_tiles(n) entries.
 int exclusive_scan_u32(uint32_t *a, int64_t n, uint32_t *sums, hipStream_t stream);
 // Keys where chi changes, compacted (count written on the device).

@@ -1,17 +1,18 @@
-// Stable LSD radix sort of float records (Sec. 3, "Other Ranges of Gray Values":
-// the values are sorted before the running sum).  A record is one 64-bit word:
-// the 32-bit order-preserving key in bits 8..39 and the voxel's change (int8)
-// in bits 0..7.  Four passes of 8-bit digits.
+// Stable LSD radix sort (Sec. 3, "Other Ranges of Gray Values": the distinct
+// values are found by sorting) of the order-preserving 32-bit keys of a
+// float image, and of the voxels' non-zero (key, change) records, 64-bit
+// words with the key in the high half, sorted on that half.  Four passes of
+// 8-bit digits.
 //
-// A workgroup owns a tile of kTile consecutive records.  A pass:
+// A workgroup owns a tile of kTile consecutive keys.  A pass:
 //  1. radix_count_kernel: digit counts per (digit, tile), digit-major;
-//  2. exclusive scan of that table: the output position of the first record
+//  2. exclusive scan of that table: the output position of the first key
 //     of each digit of each tile;
 //  3. radix_scatter_kernel: the tile is ranked stably in LDS (each wave
-//     ranks its 512 consecutive records: lanes with equal digits find each
+//     ranks its kItems * 64 consecutive keys: lanes with equal digits find each
 //     other with eight ballots and the wave keeps its digit counts in its
 //     own LDS row; then one prefix over the waves per digit), reordered by
-//     digit in LDS, and written out: records of one digit leave a tile as one
+//     digit in LDS, and written out: keys of one digit leave a tile as one
 //     contiguous run, so the stores coalesce.
 
 #include "ecc_internal.h"
@@ -20,32 +21,40 @@ namespace ecc {
 
 constexpr int kSortThreads = 1024;
 constexpr int kSortWaves = kSortThreads / kWave;
-constexpr int kItems = 8;
-constexpr int64_t kTile = (int64_t)kSortThreads * kItems;
 
-__device__ __forceinline__ uint32_t digit_of(uint64_t r, int shift) { return (uint32_t)(r >> shift) & 255u; }
+// Items per thread: the LDS tile of the scatter kernel is kItems words.
+template <typename T>
+struct SortTile {
+    static constexpr int kItems = sizeof(T) == 4 ? 8 : 8;
+    static constexpr int64_t kTile = (int64_t)kSortThreads * kItems;
+};
 
-template <bool AGG>
-__global__ void __launch_bounds__(kSortThreads) radix_count_kernel(const uint64_t *__restrict__ rec, int64_t n,
+template <typename T>
+__device__ __forceinline__ uint32_t digit_of(T r, int shift) { return (uint32_t)(r >> shift) & 255u; }
+
+template <typename T, bool AGG>
+__global__ void __launch_bounds__(kSortThreads) radix_count_kernel(const T *__restrict__ rec, int64_t n,
                                                                    int shift, int64_t tiles,
                                                                    uint32_t *__restrict__ counts) {
+    constexpr int kItems = SortTile<T>::kItems;
+    constexpr int64_t kTile = SortTile<T>::kTile;
     __shared__ uint32_t cnt[256];
     const int tid = threadIdx.x;
     if (tid < 256) cnt[tid] = 0;
     __syncthreads();
     const int64_t t0 = (int64_t)blockIdx.x * kTile;
     const int lane = tid & (kWave - 1);
-    uint64_t r[kItems];
+    T r[kItems];
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int64_t i = t0 + (int64_t)j * kSortThreads + tid;
-        r[j] = i < n ? rec[i] : 0ull;
+        r[j] = i < n ? rec[i] : T(0);
     }
-    // AGG (the top digit: sign and exponent, a handful of values): one LDS
-    // add per distinct digit of a wave's 64 records, the lanes with the same
-    // digit (found with eight ballots) adding through the lowest of them;
-    // per-lane adds serialize there (0.91 ms against 0.64 ms on 2^28
-    // records), while on the low digits the ballots cost more than they save
+    // AGG (the top digit: sign and exponent, a handful of values): same-digit
+    // lanes would serialize on one LDS address, so up to four rounds take the
+    // digit of the lowest lane not yet counted and add all its lanes through
+    // that lane; what is left (many distinct digits) adds per lane.  On the
+    // low digits per-lane adds are cheaper.
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int64_t i = t0 + (int64_t)j * kSortThreads + tid;
@@ -55,24 +64,29 @@ __global__ void __launch_bounds__(kSortThreads) radix_count_kernel(const uint64_
             if (ok) atomicAdd(&cnt[d], 1u);
             continue;
         }
-        uint64_t peers = __builtin_amdgcn_ballot_w64(ok);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const uint64_t m = __builtin_amdgcn_ballot_w64((d >> b) & 1u);
-            peers &= ((d >> b) & 1u) ? m : ~m;
+        uint64_t rem = __builtin_amdgcn_ballot_w64(ok);
+        for (int it = 0; it < 4 && rem != 0; ++it) {
+            const int l0 = (int)__builtin_ctzll(rem);
+            const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d, l0);
+            const uint64_t m = __builtin_amdgcn_ballot_w64(d == d0) & rem;
+            if (lane == l0) atomicAdd(&cnt[d0], (uint32_t)__builtin_popcountll(m));
+            rem &= ~m;
         }
-        if (ok && (int)__builtin_ctzll(peers) == lane) atomicAdd(&cnt[d], (uint32_t)__builtin_popcountll(peers));
+        if ((rem >> lane) & 1ull) atomicAdd(&cnt[d], 1u);
     }
     __syncthreads();
     if (tid < 256) counts[(int64_t)tid * tiles + blockIdx.x] = cnt[tid];
 }
 
-__global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(8))) radix_scatter_kernel(const uint64_t *__restrict__ in, int64_t n,
+template <typename T>
+__global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(8))) radix_scatter_kernel(const T *__restrict__ in, int64_t n,
                                                                      int shift, int64_t tiles,
                                                                      const uint32_t *__restrict__ offsets,
-                                                                     uint64_t *__restrict__ out) {
-    constexpr int kChunk = kItems * kWave;       // records of one wave, consecutive
-    __shared__ uint64_t buf[kTile];              // the tile reordered by digit
+                                                                     T *__restrict__ out) {
+    constexpr int kItems = SortTile<T>::kItems;
+    constexpr int64_t kTile = SortTile<T>::kTile;
+    constexpr int kChunk = kItems * kWave;       // keys of one wave, consecutive
+    __shared__ T buf[kTile];                     // the tile reordered by digit
     __shared__ uint16_t wcnt[kSortWaves][256];   // per wave: digit counts, then the wave's offset per digit
     __shared__ uint32_t start[256];              // digit totals, then the first slot of each digit
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
@@ -81,15 +95,15 @@ __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_
 #pragma unroll
     for (int q = 0; q < 4; ++q) wcnt[wave][lane * 4 + q] = 0;  // the wave's own row
 
-    // wave w ranks records t0 + w*kChunk + j*64 + lane (j = 0..kItems-1), in
+    // wave w ranks keys t0 + w*kChunk + j*64 + lane (j = 0..kItems-1), in
     // that order: tile order, so the ranking is stable
-    uint64_t r[kItems];
+    T r[kItems];
     uint32_t rank[kItems];
     const int64_t wb = t0 + (int64_t)wave * kChunk;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int64_t i = wb + (int64_t)j * kWave + lane;
-        r[j] = i < n ? in[i] : ~0ull;  // past the end: digit 255, last in the tile, never written
+        r[j] = i < n ? in[i] : ~T(0);  // past the end: digit 255, last in the tile, never written
     }
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
@@ -151,7 +165,7 @@ __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_
     for (int j = 0; j < kItems; ++j) {
         const int s = j * kSortThreads + tid;
         if (s < valid) {
-            const uint64_t v = buf[s];
+            const T v = buf[s];
             const uint32_t d = digit_of(v, shift);
             out[(int64_t)offsets[(int64_t)d * tiles + blockIdx.x] + (s - start[d])] = v;
         }
@@ -281,37 +295,48 @@ int exclusive_scan_u32(uint32_t *a, int64_t n, uint32_t *sums, hipStream_t strea
     return ECC_OK;
 }
 
-int64_t radix_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
+int64_t radix_tiles(int64_t n, int elem) {
+    const int64_t t = elem == 4 ? SortTile<uint32_t>::kTile : SortTile<uint64_t>::kTile;
+    return (n + t - 1) / t;
+}
 int64_t radix_scan_tiles(int64_t entries) { return (entries + kScanTile - 1) / kScanTile; }
 
-// Sorts rec[0] in place, rec[1] being the other buffer (four passes: the
-// result ends where it started).  counts: 256 * radix_tiles(n) entries;
-// sums: radix_scan_tiles(256 * radix_tiles(n)) entries.
-int radix_sort_records(uint64_t *rec[2], int64_t n, uint32_t *counts, uint32_t *sums, hipStream_t stream) {
+// Four passes on the 32 bits from bit `low` up: v[0] ends sorted, v[1]
+// being the other buffer.
+template <typename T>
+static int radix_sort(T *v[2], int64_t n, int low, uint32_t *counts, uint32_t *sums, hipStream_t stream) {
     if (n <= 1) return ECC_OK;
     if (n > (int64_t)UINT32_MAX) {
-        set_error("radix sort: too many records");
+        set_error("radix sort: too many keys");
         return ECC_E_UNSUPPORTED;
     }
-    const int64_t tiles = radix_tiles(n);
+    const int64_t tiles = radix_tiles(n, (int)sizeof(T));
     int cur = 0;
     for (int pass = 0; pass < 4; ++pass) {
-        const int shift = 8 + 8 * pass;  // key bits 8..39
+        const int shift = low + 8 * pass;
         if (pass == 3)
-            hipLaunchKernelGGL(radix_count_kernel<true>, dim3((unsigned)tiles), dim3(kSortThreads), 0, stream,
-                               (const uint64_t *)rec[cur], n, shift, tiles, counts);
+            hipLaunchKernelGGL((radix_count_kernel<T, true>), dim3((unsigned)tiles), dim3(kSortThreads), 0, stream,
+                               (const T *)v[cur], n, shift, tiles, counts);
         else
-            hipLaunchKernelGGL(radix_count_kernel<false>, dim3((unsigned)tiles), dim3(kSortThreads), 0, stream,
-                               (const uint64_t *)rec[cur], n, shift, tiles, counts);
+            hipLaunchKernelGGL((radix_count_kernel<T, false>), dim3((unsigned)tiles), dim3(kSortThreads), 0, stream,
+                               (const T *)v[cur], n, shift, tiles, counts);
         ECC_HIP(hipGetLastError());
         int rc = exclusive_scan_u32(counts, 256 * tiles, sums, stream);
         if (rc) return rc;
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)tiles), dim3(kSortThreads), 0, stream,
-                           (const uint64_t *)rec[cur], n, shift, tiles, (const uint32_t *)counts, rec[cur ^ 1]);
+        hipLaunchKernelGGL((radix_scatter_kernel<T>), dim3((unsigned)tiles), dim3(kSortThreads), 0, stream,
+                           (const T *)v[cur], n, shift, tiles, (const uint32_t *)counts, v[cur ^ 1]);
         ECC_HIP(hipGetLastError());
         cur ^= 1;
     }
     return ECC_OK;
+}
+
+int radix_sort_keys(uint32_t *key[2], int64_t n, uint32_t *counts, uint32_t *sums, hipStream_t stream) {
+    return radix_sort<uint32_t>(key, n, 0, counts, sums, stream);
+}
+
+int radix_sort_records(uint64_t *rec[2], int64_t n, uint32_t *counts, uint32_t *sums, hipStream_t stream) {
+    return radix_sort<uint64_t>(rec, n, 32, counts, sums, stream);
 }
 
 }  // namespace ecc

@@ -52,6 +52,17 @@ def test_float_many_ties(ecc, shape):
     check(ecc, img.astype(np.float32))
 
 
+@pytest.mark.parametrize("shape,levels", [((40, 60, 80), 4), ((300, 700), 3), ((9, 10, 11, 120), 5),
+                                          ((50, 50, 50), 1)], ids=str)
+def test_float_few_values_long_slices(ecc, shape, levels):
+    """A handful of values over 10^5 voxels: one sorted-key tile owns each
+    value, with thousands of non-zero records each (more than a tile keeps
+    in LDS), and a constant image (one key, chi = 1)."""
+    rng = np.random.default_rng(13)
+    img = rng.integers(0, levels, size=shape).astype(np.float32) * np.float32(0.75)
+    check(ecc, img)
+
+
 def test_float_signed_zero_and_infinities(ecc):
     rng = np.random.default_rng(3)
     img = rng.choice(np.array([-0.0, 0.0, 1.5, -2.0, np.inf, -np.inf], dtype=np.float32), size=(9, 11, 70))
