@@ -62,31 +62,44 @@ constexpr bool earlier(int t) {
 
 __device__ __forceinline__ uint64_t ballot64(bool b) { return __builtin_amdgcn_ballot_w64(b); }
 
-// Visiting order of the 81 directions in 4-D (digit value 1 = zero offset):
-// blocks (digit 3, digit 2) in the order (1,1) (2,1) (1,2) (2,2) (1,0) (2,0)
-// (0,1) (0,2) (0,0), each block's nine (digit 0, digit 1) pairs by
-// increasing non-zeros.  A block depends on itself and on the blocks with one
-// or both outer digits set to 1, all visited before it.
-struct Order4 {
-    int t[81];
-    constexpr Order4() : t{} {
-        const int ba[9] = {1, 2, 1, 2, 1, 2, 0, 0, 0}, bb[9] = {1, 1, 2, 2, 0, 0, 1, 2, 0};
-        const int w0[9] = {1, 0, 2, 1, 1, 0, 2, 0, 2}, w1[9] = {1, 1, 1, 0, 2, 0, 0, 2, 2};
-        for (int k = 0; k < 81; ++k) t[k] = w0[k % 9] + 3 * w1[k % 9] + 9 * bb[k / 9] + 27 * ba[k / 9];
+// m = 2 m + (lane bit of mask): one VALU op, the mask is the carry-in (the
+// carry-out goes to a scratch scalar pair).
+__device__ __forceinline__ void push_bit(uint32_t &m, uint64_t mask) {
+    uint64_t co;
+    asm("v_addc_co_u32_e64 %0, %1, %0, %0, %2" : "+v"(m), "=&s"(co) : "s"(mask));
+}
+
+// Bit layout of the direction masks: word w, bit b holds direction
+// t = w * BW + b (BW = 3^min(D, 3) directions per word, NW words).
+template <int D>
+constexpr int kBW = D >= 3 ? 27 : pow3(D);
+template <int D>
+constexpr int kNW = D == 4 ? 3 : 1;
+// bits of a 27-bit word whose digit k is 1 (no offset along that axis)
+constexpr uint32_t mid_mask(int k) {
+    uint32_t m = 0;
+    for (int b = 0; b < 27; ++b)
+        if (digit3(b, k) == 1) m |= 1u << b;
+    return m;
+}
+constexpr uint32_t kMid[3] = {mid_mask(0), mid_mask(1), mid_mask(2)};
+// directions whose box enters the sum with sign +1 (PLUS) or -1, zero
+// direction excluded
+template <int D, bool PLUS>
+struct SignMasks {
+    uint32_t m[3];
+    constexpr SignMasks() : m{} {
+        for (int t = 0; t < pow3(D); ++t) {
+            if (t == (pow3(D) - 1) / 2) continue;
+            const bool even = ((D - nonzeros<D>(t)) & 1) == 0;
+            if (even == PLUS) m[t / kBW<D>] |= 1u << (t % kBW<D>);
+        }
     }
 };
-constexpr Order4 kOrder4{};
-
-// acc += lane bit of m  /  acc -= lane bit of m  (one VALU op each: the mask is
-// the carry-in; the carry-out goes to a scratch scalar pair)
-__device__ __forceinline__ void add_bit(int32_t &acc, uint64_t m) {
-    uint64_t co;
-    asm("v_addc_co_u32_e64 %0, %1, %0, 0, %2" : "+v"(acc), "=&s"(co) : "s"(m));
-}
-__device__ __forceinline__ void sub_bit(int32_t &acc, uint64_t m) {
-    uint64_t co;
-    asm("v_subb_co_u32_e64 %0, %1, %0, 0, %2" : "+v"(acc), "=&s"(co) : "s"(m));
-}
+template <int D>
+constexpr SignMasks<D, true> kPlus{};
+template <int D>
+constexpr SignMasks<D, false> kMinus{};
 
 struct FloatView {
     int32_t n[4];       // extents, axis 0 slowest, padded in front with 1
@@ -125,6 +138,7 @@ __global__ void __launch_bounds__(T) float_change_kernel(const float *__restrict
     constexpr int C = (P - 1) / 2;             // code of the zero direction
     constexpr int S = D >= 2 ? pow3(D - 2) : 1;  // lines per slot
     constexpr int PITCH = T + 2;
+    constexpr int BW = kBW<D>, NW = kNW<D>;
     __shared__ float ring[4 * S * PITCH];
     __shared__ uint32_t region_count;
     const int32_t nx = v.n[3], n2 = v.n[2];
@@ -208,52 +222,51 @@ __global__ void __launch_bounds__(T) float_change_kernel(const float *__restrict
         const uint32_t own_bits = __float_as_uint(f0);
         const uint32_t k0 = f32_key(own_bits);
 
-        // "Neighbour t precedes v" is computed where the recursion first needs
-        // it (level by level), so that only the U masks of two adjacent levels
-        // are live in scalar registers, not all 3^D - 1 comparison masks too.
-        auto prec = [&](int t) -> uint64_t {
-            const int dx = digit3(t, 0) - 1;
-            const int dyi = D >= 2 ? digit3(t, 1) : 1;
-            const int j = D >= 3 ? t / 9 : 0;
-            // IEEE comparisons: -0 == +0, infinities are ordinary values, NaN
-            // (an absent neighbour) never precedes; a NaN in the image fails the call
-            const float fn = col[dyi][j * PITCH + dx];
-            const bool p = earlier<D>(t) ? (fn <= f0) : (fn < f0);
-            return ballot64(p);
-        };
-        // U_s, each after the U it depends on, then the signed sum
-        uint64_t U[P];
-        U[C] = 0;  // the zero direction: empty box
-        int32_t acc = 0;
-        auto visit = [&](int t) {
-            uint64_t u = prec(t);
+        // Per lane, bit b of word w says whether neighbour t = w * BW + b
+        // precedes v (IEEE comparisons: -0 == +0, infinities are ordinary
+        // values, NaN (an absent neighbour) never precedes; a NaN in the image
+        // fails the call).  The zero direction's bit is 0.
+        uint32_t M[NW];
 #pragma unroll
-            for (int j = 0; j < D; ++j)
-                if (digit3(t, j) != 1) u |= U[t + (1 - digit3(t, j)) * pow3(j)];
-            U[t] = u;
-            // (-1)^dim, dim = D - (non-zero components): subtract for even dim
-            if (((D - nonzeros<D>(t)) & 1) == 0) add_bit(acc, u);
-            else sub_bit(acc, u);
-        };
-        if constexpr (D == 4) {
-            // blocks of nine by the two outer digits, in an order that lets
-            // each block's masks die early (at most five blocks live)
+        for (int w = 0; w < NW; ++w) {
+            uint32_t m = 0;
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
-                const int t = kOrder4.t[k];
-                if (t != C) visit(t);
-                // keep the scheduler from hoisting later blocks' compares
-                // (their masks would all be live at once and spill)
-                if (k % 9 == 8) __builtin_amdgcn_sched_barrier(0);
+            for (int b = BW - 1; b >= 0; --b) {
+                const int t = w * BW + b;
+                if (t == C) {
+                    m <<= 1;
+                    continue;
+                }
+                const int dx = digit3(t, 0) - 1;
+                const int dyi = D >= 2 ? digit3(t, 1) : 1;
+                const int j = D >= 3 ? t / 9 : 0;
+                const float fn = col[dyi][j * PITCH + dx];
+                push_bit(m, ballot64(earlier<D>(t) ? (fn <= f0) : (fn < f0)));
             }
-        } else {
-            // increasing numbers of non-zero components
-#pragma unroll
-            for (int lvl = 1; lvl <= D; ++lvl)
-#pragma unroll
-                for (int t = 0; t < P; ++t)
-                    if (nonzeros<D>(t) == lvl) visit(t);
+            M[w] = m;
         }
+        // U_t (some vertex of the box spanned by v and v + t, other than v,
+        // precedes v): the OR of the bits over the box's directions, taken
+        // axis by axis (the box is a product): every digit 0 or 2 receives
+        // the bit of the same direction with that digit set to 1 (no offset).
+#pragma unroll
+        for (int k = 0; k < (D < 3 ? D : 3); ++k) {
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t mid = M[w] & kMid[k];
+                M[w] |= (mid << pow3(k)) | (mid >> pow3(k));
+            }
+        }
+        if constexpr (D == 4) {
+            M[0] |= M[1];
+            M[2] |= M[1];
+        }
+        // the signed sum of the boxes that v completes, (-1)^dim each,
+        // dim = D - (non-zero components)
+        int32_t acc = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+            acc += (int32_t)__builtin_popcount(M[w] & kPlus<D>.m[w]) - (int32_t)__builtin_popcount(M[w] & kMinus<D>.m[w]);
         if (ballot64(act && (own_bits & 0x7FFFFFFFu) > 0x7F800000u) != 0 && (threadIdx.x & (kWave - 1)) == 0)
             atomicOr(status, kStatusNaN);
         const int32_t chg = 1 - acc;
