@@ -117,7 +117,9 @@ struct FloatView {
 // line by line.  The values of the 3^D neighbourhood come from LDS: a ring of
 // four slots, one per line position along axis 2, each holding the
 // S = 3^(D-2) lines at offsets -1, 0, +1 along the axes before it, over
-// x in [xs-1, xs+T].  While line y is compared, the loads for line y+2 are in
+// x in [xs-1, xs+T], x-major (the S values of one x are adjacent: a thread's
+// 3 S neighbours in a slot lie within 12 S bytes of one address, so one
+// address per slot serves all its reads).  While line y is compared, the loads for line y+2 are in
 // flight; each line is loaded once per workgroup (one coalesced load per
 // thread and line, plus one load for the two ends of all S lines), instead of
 // 3^D - 1 scattered loads per voxel.  Absent neighbours (outside the image)
@@ -144,9 +146,10 @@ __global__ void __launch_bounds__(T) float_change_kernel(const float *__restrict
     const int32_t nx = v.n[3], n2 = v.n[2];
     const int tid = (int)threadIdx.x;
     if (tid == 0) region_count = 0;  // (the first barrier below orders it)
-    const uint32_t region = (uint32_t)blockIdx.x * (uint32_t)(T * v.run);
     // block -> (outer line over axes 0..1, run along axis 2, x block); uniform
-    int32_t r = __builtin_amdgcn_readfirstlane((int32_t)blockIdx.x);
+    const uint32_t blk = blockIdx.x;
+    const uint32_t region = blk * (uint32_t)(T * v.run);
+    int32_t r = __builtin_amdgcn_readfirstlane((int32_t)blk);
     const int32_t xs = (r % v.bpr) * T;
     r /= v.bpr;
     const int32_t y0 = (r % v.nruns) * v.run;
@@ -201,8 +204,8 @@ __global__ void __launch_bounds__(T) float_change_kernel(const float *__restrict
     auto store = [&](int32_t y, const float (&val)[S], float end) {
         float *slot = ring + (y & 3) * (S * PITCH);
 #pragma unroll
-        for (int j = 0; j < S; ++j) slot[j * PITCH + 1 + tid] = val[j];
-        if (tid < 2 * S) slot[ej * PITCH + ((tid & 1) ? T + 1 : 0)] = end;
+        for (int j = 0; j < S; ++j) slot[(1 + tid) * S + j] = val[j];
+        if (tid < 2 * S) slot[((tid & 1) ? T + 1 : 0) * S + ej] = end;
     };
 
     float val[S], end;
@@ -217,8 +220,8 @@ __global__ void __launch_bounds__(T) float_change_kernel(const float *__restrict
         // this voxel's column in the three slots around y
         const float *col[3];
 #pragma unroll
-        for (int dy = 0; dy < 3; ++dy) col[dy] = ring + ((y - 1 + dy) & 3) * (S * PITCH) + 1 + tid;
-        const float f0 = col[1][(S / 2) * PITCH];
+        for (int dy = 0; dy < 3; ++dy) col[dy] = ring + ((y - 1 + dy) & 3) * (S * PITCH) + (1 + tid) * S;
+        const float f0 = col[1][S / 2];
         const uint32_t own_bits = __float_as_uint(f0);
         const uint32_t k0 = f32_key(own_bits);
 
@@ -240,7 +243,7 @@ __global__ void __launch_bounds__(T) float_change_kernel(const float *__restrict
                 const int dx = digit3(t, 0) - 1;
                 const int dyi = D >= 2 ? digit3(t, 1) : 1;
                 const int j = D >= 3 ? t / 9 : 0;
-                const float fn = col[dyi][j * PITCH + dx];
+                const float fn = col[dyi][dx * S + j];
                 push_bit(m, ballot64(earlier<D>(t) ? (fn <= f0) : (fn < f0)));
             }
             M[w] = m;
@@ -289,8 +292,8 @@ __global__ void __launch_bounds__(T) float_change_kernel(const float *__restrict
     }
     __syncthreads();
     if (tid == 0) {
-        nz_cnt[blockIdx.x] = region_count;
-        nz_off[blockIdx.x] = region_count;
+        nz_cnt[blk] = region_count;
+        nz_off[blk] = region_count;
     }
 }
 
@@ -656,7 +659,7 @@ __global__ void __launch_bounds__(256) slice_bounds_kernel(const uint32_t *__res
     bound[t] = t == 0 ? 0 : t == nt ? nnz : rec_bound<false>(rec, 0, nnz, key[t * kFTile]);
 }
 
-constexpr int kSliceCap = 2048;  // records of a tile's slice kept in LDS
+constexpr int kSliceCap = 512;  // records of a tile's slice kept in LDS (keys and prefixes)
 
 // The tile's distinct keys are gathered in LDS in rank order, then written
 // by all threads together: coalesced stores, and one slice search each.
@@ -669,6 +672,7 @@ __global__ void __launch_bounds__(kFThreads) curve_write_kernel(const uint32_t *
                                                                int64_t *__restrict__ out_chi, int64_t *kcount) {
     __shared__ uint32_t sk[kFTile + kFTile / 16 + 1];  // the tile's keys, then its distinct keys
     __shared__ uint32_t sl[kSliceCap];
+    __shared__ int64_t sp[kSliceCap + 1];  // sp[i] = P at record j0 + i - 1 (0 before the first)
     __shared__ uint32_t ws[kFThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t t0 = (int64_t)blockIdx.x * kFTile, t1 = t0 + kFTile;
@@ -681,8 +685,13 @@ __global__ void __launch_bounds__(kFThreads) curve_write_kernel(const uint32_t *
         sk[fpad(i)] = t0 + i < n ? key[t0 + i] : 0u;
     }
     if (tid == 0) sk[fpad(kFTile)] = t1 < n ? key[t1] : 0u;
-    if (in_lds)
-        for (int i = tid; i < (int)len; i += kFThreads) sl[i] = rec_key(rec[j0 + i]);
+    if (in_lds) {
+        for (int i = tid; i < (int)len; i += kFThreads) {
+            sl[i] = rec_key(rec[j0 + i]);
+            sp[i + 1] = prefix[j0 + i];
+        }
+        if (tid == 0) sp[0] = j0 > 0 ? prefix[j0 - 1] : 0;
+    }
     __syncthreads();
     const int r0 = tid * kFItems;
     uint32_t k[kFItems + 1];
@@ -717,7 +726,7 @@ __global__ void __launch_bounds__(kFThreads) curve_write_kernel(const uint32_t *
     if (tid == 0 && (int64_t)blockIdx.x == nt - 1) *kcount = base + cnt;
     for (uint32_t q = tid; q < cnt; q += kFThreads) {
         const uint32_t v = sk[q];
-        int64_t u;
+        int64_t chi;
         if (in_lds) {
             int lo = 0, hi = (int)len;
             while (lo < hi) {
@@ -725,12 +734,13 @@ __global__ void __launch_bounds__(kFThreads) curve_write_kernel(const uint32_t *
                 if (sl[mid] <= v) lo = mid + 1;
                 else hi = mid;
             }
-            u = j0 + lo;
+            chi = sp[lo];
         } else {
-            u = rec_bound<true>(rec, j0, j1, v);
+            const int64_t u = rec_bound<true>(rec, j0, j1, v);
+            chi = u > 0 ? prefix[u - 1] : 0;
         }
         out_keys[base + q] = key_to_f32(v);
-        out_chi[base + q] = u > 0 ? prefix[u - 1] : 0;
+        out_chi[base + q] = chi;
     }
 }
 

@@ -22,6 +22,15 @@ constexpr size_t kStatusBytes = 1024;
 constexpr size_t kStatusTotalsOffset = 128;
 constexpr size_t kStatusMinMaxOffset = 32;  // two words: minimum and maximum of a 16-bit image
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Logical index of workgroup b of a grid of G: the workgroups of one XCD
+// take one contiguous range of indices (a bijection of [0, G)), so that
+// neighbouring work shares an L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
+    const uint32_t q = G / 8, rem = G % 8, x = b % 8;
+    return x * q + (x < rem ? x : rem) + b / 8;
+}
+
 void set_error(const char *fmt, ...);
 void g_err_clear();
 int hip_fail(hipError_t e, const char *what);

@@ -17,6 +17,8 @@
 
 #include "ecc_internal.h"
 
+#include <algorithm>
+
 namespace ecc {
 
 constexpr int kSortThreads = 1024;
@@ -32,50 +34,62 @@ struct SortTile {
 template <typename T>
 __device__ __forceinline__ uint32_t digit_of(T r, int shift) { return (uint32_t)(r >> shift) & 255u; }
 
+// A count workgroup takes tpw <= kCountTiles consecutive tiles, so that its
+// counts leave as runs of tpw consecutive words of the digit-major table
+// (whole 64-byte lines at tpw = 16, instead of 256 scattered words per tile);
+// small sorts take fewer tiles per workgroup to keep the chip busy.
+constexpr int kCountTiles = 16;
+
 template <typename T, bool AGG>
 __global__ void __launch_bounds__(kSortThreads) radix_count_kernel(const T *__restrict__ rec, int64_t n,
-                                                                   int shift, int64_t tiles,
+                                                                   int shift, int64_t tiles, int tpw,
                                                                    uint32_t *__restrict__ counts) {
     constexpr int kItems = SortTile<T>::kItems;
     constexpr int64_t kTile = SortTile<T>::kTile;
-    __shared__ uint32_t cnt[256];
+    __shared__ uint32_t cnt[kCountTiles][257];  // (padded: the final transpose reads a column)
     const int tid = threadIdx.x;
-    if (tid < 256) cnt[tid] = 0;
+    for (int i = tid; i < kCountTiles * 257; i += kSortThreads) (&cnt[0][0])[i] = 0;
     __syncthreads();
-    const int64_t t0 = (int64_t)blockIdx.x * kTile;
     const int lane = tid & (kWave - 1);
-    T r[kItems];
+    const int64_t tb = (int64_t)blockIdx.x * tpw;
+    for (int k = 0; k < tpw && tb + k < tiles; ++k) {
+        const int64_t t0 = (tb + k) * kTile;
+        T r[kItems];
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        const int64_t i = t0 + (int64_t)j * kSortThreads + tid;
-        r[j] = i < n ? rec[i] : T(0);
-    }
-    // AGG (the top digit: sign and exponent, a handful of values): same-digit
-    // lanes would serialize on one LDS address, so up to four rounds take the
-    // digit of the lowest lane not yet counted and add all its lanes through
-    // that lane; what is left (many distinct digits) adds per lane.  On the
-    // low digits per-lane adds are cheaper.
+        for (int j = 0; j < kItems; ++j) {
+            const int64_t i = t0 + (int64_t)j * kSortThreads + tid;
+            r[j] = i < n ? rec[i] : T(0);
+        }
+        // AGG (the top digit: sign and exponent, a handful of values): same-digit
+        // lanes would serialize on one LDS address, so up to four rounds take the
+        // digit of the lowest lane not yet counted and add all its lanes through
+        // that lane; what is left (many distinct digits) adds per lane.  On the
+        // low digits per-lane adds are cheaper.
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        const int64_t i = t0 + (int64_t)j * kSortThreads + tid;
-        const bool ok = i < n;
-        const uint32_t d = digit_of(r[j], shift);
-        if constexpr (!AGG) {
-            if (ok) atomicAdd(&cnt[d], 1u);
-            continue;
+        for (int j = 0; j < kItems; ++j) {
+            const int64_t i = t0 + (int64_t)j * kSortThreads + tid;
+            const bool ok = i < n;
+            const uint32_t d = digit_of(r[j], shift);
+            if constexpr (!AGG) {
+                if (ok) atomicAdd(&cnt[k][d], 1u);
+                continue;
+            }
+            uint64_t rem = __builtin_amdgcn_ballot_w64(ok);
+            for (int it = 0; it < 4 && rem != 0; ++it) {
+                const int l0 = (int)__builtin_ctzll(rem);
+                const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d, l0);
+                const uint64_t m = __builtin_amdgcn_ballot_w64(d == d0) & rem;
+                if (lane == l0) atomicAdd(&cnt[k][d0], (uint32_t)__builtin_popcountll(m));
+                rem &= ~m;
+            }
+            if ((rem >> lane) & 1ull) atomicAdd(&cnt[k][d], 1u);
         }
-        uint64_t rem = __builtin_amdgcn_ballot_w64(ok);
-        for (int it = 0; it < 4 && rem != 0; ++it) {
-            const int l0 = (int)__builtin_ctzll(rem);
-            const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d, l0);
-            const uint64_t m = __builtin_amdgcn_ballot_w64(d == d0) & rem;
-            if (lane == l0) atomicAdd(&cnt[d0], (uint32_t)__builtin_popcountll(m));
-            rem &= ~m;
-        }
-        if ((rem >> lane) & 1ull) atomicAdd(&cnt[d], 1u);
     }
     __syncthreads();
-    if (tid < 256) counts[(int64_t)tid * tiles + blockIdx.x] = cnt[tid];
+    for (int i = tid; i < tpw * 256; i += kSortThreads) {
+        const int k = i % tpw, d = i / tpw;
+        if (tb + k < tiles) counts[(int64_t)d * tiles + tb + k] = cnt[k][d];
+    }
 }
 
 template <typename T>
@@ -89,9 +103,14 @@ __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_
     __shared__ T buf[kTile];                     // the tile reordered by digit
     __shared__ uint16_t wcnt[kSortWaves][256];   // per wave: digit counts, then the wave's offset per digit
     __shared__ uint32_t start[256];              // digit totals, then the first slot of each digit
+    __shared__ uint32_t dest[256];               // per digit: output position minus first slot
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
-    const int64_t t0 = (int64_t)blockIdx.x * kTile;
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // neighbouring tiles on one XCD: they read neighbouring words of the
+    // offset table and write neighbouring ends of each digit's runs
+    const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t t0 = (int64_t)tile * kTile;
+    // the tile's output position per digit, loaded while the tile is ranked
+    const uint32_t gpos = tid < 256 ? offsets[(int64_t)tid * tiles + tile] : 0u;
 #pragma unroll
     for (int q = 0; q < 4; ++q) wcnt[wave][lane * 4 + q] = 0;  // the wave's own row
 
@@ -108,17 +127,22 @@ __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const uint32_t d = digit_of(r[j], shift);
-        uint64_t peers = ~0ull;
+        // peers: the lanes whose digit equals this lane's, as two 32-bit
+        // halves; per bit, keep the lanes that agree with this lane's bit
+        // (sb: all ones where the bit is set)
+        uint32_t plo = ~0u, phi = ~0u;
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            const uint64_t m = __builtin_amdgcn_ballot_w64((d >> b) & 1u);
-            peers &= ((d >> b) & 1u) ? m : ~m;
+            const uint32_t sb = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+            const uint64_t m = __builtin_amdgcn_ballot_w64(sb != 0);
+            plo &= ~((uint32_t)m ^ sb);
+            phi &= ~((uint32_t)(m >> 32) ^ sb);
         }
-        const uint32_t rw = (uint32_t)__builtin_popcountll(peers & lt);
+        const uint32_t rw = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));  // peers below
         // the wave's own count row: LDS operations of one wave take effect in order
         const uint32_t base = wcnt[wave][d];
         rank[j] = base + rw;
-        if (rw == 0) wcnt[wave][d] = (uint16_t)(base + (uint32_t)__builtin_popcountll(peers));
+        if (rw == 0) wcnt[wave][d] = (uint16_t)(base + __builtin_popcount(plo) + __builtin_popcount(phi));
     }
     __syncthreads();
     if (tid < 256) {  // per digit: the waves' offsets and the digit's total
@@ -154,6 +178,7 @@ __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_
         }
     }
     __syncthreads();
+    if (tid < 256) dest[tid] = gpos - start[tid];  // (mod 2^32: positions are below 2^32)
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const uint32_t d = digit_of(r[j], shift);
@@ -167,7 +192,7 @@ __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_
         if (s < valid) {
             const T v = buf[s];
             const uint32_t d = digit_of(v, shift);
-            out[(int64_t)offsets[(int64_t)d * tiles + blockIdx.x] + (s - start[d])] = v;
+            out[dest[d] + (uint32_t)s] = v;
         }
     }
 }
@@ -311,15 +336,17 @@ static int radix_sort(T *v[2], int64_t n, int low, uint32_t *counts, uint32_t *s
         return ECC_E_UNSUPPORTED;
     }
     const int64_t tiles = radix_tiles(n, (int)sizeof(T));
+    const int tpw = (int)std::min<int64_t>(kCountTiles, std::max<int64_t>(1, tiles / 2048));
+    const unsigned cgrid = (unsigned)((tiles + tpw - 1) / tpw);
     int cur = 0;
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = low + 8 * pass;
         if (pass == 3)
-            hipLaunchKernelGGL((radix_count_kernel<T, true>), dim3((unsigned)tiles), dim3(kSortThreads), 0, stream,
-                               (const T *)v[cur], n, shift, tiles, counts);
+            hipLaunchKernelGGL((radix_count_kernel<T, true>), dim3(cgrid), dim3(kSortThreads), 0, stream,
+                               (const T *)v[cur], n, shift, tiles, tpw, counts);
         else
-            hipLaunchKernelGGL((radix_count_kernel<T, false>), dim3((unsigned)tiles), dim3(kSortThreads), 0, stream,
-                               (const T *)v[cur], n, shift, tiles, counts);
+            hipLaunchKernelGGL((radix_count_kernel<T, false>), dim3(cgrid), dim3(kSortThreads), 0, stream,
+                               (const T *)v[cur], n, shift, tiles, tpw, counts);
         ECC_HIP(hipGetLastError());
         int rc = exclusive_scan_u32(counts, 256 * tiles, sums, stream);
         if (rc) return rc;
