@@ -448,9 +448,9 @@ int launch_nz_compact(const uint32_t *nz_key, const int32_t *nz_chg, const uint3
 //     infinity for the first tile, to plus infinity for the last): those
 //     whose last position lies in the tile.  Its records are the ones in
 //     [lower_bound(key[i0]), lower_bound(key[i1])) (one binary search per
-//     tile, all tiles at once); each distinct key then searches only that
-//     slice, from LDS when it is short.  The last tile writes K (known on
-//     the device only).
+//     tile, all tiles at once); the tile's distinct keys then look only at
+//     that slice, from LDS when it is short.  The last tile writes K (known
+//     on the device only).
 
 constexpr int kFThreads = 256;
 constexpr int kFItems = 16;
@@ -659,10 +659,22 @@ __global__ void __launch_bounds__(256) slice_bounds_kernel(const uint32_t *__res
     bound[t] = t == 0 ? 0 : t == nt ? nnz : rec_bound<false>(rec, 0, nnz, key[t * kFTile]);
 }
 
-constexpr int kSliceCap = 512;  // records of a tile's slice kept in LDS (keys and prefixes)
+// Records of a tile's slice kept in LDS (keys and prefixes): short slices
+// (most tiles) in a small copy that leaves room for many workgroups per CU;
+// the long ones (the tiles of the lowest and highest values, where the
+// critical points gather) in a second launch with a large copy.
+constexpr int kShortSlice = 512;
+constexpr int kLongSlice = 4096;
 
-// The tile's distinct keys are gathered in LDS in rank order, then written
-// by all threads together: coalesced stores, and one slice search each.
+// Thread t takes the run of kFItems sorted keys at t * kFItems of the tile
+// (16-byte loads; the key after the run from the next lane, or from memory
+// for the wave's last lane) and puts its distinct keys, in rank order, into
+// LDS; the workgroup then takes them one per thread at a time (a binary
+// search of the slice each, coalesced stores).  LONG = false takes the tiles
+// whose slice has at most kShortSlice records, LONG = true the others: up to
+// kLongSlice from LDS, beyond that (images with very few distinct values) one
+// binary search in memory per distinct key.
+template <bool LONG>
 __global__ void __launch_bounds__(kFThreads) curve_write_kernel(const uint32_t *__restrict__ key, int64_t n,
                                                                int64_t nt, const uint32_t *__restrict__ tile_base,
                                                                const int64_t *__restrict__ bound,
@@ -670,21 +682,40 @@ __global__ void __launch_bounds__(kFThreads) curve_write_kernel(const uint32_t *
                                                                const int64_t *__restrict__ prefix,
                                                                float *__restrict__ out_keys,
                                                                int64_t *__restrict__ out_chi, int64_t *kcount) {
-    __shared__ uint32_t sk[kFTile + kFTile / 16 + 1];  // the tile's keys, then its distinct keys
-    __shared__ uint32_t sl[kSliceCap];
-    __shared__ int64_t sp[kSliceCap + 1];  // sp[i] = P at record j0 + i - 1 (0 before the first)
+    constexpr int CAP = LONG ? kLongSlice : kShortSlice;
+    __shared__ uint32_t sl[CAP];
+    __shared__ int64_t sp[CAP + 1];  // sp[i] = P at record j0 + i - 1 (0 before the first)
+    __shared__ uint32_t ck[kFTile];   // the tile's distinct keys
     __shared__ uint32_t ws[kFThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t t0 = (int64_t)blockIdx.x * kFTile, t1 = t0 + kFTile;
+    const int64_t t0 = (int64_t)blockIdx.x * kFTile;
     const int64_t j0 = bound[blockIdx.x], j1 = bound[blockIdx.x + 1];
     const int64_t len = j1 - j0;
-    const bool in_lds = len <= kSliceCap;  // (uniform)
+    if ((len > kShortSlice) != LONG) return;  // (uniform) the other launch's tile
+    const bool in_lds = len <= CAP;
+    const int64_t base = tile_base[blockIdx.x];
+    const int64_t i0 = t0 + (int64_t)tid * kFItems;
+    uint32_t k[kFItems + 1];
+    static_assert(kFItems % 4 == 0, "runs of whole 16-byte groups");
+    if ((reinterpret_cast<uintptr_t>(key) & 15u) == 0 && i0 + kFItems <= n) {
+        const uint4 *k4 = reinterpret_cast<const uint4 *>(key + i0);
 #pragma unroll
-    for (int j = 0; j < kFItems; ++j) {  // coalesced: the tile and the key after it
-        const int i = j * kFThreads + tid;
-        sk[fpad(i)] = t0 + i < n ? key[t0 + i] : 0u;
+        for (int q = 0; q < kFItems / 4; ++q) {
+            const uint4 w = k4[q];
+            k[4 * q] = w.x;
+            k[4 * q + 1] = w.y;
+            k[4 * q + 2] = w.z;
+            k[4 * q + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kFItems; ++j) k[j] = i0 + j < n ? key[i0 + j] : 0u;
     }
-    if (tid == 0) sk[fpad(kFTile)] = t1 < n ? key[t1] : 0u;
+    {
+        const uint32_t nx = __shfl_down(k[0], 1, 64);  // the next lane's first key
+        const int64_t after = i0 + kFItems;
+        k[kFItems] = lane < 63 ? nx : (after < n ? key[after] : 0u);
+    }
     if (in_lds) {
         for (int i = tid; i < (int)len; i += kFThreads) {
             sl[i] = rec_key(rec[j0 + i]);
@@ -692,16 +723,11 @@ __global__ void __launch_bounds__(kFThreads) curve_write_kernel(const uint32_t *
         }
         if (tid == 0) sp[0] = j0 > 0 ? prefix[j0 - 1] : 0;
     }
-    __syncthreads();
-    const int r0 = tid * kFItems;
-    uint32_t k[kFItems + 1];
-#pragma unroll
-    for (int j = 0; j <= kFItems; ++j) k[j] = sk[fpad(r0 + j)];
     uint32_t s = 0;
     bool last[kFItems];
 #pragma unroll
     for (int j = 0; j < kFItems; ++j) {
-        const int64_t i = t0 + r0 + j;
+        const int64_t i = i0 + j;
         last[j] = i < n && (i == n - 1 || k[j] != k[j + 1]);
         s += last[j];
     }
@@ -712,23 +738,29 @@ __global__ void __launch_bounds__(kFThreads) curve_write_kernel(const uint32_t *
         if (lane >= off) x += u;
     }
     if (lane == 63) ws[wave] = x;
-    __syncthreads();  // (also: every thread has read its keys from sk)
-    uint32_t r = x - s, cnt = 0;
+    __syncthreads();  // (also: the slice is staged)
+    int64_t r = base + x - s;
+    uint32_t cnt = 0;
     for (int w = 0; w < kFThreads / 64; ++w) {
         if (w < wave) r += ws[w];
         cnt += ws[w];
     }
-#pragma unroll
-    for (int j = 0; j < kFItems; ++j)
-        if (last[j]) sk[r++] = k[j];
-    __syncthreads();
-    const int64_t base = tile_base[blockIdx.x];
     if (tid == 0 && (int64_t)blockIdx.x == nt - 1) *kcount = base + cnt;
+    // the tile's distinct keys in rank order, then one per thread at a time:
+    // a binary search of the slice each, coalesced stores
+    const uint32_t rl = (uint32_t)(r - base);
+    {
+        uint32_t q = rl;
+#pragma unroll
+        for (int j = 0; j < kFItems; ++j)
+            if (last[j]) ck[q++] = k[j];
+    }
+    __syncthreads();
     for (uint32_t q = tid; q < cnt; q += kFThreads) {
-        const uint32_t v = sk[q];
+        const uint32_t v = ck[q];
         int64_t chi;
         if (in_lds) {
-            int lo = 0, hi = (int)len;
+            int lo = 0, hi = (int)len;  // first record above v
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
                 if (sl[mid] <= v) lo = mid + 1;
@@ -772,7 +804,11 @@ int launch_float_curve(const uint32_t *key, int64_t n, const uint64_t *rec, int6
     hipLaunchKernelGGL(slice_bounds_kernel, dim3((unsigned)((nt + 256) / 256)), dim3(256), 0, stream, key, n, nt, rec,
                        nnz, bound);
     ECC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(curve_write_kernel, dim3((unsigned)nt), dim3(kFThreads), 0, stream, key, n, nt,
+    hipLaunchKernelGGL(curve_write_kernel<false>, dim3((unsigned)nt), dim3(kFThreads), 0, stream, key, n, nt,
+                       (const uint32_t *)tile_cnt, (const int64_t *)bound, rec, (const int64_t *)prefix, out_keys,
+                       out_chi, kcount);
+    ECC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(curve_write_kernel<true>, dim3((unsigned)nt), dim3(kFThreads), 0, stream, key, n, nt,
                        (const uint32_t *)tile_cnt, (const int64_t *)bound, rec, (const int64_t *)prefix, out_keys,
                        out_chi, kcount);
     ECC_HIP(hipGetLastError());

@@ -63,6 +63,15 @@ def test_float_few_values_long_slices(ecc, shape, levels):
     check(ecc, img)
 
 
+@pytest.mark.parametrize("shape", [(40, 40, 40, 40), (120, 130, 140)], ids=str)
+def test_float_iid_noise_dense_records(ecc, shape):
+    """Independent uniform values: critical points everywhere, so a tile of
+    sorted keys owns hundreds to thousands of non-zero records (the long-slice
+    launch, from LDS)."""
+    img = np.random.default_rng(14).random(shape, dtype=np.float32)
+    check(ecc, img)
+
+
 def test_float_signed_zero_and_infinities(ecc):
     rng = np.random.default_rng(3)
     img = rng.choice(np.array([-0.0, 0.0, 1.5, -2.0, np.inf, -np.inf], dtype=np.float32), size=(9, 11, 70))
