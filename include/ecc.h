@@ -99,8 +99,10 @@ int ecc_compute(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_cu
  * <= t, for t = 0..m-1.  These cell sets are not complexes in general (a face
  * can enter after the cell it bounds); chi[m-1] = 1 (the whole box).
  * Computed as the change vector of m-1-v read back reversed: the cells whose
- * maximum is t are those whose minimum of m-1-v is m-1-t.
- * Integer dtypes only; arguments, synchronisation and errors as
+ * maximum is t are those whose minimum of m-1-v is m-1-t.  Images with four
+ * axes longer than 1 go through the float path on m-1-v: chi[t] = 1 minus
+ * that image's curve at m-2-t.
+ * Integer dtypes u8 and u14; arguments, synchronisation and errors as
  * ecc_compute (ECC_E_UNSUPPORTED for ECC_F32 and ECC_U16). */
 int ecc_compute_max_entry(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_curve *curve,
                           void *stream);
@@ -138,12 +140,12 @@ int ecc_compute_quantized(const float *image, const ecc_dims *dims, float lo, fl
  * neighbouring indices (edges join voxels that share a (d-1)-face:
  * 4-connectivity in 2-D, 6 in 3-D); a cell enters at the maximum of the
  * image over its vertices.  chi[t] = chi of the cells with value <= t, for
- * t = 0..m-1.  Axes of length 1 are dropped; at most three may remain.
+ * t = 0..m-1.  Axes of length 1 are dropped (one to four may remain).
  * Computed from the largest-value convention of the image and of every face
- * of its box (inclusion-exclusion over the faces, (-1)^codim).
+ * of its box (inclusion-exclusion over the faces, (-1)^codim; the full box
+ * of a 4-D image through the float path, as ecc_compute_max_entry).
  * Integer dtypes u8 and u14; arguments, synchronisation and errors as
- * ecc_compute (ECC_E_UNSUPPORTED for ECC_F32, ECC_U16, or more than three
- * axes longer than 1). */
+ * ecc_compute (ECC_E_UNSUPPORTED for ECC_F32 and ECC_U16). */
 int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, ecc_curve *curve, void *stream);
 
 /* Stream-ordered form for integer types with device-resident data: enqueues
@@ -219,7 +221,10 @@ void ecc_autotune_reset(void);
  * (the previous chunk's last plane is kept on the device; each chunk's own
  * last plane waits for the next chunk); the changes vector stays on the
  * device and the prefix sum is taken once in ecc_stream_finish.
- * Integer dtypes only. */
+ * Integer dtypes.  ECC_U16 (m = 65536): every chunk launch runs once per
+ * window of 16384 values (five windows over the whole range, Sec. 3, "Range
+ * of Values"), each window's bins added to the changes vector.  Planes with
+ * three axes longer than 1 (4-D images): ECC_E_UNSUPPORTED. */
 typedef struct ecc_stream ecc_stream;
 
 /* Starts a stream for an image of full_dims (ndim 1..4).  The handle owns

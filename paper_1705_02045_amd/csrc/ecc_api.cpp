@@ -363,12 +363,7 @@ static int enqueue_int(const void *image_dev, const IntView &v, int dtype, int64
 // bins are dropped; the monotone clamp keeps every comparison that decides a
 // kept bin (each involves the counted value itself).  Each pass's column
 // sums go to their place in the 65536-bin changes vector, scanned once.
-struct U16Window {
-    int32_t shift;
-    int klo, khi;
-};
-
-static int plan_u16_windows(uint32_t vmin, uint32_t vmax, U16Window *w) {
+int plan_u16_windows(uint32_t vmin, uint32_t vmax, U16Window *w) {
     int n = 0;
     int64_t v = vmin;
     while (v <= (int64_t)vmax) {
@@ -381,8 +376,6 @@ static int plan_u16_windows(uint32_t vmin, uint32_t vmax, U16Window *w) {
     }
     return n;
 }
-
-constexpr int kU16MaxWindows = 5;  // 16383 + 3 * 16382 + 16383 >= 65536
 
 static int enqueue_u16(const void *image_dev, const IntView &v, int64_t *chi_dev, uint32_t *status_out,
                        hipStream_t stream, Workspace *ws, uint32_t vmin, uint32_t vmax) {
@@ -482,31 +475,28 @@ static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc
 // Integer images the integer kernel does not take (four axes longer than 1):
 // exact through the float path, whose curve is a step function over the
 // image's distinct values; chi(T_t) is its value at the largest distinct
-// value <= t.
-static int compute_int_via_float(const void *image, const ecc_dims *dims, int64_t total, ecc_dtype dtype,
-                                 ecc_curve *curve, hipStream_t s) {
+// value <= t.  max_entry: the float path runs on the inverted image (values
+// m - 1 - v) and the result is reflected (launch_reflect_curve).  out_dev
+// receives m int64: the curve, or with changes (max_entry only) the changes
+// vector.  img_dev is device memory.
+static int int_via_float_dev(const void *img_dev, const ecc_dims *dims, int64_t total, ecc_dtype dtype,
+                             bool max_entry, bool changes, int64_t *out_dev, hipStream_t s, Workspace *ws) {
     const int64_t m = threshold_count(dtype);
-    Workspace *ws = nullptr;
-    int rc = get_workspace(s, &ws);
-    if (rc) return rc;
+    if (total > (int64_t)UINT32_MAX) {
+        set_error("integer path: image too large for the float path");
+        return ECC_E_UNSUPPORTED;
+    }
     const size_t eb = elem_bytes(dtype);
-    // dual_buf: the float image, the float curve (keys, chi), the expanded curve
+    // i2f_buf: the float image, the float curve (keys, chi), the expanded curve
     const size_t o_keys = align256((size_t)total * 4), o_chi = o_keys + align256((size_t)total * 4);
     const size_t o_out = o_chi + align256((size_t)total * 8);
-    rc = ensure_bytes(&ws->dual_buf, &ws->dual_buf_bytes, o_out + (size_t)m * 8);
+    int rc = ensure_bytes(&ws->i2f_buf, &ws->i2f_buf_bytes, o_out + (size_t)m * 8);
     if (rc) return rc;
-    uint8_t *buf = (uint8_t *)ws->dual_buf;
-    const void *img_dev = image;
-    if (!is_device_ptr(image)) {
-        rc = ensure_bytes(&ws->img_tmp, &ws->img_tmp_bytes, (size_t)total * eb);
-        if (rc) return rc;
-        ECC_HIP(hipMemcpyAsync(ws->img_tmp, image, (size_t)total * eb, hipMemcpyHostToDevice, s));
-        img_dev = ws->img_tmp;
-    }
+    uint8_t *buf = (uint8_t *)ws->i2f_buf;
     uint32_t *flag = ws->status + kStatusMinMaxOffset / 4 + 3;
     rc = launch_zero(flag, 4, s);
     if (rc) return rc;
-    rc = launch_int_to_f32(img_dev, (int)eb, total, (uint32_t)m, (float *)buf, flag, s);
+    rc = launch_int_to_f32(img_dev, (int)eb, total, (uint32_t)m, max_entry ? 1 : 0, (float *)buf, flag, s);
     if (rc) return rc;
     uint32_t bad = 0;
     ECC_HIP(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, s));
@@ -521,10 +511,32 @@ static int compute_int_via_float(const void *image, const ecc_dims *dims, int64_
     fc.chi = (int64_t *)(buf + o_chi);
     rc = compute_float(buf, dims, total, &fc, s, false);
     if (rc) return rc;
-    int64_t *out = (int64_t *)(buf + o_out);
-    rc = launch_expand_steps(fc.keys, fc.chi, fc.count, (int)m, out, s);
+    int64_t *g = max_entry ? (int64_t *)(buf + o_out) : out_dev;
+    rc = launch_expand_steps(fc.keys, fc.chi, fc.count, (int)m, g, s);
     if (rc) return rc;
-    ECC_HIP(hipMemcpyAsync(curve->chi, out, (size_t)m * 8, hipMemcpyDefault, s));
+    if (max_entry) return launch_reflect_curve(g, (int)m, changes ? 1 : 0, out_dev, s);
+    return ECC_OK;
+}
+
+static int compute_int_via_float(const void *image, const ecc_dims *dims, int64_t total, ecc_dtype dtype,
+                                 ecc_curve *curve, hipStream_t s, bool max_entry) {
+    const int64_t m = threshold_count(dtype);
+    Workspace *ws = nullptr;
+    int rc = get_workspace(s, &ws);
+    if (rc) return rc;
+    const size_t eb = elem_bytes(dtype);
+    const void *img_dev = image;
+    if (!is_device_ptr(image)) {
+        rc = ensure_bytes(&ws->img_tmp, &ws->img_tmp_bytes, (size_t)total * eb);
+        if (rc) return rc;
+        ECC_HIP(hipMemcpyAsync(ws->img_tmp, image, (size_t)total * eb, hipMemcpyHostToDevice, s));
+        img_dev = ws->img_tmp;
+    }
+    rc = ensure_bytes((void **)&ws->chi_tmp, &ws->chi_tmp_bytes, (size_t)m * 8);
+    if (rc) return rc;
+    rc = int_via_float_dev(img_dev, dims, total, dtype, max_entry, false, ws->chi_tmp, s, ws);
+    if (rc) return rc;
+    ECC_HIP(hipMemcpyAsync(curve->chi, ws->chi_tmp, (size_t)m * 8, hipMemcpyDefault, s));
     ECC_HIP(hipStreamSynchronize(s));
     curve->count = m;
     return ECC_OK;
@@ -552,7 +564,7 @@ static int compute_int(const void *image, const ecc_dims *dims, int64_t total, e
     IntView v{};
     int unsup = 0;
     if (!normalize_int_view(dims, &v, &unsup)) {
-        if (!max_entry && total <= (int64_t)UINT32_MAX) return compute_int_via_float(image, dims, total, dtype, curve, s);
+        if (total <= (int64_t)UINT32_MAX) return compute_int_via_float(image, dims, total, dtype, curve, s, max_entry);
         set_error("integer path: shape not supported (4 axes longer than 1, or an extent beyond 2^31)");
         return ECC_E_UNSUPPORTED;
     }
@@ -1111,10 +1123,8 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
     int d = 0;
     for (int k = 0; k < dims->ndim; ++k)
         if (dims->n[k] > 1) n[d++] = dims->n[k];
-    if (d > 3) {
-        set_error("ecc_compute_dual: at most three axes longer than 1");
-        return ECC_E_UNSUPPORTED;
-    }
+    // (d <= 4: the full box of a 4-D image goes through the float path, its
+    // faces of at most three dimensions through the integer kernel)
     hipStream_t s = (hipStream_t)stream;
     Workspace *ws = nullptr;
     rc = get_workspace(s, &ws);
@@ -1129,7 +1139,7 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
     }
     int nf = 1;
     for (int k = 0; k < d; ++k) nf *= 3;
-    int64_t st[3] = {1, 1, 1};  // element strides of the kept axes
+    int64_t st[4] = {1, 1, 1, 1};  // element strides of the kept axes
     for (int k = d - 2; k >= 0; --k) st[k] = st[k + 1] * n[k + 1];
     int64_t face_max = 1;  // the largest face of codimension >= 1
     for (int k = 0; k < d; ++k)
@@ -1146,16 +1156,17 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
     LowFace *low_dev = (LowFace *)((uint8_t *)ws->dual_buf + low_off);
     uint8_t *face = (uint8_t *)ws->dual_buf + face_off;
     const int gsign = (d & 1) ? -1 : 1;
-    uint64_t neg = 0, skip = 0;
+    uint64_t neg[2] = {0, 0}, skip[2] = {0, 0};  // bit f of the pair: face f
+    auto set_bit = [](uint64_t *mask, int f) { mask[f >> 6] |= 1ull << (f & 63); };
     // Box edges and corners (faces of at most one dimension, below the full
     // box) have a closed-form changes vector; they are added by one launch
     // after the signed sum instead of a gather, a kernel and a merge each.
     std::vector<LowFace> low;
     for (int f = 0; f < nf; ++f) {
-        int code[3] = {0, 0, 0};
+        int code[4] = {0, 0, 0, 0};
         for (int k = 0, r = f; k < d; ++k, r /= 3) code[k] = r % 3;
         int codim = 0, nfree = 0;
-        int64_t base = 0, fs[3] = {1, 1, 1}, fst[3] = {0, 0, 0};
+        int64_t base = 0, fs[4] = {1, 1, 1, 1}, fst[4] = {0, 0, 0, 0};
         for (int k = 0; k < d; ++k) {
             if (code[k] == 0) {
                 fs[nfree] = n[k];
@@ -1173,7 +1184,15 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
             L.len = nfree ? fs[0] : 0;
             L.sign = (codim & 1) ? -gsign : gsign;
             low.push_back(L);
-            skip |= 1ull << f;
+            set_bit(skip, f);
+            continue;
+        }
+        if (nfree == 4) {  // the whole 4-D box
+            ecc_dims bd{};
+            bd.ndim = 4;
+            for (int k = 0; k < 4; ++k) bd.n[k] = n[k];
+            rc = int_via_float_dev(img_dev, &bd, total, dtype, true, true, curves + (size_t)f * m, s, ws);
+            if (rc) return rc;
             continue;
         }
         const void *src = img_dev;
@@ -1206,7 +1225,7 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
         }
         rc = enqueue_int_changes(src, v, dtype, curves + (size_t)f * m, s, ws, true, pstride);
         if (rc) return rc;
-        if (codim & 1) neg |= 1ull << f;
+        if (codim & 1) set_bit(neg, f);
     }
     rc = launch_signed_sum(curves, nf, neg, skip, gsign, (int)m, result, s);
     if (rc) return rc;

@@ -869,30 +869,33 @@ int launch_change_points(const float *keys, const int64_t *chi, int64_t K, uint3
 // float curve lists chi after each distinct value, and chi(T_t) for integer
 // t is its value at the largest distinct value <= t (0 below the first).
 
+// invert: writes limit - 1 - v (the image whose smallest-value curve gives
+// the largest-value curve, see launch_reflect_curve); values >= limit set
+// the status bit either way.
 template <typename T>
 __global__ void __launch_bounds__(256) int_to_f32_kernel(const T *__restrict__ img, int64_t n, uint32_t limit,
-                                                         float *__restrict__ out, uint32_t *status) {
+                                                         int invert, float *__restrict__ out, uint32_t *status) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     bool bad = false;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const uint32_t v = img[i];
         bad |= v >= limit;
-        out[i] = (float)v;
+        out[i] = invert ? (float)((int32_t)limit - 1 - (int32_t)v) : (float)v;
     }
     if (__builtin_amdgcn_ballot_w64(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(status, kStatusRange);
 }
 
-int launch_int_to_f32(const void *img, int elem, int64_t n, uint32_t limit, float *out, uint32_t *status,
-                      hipStream_t stream) {
+int launch_int_to_f32(const void *img, int elem, int64_t n, uint32_t limit, int invert, float *out,
+                      uint32_t *status, hipStream_t stream) {
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
     if (elem == 1)
         hipLaunchKernelGGL(int_to_f32_kernel<uint8_t>, dim3((unsigned)blocks), dim3(256), 0, stream,
-                           (const uint8_t *)img, n, limit, out, status);
+                           (const uint8_t *)img, n, limit, invert, out, status);
     else
         hipLaunchKernelGGL(int_to_f32_kernel<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, stream,
-                           (const uint16_t *)img, n, limit, out, status);
+                           (const uint16_t *)img, n, limit, invert, out, status);
     ECC_HIP(hipGetLastError());
     return ECC_OK;
 }
@@ -915,6 +918,27 @@ __global__ void __launch_bounds__(256) expand_steps_kernel(const float *__restri
 int launch_expand_steps(const float *keys, const int64_t *chi, int64_t K, int m, int64_t *out,
                         hipStream_t stream) {
     hipLaunchKernelGGL(expand_steps_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, keys, chi, K, m, out);
+    ECC_HIP(hipGetLastError());
+    return ECC_OK;
+}
+
+// Largest-value convention from the smallest-value curve g of the inverted
+// image (values m - 1 - v): a cell's largest value is <= t exactly when its
+// smallest inverted value is >= m - 1 - t, so the cells counted at t are all
+// cells (the whole box, chi = 1) less those counted in g at m - 2 - t:
+//   curve:   out[t] = 1 - g[m - 2 - t]
+//   changes: out[t] = g[m - 1 - t] - g[m - 2 - t]
+// (g[-1] = 0).
+__global__ void __launch_bounds__(256) reflect_curve_kernel(const int64_t *__restrict__ g, int m, int changes,
+                                                            int64_t *__restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    const int64_t below = t <= m - 2 ? g[m - 2 - t] : 0;
+    out[t] = changes ? g[m - 1 - t] - below : 1 - below;
+}
+
+int launch_reflect_curve(const int64_t *g, int m, int changes, int64_t *out, hipStream_t stream) {
+    hipLaunchKernelGGL(reflect_curve_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, g, m, changes, out);
     ECC_HIP(hipGetLastError());
     return ECC_OK;
 }

@@ -110,6 +110,8 @@ struct Workspace {
     size_t frec_bytes = 0;
     void *dual_buf = nullptr;    // dual complex: gathered faces of the box, per-face curves
     size_t dual_buf_bytes = 0;
+    void *i2f_buf = nullptr;     // integer images through the float path: float copy, float curve, expanded curve
+    size_t i2f_buf_bytes = 0;
     int64_t *vcec16 = nullptr;   // [65536] changes vector of a 16-bit image (window passes)
     size_t vcec16_bytes = 0;
     // Fixed scratch (the entry point that allocates nothing): the buffers
@@ -145,6 +147,19 @@ IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes, int max
 int launch_int_partial(const IntJob &job, const IntTiling &tl, int32_t *partial, uint32_t *status,
                        int64_t *zero_vcec, hipStream_t stream);
 int launch_zero(void *p, size_t bytes, hipStream_t stream);
+// dst[i] += src[i], i < n (ecc_scan.hip).
+int launch_add_i64(int64_t *dst, const int64_t *src, int64_t n, hipStream_t stream);
+// 16-bit images (m = 65536): one launch counts one window of 16384 bins,
+// bin = clamp(v - shift, 0, 16383); bins [klo, khi] are values
+// [shift + klo, shift + khi] (bin 0 / 16383 are guards where values lie
+// below / above the window).  Windows for values [vmin, vmax], at most
+// kU16MaxWindows; returns their number.
+struct U16Window {
+    int32_t shift;
+    int klo, khi;
+};
+constexpr int kU16MaxWindows = 5;  // 16383 + 3 * 16382 + 16383 >= 65536
+int plan_u16_windows(uint32_t vmin, uint32_t vmax, U16Window *w);
 // Column sums of the per-workgroup rows into vcec through int64 stage rows
 // ([merge_stage_rows(rows)][m]) and, with do_scan, the prefix sum of vcec into
 // chi (ecc_scan.hip).  The scan copies the status word to status_out (when
@@ -161,8 +176,9 @@ int launch_gather(const void *src, int elem, int64_t base, int64_t s0, int64_t s
 // Minimum and maximum of n uint16 values into out[0], out[1].
 int launch_minmax_u16(const uint16_t *img, int64_t n, uint32_t *out, hipStream_t stream);
 // out[t] = sign * sum_f (-1)^((neg_mask >> f) & 1) * curves[f * m + t], t < m.
-int launch_signed_sum(const int64_t *curves, int nf, uint64_t neg_mask, uint64_t skip_mask, int sign, int m,
-                      int64_t *out, hipStream_t stream);
+// (faces f < 128: bit f of the pair {mask[0], mask[1]})
+int launch_signed_sum(const int64_t *curves, int nf, const uint64_t neg_mask[2], const uint64_t skip_mask[2],
+                      int sign, int m, int64_t *out, hipStream_t stream);
 // A face of the box of at most one dimension: elements base + i * stride,
 // i < len (len = 0: a corner, the single element at base), added with sign.
 struct LowFace {
@@ -249,9 +265,13 @@ int exclusive_scan_u32(uint32_t *a, int64_t n, uint32_t *sums, hipStream_t strea
 // Keys where chi changes, compacted (count written on the device).
 int launch_change_points(const float *keys, const int64_t *chi, int64_t K, uint32_t *pos, uint32_t *sums,
                          float *out_keys, int64_t *out_chi, int64_t *count, hipStream_t stream);
-// Integer image (elem = 1 or 2 bytes) to float32; values >= limit set kStatusRange.
-int launch_int_to_f32(const void *img, int elem, int64_t n, uint32_t limit, float *out, uint32_t *status,
-                      hipStream_t stream);
+// Integer image (elem = 1 or 2 bytes) to float32 (invert: limit - 1 - v);
+// values >= limit set kStatusRange.
+int launch_int_to_f32(const void *img, int elem, int64_t n, uint32_t limit, int invert, float *out,
+                      uint32_t *status, hipStream_t stream);
+// Largest-value curve (changes = 0) or changes vector (changes = 1) from the
+// smallest-value curve g of the inverted image, m entries.
+int launch_reflect_curve(const int64_t *g, int m, int changes, int64_t *out, hipStream_t stream);
 // out[t] = chi at the largest key <= t (0 below keys[0]), t < m.
 int launch_expand_steps(const float *keys, const int64_t *chi, int64_t K, int m, int64_t *out,
                         hipStream_t stream);

@@ -341,24 +341,44 @@ int launch_gather(const void *src, int elem, int64_t base, int64_t s0, int64_t s
     return ECC_OK;
 }
 
-__global__ void __launch_bounds__(256) signed_sum_kernel(const int64_t *__restrict__ curves, int nf, uint64_t neg_mask,
-                                                         uint64_t skip_mask, int sign, int m,
-                                                         int64_t *__restrict__ out) {
+__global__ void __launch_bounds__(256) signed_sum_kernel(const int64_t *__restrict__ curves, int nf, uint64_t neg0,
+                                                         uint64_t neg1, uint64_t skip0, uint64_t skip1, int sign,
+                                                         int m, int64_t *__restrict__ out) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m) return;
     int64_t acc = 0;
     for (int f = 0; f < nf; ++f) {
-        if ((skip_mask >> f) & 1) continue;
+        const uint64_t skip = f < 64 ? skip0 >> f : skip1 >> (f - 64);
+        const uint64_t neg = f < 64 ? neg0 >> f : neg1 >> (f - 64);
+        if (skip & 1) continue;
         const int64_t v = curves[(size_t)f * m + t];
-        acc += ((neg_mask >> f) & 1) ? -v : v;
+        acc += (neg & 1) ? -v : v;
     }
     out[t] = sign < 0 ? -acc : acc;
 }
 
-int launch_signed_sum(const int64_t *curves, int nf, uint64_t neg_mask, uint64_t skip_mask, int sign, int m,
-                      int64_t *out, hipStream_t stream) {
-    hipLaunchKernelGGL(signed_sum_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, curves, nf, neg_mask, skip_mask,
-                       sign, m, out);
+__global__ void __launch_bounds__(256) add_i64_kernel(int64_t *__restrict__ dst, const int64_t *__restrict__ src,
+                                                      int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] += src[i];
+}
+
+int launch_add_i64(int64_t *dst, const int64_t *src, int64_t n, hipStream_t stream) {
+    if (n <= 0) return ECC_OK;
+    const int64_t blocks = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
+    hipLaunchKernelGGL(add_i64_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, dst, src, n);
+    ECC_HIP(hipGetLastError());
+    return ECC_OK;
+}
+
+int launch_signed_sum(const int64_t *curves, int nf, const uint64_t neg_mask[2], const uint64_t skip_mask[2],
+                      int sign, int m, int64_t *out, hipStream_t stream) {
+    if (nf > 128) {
+        set_error("internal error: %d faces", nf);
+        return ECC_E_ARG;
+    }
+    hipLaunchKernelGGL(signed_sum_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, curves, nf, neg_mask[0],
+                       neg_mask[1], skip_mask[0], skip_mask[1], sign, m, out);
     ECC_HIP(hipGetLastError());
     return ECC_OK;
 }

@@ -6,7 +6,11 @@
 // (to the end of the image on the last chunk) and reads planes f-2 and f-1
 // from a two-plane carry buffer (the previous push's last planes), the rest
 // from the chunk itself.
-// Counts accumulate on the device; the prefix sum is taken once.
+// Counts accumulate on the device; the prefix sum is taken once.  16-bit
+// images (m = 65536) run every launch once per window of 16384 values (Sec.
+// 3, "Range of Values"), over the whole value range, since a stream does not
+// know its values in advance; each window's kept bins are added to the
+// changes vector.
 //
 // Host chunks go through two device staging buffers filled on a copy stream
 // (hipMemcpyAsync), so the copy of chunk k+1 overlaps the kernels of chunk k.
@@ -43,6 +47,7 @@ struct ecc_stream {
     int64_t *mstage = nullptr;  // merge stage rows
     size_t mstage_bytes = 0;
     int64_t *vcec = nullptr;
+    int64_t *wvcec = nullptr;  // ECC_U16: one window's changes (16384 bins)
     uint32_t *status = nullptr;
 };
 
@@ -66,6 +71,7 @@ void destroy(ecc_stream *st) {
     if (st->partial) (void)hipFree(st->partial);
     if (st->mstage) (void)hipFree(st->mstage);
     if (st->vcec) (void)hipFree(st->vcec);
+    if (st->wvcec) (void)hipFree(st->wvcec);
     if (st->status) (void)hipFree(st->status);
     if (st->copy) (void)hipStreamDestroy(st->copy);
     if (prev >= 0) (void)hipSetDevice(prev);
@@ -108,16 +114,33 @@ int run_chunk(ecc_stream *st, const uint8_t *chunk, int64_t f, int64_t n, int64_
         j.lo_inf = lo == 0;  // else plane lo - 1 = f - 2 is carry plane a - 2 (a == 2)
         j.hi_inf = hi == n0;  // else plane hi = f + n - 1 is the chunk's last plane
         const IntTiling tl = choose_int_tiling(st->view, st->dtype, hi - lo);
-        int rc = ensure_bytes((void **)&st->partial, &st->partial_bytes, (size_t)tl.grid * st->m * sizeof(int32_t));
+        const int mloc = st->dtype == ECC_U16 ? 16384 : st->m;  // bins of one launch
+        int rc = ensure_bytes((void **)&st->partial, &st->partial_bytes, (size_t)tl.grid * mloc * sizeof(int32_t));
         if (rc) return rc;
         rc = ensure_bytes((void **)&st->mstage, &st->mstage_bytes,
-                          (size_t)merge_stage_rows(tl.grid) * st->m * sizeof(int64_t));
+                          (size_t)merge_stage_rows(tl.grid) * mloc * sizeof(int64_t));
         if (rc) return rc;
-        rc = launch_int_partial(j, tl, st->partial, st->status, nullptr, st->compute);
-        if (rc) return rc;
-        rc = launch_merge(st->partial, tl.grid, st->m, st->mstage, st->vcec, true, false, nullptr, st->status,
-                          nullptr, st->compute);
-        if (rc) return rc;
+        if (st->dtype == ECC_U16) {
+            U16Window win[kU16MaxWindows + 1];
+            const int nwin = plan_u16_windows(0, 65535, win);
+            for (int i = 0; i < nwin; ++i) {
+                j.win_shift = win[i].shift;
+                rc = launch_int_partial(j, tl, st->partial, st->status, nullptr, st->compute);
+                if (rc) return rc;
+                rc = launch_merge(st->partial, tl.grid, mloc, st->mstage, st->wvcec, false, false, nullptr,
+                                  st->status, nullptr, st->compute);
+                if (rc) return rc;
+                rc = launch_add_i64(st->vcec + win[i].shift + win[i].klo, st->wvcec + win[i].klo,
+                                    win[i].khi - win[i].klo + 1, st->compute);
+                if (rc) return rc;
+            }
+        } else {
+            rc = launch_int_partial(j, tl, st->partial, st->status, nullptr, st->compute);
+            if (rc) return rc;
+            rc = launch_merge(st->partial, tl.grid, st->m, st->mstage, st->vcec, true, false, nullptr, st->status,
+                              nullptr, st->compute);
+            if (rc) return rc;
+        }
     }
 
     // next carry: image planes [f + n - keep, f + n), keep = min(a + n, 2)
@@ -155,8 +178,8 @@ int ecc_stream_begin(const ecc_dims *full_dims, ecc_dtype dtype, void *stream, e
             set_error("n[%d] < 1", k);
             return ECC_E_ARG;
         }
-    if (dtype != ECC_U8 && dtype != ECC_U14) {
-        if (dtype == ECC_U16 || dtype == ECC_F32) {
+    if (dtype != ECC_U8 && dtype != ECC_U14 && dtype != ECC_U16) {
+        if (dtype == ECC_F32) {
             set_error("streaming: dtype %d not available in this build", (int)dtype);
             return ECC_E_UNSUPPORTED;
         }
@@ -210,6 +233,8 @@ int ecc_stream_begin(const ecc_dims *full_dims, ecc_dtype dtype, void *stream, e
     }
     if ((e = dev_malloc((void **)&st->vcec, (size_t)st->m * sizeof(int64_t))) != hipSuccess)
         return fail(hip_fail(e, "hipMalloc(vcec)"));
+    if (dtype == ECC_U16 && (e = dev_malloc((void **)&st->wvcec, (size_t)16384 * sizeof(int64_t))) != hipSuccess)
+        return fail(hip_fail(e, "hipMalloc(window vcec)"));
     if ((e = dev_malloc((void **)&st->status, kStatusBytes)) != hipSuccess) return fail(hip_fail(e, "hipMalloc(status)"));
     if ((rc = launch_zero(st->vcec, (size_t)st->m * sizeof(int64_t), st->compute))) return fail(rc);
     if ((rc = launch_zero(st->status, kStatusBytes, st->compute))) return fail(rc);

@@ -50,6 +50,17 @@ def test_dual_u8_iid(ecc, shape):
     check(ecc, gen.iid(shape, 8, seed=11), "u8")
 
 
+SHAPES_4D = [(5, 6, 7, 8), (2, 3, 40, 5), (12, 12, 12, 12), (3, 4, 5, 70), (2, 2, 2, 2), (24, 20, 33, 17)]
+
+
+@pytest.mark.parametrize("shape", SHAPES_4D, ids=str)
+def test_dual_4d(ecc, shape):
+    """Four axes longer than 1: 81 faces, the full box through the float path."""
+    print(f"\n[gpu] dual 4-D {shape}", flush=True)
+    check(ecc, gen.cfg_u14_value_noise(shape, seed=21), "u14")
+    check(ecc, gen.iid(shape, 8, seed=22), "u8")
+
+
 def test_dual_checkerboard_and_constants(ecc):
     for shape in [(9, 10), (4, 6, 5)]:
         idx = np.indices(shape).sum(axis=0)

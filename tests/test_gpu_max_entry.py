@@ -47,6 +47,25 @@ def test_max_entry_u8_iid(ecc, shape):
     check(ecc, gen.iid(shape, 8, seed=9), "u8")
 
 
+SHAPES_4D = [(5, 6, 7, 8), (2, 3, 40, 5), (12, 12, 12, 12), (3, 4, 5, 70), (1, 4, 1, 9), (24, 20, 33, 17)]
+
+
+@pytest.mark.parametrize("shape", SHAPES_4D, ids=str)
+def test_max_entry_4d(ecc, shape):
+    """Four axes longer than 1: through the float path on m - 1 - v."""
+    print(f"\n[gpu] max entry 4-D {shape}", flush=True)
+    check(ecc, gen.cfg_u14_value_noise(shape, seed=18), "u14")
+    check(ecc, gen.iid(shape, 8, seed=19), "u8")
+
+
+def test_max_entry_4d_range_error(ecc):
+    img = gen.cfg_u14_value_noise((3, 4, 5, 6), seed=20)
+    img[2, 3, 4, 5] = 16384
+    with pytest.raises(ecc.EccError) as ei:
+        ecc.compute_max_entry(dev(img), "u14")
+    assert ei.value.code == ecc.ECC_E_RANGE
+
+
 def test_max_entry_ties_and_extremes(ecc):
     rng = np.random.default_rng(5)
     for shape in [(7, 40, 70), (33, 65), (500,)]:

@@ -93,3 +93,31 @@ def test_stream_range_error(ecc):
     with pytest.raises(ecc.EccError) as ei:
         st.finish()
     assert ei.value.code == ecc.ECC_E_RANGE
+
+
+@pytest.mark.parametrize("kind", ["pageable", "device"])
+@pytest.mark.parametrize("split", ["whole", "every_plane", "uneven"])
+def test_stream_u16_full_range(ecc, kind, split):
+    """16-bit images (m = 65536): each chunk launch runs once per window of
+    16384 values; i.i.d. values over the whole range fill every window."""
+    img = gen.iid((9, 40, 70), 16, seed=25)
+    cuts = SPLITS[split](img.shape[0])
+    print(f"\n[gpu] stream u16 {img.shape} {kind} cuts={cuts}", flush=True)
+    got = stream_curve(ecc, img, "u16", cuts, kind)
+    assert (got == oracle.curve(img, m=65536)).all()
+
+
+def test_stream_u16_value_noise_and_narrow_ranges(ecc):
+    img = gen.value_noise((20, 60, 80), 16, 256, seed=26)
+    got = stream_curve(ecc, img, "u16", SPLITS["uneven"](20), "device")
+    assert (got == oracle.curve(img, m=65536)).all()
+    t = torch.from_numpy(img.view(np.int16)).cuda()
+    assert (got == ecc.compute(t, dtype="u16").cpu().numpy()).all()
+    # values on either side of window edges (16383 / 16384, 32766 ...), and a constant
+    rng = np.random.default_rng(27)
+    for lo in (0, 16380, 32764, 49146, 65530):
+        small = (lo + rng.integers(0, 6, size=(7, 11, 13))).astype(np.uint16)
+        got = stream_curve(ecc, small, "u16", [0, 3, 4, 7], "pageable")
+        assert (got == oracle.curve(small, m=65536)).all(), lo
+    const = np.full((5, 6, 7), 65535, dtype=np.uint16)
+    assert (stream_curve(ecc, const, "u16", [0, 2, 5], "device") == oracle.curve(const, m=65536)).all()
