@@ -224,7 +224,10 @@ void ecc_autotune_reset(void);
  * Integer dtypes.  ECC_U16 (m = 65536): every chunk launch runs once per
  * window of 16384 values (five windows over the whole range, Sec. 3, "Range
  * of Values"), each window's bins added to the changes vector.  Planes with
- * three axes longer than 1 (4-D images): ECC_E_UNSUPPORTED. */
+ * three axes longer than 1 (4-D images, planes of at most 2^28 voxels) go
+ * through the float path's change kernel: a launch's planes and their
+ * collars as float32 in one window buffer, the non-zero changes of the
+ * launch's planes added at their voxels' values. */
 typedef struct ecc_stream ecc_stream;
 
 /* Starts a stream for an image of full_dims (ndim 1..4).  The handle owns

@@ -107,6 +107,7 @@ struct FloatView {
     int32_t bpr;        // blocks per line of the last axis
     int32_t run;        // lines along axis 2 walked by one workgroup
     int32_t nruns;      // runs per axis-2 extent
+    int32_t e0, e1;     // axis-0 indices whose voxels are emitted (the others are neighbours only)
 };
 
 // One thread per voxel.  D = number of axes after dropping axes of extent 1
@@ -157,6 +158,13 @@ __global__ void __launch_bounds__(T) float_change_kernel(const float *__restrict
     r /= v.nruns;
     const int32_t c1 = r % v.n[1];
     const int32_t c0 = r / v.n[1];
+    if (c0 < v.e0 || c0 >= v.e1) {  // (uniform) a collar plane of a streamed chunk: nothing to emit
+        if (tid == 0) {
+            nz_cnt[blk] = 0;
+            nz_off[blk] = 0;
+        }
+        return;
+    }
     const int32_t x = xs + tid;
     const bool act = x < nx;
     __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)img, (short)0, (int)img_bytes, 0x00020000);
@@ -273,7 +281,7 @@ __global__ void __launch_bounds__(T) float_change_kernel(const float *__restrict
         if (ballot64(act && (own_bits & 0x7FFFFFFFu) > 0x7F800000u) != 0 && (threadIdx.x & (kWave - 1)) == 0)
             atomicOr(status, kStatusNaN);
         const int32_t chg = 1 - acc;
-        if (act) keys[own_index(y)] = k0;
+        if (act && keys) keys[own_index(y)] = k0;
         const uint64_t nzm = ballot64(act && chg != 0);
         if (nzm != 0) {
             const int lane = (int)(threadIdx.x & (kWave - 1));
@@ -339,6 +347,8 @@ static int float_grid(const ecc_dims *dims, FloatGrid *g) {
         set_error("float image: too many lines");
         return ECC_E_UNSUPPORTED;
     }
+    v.e0 = 0;
+    v.e1 = INT32_MAX;
     g->D = D;
     g->threads = threads;
     g->grid = grid;
@@ -353,11 +363,18 @@ int64_t float_regions(const ecc_dims *dims, int64_t *slots) {
 }
 
 int launch_float_change(const float *img_dev, const ecc_dims *dims, uint32_t *keys, uint32_t *nz_key,
-                        int32_t *nz_chg, uint32_t *nz_cnt, uint32_t *nz_off, uint32_t *status, hipStream_t stream) {
+                        int32_t *nz_chg, uint32_t *nz_cnt, uint32_t *nz_off, uint32_t *status, hipStream_t stream,
+                        int32_t e0, int32_t e1) {
     FloatGrid fg;
     int rc = float_grid(dims, &fg);
     if (rc) return rc;
-    const FloatView v = fg.v;
+    if ((e0 != 0 || e1 != INT32_MAX) && (fg.D != 4 || dims->ndim != 4)) {
+        set_error("internal error: an emit range needs four axes longer than 1");
+        return ECC_E_ARG;
+    }
+    FloatView v = fg.v;
+    v.e0 = e0;
+    v.e1 = e1;
     const int D = fg.D, threads = fg.threads;
     const int64_t grid = fg.grid;
     int64_t total = 1;
@@ -428,6 +445,35 @@ int launch_nz_compact(const uint32_t *nz_key, const int32_t *nz_chg, const uint3
     }
     hipLaunchKernelGGL(nz_compact_kernel, dim3((unsigned)regions), dim3(256), 0, stream, nz_key, nz_chg, nz_cnt, nz_off,
                        region_slots, rec);
+    ECC_HIP(hipGetLastError());
+    return ECC_OK;
+}
+
+// Integer images through the change kernel (their values as floats, exact
+// below 2^24): every region's records added to the changes vector at the
+// record's value (int64 atomics: exact in any order).  Values >= m were
+// flagged by the conversion and are skipped here.
+__global__ void __launch_bounds__(256) records_to_vcec_kernel(const uint32_t *__restrict__ nz_key,
+                                                              const int32_t *__restrict__ nz_chg,
+                                                              const uint32_t *__restrict__ nz_cnt,
+                                                              int64_t region_slots, int m,
+                                                              int64_t *__restrict__ vcec) {
+    const uint32_t c = nz_cnt[blockIdx.x];
+    const int64_t src = (int64_t)blockIdx.x * region_slots;
+    for (uint32_t i = threadIdx.x; i < c; i += blockDim.x) {
+        const uint32_t v = (uint32_t)key_to_f32(nz_key[src + i]);
+        if (v < (uint32_t)m) atomicAdd((unsigned long long *)&vcec[v], (unsigned long long)(int64_t)nz_chg[src + i]);
+    }
+}
+
+int launch_records_to_vcec(const uint32_t *nz_key, const int32_t *nz_chg, const uint32_t *nz_cnt, int64_t regions,
+                           int64_t region_slots, int m, int64_t *vcec, hipStream_t stream) {
+    if (regions > INT32_MAX) {
+        set_error("float image: too many regions");
+        return ECC_E_UNSUPPORTED;
+    }
+    hipLaunchKernelGGL(records_to_vcec_kernel, dim3((unsigned)regions), dim3(256), 0, stream, nz_key, nz_chg, nz_cnt,
+                       region_slots, m, vcec);
     ECC_HIP(hipGetLastError());
     return ECC_OK;
 }

@@ -236,8 +236,16 @@ int launch_batch_merge(const void *table_dev, int colsum_grid, int scan_grid, hi
 // nz_chg, R = slots / regions (float_regions); nz_cnt[b] and nz_off[b]
 // receive the region's record count.
 int64_t float_regions(const ecc_dims *dims, int64_t *slots);  // regions, or -1 with the error set
+// keys may be null (not written).  [e0, e1): the axis-0 planes whose voxels
+// are emitted, for an image with four axes longer than 1 (the default: all);
+// the other planes are neighbours only and their regions stay empty.
 int launch_float_change(const float *img_dev, const ecc_dims *dims, uint32_t *keys, uint32_t *nz_key,
-                        int32_t *nz_chg, uint32_t *nz_cnt, uint32_t *nz_off, uint32_t *status, hipStream_t stream);
+                        int32_t *nz_chg, uint32_t *nz_cnt, uint32_t *nz_off, uint32_t *status, hipStream_t stream,
+                        int32_t e0 = 0, int32_t e1 = INT32_MAX);
+// Integer images through the change kernel: the regions' records added to
+// vcec (m int64) at the records' values.
+int launch_records_to_vcec(const uint32_t *nz_key, const int32_t *nz_chg, const uint32_t *nz_cnt, int64_t regions,
+                           int64_t region_slots, int m, int64_t *vcec, hipStream_t stream);
 // Exclusive scan of nz_off (regions entries; sums: radix_scan_tiles(regions)),
 // then the record count into *total_dev and *total_host (host-mapped).
 int launch_nz_total(const uint32_t *nz_cnt, uint32_t *nz_off, int64_t regions, uint32_t *sums, int64_t *total_dev,

@@ -12,6 +12,13 @@
 // know its values in advance; each window's kept bins are added to the
 // changes vector.
 //
+// Planes with three axes longer than 1 (4-D images) go through the float
+// path's change kernel instead (Sec. 3, "Other Ranges of Gray Values": the
+// same owner rule on any ordered values): a launch's planes and its collars
+// are converted to float32 into one window buffer, the kernel emits the
+// changes of the launch's planes only (the collars are neighbours), and the
+// non-zero changes are added to the changes vector at their voxels' values.
+//
 // Host chunks go through two device staging buffers filled on a copy stream
 // (hipMemcpyAsync), so the copy of chunk k+1 overlaps the kernels of chunk k.
 // Device chunks are read in place.
@@ -49,6 +56,13 @@ struct ecc_stream {
     int64_t *vcec = nullptr;
     int64_t *wvcec = nullptr;  // ECC_U16: one window's changes (16384 bins)
     uint32_t *status = nullptr;
+    // 4-D images: extents, the float window of a launch and its change records
+    bool four_d = false;
+    int64_t n4[4] = {0, 0, 0, 0};
+    float *wbuf = nullptr;
+    size_t wbuf_bytes = 0;
+    uint8_t *nzbuf = nullptr;
+    size_t nzbuf_bytes = 0;
 };
 
 namespace {
@@ -72,6 +86,8 @@ void destroy(ecc_stream *st) {
     if (st->mstage) (void)hipFree(st->mstage);
     if (st->vcec) (void)hipFree(st->vcec);
     if (st->wvcec) (void)hipFree(st->wvcec);
+    if (st->wbuf) (void)hipFree(st->wbuf);
+    if (st->nzbuf) (void)hipFree(st->nzbuf);
     if (st->status) (void)hipFree(st->status);
     if (st->copy) (void)hipStreamDestroy(st->copy);
     if (prev >= 0) (void)hipSetDevice(prev);
@@ -91,6 +107,60 @@ bool is_device_ptr(const void *p) {
 
 int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
 
+// 4-D images: the changes of image planes [lo, hi) of a push whose chunk
+// holds image planes [f, f + n), the carry holding planes [f - a, f).  A
+// launch covers planes [b0, b1) with the window [b0 - 1, b1 + 1) within the
+// image, as many planes at a time as the float kernel takes (below 2^30
+// values).
+int run_chunk_4d(ecc_stream *st, const uint8_t *chunk, int64_t f, int64_t lo, int64_t hi) {
+    const int64_t n0 = st->view.n0;
+    const int64_t pe = st->n4[1] * st->n4[2] * st->n4[3];  // elements per plane
+    const int eb = st->dtype == ECC_U8 ? 1 : 2;
+    const int64_t step = (((int64_t)1 << 30) - 1) / pe - 2;  // (>= 1: planes hold at most 2^28 values)
+    const uint8_t *carry = st->carry_buf[st->cur];
+    for (int64_t b0 = lo; b0 < hi; b0 += step) {
+        const int64_t b1 = min64(b0 + step, hi);
+        const int64_t wlo = b0 > 0 ? b0 - 1 : 0, whi = b1 < n0 ? b1 + 1 : n0;
+        const int64_t p = whi - wlo;
+        const int64_t ncar = wlo < f ? f - wlo : 0;  // window planes from the carry (0..2)
+        if (ncar > st->ncarry) {
+            set_error("internal error: 4-D stream window");
+            return ECC_E_STATE;
+        }
+        int rc = ensure_bytes((void **)&st->wbuf, &st->wbuf_bytes, (size_t)(p * pe) * 4);
+        if (rc) return rc;
+        if (ncar > 0) {
+            rc = launch_int_to_f32(carry + (st->ncarry - ncar) * st->plane_bytes, eb, ncar * pe, (uint32_t)st->m, 0,
+                                   st->wbuf, st->status, st->compute);
+            if (rc) return rc;
+        }
+        const int64_t c0 = wlo + ncar;  // first window plane from the chunk
+        rc = launch_int_to_f32(chunk + (c0 - f) * st->plane_bytes, eb, (whi - c0) * pe, (uint32_t)st->m, 0,
+                               st->wbuf + ncar * pe, st->status, st->compute);
+        if (rc) return rc;
+        ecc_dims w{};
+        w.ndim = 4;
+        w.n[0] = p;
+        for (int k = 1; k < 4; ++k) w.n[k] = st->n4[k];
+        int64_t slots = 0;
+        const int64_t regions = float_regions(&w, &slots);
+        if (regions < 0) return ECC_E_UNSUPPORTED;
+        const size_t off_cnt = (size_t)slots * 8, off_off = off_cnt + (size_t)regions * 4;
+        rc = ensure_bytes((void **)&st->nzbuf, &st->nzbuf_bytes, off_off + (size_t)regions * 4);
+        if (rc) return rc;
+        uint32_t *nz_key = (uint32_t *)st->nzbuf;
+        int32_t *nz_chg = (int32_t *)(nz_key + slots);
+        uint32_t *nz_cnt = (uint32_t *)(st->nzbuf + off_cnt), *nz_off = (uint32_t *)(st->nzbuf + off_off);
+        // (a one-plane image: its plane is emitted, and the kernel sees three axes)
+        rc = launch_float_change(st->wbuf, &w, nullptr, nz_key, nz_chg, nz_cnt, nz_off, st->status, st->compute,
+                                 p > 1 ? (int32_t)(b0 - wlo) : 0, p > 1 ? (int32_t)(b1 - wlo) : INT32_MAX);
+        if (rc) return rc;
+        rc = launch_records_to_vcec(nz_key, nz_chg, nz_cnt, regions, slots / regions, st->m, st->vcec, st->compute);
+        if (rc) return rc;
+    }
+    return ECC_OK;
+}
+
 // Adds the changes of image planes [emitted, hi) of a push whose chunk holds
 // image planes [f, f + n), in one launch: buffer plane p is image plane f + p,
 // read from the chunk for p >= 0 and from the carry buffer (the previous
@@ -102,7 +172,10 @@ int run_chunk(ecc_stream *st, const uint8_t *chunk, int64_t f, int64_t n, int64_
     const int a = st->ncarry;
     uint8_t *carry = st->carry_buf[st->cur];
     const int64_t lo = st->emitted;  // f - 1, or 0 on the first push
-    if (lo < hi) {
+    if (lo < hi && st->four_d) {
+        int rc = run_chunk_4d(st, chunk, f, lo, hi);
+        if (rc) return rc;
+    } else if (lo < hi) {
         IntJob j{};
         j.src.base = chunk;
         j.src.lo_base = carry + a * pb;
@@ -200,8 +273,12 @@ int ecc_stream_begin(const ecc_dims *full_dims, ecc_dtype dtype, void *stream, e
         v.nin = 1; v.n1 = 1; v.n2 = (int32_t)ins[0];
     } else if (k == 2 && ins[0] * ins[1] <= INT32_MAX) {
         v.nin = 2; v.n1 = (int32_t)ins[0]; v.n2 = (int32_t)ins[1];
+    } else if (k == 3 && ins[0] * ins[1] * ins[2] <= ((int64_t)1 << 28)) {
+        v.nin = 3;  // 4-D: the float change kernel on a window of planes
+        v.n1 = 1;
+        v.n2 = 1;
     } else {
-        set_error("streaming: plane shape not supported (three in-plane axes, or a plane beyond 2^31 elements)");
+        set_error("streaming: plane shape not supported (a plane beyond 2^31 elements, or 2^28 with three axes)");
         return ECC_E_UNSUPPORTED;
     }
     v.n0 = full_dims->n[0];
@@ -215,6 +292,12 @@ int ecc_stream_begin(const ecc_dims *full_dims, ecc_dtype dtype, void *stream, e
     st->dtype = dtype;
     st->m = (int)threshold_count(dtype);
     st->plane_bytes = (int64_t)v.n1 * v.n2 * (dtype == ECC_U8 ? 1 : 2);
+    if (v.nin == 3) {
+        st->four_d = true;
+        st->n4[0] = full_dims->n[0];
+        for (int i = 0; i < 3; ++i) st->n4[i + 1] = ins[i];
+        st->plane_bytes = ins[0] * ins[1] * ins[2] * (dtype == ECC_U8 ? 1 : 2);
+    }
     int rc = ECC_OK;
     auto fail = [&](int code) {
         destroy(st);
@@ -233,7 +316,8 @@ int ecc_stream_begin(const ecc_dims *full_dims, ecc_dtype dtype, void *stream, e
     }
     if ((e = dev_malloc((void **)&st->vcec, (size_t)st->m * sizeof(int64_t))) != hipSuccess)
         return fail(hip_fail(e, "hipMalloc(vcec)"));
-    if (dtype == ECC_U16 && (e = dev_malloc((void **)&st->wvcec, (size_t)16384 * sizeof(int64_t))) != hipSuccess)
+    if (dtype == ECC_U16 && !st->four_d &&
+        (e = dev_malloc((void **)&st->wvcec, (size_t)16384 * sizeof(int64_t))) != hipSuccess)
         return fail(hip_fail(e, "hipMalloc(window vcec)"));
     if ((e = dev_malloc((void **)&st->status, kStatusBytes)) != hipSuccess) return fail(hip_fail(e, "hipMalloc(status)"));
     if ((rc = launch_zero(st->vcec, (size_t)st->m * sizeof(int64_t), st->compute))) return fail(rc);

@@ -121,3 +121,55 @@ def test_stream_u16_value_noise_and_narrow_ranges(ecc):
         assert (got == oracle.curve(small, m=65536)).all(), lo
     const = np.full((5, 6, 7), 65535, dtype=np.uint16)
     assert (stream_curve(ecc, const, "u16", [0, 2, 5], "device") == oracle.curve(const, m=65536)).all()
+
+
+def img_4d(shape, dtype, seed):
+    if dtype == "u8":
+        return gen.iid(shape, 8, seed=seed)
+    if dtype == "u14":
+        return gen.cfg_u14_value_noise(shape, seed=seed)
+    return gen.iid(shape, 16, seed=seed)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u14", "u16"])
+@pytest.mark.parametrize("kind", ["pageable", "device"])
+def test_stream_4d(ecc, dtype, kind):
+    """Planes with three axes longer than 1: each launch converts its planes
+    and collars into one float window for the change kernel."""
+    img = img_4d((11, 9, 10, 70), dtype, seed=28)
+    m = ecc.THRESHOLDS[dtype]
+    ref = oracle.curve(img, m=m)
+    for split in SPLITS:
+        cuts = SPLITS[split](img.shape[0])
+        print(f"\n[gpu] stream 4-D {dtype} {img.shape} {kind} cuts={cuts}", flush=True)
+        assert (stream_curve(ecc, img, dtype, cuts, kind) == ref).all(), split
+
+
+def test_stream_4d_one_plane_and_range_error(ecc):
+    img = gen.cfg_u14_value_noise((1, 6, 7, 8), seed=29)
+    assert (stream_curve(ecc, img, "u14", [0, 1], "device") == oracle.curve(img, m=16384)).all()
+    bad = gen.cfg_u14_value_noise((5, 6, 7, 8), seed=30)
+    bad[3, 1, 2, 3] = 16384
+    st = ecc.Stream(bad.shape, "u14")
+    st.push(bad[:2])
+    st.push(bad[2:])
+    with pytest.raises(ecc.EccError) as ei:
+        st.finish()
+    assert ei.value.code == ecc.ECC_E_RANGE
+
+
+def test_stream_4d_large_planes_several_launches(ecc):
+    """Planes of 2^28 voxels: one launch per plane (window of at most three
+    planes below 2^30 values), against the resident curve of the same bytes
+    (itself checked against the oracle on smaller 4-D images)."""
+    shape = (3, 256, 1024, 1024)
+    print(f"\n[gpu] stream 4-D u8 {shape}: generating", flush=True)
+    t = torch.randint(0, 256, shape, dtype=torch.uint8, generator=torch.Generator().manual_seed(31)).cuda()
+    print("[gpu] resident", flush=True)
+    res = ecc.compute(t, dtype="u8").cpu().numpy()
+    print("[gpu] streamed", flush=True)
+    torch.cuda.synchronize()
+    st = ecc.Stream(shape, "u8")
+    st.push(t)
+    got = st.finish()
+    assert res[-1] == 1 and (got == res).all()
