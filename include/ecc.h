@@ -261,7 +261,7 @@ void ecc_stream_abort(ecc_stream *st);
 typedef struct {
     const void *image; /* device pointer, prod(dims.n) elements of dtype */
     ecc_dims dims;     /* as for ecc_compute */
-    int32_t dtype;     /* ECC_U8 or ECC_U14 */
+    int32_t dtype;     /* ECC_U8, ECC_U14 or ECC_U16 */
     int64_t *chi;      /* device pointer, m int64 entries (written only if the image is valid) */
 } ecc_job;
 
@@ -277,8 +277,11 @@ int ecc_batch_create(void *stream, ecc_batch **out);
  * uint32; entry j receives 0 or ECC_STATUS_RANGE_BIT for image j.  Runs on
  * one context are ordered by its stream; a context is not for concurrent use
  * from several host threads.  The images and chi buffers must stay valid
- * until the work is done.  Errors: ECC_E_ARG (bad job), ECC_E_UNSUPPORTED
- * (shape or dtype the integer path does not take), ECC_E_NOMEM, ECC_E_HIP. */
+ * until the work is done.  u8 and u14 jobs share one persistent launch;
+ * ECC_U16 jobs (m = 65536, more bins than a workgroup histogram holds) run
+ * after it on the same stream, one launch per window of 16384 values each.
+ * Errors: ECC_E_ARG (bad job), ECC_E_UNSUPPORTED (shape or dtype the integer
+ * path does not take), ECC_E_NOMEM, ECC_E_HIP. */
 int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *status_dev);
 
 /* Waits for the context's work and frees it.  NULL is ignored. */

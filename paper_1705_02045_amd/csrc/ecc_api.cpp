@@ -418,6 +418,14 @@ static int enqueue_u16(const void *image_dev, const IntView &v, int64_t *chi_dev
     return launch_merge(nullptr, 0, mtot, nullptr, ws->vcec16, true, true, chi_dev, ws->status, status_out, stream);
 }
 
+int u16_curve_async(const void *image_dev, const IntView &v, int64_t *chi_dev, uint32_t *status_out,
+                    hipStream_t stream) {
+    Workspace *ws = nullptr;
+    int rc = get_workspace(stream, &ws);
+    if (rc) return rc;
+    return enqueue_u16(image_dev, v, chi_dev, status_out, stream, ws, 0, 65535);
+}
+
 // Changes vector only (no scan) of a device image into vcec_out; a range
 // error stays set in ws->status for a later scan to report.
 // plane_stride: elements between consecutive planes of a view with one

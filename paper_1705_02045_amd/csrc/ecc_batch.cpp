@@ -620,6 +620,7 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
     }
     if (n_jobs == 0) return ECC_OK;
     std::vector<Prepared> prep(n_jobs);
+    std::vector<int> wide;  // ECC_U16 jobs: windowed launches of their own, after the batch
     int64_t rows8 = 0, rows14 = 0, ntiles = 0, nitems = 0, vcec_words = 0;
     for (int j = 0; j < n_jobs; ++j) {
         const ecc_job &J = jobs[j];
@@ -630,15 +631,19 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
             set_error("job %d: NULL image or chi", j);
             return ECC_E_ARG;
         }
-        if (J.dtype != ECC_U8 && J.dtype != ECC_U14) {
-            set_error("job %d: batches take U8 or U14 images", j);
-            return (J.dtype == ECC_U16 || J.dtype == ECC_F32) ? ECC_E_UNSUPPORTED : ECC_E_ARG;
+        if (J.dtype != ECC_U8 && J.dtype != ECC_U14 && J.dtype != ECC_U16) {
+            set_error("job %d: batches take U8, U14 or U16 images", j);
+            return J.dtype == ECC_F32 ? ECC_E_UNSUPPORTED : ECC_E_ARG;
         }
         Prepared &P = prep[j];
         int unsup = 0;
         if (!normalize_int_view(&J.dims, &P.view, &unsup)) {
             set_error("job %d: shape not supported", j);
             return ECC_E_UNSUPPORTED;
+        }
+        if (J.dtype == ECC_U16) {
+            wide.push_back(j);
+            continue;
         }
         P.tl = batch_tiling(P.view, b->min_planes, b->split);
         P.group = (J.dtype == ECC_U14 ? 2 : 0) + (P.view.nin == 2 ? 1 : 0);
@@ -655,14 +660,17 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
     }
     // tiles of the largest images first, so the persistent workgroups end
     // on small tiles
-    std::vector<int> order(n_jobs);
-    for (int j = 0; j < n_jobs; ++j) order[j] = j;
+    std::vector<int> order;
+    for (int j = 0; j < n_jobs; ++j)
+        if (jobs[j].dtype != ECC_U16) order.push_back(j);
+    const int nb = (int)order.size();  // jobs in the persistent launch
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return prep[a].voxels > prep[c].voxels; });
     int prev = -1;
     ECC_HIP(hipGetDevice(&prev));
     if (prev != b->device) ECC_HIP(hipSetDevice(b->device));
     int rc = ECC_OK;
     do {
+        if (nb == 0) break;
         // device scratch
         if ((rc = grow(b, (void **)&b->partial8, &b->partial8_bytes, (size_t)rows8 * 256 * 4))) break;
         if ((rc = grow(b, (void **)&b->partial14, &b->partial14_bytes, (size_t)rows14 * 16384 * 4))) break;
@@ -676,21 +684,21 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
         BatchHeader hd{};
         size_t total = align_up(sizeof(BatchHeader), 16);
         hd.off_kparams = (uint32_t)total;
-        total = align_up(total + (size_t)n_jobs * kp, 16);
+        total = align_up(total + (size_t)nb * kp, 16);
         hd.off_tile_begin = (uint32_t)total;
-        total = align_up(total + (size_t)(n_jobs + 1) * 4, 16);
+        total = align_up(total + (size_t)(nb + 1) * 4, 16);
         hd.off_kind = (uint32_t)total;
-        total = align_up(total + (size_t)n_jobs * 4, 16);
+        total = align_up(total + (size_t)nb * 4, 16);
         hd.off_merge = (uint32_t)total;
-        total = align_up(total + (size_t)n_jobs * sizeof(MergeJob), 16);
+        total = align_up(total + (size_t)nb * sizeof(MergeJob), 16);
         hd.off_item_begin = (uint32_t)total;
-        total = align_up(total + (size_t)(n_jobs + 1) * 4, 256);
+        total = align_up(total + (size_t)(nb + 1) * 4, 256);
         if (total > UINT32_MAX) {
             set_error("ecc_batch_run: batch table too large");
             rc = ECC_E_UNSUPPORTED;
             break;
         }
-        hd.njobs = n_jobs;
+        hd.njobs = nb;
         hd.ntiles = (int32_t)ntiles;
         hd.nitems = (int32_t)nitems;
         hd.next_tile = 0;
@@ -729,7 +737,7 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
         tile_begin[0] = 0;
         item_begin[0] = 0;
         int64_t row8 = 0, row14 = 0, vw = 0;
-        for (int p = 0; p < n_jobs; ++p) {
+        for (int p = 0; p < nb; ++p) {
             const int j = order[p];
             const Prepared &P = prep[j];
             int32_t *part;
@@ -788,6 +796,13 @@ int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *s
         }
         b->used[s] = true;
     } while (0);
+    // 16-bit images: one launch per window of 16384 values each (the
+    // persistent kernel's histograms hold 16384 bins), on the same stream
+    for (size_t w = 0; !rc && w < wide.size(); ++w) {
+        const int j = wide[w];
+        rc = u16_curve_async(jobs[j].image, prep[j].view, jobs[j].chi, status_dev ? status_dev + j : nullptr,
+                             b->stream);
+    }
     if (prev != b->device) (void)hipSetDevice(prev);
     return rc;
 }
@@ -852,9 +867,9 @@ int ecc_job_footprint(const ecc_job *job, int64_t *bytes) {
     int64_t total = 0;
     int rc = check_dims(&job->dims, &total);
     if (rc) return rc;
-    if (job->dtype != ECC_U8 && job->dtype != ECC_U14) {
-        set_error("ecc_job_footprint: U8 or U14 images");
-        return (job->dtype == ECC_U16 || job->dtype == ECC_F32) ? ECC_E_UNSUPPORTED : ECC_E_ARG;
+    if (job->dtype != ECC_U8 && job->dtype != ECC_U14 && job->dtype != ECC_U16) {
+        set_error("ecc_job_footprint: U8, U14 or U16 images");
+        return job->dtype == ECC_F32 ? ECC_E_UNSUPPORTED : ECC_E_ARG;
     }
     IntView v{};
     int unsup = 0;
@@ -862,8 +877,8 @@ int ecc_job_footprint(const ecc_job *job, int64_t *bytes) {
         set_error("ecc_job_footprint: shape not supported");
         return ECC_E_UNSUPPORTED;
     }
-    const int64_t m = threshold_count(job->dtype);
-    *bytes = total * (int64_t)elem_bytes(job->dtype) + (int64_t)batch_tiling(v).grid * m * 4 + 2 * m * 8;
+    const int64_t m = threshold_count(job->dtype), mrow = m < 16384 ? m : 16384;  // bins of a count row
+    *bytes = total * (int64_t)elem_bytes(job->dtype) + (int64_t)batch_tiling(v).grid * mrow * 4 + 2 * m * 8;
     return ECC_OK;
 }
 
@@ -906,8 +921,8 @@ int ecc_serve(ecc_batch *b, int32_t n, const ecc_job *jobs, const double *arriva
         int rc = check_dims(&jobs[i].dims, &total);
         if (rc) return rc;
         const int64_t m = threshold_count(jobs[i].dtype);
-        if (!jobs[i].image || (jobs[i].dtype != ECC_U8 && jobs[i].dtype != ECC_U14)) {
-            set_error("request %d: NULL image, or a dtype other than U8/U14", i);
+        if (!jobs[i].image || (jobs[i].dtype != ECC_U8 && jobs[i].dtype != ECC_U14 && jobs[i].dtype != ECC_U16)) {
+            set_error("request %d: NULL image, or a dtype other than U8/U14/U16", i);
             return jobs[i].image ? ECC_E_UNSUPPORTED : ECC_E_ARG;
         }
         Req &R = req[i];

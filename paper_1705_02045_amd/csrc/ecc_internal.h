@@ -160,6 +160,10 @@ struct U16Window {
 };
 constexpr int kU16MaxWindows = 5;  // 16383 + 3 * 16382 + 16383 >= 65536
 int plan_u16_windows(uint32_t vmin, uint32_t vmax, U16Window *w);
+// The whole curve of a device-resident 16-bit image on stream (windows over
+// the whole value range), the status copied to status_out (may be null).
+int u16_curve_async(const void *image_dev, const IntView &v, int64_t *chi_dev, uint32_t *status_out,
+                    hipStream_t stream);
 // Column sums of the per-workgroup rows into vcec through int64 stage rows
 // ([merge_stage_rows(rows)][m]) and, with do_scan, the prefix sum of vcec into
 // chi (ecc_scan.hip).  The scan copies the status word to status_out (when

@@ -144,3 +144,24 @@ def test_serve_admission_by_footprint(ecc):
         m = ecc.THRESHOLDS[d]
         assert (chi[off:off + m] == oracle.curve(img, m=m)).all(), f"{d} {s}"
         off += m
+
+
+def test_batch_with_16bit_jobs(ecc):
+    """16-bit jobs (m = 65536) ride in a batch next to u8/u14 jobs: they run as
+    windowed launches of their own after the persistent kernel, on the same
+    stream; a batch of 16-bit jobs only has no persistent launch."""
+    rng = np.random.default_rng(33)
+    imgs = [gen.serving_image("u8", (40, 70), 1), gen.iid((9, 40, 70), 16, seed=34),
+            gen.serving_image("u14", (16, 30, 20), 2), gen.value_noise((20, 60, 80), 16, 256, seed=35),
+            (30000 + rng.integers(0, 5, size=(33, 65))).astype(np.uint16)]
+    dtypes = ["u8", "u16", "u14", "u16", "u16"]
+    b = ecc.Batch()
+    for sel in (range(5), [1, 3, 4]):
+        chis = [torch.full((ecc.THRESHOLDS[dtypes[i]],), -7, dtype=torch.int64, device="cuda") for i in sel]
+        status = torch.full((len(sel),), 99, dtype=torch.int32, device="cuda")
+        b.run([dev(imgs[i]) for i in sel], [dtypes[i] for i in sel], chis, status)
+        torch.cuda.synchronize()
+        assert (status.cpu().numpy() == 0).all()
+        for i, c in zip(sel, chis):
+            assert (c.cpu().numpy() == oracle.curve(imgs[i], m=ecc.THRESHOLDS[dtypes[i]])).all(), i
+    b.close()

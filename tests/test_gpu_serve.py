@@ -172,3 +172,32 @@ def test_serving_mix_4096_every_request(ecc, origin):
     b.close()
     assert rc == 0 and (st == 0).all() and (lat > 0).all()
     check_against_digests(ecc, reqs, chi, digests)
+
+
+@pytest.mark.parametrize("one_launch", [False, True])
+def test_serve_16bit_requests(ecc, one_launch):
+    """16-bit requests in a served mix, device-resident and host-origin (one
+    of them above the stream threshold, streamed through the windowed stream
+    path): every curve equals the oracle's."""
+    reqs = gen.serving_requests(12, seed=23, side_scale=0.2)
+    imgs = [gen.serving_image(*r) for r in reqs]
+    dtypes = [r[0] for r in reqs]
+    for k, shape in ((3, (9, 40, 70)), (8, (60, 50, 60))):
+        imgs.insert(k, gen.iid(shape, 16, seed=36 + k))
+        dtypes.insert(k, "u16")
+    arrival = np.cumsum(np.random.default_rng(6).exponential(1e-4, size=len(imgs)))
+    for origin in ("device", "host"):
+        src = [as_tensor(a).cuda() if origin == "device" else as_tensor(a).pin_memory() for a in imgs]
+        kw = {} if origin == "device" else dict(arena_bytes=16 << 20, stream_above_bytes=256 << 10,
+                                                chunk_bytes=64 << 10)
+        b = ecc.Batch()
+        print(f"\n[gpu] ecc_serve 16-bit requests, {origin}, one_launch={one_launch}", flush=True)
+        lat, chi, bid, st, rc = b.serve_config(src, dtypes, arrival, max_batch=4, one_launch_per_image=one_launch,
+                                               check=False, **kw)
+        b.close()
+        assert rc == ecc.ECC_OK and (st == 0).all()
+        off = 0
+        for i, (d, img) in enumerate(zip(dtypes, imgs)):
+            m = ecc.THRESHOLDS[d]
+            assert (chi[off:off + m] == oracle.curve(img, m=m)).all(), f"{origin} request {i} {d} {img.shape}"
+            off += m
