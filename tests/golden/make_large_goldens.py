@@ -19,6 +19,7 @@ Calls only the seeded input generators (gen/) and the CPU oracle (oracle/).
 
 Usage:
   python tests/golden/make_large_goldens.py stream --shape 1024 8192 8192 --seed 2 [--threads 8]
+  python tests/golden/make_large_goldens.py stream --shape 2600 14450 14450 --seed 2 --chunk 4 [--threads 8]
   python tests/golden/make_large_goldens.py serving --count 4096 --seed 4
 A stream run keeps its progress in --state (default /tmp/<name>.state.npz)
 and resumes from it.

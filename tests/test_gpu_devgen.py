@@ -6,9 +6,10 @@ The 3-D 14-bit volume of 2600 planes of 14450 x 14450 voxels (seed 2, about
     that volume, small shapes with odd rows and both element sizes);
   - its first planes, streamed from device slabs, give the oracle's curve;
   - the whole volume streamed in 64-plane slabs (the benchmark's launch
-    configuration) satisfies what holds at any size: chi = 1 at the top
-    threshold, chi = 0 below the smallest value, and the same curve for a
-    second, ragged split into chunks (Sec. 3, "Streaming": chunks add up);
+    configuration), and in ragged 100-plane slabs, gives the oracle's curve
+    element by element, stored by tests/golden/make_large_goldens.py (the
+    oracle over host-made chunks with a one-plane collar; Sec. 3,
+    "Streaming": chunks add up);
   - the 1024 x 8192 x 8192 volume (128 GiB), resident and pushed from pinned
     host chunks, gives the oracle's curve, stored by
     tests/golden/make_large_goldens.py (the oracle over host-made chunks with
@@ -131,18 +132,18 @@ def test_stream_device_slabs_first_planes_vs_oracle(ecc):
     assert ref[-1] == 1
 
 
-def test_stream_device_full_volume_properties(ecc):
+def test_stream_device_full_volume_vs_oracle(ecc):
     """The whole 2600 x 14450 x 14450 volume in 64-plane slabs, then in ragged
-    slabs of 100 planes: identical curves, chi = 1 at the top, 0 below the
-    minimum value."""
+    slabs of 100 planes: both equal the oracle's stored curve element by
+    element (and chi = 0 below the smallest value)."""
+    want = stored_curve(TB_SHAPE, TB_SEED)
     print("\n[gpu] full TB volume, 64-plane slabs", flush=True)
     a, lo = stream_device(ecc, TB_SHAPE, TB_SEED, 64)
+    assert_curve(a, want, "64-plane slabs")
     print("[gpu] full TB volume, 100-plane slabs", flush=True)
     b, lo2 = stream_device(ecc, TB_SHAPE, TB_SEED, 100)
-    assert lo == lo2
-    assert (a == b).all()
-    assert a[-1] == 1
-    assert (a[:lo] == 0).all()
+    assert_curve(b, want, "100-plane slabs")
+    assert lo == lo2 and (a[:lo] == 0).all()
 
 
 def test_stream_host_full_size_vs_oracle(ecc):
