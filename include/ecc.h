@@ -214,6 +214,20 @@ int ecc_tiling_for(const ecc_dims *dims, ecc_dtype dtype, ecc_tiling *out);
 /* Forgets every tiling ecc_autotune stored. */
 void ecc_autotune_reset(void);
 
+/* The stored tilings as a text file, so that a later process starts with
+ * them (a tuning cache).  One line per entry, fields separated by spaces:
+ *   ecc-tiling-v1 dtype nin n1 n2 planes rows tiles_per_cu waves_x ms
+ * (the shape key of an integer launch: dtype, number of in-plane axes,
+ * in-plane extents, planes).  ecc_autotune_save writes every entry (the file
+ * is replaced).  ecc_autotune_load adds the file's entries to the stored
+ * ones (an entry for the same key is replaced); a malformed line or a field
+ * outside its range fails the call with nothing stored.  Returns the number
+ * of entries written / read, or: ECC_E_ARG (NULL path, a file that cannot
+ * be opened, read or written, or a malformed entry, which ecc_last_error
+ * names). */
+int ecc_autotune_save(const char *path);
+int ecc_autotune_load(const char *path);
+
 /* ---------------------------------------------------------------------------
  * Streaming (Sec. 3, "Streaming" and "Processing one Chunk"): an image larger
  * than device memory is pushed as consecutive chunks of whole axis-0 planes.

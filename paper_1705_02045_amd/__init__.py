@@ -8,6 +8,7 @@ this package fails loudly if the library is not built.
 from __future__ import annotations
 
 import ctypes
+import os
 import pathlib
 
 _HERE = pathlib.Path(__file__).resolve().parent
@@ -72,6 +73,10 @@ _lib.ecc_tiling_for.restype = ctypes.c_int
 _lib.ecc_tiling_for.argtypes = [ctypes.POINTER(Dims), ctypes.c_int, ctypes.POINTER(Tiling)]
 _lib.ecc_autotune_reset.restype = None
 _lib.ecc_autotune_reset.argtypes = []
+_lib.ecc_autotune_save.restype = ctypes.c_int
+_lib.ecc_autotune_save.argtypes = [ctypes.c_char_p]
+_lib.ecc_autotune_load.restype = ctypes.c_int
+_lib.ecc_autotune_load.argtypes = [ctypes.c_char_p]
 _lib.ecc_batch_autotune.restype = ctypes.c_int
 _lib.ecc_batch_autotune.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
@@ -287,6 +292,22 @@ def tiling_for(shape, dtype: str) -> dict:
 
 def autotune_reset():
     _lib.ecc_autotune_reset()
+
+
+def autotune_save(path) -> int:
+    """ecc_autotune_save: the stored tilings to a text file; returns the count."""
+    n = _lib.ecc_autotune_save(os.fsencode(path))
+    if n < 0:
+        _check(n, "ecc_autotune_save")
+    return n
+
+
+def autotune_load(path) -> int:
+    """ecc_autotune_load: adds a saved file's tilings; returns the count."""
+    n = _lib.ecc_autotune_load(os.fsencode(path))
+    if n < 0:
+        _check(n, "ecc_autotune_load")
+    return n
 
 
 def compute_dual(image, dtype: str):

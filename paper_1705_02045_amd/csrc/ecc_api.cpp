@@ -1095,6 +1095,85 @@ void ecc_autotune_reset(void) {
     g_tuned.clear();
 }
 
+static const char kTuneTag[] = "ecc-tiling-v1";
+
+int ecc_autotune_save(const char *path) {
+    g_err[0] = 0;
+    if (!path) {
+        set_error("ecc_autotune_save: NULL path");
+        return ECC_E_ARG;
+    }
+    std::vector<std::pair<TuneKey, ecc_tiling>> rows;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        rows.assign(g_tuned.begin(), g_tuned.end());
+    }
+    FILE *f = fopen(path, "w");
+    if (!f) {
+        set_error("ecc_autotune_save: cannot open %s for writing", path);
+        return ECC_E_ARG;
+    }
+    bool ok = true;
+    for (const auto &r : rows)
+        ok = ok && fprintf(f, "%s %d %d %d %d %lld %d %d %d %.6g\n", kTuneTag, r.first.dtype, r.first.nin,
+                           (int)r.first.n1, (int)r.first.n2, (long long)r.first.planes, (int)r.second.rows,
+                           (int)r.second.tiles_per_cu, (int)r.second.waves_x, (double)r.second.ms) > 0;
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) {
+        set_error("ecc_autotune_save: write to %s failed", path);
+        return ECC_E_ARG;
+    }
+    return (int)rows.size();
+}
+
+int ecc_autotune_load(const char *path) {
+    g_err[0] = 0;
+    if (!path) {
+        set_error("ecc_autotune_load: NULL path");
+        return ECC_E_ARG;
+    }
+    FILE *f = fopen(path, "r");
+    if (!f) {
+        set_error("ecc_autotune_load: cannot open %s", path);
+        return ECC_E_ARG;
+    }
+    std::vector<std::pair<TuneKey, ecc_tiling>> rows;
+    char line[512];
+    int lineno = 0;
+    bool ok = true;
+    while (ok && fgets(line, sizeof line, f)) {
+        ++lineno;
+        char tag[32] = {0}, extra[2] = {0};
+        int dtype = 0, nin = 0, n1 = 0, n2 = 0, r = 0, tpc = 0, wx = 0;
+        long long planes = 0;
+        double ms = 0;
+        const int got = sscanf(line, "%31s %d %d %d %d %lld %d %d %d %lf %1s", tag, &dtype, &nin, &n1, &n2, &planes, &r,
+                               &tpc, &wx, &ms, extra);
+        if (got == EOF || (got == 1 && tag[0] == '#')) continue;  // blank line or comment
+        ok = got == 10 && strcmp(tag, kTuneTag) == 0 && threshold_count((ecc_dtype)dtype) > 0 &&
+             dtype != ECC_F32 && (nin == 1 || nin == 2) && n1 >= 1 && n2 >= 1 && planes >= 1 &&
+             (r == 2 || r == 4) && (tpc == 4 || tpc == 8 || tpc == 16) && (wx == 8 || wx == 16) && ms >= 0;
+        if (ok) {
+            ecc_tiling t{};
+            t.rows = r;
+            t.tiles_per_cu = tpc;
+            t.waves_x = wx;
+            t.ms = (float)ms;
+            rows.push_back({TuneKey{dtype, nin, n1, n2, (int64_t)planes}, t});
+        }
+    }
+    const bool read_ok = !ferror(f);
+    fclose(f);
+    if (!ok || !read_ok) {
+        if (!ok) set_error("ecc_autotune_load: %s line %d is not a tiling entry", path, lineno);
+        else set_error("ecc_autotune_load: reading %s failed", path);
+        return ECC_E_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &e : rows) g_tuned[e.first] = e.second;
+    return (int)rows.size();
+}
+
 // Dual complex (voxels as vertices, lower-star filtration).  Its cells are
 // the cells of the voxel complex away from the box's outer boundary, with
 // dimension d - dim and value the maximum over their voxels, so by

@@ -119,3 +119,41 @@ def test_job_struct_layout():
     # image, dims (int32 + pad + 4 x int64), dtype (+ pad), chi
     assert ctypes.sizeof(ecc.Job) == 8 + 40 + 8 + 8
     assert ecc.Job.chi.offset == 56
+
+
+def test_autotune_cache_save_and_load(tmp_path):
+    """The tuning cache as a text file: entries load into the table that
+    ecc_tiling_for reads, save writes them back, a malformed file stores
+    nothing (no GPU is needed for any of it)."""
+    import paper_1705_02045_amd as ecc
+    ecc.autotune_reset()
+    shape = (1024, 1024, 1024)
+    rule = ecc.tiling_for(shape, "u14")
+    assert ecc.autotune_save(tmp_path / "empty.txt") == 0 and (tmp_path / "empty.txt").read_text() == ""
+    cache = tmp_path / "tiling.txt"
+    cache.write_text("# tuned on one MI355X\n"
+                     "ecc-tiling-v1 2 2 1024 1024 1024 4 8 8 0.61\n"
+                     "\n"
+                     "ecc-tiling-v1 1 1 1 300 70 2 16 16 0.01\n")
+    assert ecc.autotune_load(cache) == 2
+    assert ecc.tiling_for(shape, "u14") == {"rows": 4, "tiles_per_cu": 8, "waves_x": 8}
+    assert ecc.tiling_for((70, 300), "u8") == {"rows": 2, "tiles_per_cu": 16, "waves_x": 16}
+    out = tmp_path / "saved.txt"
+    assert ecc.autotune_save(out) == 2
+    assert sorted(out.read_text().split("\n")) == sorted(
+        ["ecc-tiling-v1 1 1 1 300 70 2 16 16 0.01", "ecc-tiling-v1 2 2 1024 1024 1024 4 8 8 0.61", ""])
+    ecc.autotune_reset()
+    assert ecc.tiling_for(shape, "u14") == rule
+    for bad in ["ecc-tiling-v1 2 2 1024 1024 1024 3 8 8 0.61\n",          # rows 3
+                "ecc-tiling-v1 2 2 1024 1024 1024 4 8 8\n",               # a field missing
+                "ecc-tiling-v1 2 2 1024 1024 1024 4 8 8 0.61 extra\n",    # one too many
+                "ecc-tiling-v2 2 2 1024 1024 1024 4 8 8 0.61\n",          # unknown tag
+                "ecc-tiling-v1 4 2 1024 1024 1024 4 8 8 0.61\n",          # float32: no integer tiling
+                "ecc-tiling-v1 2 2 1024 1024 1024 4 8 8 0.61\ngarbage\n"]:
+        cache.write_text(bad)
+        with pytest.raises(ecc.EccError) as ei:
+            ecc.autotune_load(cache)
+        assert ei.value.code == ecc.ECC_E_ARG
+        assert ecc.tiling_for(shape, "u14") == rule  # nothing stored
+    with pytest.raises(ecc.EccError):
+        ecc.autotune_load(tmp_path / "missing.txt")

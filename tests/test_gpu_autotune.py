@@ -68,3 +68,20 @@ def test_batch_autotune(ecc):
     for (d, s), img, c in zip(specs, imgs, chis):
         assert (c.cpu().numpy() == oracle.curve(img, m=ecc.THRESHOLDS[d])).all(), f"{d} {s}"
     b.close()
+
+
+def test_autotune_cache_round_trip(ecc, tmp_path):
+    """A tiling tuned on the GPU, saved, forgotten and loaded back is the one
+    later launches use; every curve stays the oracle's."""
+    img = gen.cfg_u14_value_noise((40, 300, 260), seed=32)
+    t = dev(img)
+    ecc.autotune_reset()
+    best = ecc.autotune(t, "u14")
+    path = tmp_path / "tiling.txt"
+    assert ecc.autotune_save(path) == 1
+    ecc.autotune_reset()
+    assert ecc.autotune_load(path) == 1
+    got = ecc.tiling_for(img.shape, "u14")
+    assert got == {k: best[k] for k in ("rows", "tiles_per_cu", "waves_x")}
+    assert (ecc.compute(t, "u14").cpu().numpy() == oracle.curve(img, m=16384)).all()
+    ecc.autotune_reset()
