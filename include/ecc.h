@@ -267,6 +267,22 @@ int ecc_stream_finish(ecc_stream *st, ecc_curve *curve);
 /* Frees the handle without producing a curve.  NULL is ignored. */
 void ecc_stream_abort(ecc_stream *st);
 
+/* Checkpoint / resume of a stream (Sec. 3, "Streaming": the changes vector
+ * of the planes done, the planes a later chunk still needs as its collar and
+ * the count of planes pushed are a complete state).
+ * ecc_stream_snapshot_size: bytes of a snapshot of the stream as it is now.
+ * ecc_stream_snapshot: waits for the stream's work, then writes the
+ *   snapshot into host_buf (host memory of at least that size; the stream
+ *   stays usable).  Errors: ECC_E_ARG, ECC_E_BUFFER_TOO_SMALL, ECC_E_HIP.
+ * ecc_stream_restore: a new stream handle (on `stream`, the current device)
+ *   in the state of the snapshot; pushing the remaining planes and finishing
+ *   gives the curve of the whole image.  The snapshot is checked (its
+ *   header, every count against its dims, its size): ECC_E_ARG if it does
+ *   not describe a state of such a stream; also ECC_E_NOMEM, ECC_E_HIP. */
+int ecc_stream_snapshot_size(const ecc_stream *st, int64_t *bytes);
+int ecc_stream_snapshot(ecc_stream *st, void *host_buf, int64_t capacity);
+int ecc_stream_restore(const void *host_buf, int64_t bytes, void *stream, ecc_stream **out);
+
 /* ---------------------------------------------------------------------------
  * Batches of independent images (integer dtypes).  Curves of unrelated images
  * never merge, so one launch can carry the tiles of many images (Sec. 3,

@@ -98,6 +98,12 @@ _lib.ecc_stream_finish.restype = ctypes.c_int
 _lib.ecc_stream_finish.argtypes = [_vp, ctypes.POINTER(Curve)]
 _lib.ecc_stream_abort.restype = None
 _lib.ecc_stream_abort.argtypes = [_vp]
+_lib.ecc_stream_snapshot_size.restype = ctypes.c_int
+_lib.ecc_stream_snapshot_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
+_lib.ecc_stream_snapshot.restype = ctypes.c_int
+_lib.ecc_stream_snapshot.argtypes = [_vp, _vp, ctypes.c_int64]
+_lib.ecc_stream_restore.restype = ctypes.c_int
+_lib.ecc_stream_restore.argtypes = [_vp, ctypes.c_int64, _vp, ctypes.POINTER(_vp)]
 _lib.ecc_profile_enable.restype = ctypes.c_int
 _lib.ecc_profile_enable.argtypes = [ctypes.c_int]
 _lib.ecc_profile_reset.restype = ctypes.c_int
@@ -382,6 +388,29 @@ class Stream:
         _check(_lib.ecc_stream_finish(h, ctypes.byref(cv)), "ecc_stream_finish")
         return chi
 
+
+    def snapshot(self):
+        """ecc_stream_snapshot: the stream's resume state as a numpy uint8 array."""
+        import numpy as np
+        n = ctypes.c_int64()
+        _check(_lib.ecc_stream_snapshot_size(self._h, ctypes.byref(n)), "ecc_stream_snapshot_size")
+        buf = np.empty(n.value, dtype=np.uint8)
+        _check(_lib.ecc_stream_snapshot(self._h, buf.ctypes.data, n.value), "ecc_stream_snapshot")
+        return buf
+
+    @classmethod
+    def restore(cls, snapshot, dtype: str, stream=None):
+        """ecc_stream_restore: a stream in the state of a snapshot (numpy uint8)."""
+        import numpy as np
+        import torch
+        buf = np.ascontiguousarray(snapshot, dtype=np.uint8)
+        self = cls.__new__(cls)
+        self.dtype = dtype
+        self._h = ctypes.c_void_p()
+        s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else (
+            _stream_handle(torch.cuda.current_device()) if torch.cuda.is_available() else None)
+        _check(_lib.ecc_stream_restore(buf.ctypes.data, buf.size, s, ctypes.byref(self._h)), "ecc_stream_restore")
+        return self
     def abort(self):
         h, self._h = self._h, ctypes.c_void_p()
         _lib.ecc_stream_abort(h)

@@ -27,6 +27,7 @@
 #include "ecc_internal.h"
 
 struct ecc_stream {
+    ecc_dims dims{};  // as given to ecc_stream_begin
     int device = -1;
     hipStream_t compute = nullptr;  // caller's stream
     hipStream_t copy = nullptr;     // owned
@@ -232,6 +233,22 @@ int run_chunk(ecc_stream *st, const uint8_t *chunk, int64_t f, int64_t n, int64_
     return ECC_OK;
 }
 
+// Snapshot (a resume state, Sec. 3 "Streaming": the changes vector, the
+// planes a later chunk still needs and the count of planes pushed): a
+// header, the changes vector (m int64), the carried planes.
+constexpr uint32_t kSnapMagic = 0x53434345u;  // "ECCS"
+struct SnapHeader {
+    uint32_t magic, version;
+    ecc_dims dims;
+    int32_t dtype, m;
+    int64_t pushed, emitted, plane_bytes;
+    int32_t ncarry;
+    uint32_t status;
+};
+int64_t snap_bytes(const ecc_stream *st) {
+    return (int64_t)sizeof(SnapHeader) + (int64_t)st->m * 8 + (int64_t)st->ncarry * st->plane_bytes;
+}
+
 }  // namespace
 
 extern "C" {
@@ -287,6 +304,7 @@ int ecc_stream_begin(const ecc_dims *full_dims, ecc_dtype dtype, void *stream, e
         return ECC_E_UNSUPPORTED;
     }
     ecc_stream *st = new ecc_stream();
+    st->dims = *full_dims;
     st->compute = (hipStream_t)stream;
     st->view = v;
     st->dtype = dtype;
@@ -454,6 +472,105 @@ int ecc_stream_finish(ecc_stream *st, ecc_curve *curve) {
 }
 
 void ecc_stream_abort(ecc_stream *st) { destroy(st); }
+
+int ecc_stream_snapshot_size(const ecc_stream *st, int64_t *bytes) {
+    if (!st || !bytes) {
+        set_error("ecc_stream_snapshot_size: NULL argument");
+        return ECC_E_ARG;
+    }
+    *bytes = snap_bytes(st);
+    return ECC_OK;
+}
+
+int ecc_stream_snapshot(ecc_stream *st, void *host_buf, int64_t capacity) {
+    if (!st || !host_buf) {
+        set_error("ecc_stream_snapshot: NULL argument");
+        return ECC_E_ARG;
+    }
+    const int64_t need = snap_bytes(st);
+    if (capacity < need) {
+        set_error("ecc_stream_snapshot: %lld bytes needed, %lld given", (long long)need, (long long)capacity);
+        return ECC_E_BUFFER_TOO_SMALL;
+    }
+    int prev = -1;
+    ECC_HIP(hipGetDevice(&prev));
+    if (prev != st->device) ECC_HIP(hipSetDevice(st->device));
+    SnapHeader h{};
+    h.magic = kSnapMagic;
+    h.version = 1;
+    h.dims = st->dims;
+    h.dtype = st->dtype;
+    h.m = st->m;
+    h.pushed = st->pushed;
+    h.emitted = st->emitted;
+    h.plane_bytes = st->plane_bytes;
+    h.ncarry = st->ncarry;
+    uint8_t *out = (uint8_t *)host_buf;
+    hipError_t e = hipStreamSynchronize(st->copy);
+    if (e == hipSuccess) e = hipMemcpyAsync(out + sizeof h, st->vcec, (size_t)st->m * 8, hipMemcpyDeviceToHost, st->compute);
+    if (e == hipSuccess && st->ncarry > 0)
+        e = hipMemcpyAsync(out + sizeof h + (size_t)st->m * 8, st->carry_buf[st->cur],
+                           (size_t)(st->ncarry * st->plane_bytes), hipMemcpyDeviceToHost, st->compute);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h.status, st->status, 4, hipMemcpyDeviceToHost, st->compute);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->compute);
+    if (prev != st->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return hip_fail(e, "ecc_stream_snapshot");
+    memcpy(out, &h, sizeof h);
+    return ECC_OK;
+}
+
+int ecc_stream_restore(const void *host_buf, int64_t bytes, void *stream, ecc_stream **out) {
+    if (!host_buf || !out) {
+        set_error("ecc_stream_restore: NULL argument");
+        return ECC_E_ARG;
+    }
+    *out = nullptr;
+    SnapHeader h;
+    if (bytes < (int64_t)sizeof h) {
+        set_error("ecc_stream_restore: %lld bytes is not a snapshot", (long long)bytes);
+        return ECC_E_ARG;
+    }
+    memcpy(&h, host_buf, sizeof h);
+    if (h.magic != kSnapMagic || h.version != 1) {
+        set_error("ecc_stream_restore: not a stream snapshot (magic or version)");
+        return ECC_E_ARG;
+    }
+    ecc_stream *st = nullptr;
+    int rc = ecc_stream_begin(&h.dims, (ecc_dtype)h.dtype, stream, &st);
+    if (rc) return rc;
+    // the snapshot must describe a state of a stream of these dims: every
+    // field in range, and the size exact
+    const bool ok = h.m == st->m && h.plane_bytes == st->plane_bytes && h.pushed >= 0 && h.pushed <= st->view.n0 &&
+                    h.ncarry == (int32_t)min64(h.pushed, 2) &&
+                    h.emitted == (h.pushed == 0 ? 0 : (h.pushed == st->view.n0 ? st->view.n0 : h.pushed - 1)) &&
+                    (h.status & ~kStatusRange) == 0 &&
+                    bytes == (int64_t)sizeof h + (int64_t)h.m * 8 + (int64_t)h.ncarry * h.plane_bytes;
+    if (!ok) {
+        destroy(st);
+        set_error("ecc_stream_restore: the snapshot's state does not match its dims");
+        return ECC_E_ARG;
+    }
+    const uint8_t *in = (const uint8_t *)host_buf;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (prev != st->device) (void)hipSetDevice(st->device);
+    hipError_t e = hipMemcpyAsync(st->vcec, in + sizeof h, (size_t)h.m * 8, hipMemcpyHostToDevice, st->compute);
+    if (e == hipSuccess && h.ncarry > 0)
+        e = hipMemcpyAsync(st->carry_buf[st->cur], in + sizeof h + (size_t)h.m * 8, (size_t)(h.ncarry * h.plane_bytes),
+                           hipMemcpyHostToDevice, st->compute);
+    if (e == hipSuccess) e = hipMemcpyAsync(st->status, &h.status, 4, hipMemcpyHostToDevice, st->compute);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->compute);
+    if (prev != st->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+        destroy(st);
+        return hip_fail(e, "ecc_stream_restore");
+    }
+    st->pushed = h.pushed;
+    st->emitted = h.emitted;
+    st->ncarry = h.ncarry;
+    *out = st;
+    return ECC_OK;
+}
 
 }  // extern "C"
 

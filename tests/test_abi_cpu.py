@@ -157,3 +157,15 @@ def test_autotune_cache_save_and_load(tmp_path):
         assert ecc.tiling_for(shape, "u14") == rule  # nothing stored
     with pytest.raises(ecc.EccError):
         ecc.autotune_load(tmp_path / "missing.txt")
+
+
+def test_stream_restore_rejects_non_snapshots():
+    """Checked before any device work: too short, wrong magic."""
+    import ctypes
+    import numpy as np
+    import paper_1705_02045_amd as ecc
+    h = ctypes.c_void_p()
+    for buf in (np.zeros(8, dtype=np.uint8), np.zeros(200, dtype=np.uint8)):
+        rc = ecc._lib.ecc_stream_restore(buf.ctypes.data, buf.size, None, ctypes.byref(h))
+        assert rc == ecc.ECC_E_ARG and not h.value
+    assert ecc._lib.ecc_stream_restore(None, 0, None, ctypes.byref(h)) == ecc.ECC_E_ARG

@@ -173,3 +173,58 @@ def test_stream_4d_large_planes_several_launches(ecc):
     st.push(t)
     got = st.finish()
     assert res[-1] == 1 and (got == res).all()
+
+
+@pytest.mark.parametrize("dtype,shape", [("u14", (13, 70, 90)), ("u8", (9, 130)), ("u16", (8, 30, 40)),
+                                         ("u14", (7, 9, 10, 70))], ids=str)
+def test_stream_snapshot_and_restore(ecc, dtype, shape):
+    """Checkpoint / resume: a snapshot taken after some chunks, restored into
+    new handles (twice, independently, after the first stream was aborted),
+    and the remaining chunks pushed: every continuation gives the oracle's
+    curve.  A snapshot of a stream with nothing pushed restores too."""
+    img = img_4d(shape, dtype, seed=40) if len(shape) == 4 else (
+        gen.cfg_u14_value_noise(shape, seed=40) if dtype == "u14" else gen.iid(shape, int(dtype[1:]), seed=40))
+    ref = oracle.curve(img, m=ecc.THRESHOLDS[dtype])
+    cut = [0, 2, 5]
+    st = ecc.Stream(img.shape, dtype)
+    empty = st.snapshot()
+    for a, b in zip(cut[:-1], cut[1:]):
+        st.push(np.ascontiguousarray(img[a:b]))
+    snap = st.snapshot()
+    st.abort()
+    for _ in range(2):
+        st2 = ecc.Stream.restore(snap, dtype)
+        st2.push(np.ascontiguousarray(img[5:6]))
+        st2.push(np.ascontiguousarray(img[6:]))
+        assert (st2.finish() == ref).all()
+    st3 = ecc.Stream.restore(empty, dtype)
+    st3.push(np.ascontiguousarray(img))
+    assert (st3.finish() == ref).all()
+
+
+def test_stream_restore_rejects_bad_snapshots(ecc):
+    img = gen.cfg_u14_value_noise((6, 20, 30), seed=41)
+    st = ecc.Stream(img.shape, "u14")
+    st.push(img[:3])
+    snap = st.snapshot()
+    st.abort()
+    for bad in (snap[:-1], np.concatenate([snap, snap[:8]]), snap[:16]):
+        with pytest.raises(ecc.EccError) as ei:
+            ecc.Stream.restore(bad, "u14")
+        assert ei.value.code == ecc.ECC_E_ARG
+    wrong = snap.copy()
+    wrong.view(np.int64)[7] = 5  # planes pushed: no longer matches the planes emitted
+    with pytest.raises(ecc.EccError) as ei:
+        ecc.Stream.restore(wrong, "u14")
+    assert ei.value.code == ecc.ECC_E_ARG
+    # a range error in the planes done travels with the snapshot
+    bad_img = img.copy()
+    bad_img[1, 2, 3] = 20000
+    st = ecc.Stream(img.shape, "u14")
+    st.push(bad_img[:3])
+    st4 = ecc.Stream.restore(st.snapshot(), "u14")
+    st.abort()
+    st4.push(bad_img[3:])
+    with pytest.raises(ecc.EccError) as ei:
+        st4.finish()
+    assert ei.value.code == ecc.ECC_E_RANGE
