@@ -119,6 +119,20 @@ int run_chunk_4d(ecc_stream *st, const uint8_t *chunk, int64_t f, int64_t lo, in
     const int eb = st->dtype == ECC_U8 ? 1 : 2;
     const int64_t step = (((int64_t)1 << 30) - 1) / pe - 2;  // (>= 1: planes hold at most 2^28 values)
     const uint8_t *carry = st->carry_buf[st->cur];
+    // every buffer at its largest size first: a push that fails to allocate
+    // has added nothing, so it can be pushed again
+    {
+        ecc_dims w{};
+        w.ndim = 4;
+        w.n[0] = min64(step, hi - lo) + 2;
+        for (int k = 1; k < 4; ++k) w.n[k] = st->n4[k];
+        int64_t slots = 0;
+        const int64_t regions = float_regions(&w, &slots);
+        if (regions < 0) return ECC_E_UNSUPPORTED;
+        int rc = ensure_bytes((void **)&st->wbuf, &st->wbuf_bytes, (size_t)(w.n[0] * pe) * 4);
+        if (!rc) rc = ensure_bytes((void **)&st->nzbuf, &st->nzbuf_bytes, (size_t)slots * 8 + (size_t)regions * 8);
+        if (rc) return rc;
+    }
     for (int64_t b0 = lo; b0 < hi; b0 += step) {
         const int64_t b1 = min64(b0 + step, hi);
         const int64_t wlo = b0 > 0 ? b0 - 1 : 0, whi = b1 < n0 ? b1 + 1 : n0;

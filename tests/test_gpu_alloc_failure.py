@@ -94,3 +94,32 @@ def test_batch_and_serve(ecc, monkeypatch):
     for (d, _), x, c in zip(specs, imgs, chis):
         assert (c.cpu().numpy() == oracle.curve(x, m=ecc.THRESHOLDS[d])).all()
     b.close()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("kind", ["host", "device", "4d"])
+def test_stream_failed_push_is_pushed_again(ecc, monkeypatch, k, kind):
+    """A push whose k-th allocation fails reports ECC_E_NOMEM having added
+    nothing: the same chunk pushed again (allocation working), then the rest,
+    gives the oracle's curve (Sec. 3, "Streaming": a chunk's changes are
+    added once)."""
+    shape = (7, 9, 10, 70) if kind == "4d" else (12, 40, 70)
+    a, t = img_u14(shape, seed=5)
+    parts = [a[:5], a[5:]]
+    src = [torch.from_numpy(np.ascontiguousarray(p).view(np.int16)) for p in parts]
+    if kind != "host":
+        src = [s.cuda() for s in src]
+    st = ecc.Stream(a.shape, "u14")
+    monkeypatch.setenv("ECC_FAIL_ALLOC", str(k))
+    failed = False
+    try:
+        st.push(src[0])
+    except ecc.EccError as e:
+        assert e.code == ecc.ECC_E_NOMEM
+        failed = True
+    monkeypatch.delenv("ECC_FAIL_ALLOC")
+    if failed:
+        st.push(src[0])
+    st.push(src[1])
+    torch.cuda.synchronize()
+    assert (st.finish() == oracle.curve(a, m=16384)).all()
