@@ -228,6 +228,18 @@ void ecc_autotune_reset(void);
 int ecc_autotune_save(const char *path);
 int ecc_autotune_load(const char *path);
 
+/* Memory of long-running processes (no passage of the paper: library
+ * housekeeping).  The calls above keep, per stream, the device scratch they
+ * grew (sized by the largest image computed on that stream) for the next
+ * call.  ecc_release_workspaces frees that scratch for the current device;
+ * the next call on a stream grows what it needs again.  It first waits for
+ * all work on the device.  It must not overlap another call of the library
+ * on the same device, whose buffers it would free.  Stream, batch and serve
+ * handles own their buffers and keep them; so does the fixed scratch of
+ * ecc_compute_async_noalloc; tuned tilings are kept.
+ * Errors: ECC_E_HIP. */
+int ecc_release_workspaces(void);
+
 /* ---------------------------------------------------------------------------
  * Streaming (Sec. 3, "Streaming" and "Processing one Chunk"): an image larger
  * than device memory is pushed as consecutive chunks of whole axis-0 planes.

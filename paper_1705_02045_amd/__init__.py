@@ -77,6 +77,8 @@ _lib.ecc_autotune_save.restype = ctypes.c_int
 _lib.ecc_autotune_save.argtypes = [ctypes.c_char_p]
 _lib.ecc_autotune_load.restype = ctypes.c_int
 _lib.ecc_autotune_load.argtypes = [ctypes.c_char_p]
+_lib.ecc_release_workspaces.restype = ctypes.c_int
+_lib.ecc_release_workspaces.argtypes = []
 _lib.ecc_batch_autotune.restype = ctypes.c_int
 _lib.ecc_batch_autotune.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
@@ -314,6 +316,12 @@ def autotune_load(path) -> int:
     if n < 0:
         _check(n, "ecc_autotune_load")
     return n
+
+
+def release_workspaces() -> None:
+    """ecc_release_workspaces: frees the per-stream device scratch kept
+    between calls on the current device (waits for the device first)."""
+    _check(_lib.ecc_release_workspaces(), "ecc_release_workspaces")
 
 
 def compute_dual(image, dtype: str):

@@ -1095,6 +1095,51 @@ void ecc_autotune_reset(void) {
     g_tuned.clear();
 }
 
+// The growable scratch of every workspace of the current device is freed
+// (the small status block and host word stay, so the workspaces remain
+// valid); the next call on a stream grows its buffers again.  Work still in
+// flight on the device may use them: it is waited for first.
+int ecc_release_workspaces(void) {
+    int dev = 0;
+    ECC_HIP(hipGetDevice(&dev));
+    ECC_HIP(hipDeviceSynchronize());
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    hipError_t first = hipSuccess;
+    auto drop = [&](void *p, size_t *cap) {
+        if (p) {
+            const hipError_t e = hipFree(p);
+            if (e != hipSuccess && first == hipSuccess) first = e;
+        }
+        *cap = 0;
+    };
+    for (auto &kv : g_ws) {
+        Workspace *w = kv.second;
+        if (w->device != dev || w->fixed) continue;
+        drop(w->partial, &w->partial_bytes);
+        w->partial = nullptr;
+        drop(w->vcec, &w->vcec_bytes);
+        w->vcec = nullptr;
+        drop(w->stage, &w->stage_bytes);
+        w->stage = nullptr;
+        drop(w->chi_tmp, &w->chi_tmp_bytes);
+        w->chi_tmp = nullptr;
+        drop(w->img_tmp, &w->img_tmp_bytes);
+        w->img_tmp = nullptr;
+        drop(w->fbuf, &w->fbuf_bytes);
+        w->fbuf = nullptr;
+        drop(w->frec, &w->frec_bytes);
+        w->frec = nullptr;
+        drop(w->dual_buf, &w->dual_buf_bytes);
+        w->dual_buf = nullptr;
+        drop(w->i2f_buf, &w->i2f_buf_bytes);
+        w->i2f_buf = nullptr;
+        drop(w->vcec16, &w->vcec16_bytes);
+        w->vcec16 = nullptr;
+    }
+    if (first != hipSuccess) return hip_fail(first, "hipFree(workspace)");
+    return ECC_OK;
+}
+
 static const char kTuneTag[] = "ecc-tiling-v1";
 
 int ecc_autotune_save(const char *path) {

@@ -20,3 +20,21 @@ def _ensure_built():
 
 
 _ensure_built()
+
+
+import pytest  # noqa: E402
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _release_device_memory():
+    """After each test module: return the memory its tensors left in torch's
+    cache and the library's per-stream scratch, so that a module with large
+    images does not leave later modules short of device memory."""
+    yield
+    import torch
+    if not torch.cuda.is_available():
+        return
+    import paper_1705_02045_amd as ecc
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    ecc.release_workspaces()

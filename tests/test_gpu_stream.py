@@ -163,6 +163,8 @@ def test_stream_4d_large_planes_several_launches(ecc):
     planes below 2^30 values), against the resident curve of the same bytes
     (itself checked against the oracle on smaller 4-D images)."""
     shape = (3, 256, 1024, 1024)
+    torch.cuda.empty_cache()
+    ecc.release_workspaces()  # the resident float path below needs tens of GB of scratch
     print(f"\n[gpu] stream 4-D u8 {shape}: generating", flush=True)
     t = torch.randint(0, 256, shape, dtype=torch.uint8, generator=torch.Generator().manual_seed(31)).cuda()
     print("[gpu] resident", flush=True)
