@@ -34,9 +34,10 @@ sys.path.insert(0, str(ROOT))
 METRIC = "GVoxel/s + % HBM peak, 3D 14-bit ECC; batched images/s at p99 latency"
 HBM_PEAK_GBS = 8000.0
 # the kernel, and the host code that picks its launch parameters (tiling,
-# look-ahead depth)
-KERNEL_SOURCES = ["paper_1705_02045_amd/csrc/ecc_int.hip", "paper_1705_02045_amd/csrc/ecc_internal.h",
-                  "paper_1705_02045_amd/csrc/ecc_api.cpp"]
+# look-ahead depth): the tiling functions of ecc_api.cpp, from the first
+# marker up to the second
+KERNEL_SOURCES = ["paper_1705_02045_amd/csrc/ecc_int.hip", "paper_1705_02045_amd/csrc/ecc_internal.h"]
+TILING_SOURCE = ("paper_1705_02045_amd/csrc/ecc_api.cpp", "IntTiling make_int_tiling(", "IntTiling choose_int_tiling(")
 TRAFFIC_FILE = ROOT / "profiles" / "traffic_int_vcec_u14_1024cubed.json"
 
 
@@ -48,6 +49,10 @@ def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
         h.update((ROOT / rel).read_bytes())
+    rel, first, last = TILING_SOURCE
+    text = (ROOT / rel).read_text()
+    a = text.index(first)
+    h.update(text[a:text.index(last, a)].encode())
     return h.hexdigest()[:16]
 
 
