@@ -154,6 +154,48 @@ int get_workspace(void *stream, Workspace **out) {
     return ECC_OK;
 }
 
+// Side streams of a caller's stream: the box faces of the dual complex run
+// on them, concurrently with the full box on the caller's stream (a fork at
+// the call's start, a join before the faces' changes are summed).  Created
+// on first use per (device, caller's stream) with the default priority,
+// non-blocking, and kept for the process; each has its own workspace.
+struct SideStreams {
+    static constexpr int kCount = 4;
+    hipStream_t s[kCount] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kCount] = {};
+};
+static std::mutex g_side_mu;
+static std::map<std::pair<int, void *>, SideStreams *> g_side;
+
+static int get_side_streams(void *stream, SideStreams **out) {
+    int dev = 0;
+    ECC_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    auto key = std::make_pair(dev, stream);
+    auto it = g_side.find(key);
+    if (it == g_side.end()) {
+        SideStreams *p = new SideStreams();
+        hipError_t e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+        for (int k = 0; e == hipSuccess && k < SideStreams::kCount; ++k) {
+            e = hipStreamCreateWithFlags(&p->s[k], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join[k], hipEventDisableTiming);
+        }
+        if (e != hipSuccess) {
+            for (int k = 0; k < SideStreams::kCount; ++k) {
+                if (p->join[k]) (void)hipEventDestroy(p->join[k]);
+                if (p->s[k]) (void)hipStreamDestroy(p->s[k]);
+            }
+            if (p->fork) (void)hipEventDestroy(p->fork);
+            delete p;
+            return hip_fail(e, "side streams");
+        }
+        it = g_side.emplace(key, p).first;
+    }
+    *out = it->second;
+    return ECC_OK;
+}
+
 int check_dims(const ecc_dims *dims, int64_t *total) {
     if (!dims) {
         set_error("dims is NULL");
@@ -1276,17 +1318,37 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
     int64_t face_max = 1;  // the largest face of codimension >= 1
     for (int k = 0; k < d; ++k)
         if (total / n[k] > face_max) face_max = total / n[k];
-    // dual_buf: [nf][m] per-face changes vectors, [m] their signed sum, the
-    // table of faces of at most one dimension, then one gathered face
-    const size_t curves_bytes = (size_t)(nf + 1) * m * sizeof(int64_t);
+    // dual_buf: [nf][m] per-face changes vectors, [m] the changes of the
+    // faces of at most one dimension (all of them, signed), [m] the signed
+    // sum, the table of faces of at most one dimension
+    const size_t curves_bytes = (size_t)(nf + 2) * m * sizeof(int64_t);
     const size_t low_off = (curves_bytes + 255) & ~(size_t)255;
-    const size_t face_off = low_off + ((nf * sizeof(LowFace) + 255) & ~(size_t)255);
-    rc = ensure_bytes(&ws->dual_buf, &ws->dual_buf_bytes, face_off + (size_t)face_max * eb);
+    rc = ensure_bytes(&ws->dual_buf, &ws->dual_buf_bytes, low_off + ((nf * sizeof(LowFace) + 255) & ~(size_t)255));
     if (rc) return rc;
     int64_t *curves = (int64_t *)ws->dual_buf;
-    int64_t *result = curves + (size_t)nf * m;
+    int64_t *lowv = curves + (size_t)nf * m;
+    int64_t *result = lowv + m;
     LowFace *low_dev = (LowFace *)((uint8_t *)ws->dual_buf + low_off);
-    uint8_t *face = (uint8_t *)ws->dual_buf + face_off;
+    // Faces of two or more dimensions below the full box go round-robin to
+    // the side streams, each with its own workspace (and gather buffer in
+    // its img_tmp); the full box runs on s.
+    SideStreams *side = nullptr;
+    rc = get_side_streams(s, &side);
+    if (rc) return rc;
+    Workspace *sws[SideStreams::kCount];
+    for (int k = 0; k < SideStreams::kCount; ++k) {
+        rc = get_workspace(side->s[k], &sws[k]);
+        if (rc) return rc;
+    }
+    bool used[SideStreams::kCount] = {};
+    int next_side = 0;
+    // after the fork, every return first waits for the side streams (their
+    // work uses buffers that a later call may reallocate)
+    auto sync_sides = [&]() {
+        for (int k = 0; k < SideStreams::kCount; ++k)
+            if (used[k]) (void)hipStreamSynchronize(side->s[k]);
+    };
+    ECC_HIP(hipEventRecord(side->fork, s));  // the image (and its copy, if any) is ready here
     const int gsign = (d & 1) ? -1 : 1;
     uint64_t neg[2] = {0, 0}, skip[2] = {0, 0};  // bit f of the pair: face f
     auto set_bit = [](uint64_t *mask, int f) { mask[f >> 6] |= 1ull << (f & 63); };
@@ -1324,8 +1386,23 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
             bd.ndim = 4;
             for (int k = 0; k < 4; ++k) bd.n[k] = n[k];
             rc = int_via_float_dev(img_dev, &bd, total, dtype, true, true, curves + (size_t)f * m, s, ws);
-            if (rc) return rc;
+            if (rc) {
+                sync_sides();
+                return rc;
+            }
             continue;
+        }
+        // the full box on s, a face on the next side stream
+        const int k = codim > 0 ? (next_side++ % SideStreams::kCount) : -1;
+        hipStream_t fs_stream = k < 0 ? s : side->s[k];
+        Workspace *fws = k < 0 ? ws : sws[k];
+        if (k >= 0 && !used[k]) {
+            hipError_t e = hipStreamWaitEvent(fs_stream, side->fork, 0);
+            if (e != hipSuccess) {
+                sync_sides();
+                return hip_fail(e, "ecc_compute_dual: fork");
+            }
+            used[k] = true;
         }
         const void *src = img_dev;
         int64_t pstride = 0;
@@ -1335,15 +1412,20 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
             src = (const uint8_t *)img_dev + base * (int64_t)eb;
             pstride = fst[0];
         } else if (codim > 0) {
-            // free axes as the trailing axes of an n0 x n1 x n2 gather
+            // free axes as the trailing axes of an n0 x n1 x n2 gather, into
+            // the side stream's buffer (its faces run in stream order)
             int64_t g[3] = {1, 1, 1}, gs[3] = {0, 0, 0};
             for (int i = 0; i < nfree; ++i) {
                 g[3 - nfree + i] = fs[i];
                 gs[3 - nfree + i] = fst[i];
             }
-            rc = launch_gather(img_dev, (int)eb, base, gs[0], gs[1], gs[2], g[0], g[1], g[2], face, s);
-            if (rc) return rc;
-            src = face;
+            rc = ensure_bytes(&fws->img_tmp, &fws->img_tmp_bytes, (size_t)face_max * eb);
+            if (!rc) rc = launch_gather(img_dev, (int)eb, base, gs[0], gs[1], gs[2], g[0], g[1], g[2], fws->img_tmp, fs_stream);
+            if (rc) {
+                sync_sides();
+                return rc;
+            }
+            src = fws->img_tmp;
         }
         ecc_dims fd{};
         fd.ndim = nfree > 0 ? nfree : 1;
@@ -1352,24 +1434,59 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
         IntView v{};
         int unsup = 0;
         if (!normalize_int_view(&fd, &v, &unsup)) {
+            sync_sides();
             set_error("ecc_compute_dual: face shape not supported");
             return ECC_E_UNSUPPORTED;
         }
-        rc = enqueue_int_changes(src, v, dtype, curves + (size_t)f * m, s, ws, true, pstride);
-        if (rc) return rc;
-        if (codim & 1) set_bit(neg, f);
-    }
-    rc = launch_signed_sum(curves, nf, neg, skip, gsign, (int)m, result, s);
-    if (rc) return rc;
-    if (!low.empty()) {
-        // the host table must outlive the copy: every return below this point
-        // synchronizes the stream first
-        ECC_HIP(hipMemcpyAsync(low_dev, low.data(), low.size() * sizeof(LowFace), hipMemcpyHostToDevice, s));
-        rc = launch_low_faces(img_dev, (int)eb, low_dev, (int)low.size(), (int)m, result, s);
+        rc = enqueue_int_changes(src, v, dtype, curves + (size_t)f * m, fs_stream, fws, true, pstride);
         if (rc) {
-            (void)hipStreamSynchronize(s);
+            sync_sides();
             return rc;
         }
+        if (codim & 1) set_bit(neg, f);
+    }
+    // Box edges and corners: their table, a cleared vector and the
+    // closed-form changes on the next side stream, summed as one more face
+    // (slot nf, whose entries carry their signs already: the global sign
+    // is cancelled by the slot's own).  The host table must outlive the
+    // copy: every return below this point waits for the side streams (the
+    // join and the final synchronisation of s, or sync_sides).
+    if (!low.empty()) {
+        const int k = next_side % SideStreams::kCount;
+        hipStream_t ls = side->s[k];
+        hipError_t e = hipSuccess;
+        if (!used[k]) e = hipStreamWaitEvent(ls, side->fork, 0);
+        used[k] = true;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(low_dev, low.data(), low.size() * sizeof(LowFace), hipMemcpyHostToDevice, ls);
+        if (e != hipSuccess) {
+            sync_sides();
+            return hip_fail(e, "ecc_compute_dual: edge and corner table");
+        }
+        rc = launch_zero(lowv, (size_t)m * sizeof(int64_t), ls);
+        if (!rc) rc = launch_low_faces(img_dev, (int)eb, low_dev, (int)low.size(), (int)m, lowv, ls);
+        if (rc) {
+            sync_sides();
+            return rc;
+        }
+        if (gsign < 0) set_bit(neg, nf);
+    } else {
+        set_bit(skip, nf);
+    }
+    // join: s waits for every side stream that took work
+    for (int k = 0; k < SideStreams::kCount; ++k) {
+        if (!used[k]) continue;
+        hipError_t e = hipEventRecord(side->join[k], side->s[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, side->join[k], 0);
+        if (e != hipSuccess) {
+            sync_sides();
+            return hip_fail(e, "ecc_compute_dual: join");
+        }
+    }
+    rc = launch_signed_sum(curves, nf + 1, neg, skip, gsign, (int)m, result, s);
+    if (rc) {
+        (void)hipStreamSynchronize(s);
+        return rc;
     }
     // scan into slot 0 (its changes are summed already); the status of every
     // face launch (all read the image's values) is reported and cleared here
