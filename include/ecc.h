@@ -51,8 +51,8 @@ typedef enum {
 typedef enum {
     ECC_U8 = 1,   /* uint8,  m = 256 */
     ECC_U14 = 2,  /* uint16 storage, values < 16384, m = 16384 */
-    ECC_U16 = 3,  /* uint16, m = 65536 (ecc_compute and ecc_compute_async; counted in passes
-                     over windows of 16382 values, see ecc_compute_async) */
+    ECC_U16 = 3,  /* uint16, m = 65536 (ecc_compute and ecc_compute_async; counted in one or two
+                     passes over the image, see ecc_compute_async) */
     ECC_F32 = 4   /* float32; thresholds are the distinct values (Sec. 3, "Other Ranges of Gray Values") */
 } ecc_dtype;
 
@@ -150,10 +150,12 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
 
 /* Stream-ordered form for integer types with device-resident data: enqueues
  * the whole computation on `stream` and returns without synchronizing.
- * ECC_U16 images are counted in up to five passes over the image, each
- * counting one window of 16382 consecutive values (the workgroup histograms
- * hold 16384 bins); this form runs all five, ecc_compute only those between
- * the image's minimum and maximum (found first, one extra read).
+ * ECC_U16 images are counted in passes over the image: values that fit one
+ * window of 16384 go through one pass of 16384-bin workgroup histograms,
+ * wider ranges through 32768-bin passes (one when the values span fewer
+ * than 32768, else two, each adding the values of its half of 0..65535).
+ * This form plans for 0..65535 (two passes); ecc_compute plans from the
+ * image's minimum and maximum (found first, one extra read).
  *   image_dev: device pointer, prod(n) elements.
  *   chi_dev:   device pointer, m int64 entries; written only if the input is
  *              valid (all U14 values < 16384).
@@ -321,7 +323,7 @@ int ecc_batch_create(void *stream, ecc_batch **out);
  * from several host threads.  The images and chi buffers must stay valid
  * until the work is done.  u8 and u14 jobs share one persistent launch;
  * ECC_U16 jobs (m = 65536, more bins than a workgroup histogram holds) run
- * after it on the same stream, one launch per window of 16384 values each.
+ * after it on the same stream, as ecc_compute_async runs them (two passes).
  * Errors: ECC_E_ARG (bad job), ECC_E_UNSUPPORTED (shape or dtype the integer
  * path does not take), ECC_E_NOMEM, ECC_E_HIP. */
 int ecc_batch_run(ecc_batch *b, int32_t n_jobs, const ecc_job *jobs, uint32_t *status_dev);

@@ -59,6 +59,14 @@ constexpr int kBufferWord3 = 0x00020000;
 constexpr int kXfNone = 0;
 constexpr int kXfInvert = 1;
 constexpr int kXfWindow = 2;
+// 16-bit values in 32768-bin passes: the fields are the raw values (32-bit,
+// kInfRaw above all of them) and each update's LDS address is
+// 4 * (value - win_shift); kXfRange: every value of the image lies in the
+// pass's range; kXfRangeMasked: the adds of values outside it are masked off.
+constexpr int kXfRange = 3;
+constexpr int kXfRangeMasked = 4;
+constexpr bool raw_fields(int xf) { return xf == kXfRange || xf == kXfRangeMasked; }
+constexpr uint32_t kInfRaw = 0x10000u;
 
 // Field values are LDS byte offsets of their bins (value * 4), computed with
 // packed 16-bit ops.  The 16-bit VOP2 forms (v_lshlrev_b16, v_min_u16) write
@@ -118,6 +126,15 @@ __device__ __forceinline__ void pair_offsets(uint32_t d, uint32_t sh, uint32_t &
     asm("v_pk_min_u16 %0, %1, %2" : "=v"(m) : "v"(pv), "v"(f0));
     fx = m;
 }
+// The same without the scaling: f0 = value at x, fx = min(value at x-1,
+// value at x), both raw (high half 0).
+__device__ __forceinline__ void pair_values(uint32_t d, uint32_t sh, uint32_t &f0, uint32_t &fx) {
+    uint32_t m;
+    f0 = __builtin_amdgcn_ubfe(d, sh, 16);
+    const uint32_t pv = (uint32_t)__builtin_amdgcn_update_dpp((int)d, (int)f0, kDppWaveShr1, 0xF, 0xF, false);
+    asm("v_pk_min_u16 %0, %1, %2" : "=v"(m) : "v"(pv), "v"(f0));
+    fx = m;
+}
 // clamp(v - s, 0, 16383) on both halves; s2 = s | s << 16 (0 <= s < 65536)
 __device__ __forceinline__ uint32_t pair_window(uint32_t q, uint32_t s2) {
     uint32_t m, d, r;
@@ -164,6 +181,25 @@ __device__ __forceinline__ uint64_t ballot(bool b) { return __builtin_amdgcn_bal
                    [e2] "v"(e2), [e3] "v"(e3), [c0] "s"(c0), [c1] "s"(c1), [c2] "s"(c2), [c3] "s"(c3),          \
                    [p0] "s"(p0), [p1] "s"(p1), [p2] "s"(p2), [p3] "s"(p3), [one] "v"(one), [mone] "v"(mone) \
                  : "memory", "scc")
+
+// The select form with a further lane mask per item (r_i: the lanes whose
+// value lies in the pass's range).
+#define ECC_SELR(i) \
+    "s_xor_b64 exec, %[c" #i "], %[p" #i "]\n\ts_and_b64 exec, exec, %[r" #i "]\n\tds_add_u32 %[g" #i "], %[e" #i "]\n\t"
+__device__ __forceinline__ void update4_masked(uint32_t g0, uint32_t g1, uint32_t g2, uint32_t g3, uint64_t c0,
+                                               uint64_t c1, uint64_t c2, uint64_t c3, uint64_t p0, uint64_t p1,
+                                               uint64_t p2, uint64_t p3, uint64_t r0, uint64_t r1, uint64_t r2,
+                                               uint64_t r3, uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3) {
+    uint64_t sv;
+    asm volatile("s_mov_b64 %[sv], exec\n\t" ECC_SELR(0) ECC_SELR(1) ECC_SELR(2) ECC_SELR(3) "s_mov_b64 exec, %[sv]"
+                 : [sv] "=&s"(sv)
+                 : [g0] "v"(g0), [g1] "v"(g1), [g2] "v"(g2), [g3] "v"(g3), [e0] "v"(e0), [e1] "v"(e1),
+                   [e2] "v"(e2), [e3] "v"(e3), [c0] "s"(c0), [c1] "s"(c1), [c2] "s"(c2), [c3] "s"(c3),
+                   [p0] "s"(p0), [p1] "s"(p1), [p2] "s"(p2), [p3] "s"(p3), [r0] "s"(r0), [r1] "s"(r1),
+                   [r2] "s"(r2), [r3] "s"(r3)
+                 : "memory", "scc");
+}
+#undef ECC_SELR
 
 template <int SG, int DM>
 __device__ __forceinline__ void update4(uint32_t g0, uint32_t g1, uint32_t g2, uint32_t g3, uint64_t c0, uint64_t c1,
@@ -259,9 +295,46 @@ struct Walker {
         }
     }
 
-    static __device__ __forceinline__ void set_inf(uint32_t (&g)[NI]) {
+    // Raw-value fields (32768-bin passes): the element form and the row-pair
+    // form without the scaling to offsets.
+    static __device__ __forceinline__ void fields_raw(const uint32_t (&a)[NR], const uint32_t (&b)[NR],
+                                                      uint32_t (&g)[NI]) {
+        if constexpr (NIN == 1) {
 #pragma unroll
-        for (int i = 0; i < NI; ++i) g[i] = kInf;
+            for (int r = 0; r < R; ++r) {
+                g[2 * r + 0] = a[r];
+                g[2 * r + 1] = min_off(a[r], b[r]);
+            }
+        } else {
+            uint32_t fx[NR];
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr) fx[rr] = min_off(a[rr], b[rr]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                g[4 * r + 0] = a[r + 1];
+                g[4 * r + 1] = fx[r + 1];
+                g[4 * r + 2] = min_off(a[r], a[r + 1]);
+                g[4 * r + 3] = min_off(fx[r], fx[r + 1]);
+            }
+        }
+    }
+    static __device__ __forceinline__ void fields_pair_raw(const uint32_t (&d)[NR], uint32_t sh, uint32_t (&g)[NI]) {
+        static_assert(NIN == 2, "row pairs: two in-plane axes");
+        uint32_t f0[NR], fx[NR];
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) pair_values(d[rr], sh, f0[rr], fx[rr]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            g[4 * r + 0] = f0[r + 1];
+            g[4 * r + 1] = fx[r + 1];
+            g[4 * r + 2] = min_off(f0[r], f0[r + 1]);
+            g[4 * r + 3] = min_off(fx[r], fx[r + 1]);
+        }
+    }
+
+    static __device__ __forceinline__ void set_inf(uint32_t (&g)[NI], uint32_t inf) {
+#pragma unroll
+        for (int i = 0; i < NI; ++i) g[i] = inf;
     }
 
     // sign (-1)^(in-plane interval axes) of item i = r*K + k, k's bits = singleton axes
@@ -330,6 +403,8 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
     constexpr uint32_t kInvMask = ESZ == 1 ? 255u : 16383u;
     constexpr int NB = PD + 1;
     constexpr int U = lcm(2, NB);
+    constexpr bool RAW = raw_fields(XF);
+    constexpr uint32_t kSent = RAW ? kInfRaw : kInf;  // planes outside the image
     const int64_t pb = P.src.plane_bytes;
     const int32_t pbytes = (int32_t)pb;
     // planes zs-1 and ze are +inf outside the image
@@ -354,7 +429,7 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
     auto range_acc = [&](const uint32_t (&a)[NR]) {
         // rows owned by this wave (the collar row is checked by its owner);
         // every 16-bit value is valid for the window passes
-        if constexpr (XF != kXfWindow) {
+        if constexpr (XF == kXfNone || XF == kXfInvert) {
 #pragma unroll
             for (int rr = NR - R; rr < NR; ++rr) orv |= a[rr];
         }
@@ -364,6 +439,11 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
     // wait at once and lose the planes of look-ahead.
     const int32_t wshift = P.win_shift;
     auto fields = [&](const uint32_t (&a)[NR], const uint32_t (&b)[NR], uint32_t (&g)[NI]) {
+        if constexpr (RAW) {
+            if constexpr (PAIR) W::fields_pair_raw(a, psel, g);
+            else W::fields_raw(a, b, g);
+            return;
+        }
         if constexpr (PAIR) {
             W::fields_pair(a, psel, g, [&](uint32_t q) -> uint32_t {
                 if constexpr (XF == kXfInvert) return q ^ (kInvMask * 0x10001u);
@@ -387,6 +467,9 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
     // Compare plane z+1 (gn) with plane z (gc) and add the changes of plane z.
     constexpr int DM = group_dm<NIN, MODE>();
     const uint32_t one = 1u, mone = 0xFFFFFFFFu;
+    static_assert(!RAW || (MODE == 0 && sizeof(T) == 2), "32768-bin passes: 16-bit values, select updates");
+    const uint32_t abase = RAW ? (uint32_t)(-4 * (int64_t)P.win_shift) : 0u;
+    constexpr uint32_t kAddrEnd = RAW ? 4u * 32768u : 0u;
     auto step = [&](const uint32_t (&gc)[NI], const uint32_t (&gn)[NI], uint64_t (&cp)[NI]) {
 #pragma unroll
         for (int i = 0; i < NI; i += 4) {
@@ -395,8 +478,26 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
             for (int j = 0; j < 4; ++j) e[j] = ((DM >> j) & 1) ? one : flip_value(cp[i + j], W::sign(i + j));
             const uint64_t c0 = cmp(gn[i], gc[i], i), c1 = cmp(gn[i + 1], gc[i + 1], i + 1);
             const uint64_t c2 = cmp(gn[i + 2], gc[i + 2], i + 2), c3 = cmp(gn[i + 3], gc[i + 3], i + 3);
-            update4<W::kGroupSigns, DM>(gc[i], gc[i + 1], gc[i + 2], gc[i + 3], c0, c1, c2, c3, cp[i], cp[i + 1],
-                                        cp[i + 2], cp[i + 3], e[0], e[1], e[2], e[3], one, mone);
+            if constexpr (RAW) {
+                // LDS addresses 4 * (value - win_shift); outside the pass's
+                // range they wrap above 4 * M
+                uint32_t a[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) a[j] = (gc[i + j] << 2) + abase;
+                if constexpr (XF == kXfRangeMasked) {
+                    uint64_t r[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) r[j] = ballot(a[j] < kAddrEnd);
+                    update4_masked(a[0], a[1], a[2], a[3], c0, c1, c2, c3, cp[i], cp[i + 1], cp[i + 2], cp[i + 3],
+                                   r[0], r[1], r[2], r[3], e[0], e[1], e[2], e[3]);
+                } else {
+                    update4<W::kGroupSigns, DM>(a[0], a[1], a[2], a[3], c0, c1, c2, c3, cp[i], cp[i + 1], cp[i + 2],
+                                                cp[i + 3], e[0], e[1], e[2], e[3], one, mone);
+                }
+            } else {
+                update4<W::kGroupSigns, DM>(gc[i], gc[i + 1], gc[i + 2], gc[i + 3], c0, c1, c2, c3, cp[i], cp[i + 1],
+                                            cp[i + 2], cp[i + 3], e[0], e[1], e[2], e[3], one, mone);
+            }
             cp[i] = c0;
             cp[i + 1] = c1;
             cp[i + 2] = c2;
@@ -413,7 +514,7 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
         load_plane(zs - 1, ra[NB - 1], rb[NB - 1]);
         fields(ra[NB - 1], rb[NB - 1], g[1]);
     } else {
-        W::set_inf(g[1]);
+        W::set_inf(g[1], kSent);
     }
     load_plane(zs, ra[0], rb[0]);
     fields(ra[0], rb[0], g[0]);
@@ -452,7 +553,7 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
                     fields(ra[(u + 1) % NB], rb[(u + 1) % NB], g[(u + 1) & 1]);
                     if (zz + 1 < ze) range_acc(ra[(u + 1) % NB]);
                 } else {
-                    W::set_inf(g[(u + 1) & 1]);
+                    W::set_inf(g[(u + 1) & 1], kSent);
                 }
                 step(g[u & 1], g[(u + 1) & 1], cp);
             }
@@ -626,9 +727,11 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
 //    drops guard bins 0 / 16383 where values lie below / above it.  The
 //    monotone clamp keeps every comparison that decides a kept bin, since
 //    each involves the counted value itself.
+// (32768 bins: a 128 KiB histogram, one workgroup per CU, four waves per SIMD)
 template <typename T, int M, int NIN, int R, int MODE, int PD, int XF = kXfNone>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<NIN, R, PD>())))
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(M > 16384 ? 4 : kWavesPerEU<NIN, R, PD>())))
 int_vcec_kernel(KParams P) {
+    static_assert(raw_fields(XF) == (M == 32768), "32768 bins: raw-value passes, and only those");
     __shared__ int32_t hist[M];
     tile_body<T, M, NIN, R, MODE, PD, XF>(P, hist, blockIdx.x, gridDim.x);
 }
@@ -728,6 +831,18 @@ static int launch_transformed(const KParams &p, const IntTiling &tl, hipStream_t
     return ECC_E_UNSUPPORTED;
 }
 
+// 16-bit values in a 32768-bin pass: two rows per wave, two planes of
+// look-ahead (four rows would spill the lane masks of the range checks).
+template <int NIN, int XF>
+static int launch_range(const KParams &p, const IntTiling &tl, hipStream_t stream) {
+    if (tl.rows != 2 || tl.pd != 2) {
+        set_error("integer kernel: 32768-bin passes take 2 rows and 2 planes of look-ahead (got %d, %d)", tl.rows,
+                  tl.pd);
+        return ECC_E_UNSUPPORTED;
+    }
+    return launch_one<uint16_t, 32768, NIN, 2, 0, 2, XF>(p, tl, stream);
+}
+
 static KParams make_params(const IntJob &job, const IntTiling &tl, int32_t *partial, uint32_t *status,
                            int64_t *zero_vcec) {
     KParams p{};
@@ -762,6 +877,11 @@ int launch_int_partial(const IntJob &job, const IntTiling &tl, int32_t *partial,
                        int64_t *zero_vcec, hipStream_t stream) {
     const KParams p = make_params(job, tl, partial, status, zero_vcec);
     const int nin = job.view.nin;
+    if (job.dtype == ECC_U16 && job.range_pass == 1)  // 32768 values from win_shift on: all of the image's
+        return nin == 1 ? launch_range<1, kXfRange>(p, tl, stream) : launch_range<2, kXfRange>(p, tl, stream);
+    if (job.dtype == ECC_U16 && job.range_pass == 2)  // the same, values outside masked off
+        return nin == 1 ? launch_range<1, kXfRangeMasked>(p, tl, stream)
+                        : launch_range<2, kXfRangeMasked>(p, tl, stream);
     if (job.dtype == ECC_U16)  // one window of 16382 values per launch
         return nin == 1 ? launch_transformed<uint16_t, 16384, 1, kXfWindow>(p, tl, stream)
                         : launch_transformed<uint16_t, 16384, 2, kXfWindow>(p, tl, stream);

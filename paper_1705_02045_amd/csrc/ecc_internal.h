@@ -69,6 +69,11 @@ struct IntJob {
     int dtype;            // ECC_U8 or ECC_U14
     int invert;           // values read as M-1-v (largest-value convention)
     int32_t win_shift;    // ECC_U16: the launch counts bin = clamp(v - win_shift, 0, 16383)
+    // ECC_U16 in 32768-bin passes: 1 = every value lies in [win_shift,
+    // win_shift + 32768) and the launch counts bin = v - win_shift; 2 = the
+    // same for the values in that range, the others skipped; 0 = a window
+    // as above
+    int range_pass;
 };
 
 // Tiling of the integer kernel (chosen by choose_int_tiling in ecc_api.cpp).

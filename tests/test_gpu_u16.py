@@ -1,9 +1,12 @@
 """GPU parity of 16-bit images (m = 65536 thresholds) against the oracle,
-exact int64.  The GPU counts one window of at most 16384 values per pass of
-its 16384-bin workgroup histograms (guard bins where values lie outside the
-window); these cases put values on and around window edges, span one to all
-five windows, and run both the synchronous call (windows planned from the
-image's range) and the stream-ordered one (windows over 0..65535)."""
+exact int64.  An image whose values fit one window of 16384 values is
+counted in a 16384-bin workgroup histogram (guard bins where values lie
+outside the window); wider ranges go through 32768-bin passes (one pass when
+the values span fewer than 32768, else [0, 32768) and [32768, 65536) with
+the adds outside each pass masked off).  These cases put values on and
+around window and pass edges, span one to all five windows and both passes,
+and run both the synchronous call (planned from the image's range) and the
+stream-ordered one (passes over 0..65535)."""
 import numpy as np
 import pytest
 
@@ -73,6 +76,21 @@ def test_u16_narrow_ranges(ecc):
                    (100, 100 + 16383), (100, 100 + 16384), (0, 16383), (0, 16384), (40000, 65535)]:
         img = rng.integers(lo, hi + 1, size=(7, 33, 41)).astype(np.uint16)
         check(ecc, img)
+
+
+def test_u16_pass_edges(ecc):
+    """Values on both sides of the 32768 boundary of the two-pass form, and
+    ranges whose span is just below, at and just above one pass."""
+    rng = np.random.default_rng(17)
+    edges = np.array([0, 1, 32766, 32767, 32768, 32769, 65534, 65535], dtype=np.uint16)
+    for shape in [(40, 50), (6, 20, 30), (3000,), (9, 130, 66)]:
+        check(ecc, rng.choice(edges, size=shape))
+    for lo, hi in [(0, 32767), (0, 32768), (1, 32768), (32767, 65535), (32768, 65535), (16000, 48767),
+                   (16000, 48768), (32760, 32775)]:
+        img = rng.integers(lo, hi + 1, size=(7, 33, 42)).astype(np.uint16)
+        img.flat[0], img.flat[-1] = lo, hi
+        check(ecc, img)
+        check(ecc, np.ascontiguousarray(img[0]))  # one plane: two axes
 
 
 def test_u16_full_size_1024_cubed(ecc):
