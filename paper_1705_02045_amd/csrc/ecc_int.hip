@@ -99,6 +99,14 @@ __device__ __forceinline__ uint32_t bin_off_min(uint32_t a, uint32_t b) {
 }
 // Both inputs are zero-extended offsets, so a 32-bit minimum is exact.
 __device__ __forceinline__ uint32_t min_off(uint32_t a, uint32_t b) { return a < b ? a : b; }
+// The same for raw 16-bit values, as one 32-bit VALU op the compiler cannot
+// narrow: with zero-extended inputs it would pick v_min_u16, whose upper
+// half of the result is not written (see above).
+__device__ __forceinline__ uint32_t min_raw(uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_min_u32_e32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 
 // Row pairs (interior waves of 16-bit images with even rows, see tile_body):
 // each lane loads the aligned dword that holds the value at its column x,
@@ -303,18 +311,18 @@ struct Walker {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 g[2 * r + 0] = a[r];
-                g[2 * r + 1] = min_off(a[r], b[r]);
+                g[2 * r + 1] = min_raw(a[r], b[r]);
             }
         } else {
             uint32_t fx[NR];
 #pragma unroll
-            for (int rr = 0; rr < NR; ++rr) fx[rr] = min_off(a[rr], b[rr]);
+            for (int rr = 0; rr < NR; ++rr) fx[rr] = min_raw(a[rr], b[rr]);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 g[4 * r + 0] = a[r + 1];
                 g[4 * r + 1] = fx[r + 1];
-                g[4 * r + 2] = min_off(a[r], a[r + 1]);
-                g[4 * r + 3] = min_off(fx[r], fx[r + 1]);
+                g[4 * r + 2] = min_raw(a[r], a[r + 1]);
+                g[4 * r + 3] = min_raw(fx[r], fx[r + 1]);
             }
         }
     }
@@ -327,8 +335,8 @@ struct Walker {
         for (int r = 0; r < R; ++r) {
             g[4 * r + 0] = f0[r + 1];
             g[4 * r + 1] = fx[r + 1];
-            g[4 * r + 2] = min_off(f0[r], f0[r + 1]);
-            g[4 * r + 3] = min_off(fx[r], fx[r + 1]);
+            g[4 * r + 2] = min_raw(f0[r], f0[r + 1]);
+            g[4 * r + 3] = min_raw(fx[r], fx[r + 1]);
         }
     }
 
