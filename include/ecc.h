@@ -249,9 +249,9 @@ int ecc_release_workspaces(void);
  * (the previous chunk's last plane is kept on the device; each chunk's own
  * last plane waits for the next chunk); the changes vector stays on the
  * device and the prefix sum is taken once in ecc_stream_finish.
- * Integer dtypes.  ECC_U16 (m = 65536): every chunk launch runs once per
- * window of 16384 values (five windows over the whole range, Sec. 3, "Range
- * of Values"), each window's bins added to the changes vector.  Planes with
+ * Integer dtypes.  ECC_U16 (m = 65536): every chunk launch runs as two
+ * passes of 32768 bins (Sec. 3, "Range of Values"), each adding the values
+ * of its half of 0..65535 to that half of the changes vector.  Planes with
  * three axes longer than 1 (4-D images, planes of at most 2^28 voxels) go
  * through the float path's change kernel: a launch's planes and their
  * collars as float32 in one window buffer, the non-zero changes of the

@@ -420,6 +420,16 @@ int plan_u16_windows(uint32_t vmin, uint32_t vmax, U16Window *w) {
     return n;
 }
 
+// Tiling of a 32768-bin pass: two rows per wave, two planes of look-ahead,
+// about two workgroups per CU (one resident at a time: 1024^3, 2.21 ms for
+// the full range; one per CU 2.21, four 2.28, eight 2.43).
+IntTiling range_pass_tiling(const IntView &v, int64_t planes) {
+    IntTiling tl = make_int_tiling(v, planes, 2, env_int("ECC_U16_TILES_PER_CU", 2), 16);
+    tl.pd = 2;
+    tl.mode = 0;
+    return tl;
+}
+
 // 16-bit images in 32768-bin passes (a 128 KiB workgroup histogram, one
 // workgroup per CU): the fields and comparisons take the raw values and each
 // pass adds the changes at values [lo, lo + 32768) exactly, with no guard
@@ -437,9 +447,7 @@ static int enqueue_u16_passes(const void *image_dev, const IntView &v, int64_t *
         mode = 1;
         lo[0] = (int32_t)(vmin < (uint32_t)mpass ? vmin : (uint32_t)mpass);
     }
-    IntTiling tl = make_int_tiling(v, v.n0, 2, env_int("ECC_U16_TILES_PER_CU", 2), 16);
-    tl.pd = 2;
-    tl.mode = 0;
+    const IntTiling tl = range_pass_tiling(v, v.n0);
     int rc = ensure_bytes((void **)&ws->partial, &ws->partial_bytes, (size_t)tl.grid * mpass * sizeof(int32_t));
     if (rc) return rc;
     rc = ensure_bytes((void **)&ws->stage, &ws->stage_bytes,

@@ -146,14 +146,14 @@ int64_t threshold_count(int dtype);
 int device_cu_count();
 
 IntTiling choose_int_tiling(const IntView &v, int dtype, int64_t planes, int max_grid = 0);
+// The tiling of a 16-bit launch in 32768-bin passes (IntJob::range_pass).
+IntTiling range_pass_tiling(const IntView &v, int64_t planes);
 
 // Kernels (ecc_int.hip / ecc_scan.hip).  All enqueue on `stream`.
 // zero_vcec: when not null, workgroup 0 clears m int64 entries there first.
 int launch_int_partial(const IntJob &job, const IntTiling &tl, int32_t *partial, uint32_t *status,
                        int64_t *zero_vcec, hipStream_t stream);
 int launch_zero(void *p, size_t bytes, hipStream_t stream);
-// dst[i] += src[i], i < n (ecc_scan.hip).
-int launch_add_i64(int64_t *dst, const int64_t *src, int64_t n, hipStream_t stream);
 // 16-bit images (m = 65536): one launch counts one window of 16384 bins,
 // bin = clamp(v - shift, 0, 16383); bins [klo, khi] are values
 // [shift + klo, shift + khi] (bin 0 / 16383 are guards where values lie

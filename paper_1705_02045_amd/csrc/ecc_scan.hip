@@ -357,20 +357,6 @@ __global__ void __launch_bounds__(256) signed_sum_kernel(const int64_t *__restri
     out[t] = sign < 0 ? -acc : acc;
 }
 
-__global__ void __launch_bounds__(256) add_i64_kernel(int64_t *__restrict__ dst, const int64_t *__restrict__ src,
-                                                      int64_t n) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] += src[i];
-}
-
-int launch_add_i64(int64_t *dst, const int64_t *src, int64_t n, hipStream_t stream) {
-    if (n <= 0) return ECC_OK;
-    const int64_t blocks = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
-    hipLaunchKernelGGL(add_i64_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, dst, src, n);
-    ECC_HIP(hipGetLastError());
-    return ECC_OK;
-}
-
 int launch_signed_sum(const int64_t *curves, int nf, const uint64_t neg_mask[2], const uint64_t skip_mask[2],
                       int sign, int m, int64_t *out, hipStream_t stream) {
     if (nf > 128) {

@@ -7,10 +7,10 @@
 // from a two-plane carry buffer (the previous push's last planes), the rest
 // from the chunk itself.
 // Counts accumulate on the device; the prefix sum is taken once.  16-bit
-// images (m = 65536) run every launch once per window of 16384 values (Sec.
-// 3, "Range of Values"), over the whole value range, since a stream does not
-// know its values in advance; each window's kept bins are added to the
-// changes vector.
+// images (m = 65536) run every launch as two 32768-bin passes (Sec. 3,
+// "Range of Values"), over the whole value range, since a stream does not
+// know its values in advance; each pass adds the values of its half of
+// 0..65535 to that half of the changes vector.
 //
 // Planes with three axes longer than 1 (4-D images) go through the float
 // path's change kernel instead (Sec. 3, "Other Ranges of Gray Values": the
@@ -55,7 +55,6 @@ struct ecc_stream {
     int64_t *mstage = nullptr;  // merge stage rows
     size_t mstage_bytes = 0;
     int64_t *vcec = nullptr;
-    int64_t *wvcec = nullptr;  // ECC_U16: one window's changes (16384 bins)
     uint32_t *status = nullptr;
     // 4-D images: extents, the float window of a launch and its change records
     bool four_d = false;
@@ -86,7 +85,6 @@ void destroy(ecc_stream *st) {
     if (st->partial) (void)hipFree(st->partial);
     if (st->mstage) (void)hipFree(st->mstage);
     if (st->vcec) (void)hipFree(st->vcec);
-    if (st->wvcec) (void)hipFree(st->wvcec);
     if (st->wbuf) (void)hipFree(st->wbuf);
     if (st->nzbuf) (void)hipFree(st->nzbuf);
     if (st->status) (void)hipFree(st->status);
@@ -201,25 +199,24 @@ int run_chunk(ecc_stream *st, const uint8_t *chunk, int64_t f, int64_t n, int64_
         j.e1 = (int32_t)(hi - f);
         j.lo_inf = lo == 0;  // else plane lo - 1 = f - 2 is carry plane a - 2 (a == 2)
         j.hi_inf = hi == n0;  // else plane hi = f + n - 1 is the chunk's last plane
-        const IntTiling tl = choose_int_tiling(st->view, st->dtype, hi - lo);
-        const int mloc = st->dtype == ECC_U16 ? 16384 : st->m;  // bins of one launch
+        const bool u16 = st->dtype == ECC_U16;
+        const IntTiling tl = u16 ? range_pass_tiling(st->view, hi - lo) : choose_int_tiling(st->view, st->dtype, hi - lo);
+        const int mloc = u16 ? 32768 : st->m;  // bins of one launch
         int rc = ensure_bytes((void **)&st->partial, &st->partial_bytes, (size_t)tl.grid * mloc * sizeof(int32_t));
         if (rc) return rc;
         rc = ensure_bytes((void **)&st->mstage, &st->mstage_bytes,
                           (size_t)merge_stage_rows(tl.grid) * mloc * sizeof(int64_t));
         if (rc) return rc;
-        if (st->dtype == ECC_U16) {
-            U16Window win[kU16MaxWindows + 1];
-            const int nwin = plan_u16_windows(0, 65535, win);
-            for (int i = 0; i < nwin; ++i) {
-                j.win_shift = win[i].shift;
+        if (u16) {
+            // two 32768-bin passes, each adding the values of its half of
+            // 0..65535 into that half of the changes vector
+            j.range_pass = 2;
+            for (int i = 0; i < 2; ++i) {
+                j.win_shift = i * 32768;
                 rc = launch_int_partial(j, tl, st->partial, st->status, nullptr, st->compute);
                 if (rc) return rc;
-                rc = launch_merge(st->partial, tl.grid, mloc, st->mstage, st->wvcec, false, false, nullptr,
+                rc = launch_merge(st->partial, tl.grid, mloc, st->mstage, st->vcec + i * 32768, true, false, nullptr,
                                   st->status, nullptr, st->compute);
-                if (rc) return rc;
-                rc = launch_add_i64(st->vcec + win[i].shift + win[i].klo, st->wvcec + win[i].klo,
-                                    win[i].khi - win[i].klo + 1, st->compute);
                 if (rc) return rc;
             }
         } else {
@@ -348,9 +345,6 @@ int ecc_stream_begin(const ecc_dims *full_dims, ecc_dtype dtype, void *stream, e
     }
     if ((e = dev_malloc((void **)&st->vcec, (size_t)st->m * sizeof(int64_t))) != hipSuccess)
         return fail(hip_fail(e, "hipMalloc(vcec)"));
-    if (dtype == ECC_U16 && !st->four_d &&
-        (e = dev_malloc((void **)&st->wvcec, (size_t)16384 * sizeof(int64_t))) != hipSuccess)
-        return fail(hip_fail(e, "hipMalloc(window vcec)"));
     if ((e = dev_malloc((void **)&st->status, kStatusBytes)) != hipSuccess) return fail(hip_fail(e, "hipMalloc(status)"));
     if ((rc = launch_zero(st->vcec, (size_t)st->m * sizeof(int64_t), st->compute))) return fail(rc);
     if ((rc = launch_zero(st->status, kStatusBytes, st->compute))) return fail(rc);
