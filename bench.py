@@ -380,7 +380,7 @@ def leg_conventions(vol, reps: int):
 def leg_u16(reps: int):
     """1024^3 16-bit value noise (lattice 16, jitter +-256, seed 1, full 0..65535
     range: two 32768-bin passes) and the same volume shifted into 14-bit range
-    as 16-bit data (one window): synchronous ecc_compute, device in and out."""
+    as 16-bit data (one pass): synchronous ecc_compute, device in and out."""
     import numpy as np
     import torch
     import gen

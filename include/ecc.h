@@ -150,12 +150,10 @@ int ecc_compute_dual(const void *image, const ecc_dims *dims, ecc_dtype dtype, e
 
 /* Stream-ordered form for integer types with device-resident data: enqueues
  * the whole computation on `stream` and returns without synchronizing.
- * ECC_U16 images are counted in passes over the image: values that fit one
- * window of 16384 go through one pass of 16384-bin workgroup histograms,
- * wider ranges through 32768-bin passes (one when the values span fewer
- * than 32768, else two, each adding the values of its half of 0..65535).
- * This form plans for 0..65535 (two passes); ecc_compute plans from the
- * image's minimum and maximum (found first, one extra read).
+ * ECC_U16 images are counted in passes over the image of 32768-bin
+ * workgroup histograms, each adding the values of its half of 0..65535.
+ * This form runs both; ecc_compute runs the second only when the first has
+ * seen a value of 32768 or more.
  *   image_dev: device pointer, prod(n) elements.
  *   chi_dev:   device pointer, m int64 entries; written only if the input is
  *              valid (all U14 values < 16384).

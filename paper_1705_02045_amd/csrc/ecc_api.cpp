@@ -481,12 +481,61 @@ static int enqueue_u16_passes(const void *image_dev, const IntView &v, int64_t *
     return launch_merge(nullptr, 0, mtot, nullptr, ws->vcec16, true, true, chi_dev, ws->status, status_out, stream);
 }
 
-// The window form (16384-bin passes, eight waves per SIMD) takes the
-// images whose values fit one window (1024^3: 1.15 ms against 1.25 ms in a
-// 32768-bin pass) and the entry point that allocates nothing, whose fixed
-// scratch holds count rows of 16384 bins; the others go to the 32768-bin
-// passes (full range: 2.2 ms against 4.0 ms in five windows; 15 bits: 1.27
-// against 2.54 ms in two).
+// The synchronous call's 16-bit path: the pass over [0, 32768) first, which
+// notes whether any value lies above it (a word of host memory, read after
+// the pass), and the pass over [32768, 65536) only then.  No separate read
+// for the image's range: images below 32768 take one pass (1024^3 14-bit
+// and 15-bit data: 0.92 ms, against 1.15 and 2.54 ms for the range read and
+// one or two windows), full ranges two (1.80 ms, against 3.94 ms in five
+// windows); an image whose values all lie above 32768 reads it once in vain.
+static int enqueue_u16_adaptive(const void *image_dev, const IntView &v, int64_t *chi_dev, uint32_t *status_out,
+                                hipStream_t stream, Workspace *ws) {
+    constexpr int mpass = 32768, mtot = 65536;
+    const IntTiling tl = range_pass_tiling(v, v.n0);
+    int rc = ensure_bytes((void **)&ws->partial, &ws->partial_bytes, (size_t)tl.grid * mpass * sizeof(int32_t));
+    if (rc) return rc;
+    rc = ensure_bytes((void **)&ws->stage, &ws->stage_bytes,
+                      (size_t)merge_stage_rows(tl.grid) * mpass * sizeof(int64_t));
+    if (rc) return rc;
+    rc = ensure_bytes((void **)&ws->vcec16, &ws->vcec16_bytes, (size_t)mtot * sizeof(int64_t));
+    if (rc) return rc;
+    rc = launch_zero(ws->vcec16 + mpass, (size_t)mpass * sizeof(int64_t), stream);  // if the second pass is skipped
+    if (rc) return rc;
+    volatile uint32_t *high = ws->host_status + 1;
+    *high = 0u;
+    IntJob job{};
+    job.src.base = (const uint8_t *)image_dev;
+    job.src.lo_base = job.src.base;
+    job.src.plane_bytes = (int64_t)v.n1 * v.n2 * 2;
+    job.view = v;
+    job.e0 = 0;
+    job.e1 = (int32_t)v.n0;
+    job.lo_inf = 1;
+    job.hi_inf = 1;
+    job.dtype = ECC_U16;
+    job.range_pass = 2;
+    for (int i = 0; i < 2; ++i) {
+        job.win_shift = i * mpass;
+        job.high_flag = i == 0 ? ws->host_status_dev + 1 : nullptr;
+        rc = launch_int_partial(job, tl, ws->partial, ws->status, nullptr, stream);
+        if (rc) return rc;
+        rc = launch_merge(ws->partial, tl.grid, mpass, ws->stage, ws->vcec16 + i * mpass, false, false, nullptr,
+                          ws->status, nullptr, stream);
+        if (rc) return rc;
+        if (i == 0) {
+            ECC_HIP(hipStreamSynchronize(stream));
+            if (*high == 0u) break;
+        }
+    }
+    return launch_merge(nullptr, 0, mtot, nullptr, ws->vcec16, true, true, chi_dev, ws->status, status_out, stream);
+}
+
+// Planned from a known range (the entry point that allocates nothing, whose
+// fixed scratch holds count rows of 16384 bins, and the asynchronous calls,
+// which plan for 0..65535): values that fit one window take the window form
+// (16384-bin passes, eight waves per SIMD; 1024^3: 1.15 ms against 1.25 ms in
+// a 32768-bin pass), wider ranges the 32768-bin passes (full range: 2.2 ms
+// against 4.0 ms in five windows).
 static int enqueue_u16(const void *image_dev, const IntView &v, int64_t *chi_dev, uint32_t *status_out,
                        hipStream_t stream, Workspace *ws, uint32_t vmin, uint32_t vmax) {
     constexpr int mloc = 16384, mtot = 65536;
@@ -706,7 +755,10 @@ static int compute_int(const void *image, const ecc_dims *dims, int64_t total, e
         if (rc) return rc;
         chi_target = ws->chi_tmp;
     }
-    if (dtype == ECC_U16) {  // only the windows between the image's minimum and maximum
+    if (dtype == ECC_U16 && !ws->fixed && env_int("ECC_U16_WINDOWS", 0) == 0) {
+        *ws->host_status = 0xFFFFFFFFu;  // overwritten by the scan
+        rc = enqueue_u16_adaptive(img_dev, v, chi_target, ws->host_status_dev, s, ws);
+    } else if (dtype == ECC_U16) {  // only the windows between the image's minimum and maximum
         uint32_t *mm = ws->status + kStatusMinMaxOffset / 4;
         rc = launch_minmax_u16((const uint16_t *)img_dev, total, mm, s);
         if (rc) return rc;

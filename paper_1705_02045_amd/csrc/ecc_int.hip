@@ -50,6 +50,7 @@ struct KParams {
     uint32_t *status;
     int64_t *zero_vcec;  // cleared by workgroup 0 when not null
     int32_t pair;        // 16-bit values, two in-plane axes: row-pair layout (see tile_body)
+    uint32_t *high_flag; // 32768-bin passes: set to 1 when a value >= 32768 is loaded (may be null)
 };
 
 // Fourth word of a raw buffer resource on gfx9-family parts (32-bit data format).
@@ -437,7 +438,8 @@ __device__ __forceinline__ void walk(const KParams &P, int zs, int ze, const uin
     auto range_acc = [&](const uint32_t (&a)[NR]) {
         // rows owned by this wave (the collar row is checked by its owner);
         // every 16-bit value is valid for the window passes
-        if constexpr (XF == kXfNone || XF == kXfInvert) {
+        // (32768-bin passes: whether any value >= 32768 occurs)
+        if constexpr (XF == kXfNone || XF == kXfInvert || raw_fields(XF)) {
 #pragma unroll
             for (int rr = NR - R; rr < NR; ++rr) orv |= a[rr];
         }
@@ -714,7 +716,11 @@ __device__ __forceinline__ void tile_body(const KParams &P, int32_t *hist, const
     }
     }  // tiles
 
-    if constexpr (M != 256) {
+    if constexpr (raw_fields(XF)) {
+        // every 16-bit value is valid; the caller may want to know of the
+        // values >= 32768 (row pairs hold a second value in the high half)
+        if (P.high_flag && ((orv | (orv >> 16)) & 0x8000u)) *P.high_flag = 1u;
+    } else if constexpr (M != 256) {
         // (row pairs hold a second value in the high half)
         if (((orv | (orv >> 16)) & 0xFFFFu) >= (uint32_t)M) atomicOr(P.status, kStatusRange);
     }
@@ -878,6 +884,7 @@ static KParams make_params(const IntJob &job, const IntTiling &tl, int32_t *part
     p.partial = partial;
     p.status = status;
     p.zero_vcec = zero_vcec;
+    p.high_flag = job.high_flag;
     return p;
 }
 

@@ -74,6 +74,7 @@ struct IntJob {
     // same for the values in that range, the others skipped; 0 = a window
     // as above
     int range_pass;
+    uint32_t *high_flag;  // range passes: set to 1 when a value >= 32768 is loaded (may be null)
 };
 
 // Tiling of the integer kernel (chosen by choose_int_tiling in ecc_api.cpp).
