@@ -128,16 +128,45 @@ __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_
     for (int j = 0; j < kItems; ++j) {
         const uint32_t d = digit_of(r[j], shift);
         // peers: the lanes whose digit equals this lane's, as two 32-bit
-        // halves; per bit, keep the lanes that agree with this lane's bit
-        // (sb: all ones where the bit is set)
-        uint32_t plo = ~0u, phi = ~0u;
+        // halves: the complement of the lanes that disagree with this lane on
+        // some bit.  Per bit, sb is all ones where the bit is set (kept
+        // opaque, so that the ballot compares it instead of recomputing the
+        // bit) and m the ballot of the lanes with the bit set; per half,
+        // x = (m0 ^ sb0) | (m1 ^ sb1) | ... with one three-input op per bit
+        // after the first (x | (m ^ sb): truth table 0xF6 over (x, m, sb)).
+        // The ballots are VALU writes of scalar registers, which a VALU op may
+        // read only two wait states later: each block starts with s_nop 1.
+        uint32_t sb[8];
+        uint64_t m[8];
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            const uint32_t sb = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
-            const uint64_t m = __builtin_amdgcn_ballot_w64(sb != 0);
-            plo &= ~((uint32_t)m ^ sb);
-            phi &= ~((uint32_t)(m >> 32) ^ sb);
+            sb[b] = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+            asm("" : "+v"(sb[b]));
+            m[b] = __builtin_amdgcn_ballot_w64(sb[b] != 0);
         }
+        uint32_t xlo, xhi;
+#define ECC_MISMATCH(X, H)                                                                                       \
+    asm("s_nop 1\n\t"                                                                                           \
+        "v_xor_b32 %0, %1, %9\n\t"                                                                              \
+        "v_bitop3_b32 %0, %0, %2, %10 bitop3:0xf6\n\t"                                                          \
+        "v_bitop3_b32 %0, %0, %3, %11 bitop3:0xf6\n\t"                                                          \
+        "v_bitop3_b32 %0, %0, %4, %12 bitop3:0xf6\n\t"                                                          \
+        "v_bitop3_b32 %0, %0, %5, %13 bitop3:0xf6\n\t"                                                          \
+        "v_bitop3_b32 %0, %0, %6, %14 bitop3:0xf6\n\t"                                                          \
+        "v_bitop3_b32 %0, %0, %7, %15 bitop3:0xf6\n\t"                                                          \
+        "v_bitop3_b32 %0, %0, %8, %16 bitop3:0xf6"                                                                \
+        : "=&v"(X)                                                                                                \
+        : "s"(H(m[0])), "s"(H(m[1])), "s"(H(m[2])), "s"(H(m[3])), "s"(H(m[4])), "s"(H(m[5])), "s"(H(m[6])),    \
+          "s"(H(m[7])), "v"(sb[0]), "v"(sb[1]), "v"(sb[2]), "v"(sb[3]), "v"(sb[4]), "v"(sb[5]), "v"(sb[6]),      \
+          "v"(sb[7]))
+#define ECC_LO(v) ((uint32_t)(v))
+#define ECC_HI(v) ((uint32_t)((v) >> 32))
+        ECC_MISMATCH(xlo, ECC_LO);
+        ECC_MISMATCH(xhi, ECC_HI);
+#undef ECC_HI
+#undef ECC_LO
+#undef ECC_MISMATCH
+        const uint32_t plo = ~xlo, phi = ~xhi;
         const uint32_t rw = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));  // peers below
         // the wave's own count row: LDS operations of one wave take effect in order
         const uint32_t base = wcnt[wave][d];
