@@ -119,10 +119,18 @@ __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_
     T r[kItems];
     uint32_t rank[kItems];
     const int64_t wb = t0 + (int64_t)wave * kChunk;
+    // (a full tile, every tile but the last: loads and stores without bounds
+    // checks)
+    const bool full = t0 + kTile <= n;
+    if (full) {
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        const int64_t i = wb + (int64_t)j * kWave + lane;
-        r[j] = i < n ? in[i] : ~T(0);  // past the end: digit 255, last in the tile, never written
+        for (int j = 0; j < kItems; ++j) r[j] = in[wb + j * kWave + lane];
+    } else {
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const int64_t i = wb + (int64_t)j * kWave + lane;
+            r[j] = i < n ? in[i] : ~T(0);  // past the end: digit 255, last in the tile, never written
+        }
     }
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
@@ -214,7 +222,16 @@ __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_
         buf[start[d] + wcnt[wave][d] + rank[j]] = r[j];
     }
     __syncthreads();
-    const int64_t valid = (n - t0) < kTile ? (n - t0) : kTile;
+    if (full) {
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const int s = j * kSortThreads + tid;
+            const T v = buf[s];
+            out[dest[digit_of(v, shift)] + (uint32_t)s] = v;
+        }
+        return;
+    }
+    const int64_t valid = n - t0;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int s = j * kSortThreads + tid;
