@@ -429,7 +429,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20,
+                    help="untimed steps first (the first launches run slow while the clocks settle)")
     ap.add_argument("--size", type=int, default=1024, help="edge of the cubic volume")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="one-thread oracle sample budget (the whole volume also runs on the CPU share); 0 skips both")
