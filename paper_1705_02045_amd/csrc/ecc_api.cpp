@@ -823,13 +823,13 @@ static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc
     int64_t slots = 0;
     const int64_t regions = float_regions(dims, &slots);
     if (regions < 0) return ECC_E_UNSUPPORTED;
-    const int64_t tiles = std::max(radix_tiles(n, 4), radix_tiles(n, 8));
+    const int64_t digit_entries = std::max(radix_count_entries(n, 4), radix_count_entries(n, 8));
     const int64_t ft = float_tiles(n);
     enum { kKey0, kKey1, kNz, kNzCnt, kNzOff, kCounts, kSums, kTileA, kTileB, kBound, kCnt, kSteps, kNbuf };
     size_t off[kNbuf], total = 0;
-    const int64_t scan_entries = std::max(std::max(256 * tiles, regions), steps_only ? n : 0);
+    const int64_t scan_entries = std::max(std::max(digit_entries, regions), steps_only ? n : 0);
     const size_t sz[kNbuf] = {(size_t)n * 4, (size_t)n * 4, (size_t)slots * 8, (size_t)regions * 4,
-                              (size_t)regions * 4, (size_t)(256 * tiles) * 4,
+                              (size_t)regions * 4, (size_t)digit_entries * 4,
                               (size_t)radix_scan_tiles(scan_entries) * 4, (size_t)ft * 8, (size_t)ft * 8,
                               (size_t)(ft + 1) * 8, 64,
                               steps_only ? (size_t)n * 4 : 0};
@@ -859,6 +859,7 @@ static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc
     int64_t *nnz_dev = (int64_t *)(b + off[kCnt]);
     int64_t *count_dev = (int64_t *)(b + off[kCnt] + 8);
     int64_t *count2_dev = (int64_t *)(b + off[kCnt] + 16);
+    uint32_t *mask_dev = (uint32_t *)(b + off[kCnt] + 32);  // the key sort's top-byte mask (8 words)
     float *out_keys = direct ? curve->keys : (float *)(b + out_k);
     int64_t *out_chi = direct ? curve->chi : (int64_t *)(b + out_c);
     // the record count, read on the host while the keys are sorted: a word of
@@ -875,7 +876,7 @@ static int compute_float(const void *image, const ecc_dims *dims, int64_t n, ecc
     ECC_HIP(hipEventCreateWithFlags(&counted, hipEventDisableTiming));
     hipError_t e = hipEventRecord(counted, s);
     if (e == hipSuccess) {
-        rc = radix_sort_keys(key, n, counts, sums, s);
+        rc = radix_sort_keys(key, n, counts, sums, mask_dev, ws->host_status + 4, ws->host_status_dev + 4, s);
         e = hipEventSynchronize(counted);
     }
     (void)hipEventDestroy(counted);

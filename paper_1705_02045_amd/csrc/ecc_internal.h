@@ -99,9 +99,11 @@ struct Workspace {
     int64_t *vcec = nullptr;     // [m] changes vector
     size_t vcec_bytes = 0;
     uint32_t *status = nullptr;  // device status block (kStatusBytes)
-    // One pinned, coherent host word that the scan writes the status into
-    // (read after the stream is synchronized, without a device-to-host copy),
-    // and its device-side address.
+    // A pinned, coherent host block of 16 words: word 0, the status that the
+    // scan writes (read after the stream is synchronized, without a
+    // device-to-host copy); word 1, the 16-bit path's high-value flag; words
+    // 2-3, the float path's record count; words 4-11, the float key sort's
+    // top-byte mask.  With its device-side address.
     volatile uint32_t *host_status = nullptr;
     uint32_t *host_status_dev = nullptr;
     int64_t *stage = nullptr;    // merge stage rows
@@ -266,8 +268,17 @@ int launch_nz_compact(const uint32_t *nz_key, const int32_t *nz_chg, const uint3
 // Tiles of the radix sort for n words of elem (4 or 8) bytes.
 int64_t radix_tiles(int64_t n, int elem);
 int64_t radix_scan_tiles(int64_t entries);
-// counts: 256 * radix_tiles(n, elem) entries; sums: radix_scan_tiles of that.
-int radix_sort_keys(uint32_t *key[2], int64_t n, uint32_t *counts, uint32_t *sums, hipStream_t stream);
+// Digit-table entries of a sort of n words of elem bytes (digits of up to
+// 10 bits for keys, 8 for records); sums: radix_scan_tiles of that.
+int64_t radix_count_entries(int64_t n, int elem);
+// Sorts key[0]; on return key[0] is the sorted buffer and key[1] the other
+// (the two may be swapped).  mask_dev: 8 device words; mask_host /
+// mask_host_dev: 8 words of host-mapped memory, host and device views.
+// Synchronizes on an event recorded early in the sort (the host reads which
+// top bytes occur to choose the last passes).
+int radix_sort_keys(uint32_t *key[2], int64_t n, uint32_t *counts, uint32_t *sums, uint32_t *mask_dev,
+                    volatile uint32_t *mask_host, uint32_t *mask_host_dev, hipStream_t stream);
+// Sorts rec[0] in place (an even number of passes).
 int radix_sort_records(uint64_t *rec[2], int64_t n, uint32_t *counts, uint32_t *sums, hipStream_t stream);
 int64_t float_tiles(int64_t n);
 // From the sorted keys and the sorted records: the K distinct keys as

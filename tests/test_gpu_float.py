@@ -139,3 +139,35 @@ def test_float_4d_full_size(ecc):
     # the 4-D 128^4 value-noise workload, compared in full
     img = gen.cfg_f32_value_noise((128, 128, 128, 128), seed=3)
     check(ecc, img)
+
+
+def _top_bytes(img):
+    """Top bytes of the order-preserving 32-bit keys of a float image (-0
+    taken as +0): negative values complement all bits, others set the sign."""
+    b = np.where(img == 0, np.float32(0), img).astype(np.float32).view(np.uint32)
+    key = np.where(b >> 31 != 0, ~b, b | np.uint32(0x80000000))
+    return np.unique(key >> 24)
+
+
+# (number of sign and binade-pair groups, shape): after two passes on bits
+# 0-17 the key sort joins bits 18-23 to the rank of the top byte when at most
+# 16 top bytes occur (a 9-bit digit up to 8 of them, a 10-bit one up to 16),
+# and takes two 7-bit passes otherwise; the shapes span several 8192-key
+# tiles with a ragged last one, and one image fills a single partial tile
+PLANS = [(8, (5, 8192 * 2 + 77)), (9, (5, 8192 * 2 + 77)), (16, (5, 8192 * 2 + 77)), (17, (5, 8192 * 2 + 77)),
+         (1, (3, 7, 500)), (8, (11, 300)), (40, (4, 9, 1100)), (9, (3, 4, 5, 300)), (16, (6, 7, 8, 9))]
+
+
+@pytest.mark.parametrize("groups,shape", PLANS, ids=[f"{g}-{s}" for g, s in PLANS])
+def test_float_key_sort_plans(ecc, groups, shape):
+    """Value noise with each voxel moved to one of `groups` sign and binade
+    pairs at random: exactly `groups` distinct top bytes of the keys."""
+    rng = np.random.default_rng(40 + groups)
+    base = gen.value_noise_f32(shape, sigma=0.0, seed=21)
+    base = (np.float32(1) + np.clip(base, 0, np.float32(0.999)))  # in [1, 2): exponent 127
+    g = rng.integers(0, groups, size=shape)
+    # group i: sign (-1)^i, exponent 127 + 2 (i // 2) - 40 (one top byte each)
+    scale = np.ldexp(np.float32(1), (2 * (g // 2) - 40).astype(np.int32)).astype(np.float32)
+    img = (np.where(g % 2 == 1, -base, base) * scale).astype(np.float32)
+    assert len(_top_bytes(img)) == groups
+    check(ecc, img)
