@@ -57,13 +57,17 @@ __device__ __forceinline__ uint32_t digit_of(T r, int shift, const uint8_t *rank
 
 // The rank table of REMAP passes from the top-byte presence mask (8 words,
 // bit b of word w: byte 32 w + b occurs): rank[t] = present bytes below t.
-// Called by every thread; ends with a barrier.
+// Byte 255, when absent, takes the largest rank of a BITS-bit digit, so that
+// the all-ones keys that pad the last tile take the largest digit.  Called
+// by every thread; ends with a barrier.
+template <int BITS>
 __device__ __forceinline__ void build_rank(const uint32_t *__restrict__ mask, uint8_t *rank) {
     const int t = threadIdx.x;
     if (t < 256) {
         uint32_t c = 0;
         for (int w = 0; w < (t >> 5); ++w) c += (uint32_t)__builtin_popcount(mask[w]);
         c += (uint32_t)__builtin_popcount(mask[t >> 5] & ((1u << (t & 31)) - 1u));
+        if (t == 255 && (mask[7] >> 31) == 0u) c = (1u << (BITS - kRemapLow)) - 1u;
         rank[t] = (uint8_t)c;
     }
     __syncthreads();
@@ -92,7 +96,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_count_kernel(const T *__re
     const int tid = threadIdx.x;
     for (int i = tid; i < kCountTiles * (kDig + 1); i += kSortThreads) (&cnt[0][0])[i] = 0;
     if (MASK && tid < 256) present[tid] = 0;
-    if constexpr (REMAP) build_rank(mask, rank);  // (its barrier also orders the clearing)
+    if constexpr (REMAP) build_rank<BITS>(mask, rank);  // (its barrier also orders the clearing)
     else __syncthreads();
     const int lane = tid & (kWave - 1);
     const int64_t tb = (int64_t)blockIdx.x * tpw;
@@ -171,7 +175,9 @@ __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_
     static_assert(BITS >= 1 && BITS <= 10, "digits of at most 10 bits (LDS rows of 1024 counts per wave)");
     static_assert(kDig <= kSortThreads, "one thread per digit");
     __shared__ T buf[kTile];                     // the tile reordered by digit
-    __shared__ uint16_t wcnt[kSortWaves][kDig];  // per wave: digit counts, then the wave's offset per digit
+    // per wave: digit counts, then the wave's offset per digit (16-bit: a
+    // tile holds at most 8192 keys; pairs of digits read as one word)
+    __shared__ __attribute__((aligned(16))) uint16_t wcnt[kSortWaves][kDig];
     __shared__ uint32_t start[kDig];             // digit totals, then the first slot of each digit
     __shared__ uint32_t dest[kDig];              // per digit: output position minus first slot
     __shared__ uint8_t rank_t[REMAP ? 256 : 1];
@@ -184,7 +190,7 @@ __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_
     const uint32_t gpos = tid < kDig ? offsets[(int64_t)tid * tiles + tile] : 0u;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) wcnt[wave][lane * kPer + q] = 0;  // the wave's own row
-    if constexpr (REMAP) build_rank(mask, rank_t);
+    if constexpr (REMAP) build_rank<BITS>(mask, rank_t);
 
     // wave w ranks keys t0 + w*kChunk + j*64 + lane (j = 0..kItems-1), in
     // that order: tile order, so the ranking is stable
@@ -192,8 +198,9 @@ __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_
     uint32_t rank[kItems];
     const int64_t wb = t0 + (int64_t)wave * kChunk;
     // (a full tile, every tile but the last: loads and stores without bounds
-    // checks; in the last tile the keys past the end take the largest digit,
-    // so that they rank last in the tile and are never written)
+    // checks; in the last tile the keys past the end are all ones, whose
+    // digit is the largest (for REMAP through the rank of byte 255), so that
+    // they rank last in the tile and are never written)
     const bool full = t0 + kTile <= n;
     if (full) {
 #pragma unroll
@@ -202,13 +209,10 @@ __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_
 #pragma unroll
         for (int j = 0; j < kItems; ++j) {
             const int64_t i = wb + (int64_t)j * kWave + lane;
-            r[j] = i < n ? in[i] : T(0);
+            r[j] = i < n ? in[i] : ~T(0);
         }
     }
-    auto digit = [&](int j) -> uint32_t {
-        const uint32_t d = digit_of<T, BITS, REMAP>(r[j], shift, rank_t);
-        return full || wb + (int64_t)j * kWave + lane < n ? d : (uint32_t)(kDig - 1);
-    };
+    auto digit = [&](int j) -> uint32_t { return digit_of<T, BITS, REMAP>(r[j], shift, rank_t); };
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const uint32_t d = digit(j);
@@ -241,14 +245,18 @@ __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_
         if (rw == 0) wcnt[wave][d] = (uint16_t)(base + __builtin_popcount(plo) + __builtin_popcount(phi));
     }
     __syncthreads();
-    if (tid < kDig) {  // per digit: the waves' offsets and the digit's total
+    if (tid < kDig / 2) {  // per pair of digits: the waves' offsets and the digits' totals
+        // two 16-bit counts per word, added as one: a digit's total over
+        // the tile is at most 8192, so the low half never carries
         uint32_t acc = 0;
         for (int w = 0; w < kSortWaves; ++w) {
-            const uint32_t c = wcnt[w][tid];
-            wcnt[w][tid] = (uint16_t)acc;
+            uint32_t *cw = reinterpret_cast<uint32_t *>(&wcnt[w][0]) + tid;
+            const uint32_t c = *cw;
+            *cw = acc;
             acc += c;
         }
-        start[tid] = acc;
+        start[2 * tid] = acc & 0xFFFFu;
+        start[2 * tid + 1] = acc >> 16;
     }
     __syncthreads();
     // first slot of each digit: exclusive scan of the totals (one wave, kPer
