@@ -167,7 +167,7 @@ def leg_serving(n_req: int, slo_ms: float, budget_bytes: int, arena_bytes: int):
         _, _, span = run(np.zeros(n_req))
         sat = n_req / span
         best = None
-        for f in (0.3, 0.5, 0.7, 0.8, 0.9, 0.95):
+        for f in (0.3, 0.5, 0.7, 0.8, 0.85, 0.9, 0.95):
             lam = f * sat
             arr = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
             arr -= arr[0]

@@ -361,7 +361,10 @@ int ecc_job_footprint(const ecc_job *job, int64_t *bytes);
  * Host-origin requests: admission also reserves a block of the arena (one
  * device buffer of arena_bytes) for the image, copies it in on a copy stream
  * of the call and frees the block when the request's kernels are done; a
- * request waits while its image does not fit.
+ * request waits while its image does not fit.  Images in pinned host memory
+ * with a device-mapped, 16-byte aligned address are copied by one kernel per
+ * 32 requests of a batch, which reads them over the bus; the others
+ * (pageable memory, other alignments) by one copy each.
  * Requests whose image exceeds stream_above_bytes (0: arena_bytes / 4 for
  * host-origin requests, else never) are not batched: one at a time, each is
  * pushed through the streaming interface on a stream of its own in chunks

@@ -201,3 +201,41 @@ def test_serve_16bit_requests(ecc, one_launch):
             m = ecc.THRESHOLDS[d]
             assert (chi[off:off + m] == oracle.curve(img, m=m)).all(), f"{origin} request {i} {d} {img.shape}"
             off += m
+
+
+def _misaligned_pinned(a):
+    """A pinned copy of a whose first byte sits one element past a 16-byte boundary."""
+    t = as_tensor(a).reshape(-1)
+    buf = torch.empty(t.numel() + 16, dtype=t.dtype).pin_memory()
+    v = buf[1:1 + t.numel()]
+    v.copy_(t)
+    return v.view(a.shape)
+
+
+@pytest.mark.parametrize("one_launch", [False, True])
+def test_host_origin_pinned_pageable_misaligned(ecc, one_launch):
+    """Host-origin requests whose images are pinned (gathered by the copy
+    kernel through their device-mapped addresses), pageable, or pinned but
+    not 16-byte aligned (both copied one by one): every curve equals the
+    oracle's."""
+    reqs = gen.serving_requests(30, seed=31, side_scale=0.3)
+    imgs = [gen.serving_image(*r) for r in reqs]
+    src = []
+    for i, a in enumerate(imgs):
+        if i % 3 == 0:
+            src.append(as_tensor(a).pin_memory())
+        elif i % 3 == 1:
+            src.append(as_tensor(a))
+        else:
+            src.append(_misaligned_pinned(a))
+    assert not src[1].is_pinned() and src[2].data_ptr() % 16 != 0
+    dtypes = [r[0] for r in reqs]
+    arrival = np.cumsum(np.random.default_rng(7).exponential(1e-4, size=len(reqs)))
+    b = ecc.Batch()
+    print(f"\n[gpu] ecc_serve host-origin, pinned / pageable / misaligned, one_launch={one_launch}", flush=True)
+    lat, chi, bid, st, rc = b.serve_config(src, dtypes, arrival, max_batch=8, one_launch_per_image=one_launch,
+                                           arena_bytes=64 << 20, check=False)
+    b.close()
+    assert rc == ecc.ECC_OK and (st == 0).all()
+    for i, (r, img, c) in enumerate(zip(reqs, imgs, curves_of(ecc, reqs, chi))):
+        assert (c == oracle.curve(img, m=ecc.THRESHOLDS[r[0]])).all(), f"request {i} {r}"
