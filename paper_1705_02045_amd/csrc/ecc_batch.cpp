@@ -172,10 +172,6 @@ struct Req {
     int64_t chunk_planes = 0;  // streamed: planes per pushed chunk
 };
 
-// First-fit allocator over one device buffer in 256-byte granules: the
-// images (and streamed chunks) of host-origin requests while they are in
-// flight.  Admission takes blocks from it and completion returns them, so
-// the device memory held by requests never exceeds the arena.
 // Host-origin images to the arena in one launch: block b copies chunk
 // b - first[r] (kGatherChunk bytes, the last one shorter) of request r,
 // first[r] <= b < first[r + 1].  Sources are device-mapped addresses of
@@ -204,6 +200,10 @@ __global__ void __launch_bounds__(256) gather_images_kernel(GatherArgs a) {
     for (int64_t i = n16 * 16 + threadIdx.x; i < len; i += 256) dst[i] = src[i];
 }
 
+// First-fit allocator over one device buffer in 256-byte granules: the
+// images (and streamed chunks) of host-origin requests while they are in
+// flight.  Admission takes blocks from it and completion returns them, so
+// the device memory held by requests never exceeds the arena.
 class Arena {
   public:
     void reset(uint8_t *base, int64_t cap) {
