@@ -449,7 +449,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: this library runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(the multi-GPU design is described, not built)", file=sys.stderr)
         return 2
 

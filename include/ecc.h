@@ -43,7 +43,7 @@ typedef enum {
     ECC_E_STATE = -5,            /* streaming call out of order */
     ECC_E_NOMEM = -6,            /* device or pinned-host allocation failed */
     ECC_E_HIP = -7,              /* a HIP runtime call failed; message has hipGetErrorString */
-    ECC_E_UNSUPPORTED = -8       /* valid request this build does not implement */
+    ECC_E_UNSUPPORTED = -8       /* valid request this library does not implement */
 } ecc_status;
 
 /* Value types.  m is the number of thresholds t = 0..m-1 (Sec. 3, "Range of
@@ -174,7 +174,7 @@ int ecc_compute_async(const void *image_dev, const ecc_dims *dims, ecc_dtype dty
  * ecc_compute_async; it allocates no memory, host or device.  A launch uses
  * at most 1024 workgroups (larger images give each workgroup more tiles), so
  * every image ecc_compute_async takes fits; ECC_E_NOMEM reports a need
- * beyond the array, which this build does not produce.
+ * beyond the array, which this library does not produce.
  * Every call on one GPU shares that GPU's array and it keeps the last call's
  * contents: calls that overlap in time on one GPU (different streams, or
  * host threads) race and give wrong curves; order them, e.g. on one stream. */

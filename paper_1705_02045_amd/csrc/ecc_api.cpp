@@ -955,7 +955,7 @@ int compute_async_ws(const void *image_dev, const ecc_dims *dims, ecc_dtype dtyp
     }
     if (dtype != ECC_U8 && dtype != ECC_U14 && dtype != ECC_U16) {
         if (dtype == ECC_F32) {
-            set_error("ecc_compute_async: dtype %d not available in this build", (int)dtype);
+            set_error("ecc_compute_async: dtype %d not available in this library", (int)dtype);
             return ECC_E_UNSUPPORTED;
         }
         set_error("unknown dtype %d", (int)dtype);

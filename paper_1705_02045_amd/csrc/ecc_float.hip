@@ -323,7 +323,7 @@ static int float_grid(const ecc_dims *dims, FloatGrid *g) {
         if (dims->n[i] > 1) ext[d++] = (int32_t)dims->n[i];
     }
     if (total * 4 > (int64_t)UINT32_MAX) {
-        set_error("float images are limited to 2^30 elements in this build");
+        set_error("float images are limited to 2^30 elements");
         return ECC_E_UNSUPPORTED;
     }
     FloatView &v = g->v;

@@ -38,7 +38,7 @@ int scratch_for_current_device(uint8_t **out) {
     int dev = -1;
     ECC_HIP(hipGetDevice(&dev));
     if (dev < 0 || dev >= kMaxDevices) {
-        set_error("ecc_compute_async_noalloc: device %d beyond the %d this build tracks", dev, kMaxDevices);
+        set_error("ecc_compute_async_noalloc: device %d beyond the %d this library tracks", dev, kMaxDevices);
         return ECC_E_UNSUPPORTED;
     }
     std::lock_guard<std::mutex> lk(g_mu);

@@ -281,7 +281,7 @@ int ecc_stream_begin(const ecc_dims *full_dims, ecc_dtype dtype, void *stream, e
         }
     if (dtype != ECC_U8 && dtype != ECC_U14 && dtype != ECC_U16) {
         if (dtype == ECC_F32) {
-            set_error("streaming: dtype %d not available in this build", (int)dtype);
+            set_error("streaming: dtype %d not available in this library", (int)dtype);
             return ECC_E_UNSUPPORTED;
         }
         set_error("unknown dtype %d", (int)dtype);
